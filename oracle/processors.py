@@ -112,10 +112,16 @@ def hann_periodic(N: int) -> torch.Tensor:
     return 0.5 - 0.5 * torch.cos(2.0 * math.pi * n / N)
 
 
-def reverb_decay_bias(fs: int, hop: int) -> float:
-    """Per-frame log-magnitude decay added to the learnable decay vector so
-    that raw parameters near 0 give a 0.5 s RT60 (-60 dB = log(1e-3))."""
-    return -6.91 * hop / (0.5 * fs)
+def reverb_decay_offset(fs: int, hop: int) -> float:
+    """Offset beta of the decay map: softplus(beta) equals the per-frame
+    log-magnitude decay of a 0.5 s RT60 (-60 dB = log(1e-3) = -6.91)."""
+    return math.log(math.expm1(6.91 * hop / (0.5 * fs)))
+
+
+def reverb_decay(theta_d: torch.Tensor, fs: int, hop: int) -> torch.Tensor:
+    """Per-frame log-magnitude step of the reverb mask from the raw decay
+    parameter: -softplus(theta + beta) (always a decay; 0.5 s RT60 at 0)."""
+    return -torch.nn.functional.softplus(theta_d + reverb_decay_offset(fs, hop))
 
 
 def reverb_gain_bias(fs: int) -> float:
@@ -140,11 +146,11 @@ def reverb_fir(p: torch.Tensor, noise: torch.Tensor, fs: int, nfft: int = 384,
     """Stereo reverb FIR [2, Lr] (Sec. 3.4).
 
     For x in (mid, side): U_x = STFT of the fixed noise (periodic Hann, centred
-    frames, zero padding), mask M_x[k, m] = exp(H0[k] + g0 + m * (Hd[k] + b)) for the
+    frames, zero padding), mask M_x[k, m] = exp(H0[k] + g0 + m * d[k]) with the decay
+    d[k] = -softplus(Hd[k] + beta) (reverb_decay), for the
     nfft/2 bins below Nyquist (the Nyquist bin is 0), h_x = least-squares ISTFT
-    of U_x * M_x.  Then h_l = h_m + h_s and h_r = h_m - h_s.  b and the gain
-    bias g0 (added to H0) are the fixed offsets of reverb_decay_bias and
-    reverb_gain_bias."""
+    of U_x * M_x.  Then h_l = h_m + h_s and h_r = h_m - h_s.  The gain bias g0
+    (added to H0) is reverb_gain_bias."""
     nb = nfft // 2
     Lr = noise.shape[-1]
     pv = p.view(2, 2, nb)
@@ -152,7 +158,6 @@ def reverb_fir(p: torch.Tensor, noise: torch.Tensor, fs: int, nfft: int = 384,
     nf, idx = centred_frames(Lr, nfft, hop)
     valid = (idx >= 0) & (idx < Lr)
     safe = idx.clamp(0, Lr - 1)
-    bias = reverb_decay_bias(fs, hop)
     gbias = reverb_gain_bias(fs)
     m = torch.arange(nf, dtype=DT)[:, None]
     flat = idx.reshape(-1)
@@ -163,7 +168,7 @@ def reverb_fir(p: torch.Tensor, noise: torch.Tensor, fs: int, nfft: int = 384,
     for x in range(2):
         frames = torch.where(valid, noise[x][safe], torch.zeros((), dtype=DT)) * win
         U = torch.fft.rfft(frames, dim=-1)                         # [nf, nb+1]
-        mask = torch.exp(pv[x, 0][None, :] + gbias + m * (pv[x, 1][None, :] + bias))
+        mask = torch.exp(pv[x, 0][None, :] + gbias + m * reverb_decay(pv[x, 1], fs, hop)[None, :])
         Hm = torch.cat([U[:, :nb] * mask, torch.zeros(nf, 1, dtype=U.dtype)], dim=1)
         s = torch.fft.irfft(Hm, n=nfft, dim=-1) * win              # [nf, nfft]
         h = torch.zeros(Lr, dtype=DT)

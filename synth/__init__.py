@@ -404,26 +404,22 @@ def ground_truth_params(seed: int, graph: Graph, cfg: ConsoleConfig):
             hop = cfg.reverb_hop
             p = np.zeros((2, 2, nb))
             fk = np.arange(nb) * fs / cfg.reverb_nfft
-            bias = reverb_decay_bias_per_frame(cfg)
+            # raw values that the console maps to the drawn colouration and
+            # decay (inverse of the documented input conventions: gain offset
+            # -0.5 log(0.5 fs / (6 * 6.91)), decay -softplus(raw + beta))
+            beta = math.log(math.expm1(6.91 * hop / (0.5 * fs)))
             gbias = -0.5 * math.log(0.5 * fs / (6.0 * 6.91))
             for x in range(2):
                 rt60 = rng.uniform(0.3, 1.5)
                 dec = -6.91 * hop / (rt60 * fs) * np.where(fk > 4000.0, 1.5, 1.0)
                 p[x, 0] = rng.normal(-3.0, 0.3, size=nb) - gbias
-                p[x, 1] = dec - bias
+                p[x, 1] = np.log(np.expm1(-dec)) - beta
             p = p.reshape(-1)
         else:
             raise ValueError(t)
         theta[v] = np.asarray(p, dtype=np.float64).reshape(-1)
         wet[v] = float(_logit(rng.uniform(0.3, 0.95)))
     return theta, wet
-
-
-def reverb_decay_bias_per_frame(cfg: ConsoleConfig) -> float:
-    """Fixed per-frame log-decay added to every reverb's decay vector so that
-    the raw initialisation (all ~0) gives a 0.5 s RT60 instead of an undecayed
-    noise burst.  Stated as an input convention; both sides use this value."""
-    return -6.91 * cfg.reverb_hop / (0.5 * cfg.fs)
 
 
 def init_params(seed: int, graph: Graph, cfg: ConsoleConfig, std: float = 0.1):
@@ -446,6 +442,17 @@ def random_params(seed: int, graph: Graph, cfg: ConsoleConfig, std: float = 0.3)
     rng = _rng(seed, 977)
     th = {v: gt[v] + rng.normal(0.0, std, size=gt[v].shape) for v in gt}
     we = {v: gw[v] + float(rng.normal(0.0, std)) for v in gw}
+    # delay angular frequencies stay inside the unit disk, where the
+    # surrogate of Sec. 3.7 is defined: radius drawn in [0.5, 0.95]
+    Kc = (cfg.delay_fir_taps + 1) // 2
+    for v, t in enumerate(graph.types):
+        if t == "d":
+            p = th[v].reshape(2, cfg.delay_taps, 2 + Kc)
+            r = rng.uniform(0.5, 0.95, size=(2, cfg.delay_taps))
+            ang = np.arctan2(p[:, :, 1], p[:, :, 0])
+            p[:, :, 0] = r * np.cos(ang)
+            p[:, :, 1] = r * np.sin(ang)
+            th[v] = p.reshape(-1)
     return th, we
 
 

@@ -118,7 +118,7 @@ def test_reverb_unit_mask_reconstructs_noise():
     noise = torch.tensor(rng.uniform(-1, 1, (2, Lr)), dtype=DT)
     p = torch.zeros(2, 2, 192, dtype=DT)
     p[:, 0] = -P.reverb_gain_bias(fs)
-    p[:, 1] = -P.reverb_decay_bias(fs, 192)
+    p[:, 1] = -80.0                 # decay -softplus(-80 + beta) ~ -1e-35 per frame
     h = P.reverb_fir(p.reshape(-1), noise, fs)
     # removing the Nyquist bin removes the (-1)^n component of each frame;
     # compare against the noise with that component projected out per frame
@@ -154,7 +154,7 @@ def test_reverb_unit_mask_on_bin_sinusoids_is_exact():
     noise = torch.tensor(sig, dtype=DT)
     p = torch.zeros(2, 2, 192, dtype=DT)
     p[:, 0] = -P.reverb_gain_bias(fs)
-    p[:, 1] = -P.reverb_decay_bias(fs, 192)
+    p[:, 1] = -80.0
     h = P.reverb_fir(p.reshape(-1), noise, fs)
     sl = slice(192, Lr - 192)
     assert torch.allclose(h[0, sl], (noise[0] + noise[1])[sl], atol=1e-12)
@@ -171,6 +171,17 @@ def test_stft_frames_match_explicit_dft():
     ref = Dm @ (x * win)
     got = torch.fft.rfft(torch.tensor(x * win)).numpy()
     assert np.allclose(got, ref, atol=1e-11)
+
+
+def test_reverb_decay_map():
+    """theta = 0 gives the 0.5 s RT60 step; the step is always a decay and
+    approaches 0 (no decay) for very negative theta."""
+    fs, hop = 44100, 192
+    d0 = float(P.reverb_decay(torch.tensor(0.0, dtype=DT), fs, hop))
+    assert abs(d0 - (-6.91 * hop / (0.5 * fs))) < 1e-15
+    th = torch.linspace(-40, 40, 101, dtype=DT)
+    d = P.reverb_decay(th, fs, hop)
+    assert bool((d < 0).all()) and bool((d[1:] < d[:-1]).all())
 
 
 def test_reverb_output_is_causal_direct_convolution():
@@ -394,7 +405,8 @@ def test_reverb_frame_decay_closed_form():
     noise = torch.tensor(np.stack([x, np.zeros(Lr)]), dtype=DT)
     p = torch.zeros(2, 2, 192, dtype=DT)
     p[:, 0] = c0 - P.reverb_gain_bias(fs)
-    p[:, 1] = delta - P.reverb_decay_bias(fs, hop)
+    # raw decay that maps to delta: softplus(theta + beta) = -delta
+    p[:, 1] = math.log(math.expm1(-delta)) - P.reverb_decay_offset(fs, hop)
     h = P.reverb_fir(p.reshape(-1), noise, fs).numpy()
     w2 = P.hann_periodic(384).numpy() ** 2
     q, r = n // hop, n % hop
