@@ -1,0 +1,182 @@
+/* mixgraph: batched mixing-console forward/backward, MRSTFT loss and masked
+ * pruning evaluation on one MI355X (gfx950).
+ *
+ * The calls follow the problem statement of "Reverse Engineering of Music
+ * Mixing Graphs with Differentiable Processors and Iterative Pruning"
+ * (arxiv 2509.15948): given dry tracks S, a graph G = (T, E) (Sec. 1.1,
+ * Sec. 4: node-type vector and 2 x |E| edge tensor), parameters
+ * P = (P_bar, w) and dry/wet masks, compute the mix y_hat = G(S; P)
+ * (Alg. 1), the audio loss L_a and regularisers (Sec. 5.1, Sec. 6.3), and
+ * gradients of L with respect to P_bar and the dry/wet logits.
+ *
+ * Conventions shared by every call
+ *  - Return value: MG_OK (0) or one of the MG_ERR_* codes below; after a
+ *    failure mg_last_error() returns a message (thread-local, valid until the
+ *    next call on the same thread).  Nothing is thrown across the ABI.
+ *  - "dev" pointers are HIP device memory owned by the caller; "host"
+ *    pointers are ordinary host memory owned by the caller.  The library owns
+ *    only the mg_graph object (host memory) and never allocates device memory:
+ *    every device buffer it uses lives in the caller's workspace.
+ *  - stream is a hipStream_t passed as void*; compute calls only enqueue
+ *    work on it and return.  Results are valid after the stream completes.
+ *    Asynchronous device faults surface as MG_ERR_HIP on a later call.
+ *  - Audio is FP32, planar [channel][sample]; a track is [C][L] with C = 1
+ *    (mono, used for both channels) or C = 2.
+ *  - Parameters: theta is one flat FP32 vector; for each processor type t in
+ *    the order e c n x s g d r it holds the block P[t] of shape [|V_t|][N_t],
+ *    rows in the library's node order sigma (Alg. 1 "Reorder").  The offset
+ *    of every node's row is reported by mg_graph_layout.  The dry/wet logits
+ *    are a separate FP32 vector wet[P] over processors in sigma order
+ *    (w = sigmoid(logit) * mask, Sec. 5.1 initialisation).
+ */
+#ifndef MIXGRAPH_H
+#define MIXGRAPH_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum mg_status {
+  MG_OK = 0,
+  MG_ERR_INVALID_ARG = 1, /* null pointer, bad size or unsupported option  */
+  MG_ERR_GRAPH = 2,       /* cycle, bad arity, unknown type, != 1 output    */
+  MG_ERR_SHAPE = 3,       /* sizes inconsistent with the graph or workspace */
+  MG_ERR_STATE = 4,       /* call order violated (e.g. backward w/o forward) */
+  MG_ERR_HIP = 5          /* a HIP runtime call failed                      */
+};
+
+/* Node types (Sec. 1.1): auxiliary input i, mix m, output o; processors
+ * equalizer e, compressor c, noisegate n, tanh waveshaper x, stereo imager s,
+ * gain/panning g, multitap delay d, reverb r. */
+enum mg_type {
+  MG_IN = 0, MG_MIX = 1, MG_OUT = 2, MG_EQ = 3, MG_COMP = 4, MG_GATE = 5,
+  MG_DIST = 6, MG_IMAGER = 7, MG_GAINPAN = 8, MG_DELAY = 9, MG_REVERB = 10
+};
+
+/* Per-graph configuration.  Sizes of the processors (Sec. 3) and the loss
+ * (Sec. 5.1). */
+typedef struct mg_config {
+  int64_t length;          /* L: samples per channel                          */
+  int32_t sample_rate;     /* fs in Hz                                        */
+  int32_t eq_taps;         /* N of the zero-phase EQ FIR, odd (Sec. 3.3)      */
+  int32_t comp_mode;       /* 0: one coefficient (Sec. 3.5); 1: attack/release */
+  int32_t delay_taps;      /* M delays per channel (Sec. 3.7)                 */
+  int32_t delay_range;     /* D: samples per delay range                      */
+  int32_t delay_fir_taps;  /* length of each tap's zero-phase FIR, odd        */
+  int32_t reverb_length;   /* L_r: reverb FIR length (Sec. 3.4)              */
+  int32_t reverb_nfft;     /* STFT size of the reverb mask (384)              */
+  int32_t reverb_hop;      /* hop (nfft / 2)                                  */
+  int32_t n_loss_ffts;     /* number of MRSTFT resolutions (<= 8)             */
+  int32_t loss_ffts[8];    /* FFT sizes, powers of two in [64, 4096]          */
+  int32_t n_mels;          /* Mel bands (96)                                  */
+  int32_t loss_skip;       /* leading samples excluded from the loss          */
+  double alpha_g;          /* gain-staging regulariser weight                 */
+  double alpha_p;          /* dry/wet l1 regulariser weight                   */
+} mg_config;
+
+typedef struct mg_graph mg_graph;
+
+/* Sizes derived by mg_graph_create. */
+typedef struct mg_info {
+  int32_t n_nodes;
+  int32_t n_processors;    /* P: length of the dry/wet logit and mask vectors */
+  int32_t n_stages;        /* N + 1 of Alg. 1, input stage included          */
+  int32_t fft_size;        /* FFT length used for the FIR convolutions        */
+  int64_t n_theta;         /* length of the flat parameter vector             */
+  int32_t n_reverbs;       /* rows of the reverb noise input                  */
+  int32_t n_losses;        /* values written per loss record (7)              */
+} mg_info;
+
+/* Validate a graph and build its schedule, node order and parameter layout
+ * on the host (Alg. 1 ScheduleBatchedProcessing, OptimizeNodeOrder,
+ * Reorder, GetReadWriteIndex; Sec. 4.2 type scheduling).
+ *   types       host int32[n_nodes], values of enum mg_type
+ *   edges       host int32[2][n_edges]: row 0 sources, row 1 destinations
+ *   input_track host int32[n_nodes]: dry-track index of each MG_IN node,
+ *               ignored for other nodes
+ *   n_tracks, track_channels: shape [n_tracks][track_channels][L] of the dry
+ *               input; track_channels is 1 or 2
+ *   cfg         host, copied
+ * Errors: MG_ERR_GRAPH for a cycle, an unknown type, an input with
+ * predecessors, a processor or mix without inputs, an output count != 1, a
+ * node that cannot reach the output; MG_ERR_INVALID_ARG for bad sizes.     */
+int mg_graph_create(int32_t n_nodes, const int32_t* types, int32_t n_edges,
+                    const int32_t* edges, const int32_t* input_track,
+                    int32_t n_tracks, int32_t track_channels,
+                    const mg_config* cfg, mg_graph** out);
+
+int mg_graph_destroy(mg_graph* g);
+
+int mg_graph_info(const mg_graph* g, mg_info* out);
+
+/* Layout of the parameters and schedule (all host arrays of n_nodes, any may
+ * be NULL):
+ *   param_offset  offset of the node's row in theta, -1 for i/m/o
+ *   proc_index    index of the node in wet/mask vectors, -1 for i/m/o
+ *   stage         stage (0 = inputs) of Alg. 1's subset sequence
+ *   type_row      row of the node inside its type block P[t]
+ *   schedule      host char[n_stages + 1]: the type string, NUL-terminated */
+int mg_graph_layout(const mg_graph* g, int64_t* param_offset, int32_t* proc_index,
+                    int32_t* stage, int32_t* type_row, char* schedule);
+
+/* Device workspace needed by the graph (bytes).  mode 0: forward only;
+ * mode 1: forward and backward. */
+int mg_workspace_size(const mg_graph* g, int32_t mode, size_t* bytes);
+
+/* Bind a caller-owned device workspace (>= mg_workspace_size bytes, 256-byte
+ * aligned) and prepare per-graph device tables: FFT twiddles, Mel/A-weight
+ * tables, the STFT of every reverb's fixed noise, and the Mel spectra of the
+ * target mix (Sec. 5.1, "target features are resident").
+ *   reverb_noise dev float[n_reverbs][2][L_r], rows in type_row order of the
+ *                reverb nodes: uniform noise for the mid and side FIR (Sec. 3.4)
+ *   target       dev float[2][L]: the target mix y                            */
+int mg_setup(mg_graph* g, void* workspace, size_t workspace_bytes, int32_t mode,
+             const float* reverb_noise, const float* target, void* stream);
+
+/* Alg. 1 forward pass and the loss (Sec. 5.1):
+ *   dry      dev float[n_tracks][track_channels][L]
+ *   theta    dev float[n_theta]
+ *   wet      dev float[P] dry/wet logits
+ *   mask     dev float[P] multiplied into w (Alg. 2 Evaluate), or NULL
+ *   mix      dev float[2][L] output y_hat, or NULL
+ *   losses   dev double[7]: L, L_a, L_lr, L_m, L_s, L_g, L_p, with
+ *            L = L_a + alpha_g L_g + alpha_p L_p
+ * With mode 1 the forward also keeps what mg_backward needs in the
+ * workspace; dry/theta/wet/mask must stay unchanged until mg_backward. */
+int mg_forward(mg_graph* g, const float* dry, const float* theta, const float* wet,
+               const float* mask, float* mix, double* losses, void* stream);
+
+/* Gradients of L from the last mg_forward (hand-written adjoints of every
+ * processor, Sec. 3; delay z entries follow the Sec. 3.7 update rule).
+ *   grad_theta dev float[n_theta] (overwritten)
+ *   grad_wet   dev float[P]       (overwritten)                              */
+int mg_backward(mg_graph* g, float* grad_theta, float* grad_wet, void* stream);
+
+/* Pruning trials (Alg. 2 Evaluate with w * m * m_cand): the forward pass and
+ * loss for B masks, one after another on the stream, all results kept.
+ *   masks  dev float[B][P];  losses dev double[B][7].                        */
+int mg_forward_masked(mg_graph* g, const float* dry, const float* theta, const float* wet,
+                      const float* masks, int32_t B, double* losses, void* stream);
+
+/* One Adam step (Kingma & Ba) on n parameters, in place on theta, m, v.
+ * step counts from 1.  All pointers dev float[n]. */
+int mg_adam_step(float* theta, float* m, float* v, const float* grad, int64_t n,
+                 float lr, float beta1, float beta2, float eps, int32_t step, void* stream);
+
+/* Graph surgery for pruning (Sec. 1.2: removing a node and rerouting its
+ * edges is equivalent to bypass).  keep: host uint8[P] over processors in
+ * proc_index order.  Produces a new graph; old_to_new (host int32[n_nodes],
+ * may be NULL) maps old node ids to new ids (-1 for removed nodes).  The new
+ * graph has its own layout and needs its own workspace and mg_setup. */
+int mg_graph_prune(const mg_graph* g, const uint8_t* keep, mg_graph** out,
+                   int32_t* old_to_new);
+
+const char* mg_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,739 @@
+// FIR convolution engine: FP32 four-step FFT of length N = N1 * N2 over HBM,
+// each sub-transform staged in LDS (mg_device.h), used by every FIR processor
+// of the console (Sec. 3.3 equalizer, Sec. 3.4 reverb, Sec. 3.7 multitap
+// delay) for the forward convolution and for both backward correlations.
+//
+// Index map: x[n1 + N1 n2]; spectrum stored as S[k2][k1] = X[k2 + N2 k1].
+//   cols  (KA): per column n1, FFT over n2 (length N2), twiddle W_N^{n1 k2},
+//               write T[k2][n1]                       (loader functor fills x)
+//   rows  (KB): per row pair (k2, N2-k2), FFT over n1 (length N1) -> S rows,
+//               spectral product (with the mirrored bins that separate the
+//               packed left/right spectra), inverse FFT over k1, twiddle
+//               W_N^{-n1 k2}
+//   icols (KC): per column n1, inverse FFT over k2, scale 1/N (store functor
+//               consumes x: dry/wet output, input gradient or FIR gradient)
+// Stereo signals are packed as l + i r; the FIRs as h_l + i h_r.  With N at
+// least L plus the FIR's extent, circular convolution equals the linear one.
+#include <cstring>
+#include <vector>
+
+#include "mg_device.h"
+#include "mg_kernels.h"
+
+namespace mg {
+
+// W_N^e for e in [0, N), from two FP32 tables rounded from FP64 on the host:
+// twhi[j] = W_N^{1024 j}, twlo[j] = W_N^j.
+__device__ __forceinline__ float2 big_tw(const float2* __restrict__ twhi, const float2* __restrict__ twlo, int64_t e) {
+  return c_mul(twhi[e >> 10], twlo[e & 1023]);
+}
+
+__device__ __forceinline__ int64_t signed_lag(int64_t n, int64_t N) { return n < N / 2 ? n : n - N; }
+
+struct EngineArgs {
+  int N, N1, N2;
+  const float2* tw;
+  const float2* twhi;
+  const float2* twlo;
+};
+
+// ---------------------------------------------------------------- loaders
+struct NodeView {
+  const NodeDesc* desc;
+  const float* dry;
+  const float* U;
+  const float* G;
+  int64_t L;
+  int C;
+};
+
+__device__ __forceinline__ const float* node_input(const NodeView& v, const NodeDesc& d, int64_t& cs) {
+  if (d.in_kind == 0) {
+    cs = (v.C == 1) ? 0 : v.L;
+    return v.dry + (int64_t)d.in_slot * v.C * v.L;
+  }
+  cs = v.L;
+  return v.U + (int64_t)d.in_slot * 2 * v.L;
+}
+
+// forward input u packed l + i r
+struct LdSignal {
+  NodeView v;
+  const float* u;
+  int64_t cs;
+  __device__ void begin(int j) {
+    const NodeDesc d = v.desc[j];
+    u = node_input(v, d, cs);
+  }
+  __device__ float2 load(int64_t n) const { return n < v.L ? make_float2(u[n], u[cs + n]) : make_float2(0.f, 0.f); }
+  __device__ void end(int, int) {}
+};
+
+// compact FIR [2][Nh] (or [Nh] shared) whose first tap sits at lag lag0
+struct LdFir {
+  const NodeDesc* desc;
+  const float* h;      // base of the compact FIRs of this type
+  int64_t Nh, lag0, N, stride;
+  int shared;          // 1: one FIR for both channels
+  const float* hl;
+  const float* hr;
+  __device__ void begin(int j) {
+    const NodeDesc d = desc[j];
+    hl = h + (int64_t)d.aux * stride;
+    hr = shared ? hl : hl + Nh;
+  }
+  __device__ float2 load(int64_t n) const {
+    const int64_t i = signed_lag(n, N) - lag0;
+    return (i >= 0 && i < Nh) ? make_float2(hl[i], hr[i]) : make_float2(0.f, 0.f);
+  }
+  __device__ void end(int, int) {}
+};
+
+// multitap delay FIR from its tap table: per node [2][M] delays (as float
+// holding an exact integer) followed by [2][M][taps] coefficients
+struct LdDelay {
+  const NodeDesc* desc;
+  const float* tab;
+  int M, taps, half;
+  int64_t N, stride;
+  const float* t;
+  __device__ void begin(int j) { t = tab + (int64_t)desc[j].aux * stride; }
+  __device__ float2 load(int64_t n) const {
+    const int64_t lag = signed_lag(n, N);
+    float a[2] = {0.f, 0.f};
+    for (int c = 0; c < 2; ++c)
+      for (int m = 0; m < M; ++m) {
+        const int64_t k = lag - (int64_t)t[c * M + m] + half;
+        if (k >= 0 && k < taps) a[c] += t[2 * M + (c * M + m) * taps + k];
+      }
+    return make_float2(a[0], a[1]);
+  }
+  __device__ void end(int, int) {}
+};
+
+// backward: dL/dybar = w dL/dy + alpha_g s ybar_m / E_ybar, and the dry/wet
+// partial sum of dL/dy * (ybar - u)
+struct LdGrad {
+  NodeView v;
+  const float* ybar_base;
+  const double* lg;
+  const float* wet;
+  const float* mask;
+  float alpha_g;
+  int yb0;             // ybar slot of type row 0
+  float* part;
+  int PB;
+  const float* dy;
+  const float* yb;
+  const float* u;
+  int64_t cs;
+  float w, kreg;
+  float acc;
+  __device__ void begin(int j) {
+    const NodeDesc d = v.desc[j];
+    u = node_input(v, d, cs);
+    dy = v.G + (int64_t)d.gout * 2 * v.L;
+    yb = ybar_base + (int64_t)(yb0 + d.aux) * 2 * v.L;
+    w = 1.0f / (1.0f + expf(-wet[d.proc]));
+    if (mask) w *= mask[d.proc];
+    const double Ey = lg[2 * j] + 1e-12, Eu = lg[2 * j + 1] + 1e-12;
+    const double diff = 0.5 * log(Ey) - 0.5 * log(Eu);
+    const double s = diff > 0 ? 1.0 : (diff < 0 ? -1.0 : 0.0);
+    kreg = (float)((double)alpha_g * s / Ey);
+    acc = 0.f;
+  }
+  __device__ float2 load(int64_t n) {
+    if (n >= v.L) return make_float2(0.f, 0.f);
+    const float gl = dy[n], gr = dy[v.L + n];
+    const float bl = yb[n], br = yb[v.L + n];
+    acc += gl * (bl - u[n]) + gr * (br - u[cs + n]);
+    const float rm = kreg * (bl + br);
+    return make_float2(w * gl + rm, w * gr + rm);
+  }
+  __device__ void end(int j, int blk) {
+    __shared__ float red[MG_BLOCK];
+    const float s = block_sum<MG_BLOCK>(acc, red);
+    if (threadIdx.x == 0) part[((int64_t)j * PB + blk) * PK + 2] = s;
+  }
+};
+
+// ---------------------------------------------------------------- stores
+// forward: ybar from the engine; y = w ybar + (1 - w) u; L_g energies
+struct StFwd {
+  NodeView v;
+  float* ybar_base;
+  const float* wet;
+  const float* mask;
+  int yb0;
+  float* part;
+  int PB;
+  float* y;
+  float* yb;
+  const float* u;
+  int64_t cs;
+  float w, ey, eu;
+  __device__ void begin(int j) {
+    const NodeDesc d = v.desc[j];
+    u = node_input(v, d, cs);
+    y = const_cast<float*>(v.U) + (int64_t)d.out_slot * 2 * v.L;
+    yb = ybar_base ? ybar_base + (int64_t)(yb0 + d.aux) * 2 * v.L : nullptr;
+    w = 1.0f / (1.0f + expf(-wet[d.proc]));
+    if (mask) w *= mask[d.proc];
+    ey = eu = 0.f;
+  }
+  __device__ void store(int64_t n, float2 val) {
+    if (n >= v.L) return;
+    const float l = u[n], r = u[cs + n];
+    if (yb) {
+      yb[n] = val.x;
+      yb[v.L + n] = val.y;
+    }
+    y[n] = w * val.x + (1.0f - w) * l;
+    y[v.L + n] = w * val.y + (1.0f - w) * r;
+    const float m = val.x + val.y, um = l + r;
+    ey += m * m;
+    eu += um * um;
+  }
+  __device__ void end(int j, int blk) {
+    __shared__ float red[MG_BLOCK];
+    const float a = block_sum<MG_BLOCK>(ey, red);
+    const float b = block_sum<MG_BLOCK>(eu, red);
+    if (threadIdx.x == 0) {
+      part[((int64_t)j * PB + blk) * PK + 0] = a;
+      part[((int64_t)j * PB + blk) * PK + 1] = b;
+    }
+  }
+};
+
+// backward dL/du = (1 - w) dL/dy + corr(dL/dybar, h) - alpha_g s u_m / E_u
+struct StGradU {
+  NodeView v;
+  const double* lg;
+  const float* wet;
+  const float* mask;
+  float alpha_g;
+  float* gin;
+  const float* dy;
+  const float* u;
+  int64_t cs;
+  float w, kreg;
+  bool active;
+  __device__ void begin(int j) {
+    const NodeDesc d = v.desc[j];
+    active = d.gin >= 0;
+    gin = active ? const_cast<float*>(v.G) + (int64_t)d.gin * 2 * v.L : nullptr;
+    dy = v.G + (int64_t)d.gout * 2 * v.L;
+    u = node_input(v, d, cs);
+    w = 1.0f / (1.0f + expf(-wet[d.proc]));
+    if (mask) w *= mask[d.proc];
+    const double Ey = lg[2 * j] + 1e-12, Eu = lg[2 * j + 1] + 1e-12;
+    const double diff = 0.5 * log(Ey) - 0.5 * log(Eu);
+    const double s = diff > 0 ? 1.0 : (diff < 0 ? -1.0 : 0.0);
+    kreg = (float)((double)alpha_g * s / Eu);
+  }
+  __device__ void store(int64_t n, float2 val) {
+    if (!active || n >= v.L) return;
+    const float um = u[n] + u[cs + n];
+    gin[n] = (1.0f - w) * dy[n] + val.x - kreg * um;
+    gin[v.L + n] = (1.0f - w) * dy[v.L + n] + val.y - kreg * um;
+  }
+  __device__ void end(int, int) {}
+};
+
+// backward dL/dh at the FIR's lags: compact [2][Nh] (shared: [Nh], channels summed)
+struct StGradH {
+  const NodeDesc* desc;
+  float* dh;
+  int64_t Nh, lag0, N, stride;
+  int shared;
+  float* o;
+  __device__ void begin(int j) { o = dh + (int64_t)desc[j].aux * stride; }
+  __device__ void store(int64_t n, float2 val) {
+    const int64_t i = signed_lag(n, N) - lag0;
+    if (i < 0 || i >= Nh) return;
+    if (shared) o[i] = val.x + val.y;
+    else {
+      o[i] = val.x;
+      o[Nh + i] = val.y;
+    }
+  }
+  __device__ void end(int, int) {}
+};
+
+// ---------------------------------------------------------------- KA: columns forward
+template <int N2, int TC, typename LD>
+__global__ __launch_bounds__(MG_BLOCK) void k_cols(LD ld, float2* __restrict__ T, EngineArgs ea) {
+  constexpr int BS = N2 + 1;
+  __shared__ float2 buf[TC * BS];
+  const int j = blockIdx.y;
+  const int c0 = blockIdx.x * TC;
+  const int N1 = ea.N1;
+  ld.begin(j);
+  for (int idx = threadIdx.x; idx < TC * N2; idx += MG_BLOCK) {
+    const int n2 = idx / TC, cc = idx % TC;
+    buf[cc * BS + n2] = ld.load((int64_t)(c0 + cc) + (int64_t)N1 * n2);
+  }
+  ld.end(j, blockIdx.x);
+  __syncthreads();
+  fft_lds<N2, TC, BS, MG_BLOCK, -1>(buf, ea.tw);
+  float2* Tn = T + (int64_t)j * ea.N;
+  const int64_t mask = ea.N - 1;
+  for (int idx = threadIdx.x; idx < TC * N2; idx += MG_BLOCK) {
+    const int k2 = idx / TC, cc = idx % TC;
+    const int n1 = c0 + cc;
+    const float2 w = big_tw(ea.twhi, ea.twlo, ((int64_t)n1 * k2) & mask);
+    Tn[(int64_t)k2 * N1 + n1] = c_mul(buf[cc * BS + k2], w);
+  }
+}
+
+// ---------------------------------------------------------------- KC: columns inverse
+template <int N2, int TC, typename ST>
+__global__ __launch_bounds__(MG_BLOCK) void k_icols(ST st, const float2* __restrict__ T, EngineArgs ea) {
+  constexpr int BS = N2 + 1;
+  __shared__ float2 buf[TC * BS];
+  const int j = blockIdx.y;
+  const int c0 = blockIdx.x * TC;
+  const int N1 = ea.N1;
+  const float2* Tn = T + (int64_t)j * ea.N;
+  for (int idx = threadIdx.x; idx < TC * N2; idx += MG_BLOCK) {
+    const int k2 = idx / TC, cc = idx % TC;
+    buf[cc * BS + k2] = Tn[(int64_t)k2 * N1 + c0 + cc];
+  }
+  __syncthreads();
+  fft_lds<N2, TC, BS, MG_BLOCK, +1>(buf, ea.tw);
+  const float sc = 1.0f / (float)ea.N;
+  st.begin(j);
+  for (int idx = threadIdx.x; idx < TC * N2; idx += MG_BLOCK) {
+    const int n2 = idx / TC, cc = idx % TC;
+    st.store((int64_t)(c0 + cc) + (int64_t)N1 * n2, c_scale(buf[cc * BS + n2], sc));
+  }
+  st.end(j, blockIdx.x);
+}
+
+// ---------------------------------------------------------------- KB: rows
+// the two rows of workgroup p: (0, N2/2) for p = 0, else (p, N2 - p)
+__device__ __forceinline__ void row_pair(int p, int N2, int& ra, int& rb) {
+  ra = p;
+  rb = (p == 0) ? N2 / 2 : N2 - p;
+}
+
+// pair q of workgroup p -> LDS indices (ia, ib) of bin k and bin -k.
+// returns false when q is past the end.
+template <int N1>
+__device__ __forceinline__ bool mirror_pair(int p, int q, int& ia, int& ib) {
+  if (p != 0) {
+    if (q >= N1) return false;
+    ia = q;
+    ib = N1 + (N1 - 1 - q);
+    return true;
+  }
+  if (q <= N1 / 2) {  // row 0: k1 <-> (N1 - k1) mod N1
+    ia = q;
+    ib = (N1 - q) & (N1 - 1);
+    return true;
+  }
+  q -= N1 / 2 + 1;   // row N2/2: k1 <-> N1 - 1 - k1
+  if (q >= N1 / 2) return false;
+  ia = N1 + q;
+  ib = N1 + (N1 - 1 - q);
+  return true;
+}
+
+__device__ __forceinline__ void split_lr(float2 z, float2 zm, float2& l, float2& r) {
+  // l = (z + conj(zm)) / 2, r = -i (z - conj(zm)) / 2
+  l = make_float2(0.5f * (z.x + zm.x), 0.5f * (z.y - zm.y));
+  const float2 d = make_float2(0.5f * (z.x - zm.x), 0.5f * (z.y + zm.y));
+  r = make_float2(d.y, -d.x);
+}
+
+__device__ __forceinline__ float2 pack_lr(float2 l, float2 r) {  // l + i r
+  return make_float2(l.x - r.y, l.y + r.x);
+}
+
+template <int N1>
+__device__ __forceinline__ void load_rows(float2* buf, const float2* __restrict__ Tn, int ra, int rb) {
+  for (int i = threadIdx.x; i < N1; i += MG_BLOCK) {
+    buf[i] = Tn[(int64_t)ra * N1 + i];
+    buf[N1 + i] = Tn[(int64_t)rb * N1 + i];
+  }
+}
+
+template <int N1>
+__device__ __forceinline__ void store_rows(const float2* buf, float2* __restrict__ To, int ra, int rb,
+                                           const EngineArgs& ea) {
+  const int64_t mask = ea.N - 1;
+  for (int i = threadIdx.x; i < N1; i += MG_BLOCK) {
+    float2 wa = big_tw(ea.twhi, ea.twlo, ((int64_t)i * ra) & mask);
+    float2 wb = big_tw(ea.twhi, ea.twlo, ((int64_t)i * rb) & mask);
+    To[(int64_t)ra * N1 + i] = c_mul(buf[i], c_conj(wa));
+    To[(int64_t)rb * N1 + i] = c_mul(buf[N1 + i], c_conj(wb));
+  }
+}
+
+// spectrum only: S rows of the FIR -> ZH
+template <int N1>
+__global__ __launch_bounds__(MG_BLOCK) void k_rows_spec(const float2* __restrict__ T, float2* __restrict__ Z,
+                                                         int z0, const NodeDesc* __restrict__ desc, EngineArgs ea) {
+  __shared__ float2 buf[2 * N1];
+  const int j = blockIdx.y;
+  int ra, rb;
+  row_pair(blockIdx.x, ea.N2, ra, rb);
+  load_rows<N1>(buf, T + (int64_t)j * ea.N, ra, rb);
+  __syncthreads();
+  fft_lds<N1, 2, N1, MG_BLOCK, -1>(buf, ea.tw);
+  float2* Zn = Z + (int64_t)(z0 + desc[j].aux) * ea.N;
+  for (int i = threadIdx.x; i < N1; i += MG_BLOCK) {
+    Zn[(int64_t)ra * N1 + i] = buf[i];
+    Zn[(int64_t)rb * N1 + i] = buf[N1 + i];
+  }
+}
+
+// forward convolution: Y = Xl Hl + i Xr Hr
+template <int N1>
+__global__ __launch_bounds__(MG_BLOCK) void k_rows_conv(const float2* __restrict__ Tin, float2* __restrict__ Tout,
+                                                         const float2* __restrict__ ZH, float2* __restrict__ ZU,
+                                                         int z0, const NodeDesc* __restrict__ desc, EngineArgs ea) {
+  __shared__ float2 buf[2 * N1];
+  const int j = blockIdx.y;
+  const int p = blockIdx.x;
+  int ra, rb;
+  row_pair(p, ea.N2, ra, rb);
+  load_rows<N1>(buf, Tin + (int64_t)j * ea.N, ra, rb);
+  __syncthreads();
+  fft_lds<N1, 2, N1, MG_BLOCK, -1>(buf, ea.tw);
+  const int64_t zr = (int64_t)(z0 + desc[j].aux) * ea.N;
+  const float2* H = ZH + zr;
+  if (ZU) {
+    float2* Zs = ZU + zr;
+    for (int i = threadIdx.x; i < N1; i += MG_BLOCK) {
+      Zs[(int64_t)ra * N1 + i] = buf[i];
+      Zs[(int64_t)rb * N1 + i] = buf[N1 + i];
+    }
+  }
+  for (int q = threadIdx.x; q < N1 + 1; q += MG_BLOCK) {
+    int ia, ib;
+    if (!mirror_pair<N1>(p, q, ia, ib)) continue;
+    const int64_t ga = (ia < N1) ? (int64_t)ra * N1 + ia : (int64_t)rb * N1 + (ia - N1);
+    const int64_t gb = (ib < N1) ? (int64_t)ra * N1 + ib : (int64_t)rb * N1 + (ib - N1);
+    const float2 za = buf[ia], zb = buf[ib];
+    const float2 ha = H[ga], hb = H[gb];
+    float2 xl, xr, hl, hr;
+    split_lr(za, zb, xl, xr);
+    split_lr(ha, hb, hl, hr);
+    const float2 ya = pack_lr(c_mul(xl, hl), c_mul(xr, hr));
+    split_lr(zb, za, xl, xr);
+    split_lr(hb, ha, hl, hr);
+    const float2 yb = pack_lr(c_mul(xl, hl), c_mul(xr, hr));
+    buf[ia] = ya;
+    buf[ib] = yb;
+  }
+  __syncthreads();
+  fft_lds<N1, 2, N1, MG_BLOCK, +1>(buf, ea.tw);
+  store_rows<N1>(buf, Tout + (int64_t)j * ea.N, ra, rb, ea);
+}
+
+// backward: P1 = Gl conj(Hl) + i Gr conj(Hr)   (input gradient)
+//           P2 = Gl conj(Xl) + i Gr conj(Xr)   (FIR gradient)
+template <int N1>
+__global__ __launch_bounds__(MG_BLOCK) void k_rows_bwd(const float2* __restrict__ Tin, float2* __restrict__ Tu,
+                                                        float2* __restrict__ Th, const float2* __restrict__ ZH,
+                                                        const float2* __restrict__ ZU, int z0,
+                                                        const NodeDesc* __restrict__ desc, int want_u,
+                                                        EngineArgs ea) {
+  __shared__ float2 buf[4 * N1];
+  float2* b1 = buf;
+  float2* b2 = buf + 2 * N1;
+  const int j = blockIdx.y;
+  const int p = blockIdx.x;
+  int ra, rb;
+  row_pair(p, ea.N2, ra, rb);
+  load_rows<N1>(b1, Tin + (int64_t)j * ea.N, ra, rb);
+  __syncthreads();
+  fft_lds<N1, 2, N1, MG_BLOCK, -1>(b1, ea.tw);
+  const int64_t zr = (int64_t)(z0 + desc[j].aux) * ea.N;
+  const float2* H = ZH + zr;
+  const float2* X = ZU + zr;
+  for (int q = threadIdx.x; q < N1 + 1; q += MG_BLOCK) {
+    int ia, ib;
+    if (!mirror_pair<N1>(p, q, ia, ib)) continue;
+    const int64_t ga = (ia < N1) ? (int64_t)ra * N1 + ia : (int64_t)rb * N1 + (ia - N1);
+    const int64_t gb = (ib < N1) ? (int64_t)ra * N1 + ib : (int64_t)rb * N1 + (ib - N1);
+    const float2 za = b1[ia], zb = b1[ib];
+    const float2 ha = H[ga], hb = H[gb];
+    const float2 xa = X[ga], xb = X[gb];
+    float2 gl, gr, hl, hr, xl, xr;
+    // bin k
+    split_lr(za, zb, gl, gr);
+    split_lr(ha, hb, hl, hr);
+    split_lr(xa, xb, xl, xr);
+    const float2 u_a = pack_lr(c_mulc(gl, hl), c_mulc(gr, hr));
+    const float2 h_a = pack_lr(c_mulc(gl, xl), c_mulc(gr, xr));
+    // bin -k
+    split_lr(zb, za, gl, gr);
+    split_lr(hb, ha, hl, hr);
+    split_lr(xb, xa, xl, xr);
+    const float2 u_b = pack_lr(c_mulc(gl, hl), c_mulc(gr, hr));
+    const float2 h_b = pack_lr(c_mulc(gl, xl), c_mulc(gr, xr));
+    b1[ia] = u_a;
+    b1[ib] = u_b;
+    b2[ia] = h_a;
+    b2[ib] = h_b;
+  }
+  __syncthreads();
+  if (want_u) {
+    fft_lds<N1, 2, N1, MG_BLOCK, +1>(b1, ea.tw);
+    store_rows<N1>(b1, Tu + (int64_t)j * ea.N, ra, rb, ea);
+  }
+  fft_lds<N1, 2, N1, MG_BLOCK, +1>(b2, ea.tw);
+  store_rows<N1>(b2, Th + (int64_t)j * ea.N, ra, rb, ea);
+}
+
+// ---------------------------------------------------------------- dispatch
+template <typename LD>
+void run_cols(const Ctx& c, const LD& ld, float2* T, int n, const EngineArgs& ea) {
+  const int N2 = ea.N2;
+  const int TC = 8192 / N2;
+  dim3 grid(ea.N1 / TC, n), blk(MG_BLOCK);
+  switch (N2) {
+#define MG_CASE(NN)                                                                   \
+  case NN:                                                                            \
+    hipLaunchKernelGGL((k_cols<NN, 8192 / NN, LD>), grid, blk, 0, c.st, ld, T, ea); \
+    break;
+    MG_CASE(16) MG_CASE(32) MG_CASE(64) MG_CASE(128) MG_CASE(256) MG_CASE(512) MG_CASE(1024)
+#undef MG_CASE
+  }
+}
+
+template <typename ST>
+void run_icols(const Ctx& c, const ST& st, const float2* T, int n, const EngineArgs& ea) {
+  const int N2 = ea.N2;
+  const int TC = 8192 / N2;
+  dim3 grid(ea.N1 / TC, n), blk(MG_BLOCK);
+  switch (N2) {
+#define MG_CASE(NN)                                                                    \
+  case NN:                                                                             \
+    hipLaunchKernelGGL((k_icols<NN, 8192 / NN, ST>), grid, blk, 0, c.st, st, T, ea); \
+    break;
+    MG_CASE(16) MG_CASE(32) MG_CASE(64) MG_CASE(128) MG_CASE(256) MG_CASE(512) MG_CASE(1024)
+#undef MG_CASE
+  }
+}
+
+static EngineArgs engine_args(const Ctx& c) {
+  const mg_graph* g = c.g;
+  EngineArgs ea;
+  ea.N = g->fft.N;
+  ea.N1 = g->fft.N1;
+  ea.N2 = g->fft.N2;
+  ea.tw = wsp<float2>(c, g->ws.tw);
+  ea.twhi = wsp<float2>(c, g->ws.twhi);
+  ea.twlo = wsp<float2>(c, g->ws.twlo);
+  return ea;
+}
+
+// slot of row 0 of each FIR type in the ybar / spectrum arrays
+static int conv_base(const mg_graph* g, int type) {
+  if (type == MG_EQ) return 0;
+  if (type == MG_DELAY) return g->type_count[MG_EQ];
+  return g->type_count[MG_EQ] + g->type_count[MG_DELAY];
+}
+
+static NodeView node_view(const Ctx& c, int desc_off) {
+  NodeView v;
+  v.desc = c.desc + desc_off;
+  v.dry = c.dry;
+  v.U = c.U;
+  v.G = c.G;
+  v.L = c.L;
+  v.C = c.C;
+  return v;
+}
+
+template <int N1>
+static void rows_spec_n(const Ctx& c, const float2* T, float2* Z, int z0, int desc_off, int n, const EngineArgs& ea) {
+  hipLaunchKernelGGL(k_rows_spec<N1>, dim3(ea.N2 / 2, n), dim3(MG_BLOCK), 0, c.st, T, Z, z0, c.desc + desc_off, ea);
+}
+template <int N1>
+static void rows_conv_n(const Ctx& c, const float2* Tin, float2* Tout, const float2* ZH, float2* ZU, int z0,
+                        int desc_off, int n, const EngineArgs& ea) {
+  hipLaunchKernelGGL(k_rows_conv<N1>, dim3(ea.N2 / 2, n), dim3(MG_BLOCK), 0, c.st, Tin, Tout, ZH, ZU, z0,
+                     c.desc + desc_off, ea);
+}
+template <int N1>
+static void rows_bwd_n(const Ctx& c, const float2* Tin, float2* Tu, float2* Th, const float2* ZH, const float2* ZU,
+                       int z0, int desc_off, int n, int want_u, const EngineArgs& ea) {
+  hipLaunchKernelGGL(k_rows_bwd<N1>, dim3(ea.N2 / 2, n), dim3(MG_BLOCK), 0, c.st, Tin, Tu, Th, ZH, ZU, z0,
+                     c.desc + desc_off, want_u, ea);
+}
+
+#define MG_N1_SWITCH(FN, ...)                   \
+  switch (ea.N1) {                              \
+    case 512: FN<512>(__VA_ARGS__); break;      \
+    case 1024: FN<1024>(__VA_ARGS__); break;    \
+    case 2048: FN<2048>(__VA_ARGS__); break;    \
+    case 4096: FN<4096>(__VA_ARGS__); break;    \
+  }
+
+// FIR spectra of the stage's nodes -> ZH (from the compact FIRs)
+void conv_fir_spectrum(const Ctx& c, int type, int desc_off, int n) {
+  const mg_graph* g = c.g;
+  const mg_config& cf = g->cfg;
+  EngineArgs ea = engine_args(c);
+  float2* T1 = wsp<float2>(c, g->ws.T1);
+  float2* ZH = wsp<float2>(c, g->ws.ZH);
+  const int z0 = conv_base(g, type);
+  if (type == MG_EQ) {
+    LdFir ld;
+    ld.desc = c.desc + desc_off;
+    ld.h = wsp<float>(c, g->ws.eq_h);
+    ld.Nh = cf.eq_taps;
+    ld.lag0 = -(cf.eq_taps - 1) / 2;
+    ld.N = ea.N;
+    ld.stride = cf.eq_taps;
+    ld.shared = 1;
+    run_cols(c, ld, T1, n, ea);
+  } else if (type == MG_REVERB) {
+    LdFir ld;
+    ld.desc = c.desc + desc_off;
+    ld.h = wsp<float>(c, g->ws.rv_h);
+    ld.Nh = cf.reverb_length;
+    ld.lag0 = 0;
+    ld.N = ea.N;
+    ld.stride = 2 * (int64_t)cf.reverb_length;
+    ld.shared = 0;
+    run_cols(c, ld, T1, n, ea);
+  } else {
+    LdDelay ld;
+    ld.desc = c.desc + desc_off;
+    ld.tab = wsp<float>(c, g->ws.dl_tab);
+    ld.M = cf.delay_taps;
+    ld.taps = cf.delay_fir_taps;
+    ld.half = (cf.delay_fir_taps - 1) / 2;
+    ld.N = ea.N;
+    ld.stride = 2 * (int64_t)cf.delay_taps * (1 + cf.delay_fir_taps);
+    run_cols(c, ld, T1, n, ea);
+  }
+  MG_N1_SWITCH(rows_spec_n, c, T1, ZH, z0, desc_off, n, ea);
+}
+
+void conv_forward(const Ctx& c, int type, int desc_off, int n, bool keep_input_spectrum) {
+  const mg_graph* g = c.g;
+  EngineArgs ea = engine_args(c);
+  float2* T1 = wsp<float2>(c, g->ws.T1);
+  float2* T2 = wsp<float2>(c, g->ws.T2);
+  float2* ZH = wsp<float2>(c, g->ws.ZH);
+  float2* ZU = keep_input_spectrum ? wsp<float2>(c, g->ws.ZU) : nullptr;
+  const int z0 = conv_base(g, type);
+  LdSignal ld;
+  ld.v = node_view(c, desc_off);
+  run_cols(c, ld, T1, n, ea);
+  MG_N1_SWITCH(rows_conv_n, c, T1, T2, ZH, ZU, z0, desc_off, n, ea);
+  StFwd st;
+  st.v = node_view(c, desc_off);
+  st.ybar_base = keep_input_spectrum ? wsp<float>(c, g->ws.YB) : nullptr;
+  st.wet = c.wet;
+  st.mask = c.mask;
+  st.yb0 = z0;
+  st.part = c.part + (int64_t)desc_off * c.PB * PK;
+  st.PB = c.PB;
+  if (!keep_input_spectrum) {
+    // forward-only: no ybar buffer; StFwd skips the ybar store
+    st.ybar_base = nullptr;
+  }
+  run_icols(c, st, T2, n, ea);
+  launch_reduce_lg(c, desc_off, n, ea.N1 / (8192 / ea.N2));
+}
+
+void conv_backward(const Ctx& c, int type, int desc_off, int n) {
+  const mg_graph* g = c.g;
+  const mg_config& cf = g->cfg;
+  EngineArgs ea = engine_args(c);
+  float2* T1 = wsp<float2>(c, g->ws.T1);
+  float2* T2 = wsp<float2>(c, g->ws.T2);
+  float2* T3 = wsp<float2>(c, g->ws.T3);
+  const float2* ZH = wsp<float2>(c, g->ws.ZH);
+  const float2* ZU = wsp<float2>(c, g->ws.ZU);
+  const int z0 = conv_base(g, type);
+  LdGrad ld;
+  ld.v = node_view(c, desc_off);
+  ld.ybar_base = wsp<float>(c, g->ws.YB);
+  ld.lg = c.lg + 2 * desc_off;
+  ld.wet = c.wet;
+  ld.mask = c.mask;
+  ld.alpha_g = c.alpha_g;
+  ld.yb0 = z0;
+  ld.part = c.part + (int64_t)desc_off * c.PB * PK;
+  ld.PB = c.PB;
+  run_cols(c, ld, T1, n, ea);
+  int want_u = 0;
+  for (int j = 0; j < n; ++j)
+    if (g->desc[desc_off + j].gin >= 0) want_u = 1;
+  MG_N1_SWITCH(rows_bwd_n, c, T1, T2, T3, ZH, ZU, z0, desc_off, n, want_u, ea);
+  if (want_u) {
+    StGradU su;
+    su.v = node_view(c, desc_off);
+    su.lg = c.lg + 2 * desc_off;
+    su.wet = c.wet;
+    su.mask = c.mask;
+    su.alpha_g = c.alpha_g;
+    run_icols(c, su, T2, n, ea);
+  }
+  StGradH sh;
+  sh.desc = c.desc + desc_off;
+  sh.N = ea.N;
+  if (type == MG_EQ) {
+    sh.dh = wsp<float>(c, g->ws.eq_dh);
+    sh.Nh = cf.eq_taps;
+    sh.lag0 = -(cf.eq_taps - 1) / 2;
+    sh.stride = cf.eq_taps;
+    sh.shared = 1;
+  } else if (type == MG_REVERB) {
+    sh.dh = wsp<float>(c, g->ws.rv_dh);
+    sh.Nh = cf.reverb_length;
+    sh.lag0 = 0;
+    sh.stride = 2 * (int64_t)cf.reverb_length;
+    sh.shared = 0;
+  } else {
+    sh.dh = wsp<float>(c, g->ws.dl_dh);
+    sh.Nh = g->dl_len;
+    sh.lag0 = -(cf.delay_fir_taps - 1) / 2;
+    sh.stride = 2 * g->dl_len;
+    sh.shared = 0;
+  }
+  run_icols(c, sh, T3, n, ea);
+}
+
+// tables for the LDS FFT (size MG_TWN) and for the big twiddles of N
+void fft_init_tables(const Ctx& c, float2* tw, float2* twhi, float2* twlo, int N, hipStream_t st) {
+  std::vector<float2> a(MG_TWN);
+  const double pi = 3.14159265358979323846;
+  for (int m = 0; m < MG_TWN; ++m) {
+    double ang = -2.0 * pi * (double)m / MG_TWN;
+    a[m] = make_float2((float)cos(ang), (float)sin(ang));
+  }
+  hipMemcpyAsync(tw, a.data(), a.size() * sizeof(float2), hipMemcpyHostToDevice, st);
+  std::vector<double2> ad(MG_TWN);
+  for (int m = 0; m < MG_TWN; ++m) {
+    double ang = -2.0 * pi * (double)m / MG_TWN;
+    ad[m] = make_double2(cos(ang), sin(ang));
+  }
+  hipMemcpyAsync(wsp<double2>(c, c.g->ws.twd), ad.data(), ad.size() * sizeof(double2), hipMemcpyHostToDevice, st);
+  if (N > 0) {
+    std::vector<float2> hi(N / 1024 > 0 ? N / 1024 : 1), lo(1024);
+    for (size_t j = 0; j < hi.size(); ++j) {
+      double ang = -2.0 * pi * (double)(1024 * (int64_t)j) / N;
+      hi[j] = make_float2((float)cos(ang), (float)sin(ang));
+    }
+    for (int j = 0; j < 1024; ++j) {
+      double ang = -2.0 * pi * (double)j / N;
+      lo[j] = make_float2((float)cos(ang), (float)sin(ang));
+    }
+    hipMemcpyAsync(twhi, hi.data(), hi.size() * sizeof(float2), hipMemcpyHostToDevice, st);
+    hipMemcpyAsync(twlo, lo.data(), lo.size() * sizeof(float2), hipMemcpyHostToDevice, st);
+    hipStreamSynchronize(st);  // host vectors go out of scope
+  } else {
+    hipStreamSynchronize(st);
+  }
+}
+
+}  // namespace mg

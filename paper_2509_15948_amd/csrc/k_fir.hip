@@ -1,0 +1,488 @@
+// FIR synthesis of the FIR processors and the adjoints back to their raw
+// parameters.
+//  * equalizer (Sec. 3.3): h[n] = cos^2(pi n/N) (H0 + 2 sum_k H_k cos(2 pi k n/N)) / N,
+//    H_k = exp(p_k), n = -(N-1)/2..(N-1)/2; angles reduced exactly as (k n mod N)
+//  * multitap delay (Sec. 3.7): per channel and tap an integer delay from the
+//    angle of z and a zero-phase FIR c_m built like the equalizer; the z
+//    gradient is the straight-through surrogate with the normalised update rule
+//  * reverb (Sec. 3.4): masked STFT of fixed noise -> least-squares ISTFT ->
+//    mid/side to left/right; mask exp(H0 + g0 + m d) with the per-frame decay
+//    d = -softplus(H_delta + beta)
+// These are small next to the convolutions; they use FP64 accumulation.
+#include <cstring>
+#include <vector>
+
+#include "mg_device.h"
+#include "mg_kernels.h"
+
+namespace mg {
+
+// ---------------------------------------------------------------- equalizer
+// grid (ceil(N/256), nodes): one output tap per thread
+__global__ __launch_bounds__(MG_BLOCK) void k_eq_synth(const NodeDesc* __restrict__ desc,
+                                                        const float* __restrict__ theta,
+                                                        const float* __restrict__ cosN, int N,
+                                                        float* __restrict__ h_out) {
+  __shared__ float H[4096];
+  __shared__ float cs[8192];
+  const NodeDesc d = desc[blockIdx.y];
+  const int K = (N + 1) / 2;
+  const float* p = theta + d.theta_off;
+  for (int k = threadIdx.x; k < K; k += MG_BLOCK) H[k] = expf(p[k]);
+  for (int m = threadIdx.x; m < N; m += MG_BLOCK) cs[m] = cosN[m];
+  __syncthreads();
+  const int i = blockIdx.x * MG_BLOCK + threadIdx.x;
+  if (i >= N) return;
+  const int half = (N - 1) / 2;
+  const int n = i - half;
+  const int nn = ((n % N) + N) % N;
+  double acc = 0.0;
+  int idx = 0;
+  for (int k = 1; k < K; ++k) {
+    idx += nn;
+    if (idx >= N) idx -= N;
+    acc += (double)H[k] * (double)cs[idx];
+  }
+  const double h0 = ((double)H[0] + 2.0 * acc) / (double)N;
+  const double v = 0.5 * (1.0 + (double)cs[nn]);  // cos^2(pi n / N)
+  h_out[(int64_t)d.aux * N + i] = (float)(v * h0);
+}
+
+// dL/dp_k = H_k (c_k / N) sum_n v[n] dh[n] cos(2 pi k n / N); grid (ceil(K/256), nodes)
+__global__ __launch_bounds__(MG_BLOCK) void k_eq_adjoint(const NodeDesc* __restrict__ desc,
+                                                          const float* __restrict__ theta,
+                                                          const float* __restrict__ cosN, int N,
+                                                          const float* __restrict__ dh,
+                                                          float* __restrict__ grad_theta) {
+  __shared__ float g[8192];
+  __shared__ float cs[8192];
+  const NodeDesc d = desc[blockIdx.y];
+  const int K = (N + 1) / 2;
+  const int half = (N - 1) / 2;
+  for (int m = threadIdx.x; m < N; m += MG_BLOCK) {
+    cs[m] = cosN[m];
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < N; i += MG_BLOCK) {
+    const int n = i - half;
+    const int nn = ((n % N) + N) % N;
+    g[i] = 0.5f * (1.0f + cs[nn]) * dh[(int64_t)d.aux * N + i];
+  }
+  __syncthreads();
+  const int k = blockIdx.x * MG_BLOCK + threadIdx.x;
+  if (k >= K) return;
+  double acc = 0.0;
+  // n runs over -half..half; (k n) mod N advanced incrementally
+  int idx = ((-(int64_t)half * k) % N + N) % N;
+  for (int i = 0; i < N; ++i) {
+    acc += (double)g[i] * (double)cs[idx];
+    idx += k;
+    if (idx >= N) idx -= N;
+  }
+  const double ck = (k == 0) ? 1.0 : 2.0;
+  const float* p = theta + d.theta_off;
+  grad_theta[d.theta_off + k] = (float)(exp((double)p[k]) * ck / (double)N * acc);
+}
+
+// ---------------------------------------------------------------- multitap delay
+// Per node table: [2][M] integer delays (stored as float) then [2][M][taps]
+// coefficients.  grid (nodes), block 256.
+__global__ __launch_bounds__(MG_BLOCK) void k_delay_synth(const NodeDesc* __restrict__ desc,
+                                                           const float* __restrict__ theta,
+                                                           const float* __restrict__ cosT, int M, int D, int taps,
+                                                           float* __restrict__ tab) {
+  const NodeDesc d = desc[blockIdx.x];
+  const int Kc = (taps + 1) / 2;
+  const int half = (taps - 1) / 2;
+  const float* p = theta + d.theta_off;
+  float* t = tab + (int64_t)d.aux * 2 * M * (1 + taps);
+  const int stride = 2 + Kc;
+  for (int cm = threadIdx.x; cm < 2 * M; cm += MG_BLOCK) {
+    const int m = cm % M;
+    const double zr = p[cm * stride], zi = p[cm * stride + 1];
+    const double phi = atan2(zi, zr);
+    long long r = (long long)floor(-phi * (double)D / (2.0 * 3.14159265358979323846) + 0.5);
+    r %= D;
+    if (r < 0) r += D;
+    t[cm] = (float)((long long)m * D + r);
+  }
+  for (int e = threadIdx.x; e < 2 * M * taps; e += MG_BLOCK) {
+    const int cm = e / taps, i = e % taps;
+    const float* lm = p + cm * stride + 2;
+    const int n = i - half;
+    const int nn = ((n % taps) + taps) % taps;
+    double acc = 0.0;
+    int idx = 0;
+    for (int k = 1; k < Kc; ++k) {
+      idx += nn;
+      if (idx >= taps) idx -= taps;
+      acc += exp((double)lm[k]) * (double)cosT[idx];
+    }
+    const double h0 = (exp((double)lm[0]) + 2.0 * acc) / (double)taps;
+    const double v = 0.5 * (1.0 + (double)cosT[nn]);
+    t[2 * M + e] = (float)(v * h0);
+  }
+}
+
+// P(a) = sum_{k=1}^{D-1} k a^{k-1}, closed form away from a = 1, Horner near it
+__device__ inline void poly_P(double ar, double ai, int D, double zDr, double zDi, double zD1r, double zD1i,
+                              double wr, double wi, double& pr, double& pi) {
+  // a = z w^q; a^D = z^D; a^{D-1} = z^{D-1} w^{-q}
+  const double br = 1.0 - ar, bi = -ai;
+  const double bb = br * br + bi * bi;
+  if (bb > 1e-12) {
+    // numerator 1 - D a^{D-1} + (D-1) a^D
+    const double a1r = zD1r * wr + zD1i * wi, a1i = zD1i * wr - zD1r * wi;  // z^{D-1} conj(w^q)
+    const double nr = 1.0 - D * a1r + (D - 1) * zDr;
+    const double ni = -D * a1i + (D - 1) * zDi;
+    // divide by (1 - a)^2
+    const double sr = br * br - bi * bi, si = 2.0 * br * bi;
+    const double ss = sr * sr + si * si;
+    pr = (nr * sr + ni * si) / ss;
+    pi = (ni * sr - nr * si) / ss;
+  } else {
+    double accr = D - 1, acci = 0.0;
+    for (int k = D - 2; k >= 1; --k) {
+      const double tr = accr * ar - acci * ai + k;
+      const double ti = accr * ai + acci * ar;
+      accr = tr;
+      acci = ti;
+    }
+    pr = accr;
+    pi = acci;
+  }
+}
+
+// One workgroup per (node, channel, tap): dL/dc_m (-> log-magnitudes) and the
+// straight-through z gradient
+//   f'(z) = (1/D) sum_q Gc[q] w^q P(z w^q),  Gc[q] = sum_j c_m[j] dh[m D + q + j],
+//   g = conj(f'(z)),  update = g/|g| + gamma (|z| - 1) z/|z|.
+__global__ __launch_bounds__(MG_BLOCK) void k_delay_adjoint(const NodeDesc* __restrict__ desc,
+                                                             const float* __restrict__ theta,
+                                                             const float* __restrict__ tab,
+                                                             const float* __restrict__ cosT, int M, int D,
+                                                             int taps, int64_t dl_len,
+                                                             const float* __restrict__ dh,
+                                                             float* __restrict__ grad_theta, float gamma) {
+  __shared__ double red_r[MG_BLOCK];
+  __shared__ double red_i[MG_BLOCK];
+  __shared__ float cm[256];
+  __shared__ float dc[256];
+  const int j = blockIdx.y;
+  const NodeDesc d = desc[j];
+  const int cmi = blockIdx.x;  // c * M + m
+  const int c = cmi / M, m = cmi % M;
+  const int Kc = (taps + 1) / 2;
+  const int half = (taps - 1) / 2;
+  const int stride = 2 + Kc;
+  const float* t = tab + (int64_t)d.aux * 2 * M * (1 + taps);
+  const int dm = (int)t[cmi];
+  const float* dhc = dh + (int64_t)d.aux * 2 * dl_len + (int64_t)c * dl_len;
+  for (int i = threadIdx.x; i < taps; i += MG_BLOCK) {
+    cm[i] = t[2 * M + cmi * taps + i];
+    dc[i] = dhc[dm + i];  // compact index of lag dm + (i - half) is dm + i
+  }
+  __syncthreads();
+  const float* p = theta + d.theta_off + (int64_t)cmi * stride;
+  float* gp = grad_theta + d.theta_off + (int64_t)cmi * stride;
+  // log-magnitudes of c_m
+  for (int k = threadIdx.x; k < Kc; k += MG_BLOCK) {
+    double acc = 0.0;
+    for (int i = 0; i < taps; ++i) {
+      const int n = i - half;
+      const int nn = ((n % taps) + taps) % taps;
+      const int idx = (int)(((int64_t)k * nn) % taps);
+      acc += 0.5 * (1.0 + (double)cosT[nn]) * (double)dc[i] * (double)cosT[idx];
+    }
+    const double ck = (k == 0) ? 1.0 : 2.0;
+    gp[2 + k] = (float)(exp((double)p[2 + k]) * ck / (double)taps * acc);
+  }
+  // z surrogate gradient
+  const double zr = p[0], zi = p[1];
+  const double lz = 0.5 * log(zr * zr + zi * zi), az = atan2(zi, zr);
+  const double mD = exp(D * lz), mD1 = exp((D - 1) * lz);
+  const double zDr = mD * cos(D * az), zDi = mD * sin(D * az);
+  const double zD1r = mD1 * cos((D - 1) * az), zD1i = mD1 * sin((D - 1) * az);
+  double sr = 0.0, si = 0.0;
+  for (int q = threadIdx.x; q < D; q += MG_BLOCK) {
+    double gc = 0.0;
+    const int64_t base = (int64_t)m * D + q;
+    for (int i = 0; i < taps; ++i) gc += (double)cm[i] * (double)dhc[base + i];
+    double wr, wi;
+    sincospi(2.0 * (double)q / (double)D, &wi, &wr);
+    const double ar = zr * wr - zi * wi, ai = zr * wi + zi * wr;
+    double pr, pi;
+    poly_P(ar, ai, D, zDr, zDi, zD1r, zD1i, wr, wi, pr, pi);
+    // w^q P
+    const double tr = wr * pr - wi * pi, ti = wr * pi + wi * pr;
+    sr += gc * tr;
+    si += gc * ti;
+  }
+  red_r[threadIdx.x] = sr;
+  red_i[threadIdx.x] = si;
+  __syncthreads();
+  for (int s = MG_BLOCK / 2; s > 0; s >>= 1) {
+    if (threadIdx.x < s) {
+      red_r[threadIdx.x] += red_r[threadIdx.x + s];
+      red_i[threadIdx.x] += red_i[threadIdx.x + s];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const double fr = red_r[0] / D, fi = red_i[0] / D;
+    double gr = fr, gi = -fi;  // conj(f')
+    const double ag = sqrt(gr * gr + gi * gi);
+    const double amz = sqrt(zr * zr + zi * zi);
+    double ur = 0.0, ui = 0.0;
+    if (ag > 0.0) {
+      ur = gr / ag;
+      ui = gi / ag;
+    }
+    if (amz > 0.0) {
+      ur += (double)gamma * (amz - 1.0) * zr / amz;
+      ui += (double)gamma * (amz - 1.0) * zi / amz;
+    }
+    gp[0] = (float)ur;
+    gp[1] = (float)ui;
+  }
+}
+
+// ---------------------------------------------------------------- reverb
+// noise STFT (setup): U[row][x][m][k] = sum_t w[t] noise_x[m hop - nfft/2 + t] e^{-2 pi i k t / nfft}
+__global__ __launch_bounds__(MG_BLOCK) void k_rv_noise_stft(const float* __restrict__ noise, int Lr, int nf,
+                                                             const float2* __restrict__ cs384,
+                                                             const float* __restrict__ win,
+                                                             float2* __restrict__ Uout) {
+  __shared__ float fr[384];
+  const int m = blockIdx.x, x = blockIdx.y, row = blockIdx.z;
+  const float* nz = noise + ((int64_t)row * 2 + x) * Lr;
+  for (int t = threadIdx.x; t < 384; t += MG_BLOCK) {
+    const int64_t n = (int64_t)m * 192 - 192 + t;
+    fr[t] = (n >= 0 && n < Lr) ? win[t] * nz[n] : 0.0f;
+  }
+  __syncthreads();
+  for (int k = threadIdx.x; k < 192; k += MG_BLOCK) {
+    double ar = 0.0, ai = 0.0;
+    int idx = 0;
+    for (int t = 0; t < 384; ++t) {
+      const float2 e = cs384[idx];  // (cos, sin) of 2 pi idx / 384
+      ar += (double)fr[t] * (double)e.x;
+      ai -= (double)fr[t] * (double)e.y;
+      idx += k;
+      if (idx >= 384) idx -= 384;
+    }
+    Uout[(((int64_t)row * 2 + x) * nf + m) * 192 + k] = make_float2((float)ar, (float)ai);
+  }
+}
+
+// frames: fr[row][x][m][t] = w[t] (1/384) sum_{k<192} c_k Re(U M e^{+2 pi i k t/384})
+// grid (nf, 2, nodes), block 128 (3 samples per thread)
+__global__ __launch_bounds__(128) void k_rv_frames(const NodeDesc* __restrict__ desc, const float* __restrict__ theta,
+                                                    const float2* __restrict__ Unz, int nf,
+                                                    const float2* __restrict__ cs384,
+                                                    const float* __restrict__ win, float gbias, float beta,
+                                                    float* __restrict__ frames) {
+  __shared__ float2 Hm[192];
+  const int m = blockIdx.x, x = blockIdx.y;
+  const NodeDesc d = desc[blockIdx.z];
+  const float* p = theta + d.theta_off + x * 384;  // [H0 (192), Hd (192)]
+  const float2* U = Unz + (((int64_t)d.aux * 2 + x) * nf + m) * 192;
+  for (int k = threadIdx.x; k < 192; k += 128) {
+    // decay per frame -softplus(theta + beta) (FP64 for the small argument range)
+    const double dk = -log1p(exp((double)p[192 + k] + (double)beta));
+    const float mk = (float)exp((double)p[k] + (double)gbias + (double)m * dk);
+    const float sc = (k == 0 ? 1.0f : 2.0f) / 384.0f * mk;
+    const float2 u = U[k];
+    Hm[k] = make_float2(u.x * sc, u.y * sc);
+  }
+  __syncthreads();
+  float* out = frames + (((int64_t)d.aux * 2 + x) * nf + m) * 384;
+  for (int t = threadIdx.x; t < 384; t += 128) {
+    double acc = 0.0;
+    int idx = 0;
+    for (int k = 0; k < 192; ++k) {
+      const float2 e = cs384[idx];
+      acc += (double)Hm[k].x * (double)e.x - (double)Hm[k].y * (double)e.y;
+      idx += t;
+      if (idx >= 384) idx -= 384;
+    }
+    out[t] = (float)(acc * (double)win[t]);
+  }
+}
+
+// overlap-add + LS normalisation + mid/side -> left/right; grid (ceil(Lr/256), nodes)
+__global__ __launch_bounds__(MG_BLOCK) void k_rv_ola(const NodeDesc* __restrict__ desc,
+                                                      const float* __restrict__ frames, int nf, int Lr,
+                                                      const float* __restrict__ wsum, float* __restrict__ h) {
+  const NodeDesc d = desc[blockIdx.y];
+  const int n = blockIdx.x * MG_BLOCK + threadIdx.x;
+  if (n >= Lr) return;
+  const int q = n / 192, r = n % 192;
+  float hx[2];
+  for (int x = 0; x < 2; ++x) {
+    const float* f = frames + ((int64_t)d.aux * 2 + x) * nf * 384;
+    hx[x] = (f[(int64_t)q * 384 + r + 192] + f[(int64_t)(q + 1) * 384 + r]) / wsum[r];
+  }
+  float* o = h + (int64_t)d.aux * 2 * Lr;
+  o[n] = hx[0] + hx[1];
+  o[Lr + n] = hx[0] - hx[1];
+}
+
+// adjoint per (frame, x, node): dM[k] M[k] (for H0) and m dM[k] M[k] (for Hd)
+__global__ __launch_bounds__(MG_BLOCK) void k_rv_adj_frames(const NodeDesc* __restrict__ desc,
+                                                             const float* __restrict__ theta,
+                                                             const float2* __restrict__ Unz, int nf, int Lr,
+                                                             const float2* __restrict__ cs384,
+                                                             const float* __restrict__ win,
+                                                             const float* __restrict__ wsum, float gbias,
+                                                             float beta, const float* __restrict__ dh,
+                                                             float* __restrict__ dMout) {
+  __shared__ float df[384];
+  const int m = blockIdx.x, x = blockIdx.y;
+  const NodeDesc d = desc[blockIdx.z];
+  const float* dhn = dh + (int64_t)d.aux * 2 * Lr;
+  for (int t = threadIdx.x; t < 384; t += MG_BLOCK) {
+    const int64_t n = (int64_t)m * 192 - 192 + t;
+    float v = 0.0f;
+    if (n >= 0 && n < Lr) {
+      const float g = x == 0 ? dhn[n] + dhn[Lr + n] : dhn[n] - dhn[Lr + n];
+      v = win[t] * g / wsum[t % 192];
+    }
+    df[t] = v;
+  }
+  __syncthreads();
+  const float* p = theta + d.theta_off + x * 384;
+  const float2* U = Unz + (((int64_t)d.aux * 2 + x) * nf + m) * 192;
+  float* o = dMout + (((int64_t)d.aux * 2 + x) * nf + m) * 192;
+  for (int k = threadIdx.x; k < 192; k += MG_BLOCK) {
+    double cr = 0.0, ci = 0.0;
+    int idx = 0;
+    for (int t = 0; t < 384; ++t) {
+      const float2 e = cs384[idx];
+      cr += (double)df[t] * (double)e.x;
+      ci += (double)df[t] * (double)e.y;
+      idx += k;
+      if (idx >= 384) idx -= 384;
+    }
+    const double ck = (k == 0 ? 1.0 : 2.0) / 384.0;
+    const double dRe = ck * cr, dIm = -ck * ci;
+    const float2 u = U[k];
+    const double dM = dRe * (double)u.x + dIm * (double)u.y;
+    const double dk = -log1p(exp((double)p[192 + k] + (double)beta));
+    const double mk = exp((double)p[k] + gbias + (double)m * dk);
+    o[k] = (float)(dM * mk);
+  }
+}
+
+// reduce over frames: dH0[k] = sum_m dMM[m][k];
+// dtheta_d[k] = -sigmoid(theta_d[k] + beta) sum_m m dMM[m][k]
+__global__ __launch_bounds__(MG_BLOCK) void k_rv_adj_reduce(const NodeDesc* __restrict__ desc, int nf,
+                                                             const float* __restrict__ dM,
+                                                             const float* __restrict__ theta, float beta,
+                                                             float* __restrict__ grad_theta) {
+  const int x = blockIdx.x;
+  const NodeDesc d = desc[blockIdx.y];
+  const float* src = dM + ((int64_t)d.aux * 2 + x) * nf * 192;
+  for (int k = threadIdx.x; k < 192; k += MG_BLOCK) {
+    double a = 0.0, b = 0.0;
+    for (int m = 0; m < nf; ++m) {
+      const double v = src[(int64_t)m * 192 + k];
+      a += v;
+      b += (double)m * v;
+    }
+    const double sg = 1.0 / (1.0 + exp(-((double)theta[d.theta_off + x * 384 + 192 + k] + (double)beta)));
+    grad_theta[d.theta_off + x * 384 + k] = (float)a;
+    grad_theta[d.theta_off + x * 384 + 192 + k] = (float)(-sg * b);
+  }
+}
+
+// ---------------------------------------------------------------- host side
+static double reverb_gain_bias(int fs) { return -0.5 * log(0.5 * fs / (6.0 * 6.91)); }
+// beta with softplus(beta) = per-frame log decay of a 0.5 s RT60
+static double reverb_decay_offset(int fs, int hop) { return log(expm1(6.91 * hop / (0.5 * fs))); }
+
+void fir_setup(const Ctx& c, const float* reverb_noise) {
+  const mg_graph* g = c.g;
+  const mg_config& cf = g->cfg;
+  const double pi = 3.14159265358979323846;
+  if (g->type_count[MG_EQ] > 0) {
+    std::vector<float> t(cf.eq_taps);
+    for (int m = 0; m < cf.eq_taps; ++m) t[m] = (float)cos(2.0 * pi * m / cf.eq_taps);
+    hipMemcpyAsync(wsp<float>(c, g->ws.eq_cos), t.data(), t.size() * 4, hipMemcpyHostToDevice, c.st);
+    hipStreamSynchronize(c.st);
+  }
+  if (g->type_count[MG_DELAY] > 0) {
+    std::vector<float> t(cf.delay_fir_taps);
+    for (int m = 0; m < cf.delay_fir_taps; ++m) t[m] = (float)cos(2.0 * pi * m / cf.delay_fir_taps);
+    hipMemcpyAsync(wsp<float>(c, g->ws.dl_cos), t.data(), t.size() * 4, hipMemcpyHostToDevice, c.st);
+    hipStreamSynchronize(c.st);
+  }
+  if (g->type_count[MG_REVERB] > 0) {
+    std::vector<float2> cs(384);
+    std::vector<float> win(384), ws(192);
+    for (int m = 0; m < 384; ++m) {
+      cs[m] = make_float2((float)cos(2.0 * pi * m / 384), (float)sin(2.0 * pi * m / 384));
+      win[m] = (float)(0.5 - 0.5 * cos(2.0 * pi * m / 384));
+    }
+    for (int r = 0; r < 192; ++r) {
+      const double a = 0.5 - 0.5 * cos(2.0 * pi * r / 384), b = 0.5 - 0.5 * cos(2.0 * pi * (r + 192) / 384);
+      ws[r] = (float)(a * a + b * b);
+    }
+    hipMemcpyAsync(wsp<float2>(c, g->ws.rv_cs), cs.data(), cs.size() * sizeof(float2), hipMemcpyHostToDevice, c.st);
+    hipMemcpyAsync(wsp<float>(c, g->ws.rv_win), win.data(), win.size() * 4, hipMemcpyHostToDevice, c.st);
+    hipMemcpyAsync(wsp<float>(c, g->ws.rv_wsum), ws.data(), ws.size() * 4, hipMemcpyHostToDevice, c.st);
+    const int nrv = g->type_count[MG_REVERB];
+    hipLaunchKernelGGL(k_rv_noise_stft, dim3(g->nf_rev, 2, nrv), dim3(MG_BLOCK), 0, c.st, reverb_noise,
+                       cf.reverb_length, g->nf_rev, wsp<float2>(c, g->ws.rv_cs), wsp<float>(c, g->ws.rv_win),
+                       wsp<float2>(c, g->ws.rv_U));
+    hipStreamSynchronize(c.st);
+  }
+}
+
+void fir_synth(const Ctx& c, int type, int desc_off, int n) {
+  const mg_graph* g = c.g;
+  const mg_config& cf = g->cfg;
+  const NodeDesc* d = c.desc + desc_off;
+  if (type == MG_EQ) {
+    hipLaunchKernelGGL(k_eq_synth, dim3((cf.eq_taps + MG_BLOCK - 1) / MG_BLOCK, n), dim3(MG_BLOCK), 0, c.st, d,
+                       c.theta, wsp<float>(c, g->ws.eq_cos), cf.eq_taps, wsp<float>(c, g->ws.eq_h));
+  } else if (type == MG_DELAY) {
+    hipLaunchKernelGGL(k_delay_synth, dim3(n), dim3(MG_BLOCK), 0, c.st, d, c.theta, wsp<float>(c, g->ws.dl_cos),
+                       cf.delay_taps, cf.delay_range, cf.delay_fir_taps, wsp<float>(c, g->ws.dl_tab));
+  } else if (type == MG_REVERB) {
+    const float gb = (float)reverb_gain_bias(cf.sample_rate);
+    const float db = (float)reverb_decay_offset(cf.sample_rate, cf.reverb_hop);
+    hipLaunchKernelGGL(k_rv_frames, dim3(g->nf_rev, 2, n), dim3(128), 0, c.st, d, c.theta,
+                       wsp<float2>(c, g->ws.rv_U), g->nf_rev, wsp<float2>(c, g->ws.rv_cs),
+                       wsp<float>(c, g->ws.rv_win), gb, db, wsp<float>(c, g->ws.rv_fr));
+    hipLaunchKernelGGL(k_rv_ola, dim3((cf.reverb_length + MG_BLOCK - 1) / MG_BLOCK, n), dim3(MG_BLOCK), 0, c.st, d,
+                       wsp<float>(c, g->ws.rv_fr), g->nf_rev, cf.reverb_length, wsp<float>(c, g->ws.rv_wsum),
+                       wsp<float>(c, g->ws.rv_h));
+  }
+}
+
+void fir_adjoint(const Ctx& c, int type, int desc_off, int n, float* grad_theta) {
+  const mg_graph* g = c.g;
+  const mg_config& cf = g->cfg;
+  const NodeDesc* d = c.desc + desc_off;
+  if (type == MG_EQ) {
+    const int K = (cf.eq_taps + 1) / 2;
+    hipLaunchKernelGGL(k_eq_adjoint, dim3((K + MG_BLOCK - 1) / MG_BLOCK, n), dim3(MG_BLOCK), 0, c.st, d, c.theta,
+                       wsp<float>(c, g->ws.eq_cos), cf.eq_taps, wsp<float>(c, g->ws.eq_dh), grad_theta);
+  } else if (type == MG_DELAY) {
+    hipLaunchKernelGGL(k_delay_adjoint, dim3(2 * cf.delay_taps, n), dim3(MG_BLOCK), 0, c.st, d, c.theta,
+                       wsp<float>(c, g->ws.dl_tab), wsp<float>(c, g->ws.dl_cos), cf.delay_taps, cf.delay_range,
+                       cf.delay_fir_taps, g->dl_len, wsp<float>(c, g->ws.dl_dh), grad_theta, 0.01f);
+  } else if (type == MG_REVERB) {
+    const float gb = (float)reverb_gain_bias(cf.sample_rate);
+    const float db = (float)reverb_decay_offset(cf.sample_rate, cf.reverb_hop);
+    hipLaunchKernelGGL(k_rv_adj_frames, dim3(g->nf_rev, 2, n), dim3(MG_BLOCK), 0, c.st, d, c.theta,
+                       wsp<float2>(c, g->ws.rv_U), g->nf_rev, cf.reverb_length, wsp<float2>(c, g->ws.rv_cs),
+                       wsp<float>(c, g->ws.rv_win), wsp<float>(c, g->ws.rv_wsum), gb, db,
+                       wsp<float>(c, g->ws.rv_dh), wsp<float>(c, g->ws.rv_dM));
+    hipLaunchKernelGGL(k_rv_adj_reduce, dim3(2, n), dim3(MG_BLOCK), 0, c.st, d, g->nf_rev,
+                       wsp<float>(c, g->ws.rv_dM), c.theta, db, grad_theta);
+  }
+}
+
+}  // namespace mg

@@ -1,0 +1,478 @@
+// Fused multi-resolution STFT loss (Sec. 5.1), evaluated in FP64 from the
+// FP32 mix (a log-magnitude loss turns FP32 transform noise in quiet Mel
+// cells into a bias).  For every resolution N (hop
+// N/4, periodic Hann, frames fully inside [skip, L)) the packed stereo frame
+// l + i r is transformed once in LDS; the left/right spectra are separated
+// with the mirrored bins, mid = l + r and side = l - r are formed from the
+// spectra, magnitudes are A-weighted per bin and projected on the Mel
+// triangles (banded, no dense product), and the log-l1 and
+// spectral-convergence partial sums are reduced in a fixed order.  Target
+// Mel spectra are computed once at setup and stay resident.
+// The adjoint recomputes each frame, forms dL/dX per bin, packs the two
+// channel gradients into one Hermitian-split spectrum, inverse transforms it
+// and windows it; a gather kernel overlap-adds the four frames per sample.
+#include <cstring>
+#include <vector>
+
+#include "mg_device.h"
+#include "mg_kernels.h"
+
+namespace mg {
+
+constexpr double LOG_EPS = 1e-7;
+
+// Frames per workgroup: 2048 complex FP64 points per batch (32 KB of LDS),
+// one frame for the 4096-point resolution.
+template <int N>
+constexpr int loss_fpb() { return N >= 2048 ? 1 : 2048 / N; }
+
+struct LossTabs {
+  const double* win;    // [N]
+  const double* aw;     // [N/2+1]
+  const int* band_lo;   // [nm]
+  const int* band_cnt;  // [nm]
+  const int* band_off;  // [nm]
+  const double* band_w; // [sum cnt]
+  const int* bin_band;  // [N/2+1][2], -1 = none
+  const double* bin_w;  // [N/2+1][2]
+};
+
+struct LossArgs {
+  const float* y;       // [2][L] signal
+  int64_t L;
+  int skip, hop, F, nm;
+  double* tgt;          // [F][4][nm]
+  double* part;         // [blocks][8]
+  float* scratch;       // [F][N][2] (backward)
+  const double* stats;  // [4][4] of this resolution (backward)
+  LossTabs tb;
+  const double2* tw;
+};
+
+template <int N>
+__device__ __forceinline__ void load_frames(double2* buf, const LossArgs& a, int f0) {
+  constexpr int FPB = loss_fpb<N>();
+  for (int idx = threadIdx.x; idx < FPB * N; idx += MG_BLOCK) {
+    const int fl = idx / N, t = idx % N;
+    const int f = f0 + fl;
+    double2 z = make_double2(0.0, 0.0);
+    if (f < a.F) {
+      const int64_t s = (int64_t)a.skip + (int64_t)f * a.hop + t;
+      const double wv = a.tb.win[t];
+      z = make_double2((double)a.y[s] * wv, (double)a.y[a.L + s] * wv);
+    }
+    buf[idx] = z;
+  }
+}
+
+// packed spectrum z (bin k) and zm (bin N-k) -> left and right spectra
+__device__ __forceinline__ void split_pair(double2 z, double2 zm, double2& xl, double2& xr) {
+  xl = make_double2(0.5 * (z.x + zm.x), 0.5 * (z.y - zm.y));
+  xr = make_double2(0.5 * (z.y + zm.y), -0.5 * (z.x - zm.x));
+}
+
+template <int N>
+__device__ __forceinline__ void frame_mags(const double2* buf, double* mag, const LossArgs& a) {
+  constexpr int FPB = loss_fpb<N>();
+  constexpr int NB = N / 2 + 1;
+  for (int idx = threadIdx.x; idx < FPB * NB; idx += MG_BLOCK) {
+    const int fl = idx / NB, k = idx % NB;
+    double2 xl, xr;
+    split_pair(buf[fl * N + k], buf[fl * N + ((N - k) & (N - 1))], xl, xr);
+    const double aw = a.tb.aw[k];
+    double* m = mag + (fl * 4) * NB + k;
+    m[0] = aw * sqrt(xl.x * xl.x + xl.y * xl.y);
+    m[NB] = aw * sqrt(xr.x * xr.x + xr.y * xr.y);
+    const double mr = xl.x + xr.x, mi = xl.y + xr.y, sr = xl.x - xr.x, si = xl.y - xr.y;
+    m[2 * NB] = aw * sqrt(mr * mr + mi * mi);
+    m[3 * NB] = aw * sqrt(sr * sr + si * si);
+  }
+}
+
+template <int N>
+__device__ __forceinline__ double mel_of(const double* mag, const LossArgs& a, int fl, int x, int b) {
+  constexpr int NB = N / 2 + 1;
+  const double* m = mag + (fl * 4 + x) * NB + a.tb.band_lo[b];
+  const double* wt = a.tb.band_w + a.tb.band_off[b];
+  double yh = 0.0;
+  for (int j = 0; j < a.tb.band_cnt[b]; ++j) yh = fma(wt[j], m[j], yh);
+  return yh;
+}
+
+// MODE 0: target features (write tgt, partial sum Y^2); MODE 1: loss partials
+template <int N, int MODE>
+__global__ __launch_bounds__(MG_BLOCK) void k_loss_fwd(LossArgs a) {
+  constexpr int FPB = loss_fpb<N>();
+  constexpr int NB = N / 2 + 1;
+  __shared__ double2 buf[FPB * N];
+  __shared__ double mag[FPB * 4 * NB];
+  __shared__ double red[MG_BLOCK];
+  const int f0 = blockIdx.x * FPB;
+  load_frames<N>(buf, a, f0);
+  __syncthreads();
+  fft_lds<N, FPB, N, MG_BLOCK, -1>(buf, a.tw);
+  frame_mags<N>(buf, mag, a);
+  __syncthreads();
+  double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  const int items = FPB * 4 * a.nm;
+  for (int it = threadIdx.x; it < items; it += MG_BLOCK) {
+    const int fl = it / (4 * a.nm), x = (it / a.nm) % 4, b = it % a.nm;
+    const int f = f0 + fl;
+    if (f >= a.F) continue;
+    const double yh = mel_of<N>(mag, a, fl, x, b);
+    double* tp = a.tgt + ((int64_t)f * 4 + x) * a.nm + b;
+    if (MODE == 0) {
+      *tp = yh;
+      acc[x] += yh * yh;
+    } else {
+      const double yt = *tp;
+      acc[x] += fabs(log(yt + LOG_EPS) - log(yh + LOG_EPS));
+      const double dd = yt - yh;
+      acc[4 + x] += dd * dd;
+    }
+  }
+  for (int k = 0; k < 8; ++k) {
+    const double s = block_sum<MG_BLOCK>(acc[k], red);
+    if (threadIdx.x == 0) a.part[(int64_t)blockIdx.x * 8 + k] = s;
+  }
+}
+
+// stats[x][0] = sum Y^2 (MODE 0), [1] = sum (Y - Yh)^2, [2] = sum|dlog| / cells
+__global__ void k_loss_reduce(const double* __restrict__ part, int nblocks, int cells, int mode,
+                              double* __restrict__ stats) {
+  const int x = threadIdx.x;
+  if (x >= 4) return;
+  double s0 = 0.0, s1 = 0.0;
+  for (int b = 0; b < nblocks; ++b) {
+    s0 += part[(int64_t)b * 8 + x];
+    s1 += part[(int64_t)b * 8 + 4 + x];
+  }
+  if (mode == 0) {
+    stats[x * 4 + 0] = s0;
+  } else {
+    stats[x * 4 + 2] = s0 / (double)cells;
+    stats[x * 4 + 1] = s1;
+  }
+}
+
+// per frame: dL/dy for the frame's samples (windowed), to scratch [F][N][2]
+template <int N>
+__global__ __launch_bounds__(MG_BLOCK) void k_loss_bwd(LossArgs a) {
+  constexpr int FPB = loss_fpb<N>();
+  constexpr int NB = N / 2 + 1;
+  __shared__ double2 buf[FPB * N];
+  __shared__ double mag[FPB * 4 * NB];
+  __shared__ double dyh[FPB * 4 * 128];
+  const int f0 = blockIdx.x * FPB;
+  load_frames<N>(buf, a, f0);
+  __syncthreads();
+  fft_lds<N, FPB, N, MG_BLOCK, -1>(buf, a.tw);
+  frame_mags<N>(buf, mag, a);
+  __syncthreads();
+  // dL/dYh per (frame, combo, band); every combo carries weight 1/4 in L_a
+  const double cells = (double)a.F * (double)a.nm;
+  double kl[4], ksc[4];
+  for (int x = 0; x < 4; ++x) {
+    const double Y2 = a.stats[x * 4 + 0], D2 = a.stats[x * 4 + 1];
+    const double D = sqrt(D2);
+    kl[x] = 0.25 / cells;
+    ksc[x] = D > 0.0 ? 0.25 / (D * (sqrt(Y2) + 1e-12)) : 0.0;
+  }
+  const int items = FPB * 4 * a.nm;
+  for (int it = threadIdx.x; it < items; it += MG_BLOCK) {
+    const int fl = it / (4 * a.nm), x = (it / a.nm) % 4, b = it % a.nm;
+    const int f = f0 + fl;
+    double g = 0.0;
+    if (f < a.F) {
+      const double yh = mel_of<N>(mag, a, fl, x, b);
+      const double yt = a.tgt[((int64_t)f * 4 + x) * a.nm + b];
+      const double dl = log(yh + LOG_EPS) - log(yt + LOG_EPS);
+      const double sg = dl > 0.0 ? 1.0 : (dl < 0.0 ? -1.0 : 0.0);
+      g = kl[x] * sg / (yh + LOG_EPS) + ksc[x] * (yh - yt);
+    }
+    dyh[(fl * 4 + x) * 128 + b] = g;
+  }
+  __syncthreads();
+  // per bin pair (k, N-k): dL/dX for l and r, packed Hermitian spectrum
+  for (int idx = threadIdx.x; idx < FPB * NB; idx += MG_BLOCK) {
+    const int fl = idx / NB, k = idx % NB;
+    const int km = (N - k) & (N - 1);
+    double2 xl, xr;
+    split_pair(buf[fl * N + k], buf[fl * N + km], xl, xr);
+    const double2 X[4] = {xl, xr, c_add(xl, xr), c_sub(xl, xr)};
+    double2 dX[4];
+    const double aw = a.tb.aw[k];
+    for (int x = 0; x < 4; ++x) {
+      double dm = 0.0;
+      for (int s = 0; s < 2; ++s) {
+        const int b = a.tb.bin_band[2 * k + s];
+        if (b >= 0) dm += a.tb.bin_w[2 * k + s] * dyh[(fl * 4 + x) * 128 + b];
+      }
+      dm *= aw;
+      const double mg = sqrt(X[x].x * X[x].x + X[x].y * X[x].y);
+      dX[x] = mg > 0.0 ? c_scale(X[x], dm / mg) : make_double2(0.0, 0.0);
+    }
+    const double2 gl = c_add(c_add(dX[0], dX[2]), dX[3]);
+    const double2 gr = c_sub(c_add(dX[1], dX[2]), dX[3]);
+    if (k == 0 || k == N / 2) {
+      buf[fl * N + k] = make_double2(gl.x, gr.x);
+    } else {
+      // P[k] = (gl + i gr)/2, P[N-k] = (conj(gl) + i conj(gr))/2
+      buf[fl * N + k] = make_double2(0.5 * (gl.x - gr.y), 0.5 * (gl.y + gr.x));
+      buf[fl * N + km] = make_double2(0.5 * (gl.x + gr.y), 0.5 * (-gl.y + gr.x));
+    }
+  }
+  __syncthreads();
+  fft_lds<N, FPB, N, MG_BLOCK, +1>(buf, a.tw);
+  for (int idx = threadIdx.x; idx < FPB * N; idx += MG_BLOCK) {
+    const int fl = idx / N, t = idx % N;
+    const int f = f0 + fl;
+    if (f >= a.F) continue;
+    const double wv = a.tb.win[t];
+    const double2 v = buf[idx];
+    float* o = a.scratch + ((int64_t)f * N + t) * 2;
+    o[0] = (float)(v.x * wv);
+    o[1] = (float)(v.y * wv);
+  }
+}
+
+struct GatherRes {
+  const float* scratch;
+  int N, hop, F;
+};
+
+struct GatherArgs {
+  GatherRes r[8];
+  int nres;
+  int skip;
+  int64_t L;
+  float* out;  // [2][L]
+};
+
+__global__ __launch_bounds__(MG_BLOCK) void k_loss_gather(GatherArgs a) {
+  for (int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; n < a.L; n += (int64_t)gridDim.x * blockDim.x) {
+    float sl = 0.f, sr = 0.f;
+    const int64_t m = n - a.skip;
+    if (m >= 0) {
+      for (int i = 0; i < a.nres; ++i) {
+        const GatherRes& R = a.r[i];
+        int64_t fh = m / R.hop;
+        for (int64_t f = fh - 3; f <= fh; ++f) {
+          if (f < 0 || f >= R.F) continue;
+          const int64_t t = m - f * R.hop;
+          if (t < 0 || t >= R.N) continue;
+          const float* s = R.scratch + (f * R.N + t) * 2;
+          sl += s[0];
+          sr += s[1];
+        }
+      }
+    }
+    a.out[n] = sl;
+    a.out[a.L + n] = sr;
+  }
+}
+
+// ---------------------------------------------------------------- host
+static LossTabs tabs_of(const Ctx& c, const LossRes& r) {
+  const mg_graph* g = c.g;
+  LossTabs t;
+  const char* b = c.base + r.tab_off;
+  const int N = r.nfft, NB = N / 2 + 1, nm = g->cfg.n_mels;
+  size_t o = 0;
+  t.win = (const double*)(b + o);
+  o += N * 8;
+  t.aw = (const double*)(b + o);
+  o += NB * 8;
+  t.band_lo = (const int*)(b + o);
+  o += nm * 4;
+  t.band_cnt = (const int*)(b + o);
+  o += nm * 4;
+  t.band_off = (const int*)(b + o);
+  o += nm * 4;
+  t.bin_band = (const int*)(b + o);
+  o += 2 * NB * 4;
+  o = (o + 7) / 8 * 8;
+  t.bin_w = (const double*)(b + o);
+  o += 2 * NB * 8;
+  t.band_w = (const double*)(b + o);
+  return t;
+}
+
+// host: build the table blob of one resolution (layout of tabs_of)
+size_t loss_table_bytes(int N, int nm, int fs, std::vector<char>* blob) {
+  const int NB = N / 2 + 1;
+  const double pi = 3.14159265358979323846;
+  auto hz2mel = [](double f) { return 2595.0 * log10(1.0 + f / 700.0); };
+  auto mel2hz = [](double m) { return 700.0 * (pow(10.0, m / 2595.0) - 1.0); };
+  std::vector<double> pts(nm + 2);
+  const double mmax = hz2mel(fs / 2.0);
+  for (int i = 0; i < nm + 2; ++i) pts[i] = mel2hz(mmax * i / (nm + 1));
+  std::vector<int> lo(nm), cnt(nm), off(nm), bb(2 * NB, -1);
+  std::vector<double> bw, binw(2 * NB, 0.0);
+  for (int b = 0; b < nm; ++b) {
+    int first = -1, last = -1;
+    std::vector<float> ws;
+    for (int k = 0; k < NB; ++k) {
+      const double f = (double)k * fs / N;
+      const double up = (f - pts[b]) / (pts[b + 1] - pts[b]);
+      const double dn = (pts[b + 2] - f) / (pts[b + 2] - pts[b + 1]);
+      const double w = std::max(0.0, std::min(up, dn));
+      if (w > 0.0) {
+        if (first < 0) first = k;
+        last = k;
+      }
+    }
+    if (first < 0) {
+      first = 0;
+      last = -1;
+    }
+    lo[b] = first;
+    cnt[b] = last - first + 1;
+    off[b] = (int)bw.size();
+    for (int k = first; k <= last; ++k) {
+      const double f = (double)k * fs / N;
+      const double up = (f - pts[b]) / (pts[b + 1] - pts[b]);
+      const double dn = (pts[b + 2] - f) / (pts[b + 2] - pts[b + 1]);
+      const double w = std::max(0.0, std::min(up, dn));
+      bw.push_back(w);
+      if (w > 0.0) {
+        const int s = (bb[2 * k] < 0) ? 0 : 1;
+        bb[2 * k + s] = b;
+        binw[2 * k + s] = w;
+      }
+    }
+  }
+  auto ra = [](double x) {
+    const double x2 = x * x;
+    return (12194.0 * 12194.0 * x2 * x2) /
+           ((x2 + 20.6 * 20.6) * sqrt((x2 + 107.7 * 107.7) * (x2 + 737.9 * 737.9)) * (x2 + 12194.0 * 12194.0));
+  };
+  const double r1k = ra(1000.0);
+  size_t o_int = (size_t)N * 8 + NB * 8 + 3 * nm * 4 + 2 * NB * 4;
+  size_t o_binw = (o_int + 7) / 8 * 8;
+  size_t bytes = o_binw + 2 * NB * 8 + bw.size() * 8;
+  if (blob) {
+    blob->assign(bytes, 0);
+    char* p = blob->data();
+    size_t o = 0;
+    for (int t = 0; t < N; ++t) ((double*)(p + o))[t] = 0.5 - 0.5 * cos(2.0 * pi * t / N);
+    o += N * 8;
+    for (int k = 0; k < NB; ++k) ((double*)(p + o))[k] = ra((double)k * fs / N) / r1k;
+    o += NB * 8;
+    memcpy(p + o, lo.data(), nm * 4);
+    o += nm * 4;
+    memcpy(p + o, cnt.data(), nm * 4);
+    o += nm * 4;
+    memcpy(p + o, off.data(), nm * 4);
+    o += nm * 4;
+    memcpy(p + o, bb.data(), 2 * NB * 4);
+    o = o_binw;
+    memcpy(p + o, binw.data(), 2 * NB * 8);
+    o += 2 * NB * 8;
+    if (!bw.empty()) memcpy(p + o, bw.data(), bw.size() * 8);
+  }
+  return bytes;
+}
+
+static LossArgs loss_args(const Ctx& c, int i, const float* y) {
+  const mg_graph* g = c.g;
+  const LossRes& r = g->lres[i];
+  LossArgs a;
+  a.y = y;
+  a.L = c.L;
+  a.skip = g->cfg.loss_skip;
+  a.hop = r.hop;
+  a.F = r.frames;
+  a.nm = g->cfg.n_mels;
+  a.tgt = (double*)(c.base + r.tgt_off);
+  a.part = (double*)(c.base + r.part_off);
+  a.scratch = (float*)(c.base + g->ws.ls_part) + 0;  // set per resolution below
+  a.stats = (const double*)(c.base + g->ws.ls_stats) + i * 16;
+  a.tb = tabs_of(c, r);
+  a.tw = wsp<double2>(c, g->ws.twd);
+  return a;
+}
+
+template <int N, int MODE>
+static void fwd_n(const Ctx& c, const LossArgs& a, int blocks) {
+  hipLaunchKernelGGL((k_loss_fwd<N, MODE>), dim3(blocks), dim3(MG_BLOCK), 0, c.st, a);
+}
+template <int N>
+static void bwd_n(const Ctx& c, const LossArgs& a, int blocks) {
+  hipLaunchKernelGGL(k_loss_bwd<N>, dim3(blocks), dim3(MG_BLOCK), 0, c.st, a);
+}
+
+#define MG_LOSS_SWITCH(N_, CALL)   \
+  switch (N_) {                    \
+    case 256: CALL(256); break;    \
+    case 512: CALL(512); break;    \
+    case 1024: CALL(1024); break;  \
+    case 2048: CALL(2048); break;  \
+    case 4096: CALL(4096); break;  \
+  }
+
+static void run_loss_fwd(const Ctx& c, const float* y, int mode) {
+  const mg_graph* g = c.g;
+  double* stats = wsp<double>(c, g->ws.ls_stats);
+  for (size_t i = 0; i < g->lres.size(); ++i) {
+    const LossRes& r = g->lres[i];
+    LossArgs a = loss_args(c, (int)i, y);
+    const int FPB = r.nfft >= 2048 ? 1 : 2048 / r.nfft;
+    const int blocks = (r.frames + FPB - 1) / FPB;
+#define MG_F0(NN) fwd_n<NN, 0>(c, a, blocks)
+#define MG_F1(NN) fwd_n<NN, 1>(c, a, blocks)
+    if (mode == 0) {
+      MG_LOSS_SWITCH(r.nfft, MG_F0)
+    } else {
+      MG_LOSS_SWITCH(r.nfft, MG_F1)
+    }
+#undef MG_F0
+#undef MG_F1
+    hipLaunchKernelGGL(k_loss_reduce, dim3(1), dim3(64), 0, c.st, a.part, blocks, r.frames * g->cfg.n_mels, mode,
+                       stats + i * 16);
+  }
+}
+
+void loss_setup(const Ctx& c, const float* target) {
+  const mg_graph* g = c.g;
+  for (size_t i = 0; i < g->lres.size(); ++i) {
+    std::vector<char> blob;
+    loss_table_bytes(g->lres[i].nfft, g->cfg.n_mels, g->cfg.sample_rate, &blob);
+    hipMemcpyAsync(c.base + g->lres[i].tab_off, blob.data(), blob.size(), hipMemcpyHostToDevice, c.st);
+    hipStreamSynchronize(c.st);
+  }
+  launch_zero(c.base + g->ws.ls_stats, 8 * sizeof(double) * 16, c.st);
+  run_loss_fwd(c, target, 0);
+}
+
+void loss_forward(const Ctx& c, const float* yhat) { run_loss_fwd(c, yhat, 1); }
+
+void loss_backward(const Ctx& c, const float* yhat, float* dyhat) {
+  const mg_graph* g = c.g;
+  GatherArgs ga;
+  ga.nres = (int)g->lres.size();
+  ga.skip = g->cfg.loss_skip;
+  ga.L = c.L;
+  ga.out = dyhat;
+  size_t off = g->ws.ls_part;
+  for (size_t i = 0; i < g->lres.size(); ++i) {
+    const LossRes& r = g->lres[i];
+    LossArgs a = loss_args(c, (int)i, yhat);
+    a.scratch = (float*)(c.base + off);
+    const int FPB = r.nfft >= 2048 ? 1 : 2048 / r.nfft;
+    const int blocks = (r.frames + FPB - 1) / FPB;
+#define MG_B(NN) bwd_n<NN>(c, a, blocks)
+    MG_LOSS_SWITCH(r.nfft, MG_B)
+#undef MG_B
+    ga.r[i].scratch = a.scratch;
+    ga.r[i].N = r.nfft;
+    ga.r[i].hop = r.hop;
+    ga.r[i].F = r.frames;
+    off += (((size_t)r.frames * r.nfft * 2 * 4) + 255) / 256 * 256;
+  }
+  int64_t blocks = (c.L + MG_BLOCK - 1) / MG_BLOCK;
+  if (blocks > 2048) blocks = 2048;
+  hipLaunchKernelGGL(k_loss_gather, dim3((unsigned)blocks), dim3(MG_BLOCK), 0, c.st, ga);
+}
+
+}  // namespace mg

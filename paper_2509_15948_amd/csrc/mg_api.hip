@@ -1,0 +1,307 @@
+// C-ABI entry points that touch the device: workspace planning and binding,
+// the forward pass (Alg. 1 stage loop, then the loss of Sec. 5.1), the
+// backward pass (stages in reverse with hand-written adjoints), the masked
+// pruning evaluation (Alg. 2 Evaluate) and Adam.  All work is enqueued on
+// the caller's stream; nothing here allocates device memory.
+#include <algorithm>
+#include <cstring>
+#include <string>
+
+#include "mg_device.h"
+#include "mg_kernels.h"
+
+namespace mg {
+int fail(int code, const std::string& msg);
+size_t loss_table_bytes(int N, int nm, int fs, std::vector<char>* blob);
+
+static size_t align256(size_t x) { return (x + 255) / 256 * 256; }
+
+static int hip_check(hipError_t e, const char* what) {
+  if (e != hipSuccess) return fail(MG_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
+  return MG_OK;
+}
+
+// Carve the workspace.  Returns total bytes; fills g.ws when commit is set.
+static size_t plan_ws(mg_graph& g, int mode, bool commit) {
+  const mg_config& c = g.cfg;
+  const int64_t L = c.length;
+  WsPlan w;
+  size_t o = 0;
+  auto take = [&](size_t& field, size_t bytes) {
+    field = o;
+    o += align256(bytes);
+  };
+  const int n_desc = (int)g.desc.size();
+  const int n_eq = g.type_count[MG_EQ], n_dl = g.type_count[MG_DELAY], n_rv = g.type_count[MG_REVERB];
+  const int n_conv = n_eq + n_dl + n_rv;
+  const int n_dyn = g.type_count[MG_COMP] + g.type_count[MG_GATE];
+  const int64_t N = g.fft.N;
+  take(w.desc, std::max<size_t>(1, n_desc) * sizeof(NodeDesc));
+  take(w.srcs, std::max<size_t>(1, g.srcs.size() + g.gsrcs.size()) * sizeof(SrcRef));
+  take(w.losses_tmp, std::max(1, n_desc) * sizeof(int));
+  take(w.U, (size_t)g.n_uslots * 2 * L * 4);
+  if (mode) {
+    take(w.YB, (size_t)n_conv * 2 * L * 4);
+    take(w.ENV, (size_t)n_dyn * L * 4);
+    take(w.G, (size_t)g.n_gslots * 2 * L * 4);
+  }
+  if (N > 0) {
+    take(w.ZH, (size_t)n_conv * N * 8);
+    if (mode) take(w.ZU, (size_t)n_conv * N * 8);
+    take(w.T1, (size_t)g.max_conv_stage * N * 8);
+    take(w.T2, (size_t)g.max_conv_stage * N * 8);
+    if (mode) take(w.T3, (size_t)g.max_conv_stage * N * 8);
+    take(w.twhi, (size_t)std::max<int64_t>(1, N / 1024) * 8);
+    take(w.twlo, 1024 * 8);
+  }
+  take(w.tw, MG_TWN * 8);
+  take(w.twd, MG_TWN * 16);
+  if (n_eq) {
+    take(w.eq_h, (size_t)n_eq * c.eq_taps * 4);
+    if (mode) take(w.eq_dh, (size_t)n_eq * c.eq_taps * 4);
+    take(w.eq_cos, (size_t)c.eq_taps * 4);
+  }
+  if (n_dl) {
+    take(w.dl_tab, (size_t)n_dl * 2 * c.delay_taps * (1 + c.delay_fir_taps) * 4);
+    if (mode) take(w.dl_dh, (size_t)n_dl * 2 * g.dl_len * 4);
+    take(w.dl_cos, (size_t)c.delay_fir_taps * 4);
+  }
+  if (n_rv) {
+    take(w.rv_U, (size_t)n_rv * 2 * g.nf_rev * 192 * 8);
+    take(w.rv_fr, (size_t)n_rv * 2 * g.nf_rev * 384 * 4);
+    take(w.rv_h, (size_t)n_rv * 2 * c.reverb_length * 4);
+    if (mode) {
+      take(w.rv_dh, (size_t)n_rv * 2 * c.reverb_length * 4);
+      take(w.rv_dM, (size_t)n_rv * 2 * g.nf_rev * 192 * 4);
+    }
+    take(w.rv_cs, 384 * 8);
+    take(w.rv_win, 384 * 4);
+    take(w.rv_wsum, 192 * 4);
+  }
+  if (n_dyn) {
+    take(w.cmp_sum, (size_t)std::max(1, g.max_stage) * g.dyn_chunks * 4);
+    take(w.cmp_carry, (size_t)std::max(1, g.max_stage) * g.dyn_chunks * 8);
+  }
+  take(w.part, (size_t)std::max(1, n_desc) * g.part_blocks * PK * 4);
+  take(w.lg, (size_t)std::max(1, n_desc) * 2 * 8);
+  take(w.ls_stats, 8 * 16 * 8);
+  for (auto& r : g.lres) {
+    const int FPB = r.nfft >= 2048 ? 1 : 2048 / r.nfft;
+    const int blocks = (r.frames + FPB - 1) / FPB;
+    size_t tgt, part, tab;
+    take(tgt, (size_t)r.frames * 4 * c.n_mels * 8);
+    take(part, (size_t)blocks * 8 * 8);
+    take(tab, loss_table_bytes(r.nfft, c.n_mels, c.sample_rate, nullptr));
+    if (commit) {
+      r.tgt_off = tgt;
+      r.part_off = part;
+      r.tab_off = tab;
+    }
+  }
+  if (mode) {
+    size_t s = 0;
+    for (auto& r : g.lres) s += align256((size_t)r.frames * r.nfft * 2 * 4);
+    take(w.ls_part, s);
+  }
+  w.total = o;
+  if (commit) g.ws = w;
+  return o;
+}
+
+static void finish_compile(mg_graph& g) {
+  g.dyn_chunks = (int)((g.cfg.length + 4095) / 4096);
+  int pb = 128;
+  if (g.fft.N > 0) pb = std::max(pb, g.fft.N / 8192);
+  pb = std::max(pb, g.dyn_chunks);
+  g.part_blocks = pb;
+}
+
+static Ctx make_ctx(const mg_graph* g, hipStream_t st) {
+  Ctx c;
+  c.g = g;
+  c.st = st;
+  c.L = g->cfg.length;
+  c.C = g->track_ch;
+  c.base = g->base;
+  c.U = (float*)(g->base + g->ws.U);
+  c.G = g->mode ? (float*)(g->base + g->ws.G) : nullptr;
+  c.dry = g->f_dry;
+  c.theta = g->f_theta;
+  c.wet = g->f_wet;
+  c.mask = g->f_mask;
+  c.desc = (const NodeDesc*)(g->base + g->ws.desc);
+  c.srcs = (const SrcRef*)(g->base + g->ws.srcs);
+  c.part = (float*)(g->base + g->ws.part);
+  c.PB = g->part_blocks;
+  c.lg = (double*)(g->base + g->ws.lg);
+  c.alpha_g = (float)g->cfg.alpha_g;
+  c.alpha_p = (float)g->cfg.alpha_p;
+  return c;
+}
+
+static void run_forward(mg_graph* g, hipStream_t st, bool keep, double* losses, float* mix) {
+  Ctx c = make_ctx(g, st);
+  const int n_desc = (int)g->desc.size();
+  for (size_t s = 1; s < g->stages.size(); ++s) {
+    const Stage& S = g->stages[s];
+    const int n = (int)S.nodes.size();
+    const int off = S.desc_off;
+    const int t = S.type;
+    if (t == MG_MIX || t == MG_OUT) {
+      launch_sum(c, off, n, c.srcs, c.U, 0);
+      continue;
+    }
+    // processors whose input is a sum of several nodes: gather it first
+    bool any_sum = false;
+    for (int j = 0; j < n; ++j)
+      if (g->desc[off + j].src_count > 0) any_sum = true;
+    if (any_sum) launch_sum(c, off, n, c.srcs, c.U, 2);
+    if (t == MG_GAINPAN || t == MG_IMAGER || t == MG_DIST) {
+      launch_pointwise_fwd(c, t, off, n);
+    } else if (t == MG_COMP || t == MG_GATE) {
+      dyn_forward(c, t, off, n);
+    } else if (is_conv(t)) {
+      fir_synth(c, t, off, n);
+      conv_fir_spectrum(c, t, off, n);
+      conv_forward(c, t, off, n, keep);
+    }
+  }
+  const float* yhat = c.U + (int64_t)g->uslot[g->output_node] * 2 * c.L;
+  loss_forward(c, yhat);
+  launch_finalize_losses(c, losses, (const double*)(g->base + g->ws.ls_stats), (int)g->lres.size(), nullptr,
+                         n_desc);
+  if (mix) hipMemcpyAsync(mix, yhat, (size_t)2 * c.L * 4, hipMemcpyDeviceToDevice, st);
+}
+
+}  // namespace mg
+
+using namespace mg;
+
+extern "C" int mg_workspace_size(const mg_graph* g, int32_t mode, size_t* bytes) {
+  if (!g || !bytes || (mode != 0 && mode != 1)) return fail(MG_ERR_INVALID_ARG, "bad arguments");
+  mg_graph tmp = *g;
+  finish_compile(tmp);
+  *bytes = plan_ws(tmp, mode, false);
+  return MG_OK;
+}
+
+extern "C" int mg_setup(mg_graph* g, void* workspace, size_t workspace_bytes, int32_t mode,
+                        const float* reverb_noise, const float* target, void* stream) {
+  if (!g || !workspace || !target || (mode != 0 && mode != 1)) return fail(MG_ERR_INVALID_ARG, "bad arguments");
+  if (((uintptr_t)workspace) & 255) return fail(MG_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
+  if (g->type_count[MG_REVERB] > 0 && !reverb_noise) return fail(MG_ERR_INVALID_ARG, "reverb noise required");
+  finish_compile(*g);
+  const size_t need = plan_ws(*g, mode, true);
+  if (workspace_bytes < need) return fail(MG_ERR_SHAPE, "workspace too small: need " + std::to_string(need));
+  hipStream_t st = (hipStream_t)stream;
+  g->base = (char*)workspace;
+  g->ws_bytes = workspace_bytes;
+  g->mode = mode;
+  g->have_forward = false;
+  // descriptor tables
+  std::vector<SrcRef> all = g->srcs;
+  all.insert(all.end(), g->gsrcs.begin(), g->gsrcs.end());
+  std::vector<int> flag(std::max<size_t>(1, g->desc.size()), 0);
+  for (size_t j = 0; j < g->desc.size(); ++j) {
+    const int t = g->type[g->desc[j].node];
+    flag[j] = (t == MG_EQ || t == MG_DELAY || t == MG_REVERB) ? 1 : 0;
+  }
+  int rc;
+  if (!g->desc.empty() &&
+      (rc = hip_check(hipMemcpyAsync(g->base + g->ws.desc, g->desc.data(), g->desc.size() * sizeof(NodeDesc),
+                                     hipMemcpyHostToDevice, st), "descriptor upload")))
+    return rc;
+  if (!all.empty() && (rc = hip_check(hipMemcpyAsync(g->base + g->ws.srcs, all.data(), all.size() * sizeof(SrcRef),
+                                                     hipMemcpyHostToDevice, st), "source upload")))
+    return rc;
+  if ((rc = hip_check(hipMemcpyAsync(g->base + g->ws.losses_tmp, flag.data(), flag.size() * sizeof(int),
+                                     hipMemcpyHostToDevice, st), "flag upload")))
+    return rc;
+  Ctx c = make_ctx(g, st);
+  fft_init_tables(c, (float2*)(g->base + g->ws.tw), g->fft.N ? (float2*)(g->base + g->ws.twhi) : nullptr,
+                  g->fft.N ? (float2*)(g->base + g->ws.twlo) : nullptr, g->fft.N, st);
+  launch_zero(g->base + g->ws.part, (size_t)std::max<size_t>(1, g->desc.size()) * g->part_blocks * PK * 4, st);
+  launch_zero(g->base + g->ws.lg, (size_t)std::max<size_t>(1, g->desc.size()) * 16, st);
+  fir_setup(c, reverb_noise);
+  loss_setup(c, target);
+  if ((rc = hip_check(hipStreamSynchronize(st), "setup"))) return rc;
+  if ((rc = hip_check(hipGetLastError(), "setup launch"))) return rc;
+  g->ready = true;
+  return MG_OK;
+}
+
+extern "C" int mg_forward(mg_graph* g, const float* dry, const float* theta, const float* wet, const float* mask,
+                          float* mix, double* losses, void* stream) {
+  if (!g || !dry || !wet || !losses || (!theta && g->n_theta > 0)) return fail(MG_ERR_INVALID_ARG, "NULL argument");
+  if (!g->ready) return fail(MG_ERR_STATE, "mg_setup has not been called");
+  g->f_dry = dry;
+  g->f_theta = theta;
+  g->f_wet = wet;
+  g->f_mask = mask;
+  run_forward(g, (hipStream_t)stream, g->mode == 1, losses, mix);
+  int rc = hip_check(hipGetLastError(), "forward launch");
+  if (rc) return rc;
+  g->have_forward = (g->mode == 1);
+  return MG_OK;
+}
+
+extern "C" int mg_forward_masked(mg_graph* g, const float* dry, const float* theta, const float* wet,
+                                 const float* masks, int32_t B, double* losses, void* stream) {
+  if (!g || !dry || !wet || !losses || !masks || B < 1) return fail(MG_ERR_INVALID_ARG, "bad arguments");
+  if (!g->ready) return fail(MG_ERR_STATE, "mg_setup has not been called");
+  g->f_dry = dry;
+  g->f_theta = theta;
+  g->f_wet = wet;
+  for (int b = 0; b < B; ++b) {
+    g->f_mask = masks + (int64_t)b * g->n_proc;
+    run_forward(g, (hipStream_t)stream, false, losses + (int64_t)b * 7, nullptr);
+  }
+  g->have_forward = false;
+  return hip_check(hipGetLastError(), "masked forward launch");
+}
+
+extern "C" int mg_backward(mg_graph* g, float* grad_theta, float* grad_wet, void* stream) {
+  if (!g || !grad_wet || (!grad_theta && g->n_theta > 0)) return fail(MG_ERR_INVALID_ARG, "NULL argument");
+  if (!g->ready || g->mode != 1) return fail(MG_ERR_STATE, "graph not set up for backward (mode 1)");
+  if (!g->have_forward) return fail(MG_ERR_STATE, "mg_backward needs a preceding mg_forward");
+  for (int v = 0; v < g->n_nodes; ++v)
+    if (g->succs[v].size() > 1) return fail(MG_ERR_GRAPH, "backward through a node with several consumers is not supported");
+  hipStream_t st = (hipStream_t)stream;
+  Ctx c = make_ctx(g, st);
+  const int o = g->output_node;
+  const float* yhat = c.U + (int64_t)g->uslot[o] * 2 * c.L;
+  float* dy = c.G + (int64_t)g->gslot[o] * 2 * c.L;
+  loss_backward(c, yhat, dy);
+  const mg_config& cf = g->cfg;
+  for (size_t s = g->stages.size() - 1; s >= 1; --s) {
+    const Stage& S = g->stages[s];
+    const int n = (int)S.nodes.size();
+    const int off = S.desc_off;
+    const int t = S.type;
+    if (t == MG_MIX || t == MG_OUT) continue;
+    if (t == MG_GAINPAN || t == MG_IMAGER || t == MG_DIST) {
+      launch_pointwise_bwd(c, t, off, n);
+      launch_finish_grads(c, off, n, 128, g->type_np[t], grad_theta, grad_wet);
+    } else if (t == MG_COMP || t == MG_GATE) {
+      dyn_backward(c, t, off, n);
+      const bool ar = (t == MG_COMP && cf.comp_mode == 1);
+      launch_finish_grads(c, off, n, ar ? 1 : g->dyn_chunks, g->type_np[t], grad_theta, grad_wet);
+    } else if (is_conv(t)) {
+      conv_backward(c, t, off, n);
+      fir_adjoint(c, t, off, n, grad_theta);
+      launch_finish_grads(c, off, n, g->fft.N1 / (8192 / g->fft.N2), 0, grad_theta, grad_wet);
+    }
+    // processors with several predecessors: every predecessor's dL/dy is
+    // this node's dL/du (aliased slots), nothing to scatter
+  }
+  g->have_forward = false;
+  return hip_check(hipGetLastError(), "backward launch");
+}
+
+extern "C" int mg_adam_step(float* theta, float* m, float* v, const float* grad, int64_t n, float lr, float beta1,
+                            float beta2, float eps, int32_t step, void* stream) {
+  if (!theta || !m || !v || !grad || n < 0 || step < 1) return fail(MG_ERR_INVALID_ARG, "bad arguments");
+  if (n == 0) return MG_OK;
+  launch_adam(theta, m, v, grad, n, lr, beta1, beta2, eps, step, (hipStream_t)stream);
+  return hip_check(hipGetLastError(), "adam launch");
+}

@@ -1,0 +1,171 @@
+// Device-side helpers shared by the mixgraph kernels (gfx950, wave64).
+//
+//  * complex float arithmetic on float2
+//  * an LDS-resident, batched, Stockham-autosort complex FFT (radix-4 passes
+//    plus one radix-2 pass when log2 n is odd), data kept in LDS and each
+//    butterfly's operands in registers between a read phase and a write phase,
+//    so one buffer of n complex values per transform suffices
+//  * fixed-order block reductions (no floating-point atomics anywhere, so every
+//    result is bitwise reproducible)
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#define MG_TWN 8192          // size of the LDS-FFT twiddle table
+#define MG_BLOCK 256         // threads per workgroup for most kernels
+
+__device__ __forceinline__ float2 c_add(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ float2 c_sub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ float2 c_scale(float2 a, float s) { return make_float2(a.x * s, a.y * s); }
+__device__ __forceinline__ float2 c_mul(float2 a, float2 b) {
+  return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+// a * conj(b)
+__device__ __forceinline__ float2 c_mulc(float2 a, float2 b) {
+  return make_float2(a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y);
+}
+__device__ __forceinline__ float2 c_conj(float2 a) { return make_float2(a.x, -a.y); }
+
+__device__ __forceinline__ double2 c_add(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ double2 c_sub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ double2 c_scale(double2 a, double s) { return make_double2(a.x * s, a.y * s); }
+__device__ __forceinline__ double2 c_mul(double2 a, double2 b) {
+  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ double2 c_conj(double2 a) { return make_double2(a.x, -a.y); }
+
+// multiply by -i (DIR < 0) or +i (DIR > 0)
+template <int DIR, typename V>
+__device__ __forceinline__ V c_rot(V a) {
+  V r;
+  if (DIR < 0) {
+    r.x = a.y;
+    r.y = -a.x;
+  } else {
+    r.x = -a.y;
+    r.y = a.x;
+  }
+  return r;
+}
+
+constexpr int ilog2c(int n) { return n <= 1 ? 0 : 1 + ilog2c(n >> 1); }
+
+// Twiddle W = exp(DIR * 2 pi i * e / n) for e < n, from the table
+// tw[m] = exp(-2 pi i m / MG_TWN) (rounded from FP64 on the host).
+template <int DIR, typename V>
+__device__ __forceinline__ V tw_get(const V* __restrict__ tw, int m) {
+  V w = tw[m];
+  if (DIR > 0) w.y = -w.y;
+  return w;
+}
+
+// One radix-4 Stockham pass over B transforms of length N stored at
+// buf[b * BS + i].  Ns is the product of the radices of the earlier passes.
+template <int N, int B, int BS, int NT, int DIR, typename V>
+__device__ __forceinline__ void fft_r4_pass(V* buf, const V* __restrict__ tw, int Ns) {
+  constexpr int Q = N / 4;
+  constexpr int NB = B * Q;
+  constexpr int PER = NB / NT;
+  static_assert(NB % NT == 0, "butterflies must divide evenly");
+  V v[PER][4];
+  const int tid = threadIdx.x;
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const int g = tid + q * NT;
+    const int b = g / Q, j = g % Q;
+    const V* base = buf + b * BS;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) v[q][r] = base[j + r * Q];
+  }
+  __syncthreads();
+  const int stride = MG_TWN / (4 * Ns);
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const int g = tid + q * NT;
+    const int b = g / Q, j = g % Q;
+    const int k = j & (Ns - 1);
+    if (Ns > 1) {
+      v[q][1] = c_mul(v[q][1], tw_get<DIR>(tw, k * stride));
+      v[q][2] = c_mul(v[q][2], tw_get<DIR>(tw, 2 * k * stride));
+      v[q][3] = c_mul(v[q][3], tw_get<DIR>(tw, 3 * k * stride));
+    }
+    V t0 = c_add(v[q][0], v[q][2]);
+    V t1 = c_sub(v[q][0], v[q][2]);
+    V t2 = c_add(v[q][1], v[q][3]);
+    V t3 = c_rot<DIR>(c_sub(v[q][1], v[q][3]));
+    V* base = buf + b * BS;
+    const int idx = (j - k) * 4 + k;
+    base[idx] = c_add(t0, t2);
+    base[idx + Ns] = c_add(t1, t3);
+    base[idx + 2 * Ns] = c_sub(t0, t2);
+    base[idx + 3 * Ns] = c_sub(t1, t3);
+  }
+  __syncthreads();
+}
+
+template <int N, int B, int BS, int NT, int DIR, typename V>
+__device__ __forceinline__ void fft_r2_pass(V* buf, const V* __restrict__ tw, int Ns) {
+  constexpr int Q = N / 2;
+  constexpr int NB = B * Q;
+  constexpr int PER = NB / NT;
+  static_assert(NB % NT == 0, "butterflies must divide evenly");
+  V v[PER][2];
+  const int tid = threadIdx.x;
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const int g = tid + q * NT;
+    const int b = g / Q, j = g % Q;
+    const V* base = buf + b * BS;
+    v[q][0] = base[j];
+    v[q][1] = base[j + Q];
+  }
+  __syncthreads();
+  const int stride = MG_TWN / (2 * Ns);
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const int g = tid + q * NT;
+    const int b = g / Q, j = g % Q;
+    const int k = j & (Ns - 1);
+    if (Ns > 1) v[q][1] = c_mul(v[q][1], tw_get<DIR>(tw, k * stride));
+    V* base = buf + b * BS;
+    const int idx = (j - k) * 2 + k;
+    base[idx] = c_add(v[q][0], v[q][1]);
+    base[idx + Ns] = c_sub(v[q][0], v[q][1]);
+  }
+  __syncthreads();
+}
+
+// B unnormalised transforms of length N (4 <= N <= MG_TWN), in place in LDS.
+// DIR = -1: X[k] = sum x[n] e^{-2 pi i nk/N};  DIR = +1: the inverse sign.
+// V is float2 or double2 (with a twiddle table of the same type).
+// The caller must __syncthreads() after filling buf.
+template <int N, int B, int BS, int NT, int DIR, typename V>
+__device__ __forceinline__ void fft_lds(V* buf, const V* __restrict__ tw) {
+  constexpr int LOG = ilog2c(N);
+  static_assert((1 << LOG) == N, "power of two");
+  int Ns = 1;
+#pragma unroll
+  for (int p = 0; p < LOG / 2; ++p) {
+    fft_r4_pass<N, B, BS, NT, DIR>(buf, tw, Ns);
+    Ns *= 4;
+  }
+  if (LOG & 1) fft_r2_pass<N, B, BS, NT, DIR>(buf, tw, Ns);
+}
+
+// Fixed-order sum over the workgroup; every thread gets the result.
+template <int NT, typename T>
+__device__ __forceinline__ T block_sum(T v, T* red) {
+  const int tid = threadIdx.x;
+  red[tid] = v;
+  __syncthreads();
+#pragma unroll
+  for (int s = NT / 2; s > 0; s >>= 1) {
+    if (tid < s) red[tid] += red[tid + s];
+    __syncthreads();
+  }
+  T r = red[0];
+  __syncthreads();
+  return r;
+}
+
+__device__ __forceinline__ float sigmoidf_(float x) { return 1.0f / (1.0f + __expf(-x)); }

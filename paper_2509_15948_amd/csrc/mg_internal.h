@@ -1,0 +1,131 @@
+// Internal structures of the mixgraph library: the compiled graph (host),
+// per-stage node descriptors (device-visible PODs) and kernel launchers.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <string>
+#include <vector>
+
+#include "../../include/mixgraph.h"
+
+namespace mg {
+
+constexpr int NTYPES = 11;
+// processor types in parameter-block order
+constexpr int kProcOrder[8] = {MG_EQ, MG_COMP, MG_GATE, MG_DIST, MG_IMAGER, MG_GAINPAN, MG_DELAY, MG_REVERB};
+inline bool is_proc(int t) { return t >= MG_EQ && t <= MG_REVERB; }
+inline bool is_conv(int t) { return t == MG_EQ || t == MG_DELAY || t == MG_REVERB; }
+inline bool is_dyn(int t) { return t == MG_COMP || t == MG_GATE; }
+inline char type_char(int t) {
+  static const char c[] = "imoecnxsgdr";
+  return (t >= 0 && t < NTYPES) ? c[t] : '?';
+}
+
+// One node of a stage, as the kernels see it.  Pointers are resolved from
+// slots: U slot -> U + slot * 2L; dry track -> dry + slot * C * L.
+struct NodeDesc {
+  int32_t node;       // user node id
+  int32_t proc;       // processor index (sigma order), -1 for m/o
+  int32_t in_kind;    // 0: dry track, 1: U slot
+  int32_t in_slot;
+  int32_t out_slot;   // U slot of the output
+  int32_t aux;        // row inside the type block (ybar/env/conv/fir tables)
+  int32_t gin;        // gradient slot receiving dL/du (-1: not needed)
+  int32_t gout;       // gradient slot holding dL/dy
+  int64_t theta_off;  // offset of the parameter row in theta
+  int32_t src_begin;  // m/o/sum: range in the source list
+  int32_t src_count;
+};
+
+// One source of a sum: kind 0 dry track, 1 U slot, 2 gradient slot
+struct SrcRef {
+  int32_t kind;
+  int32_t slot;
+};
+
+struct Stage {
+  int type;
+  std::vector<int> nodes;       // user ids, in sigma order
+  int desc_off = 0;             // offset (elements) in the device descriptor array
+};
+
+// FFT plan for the FIR convolutions: N = N1 * N2, x[n1 + N1 n2].
+struct FftPlan {
+  int N = 0, N1 = 0, N2 = 0, log2N = 0;
+};
+
+// Offsets (bytes) of everything carved out of the caller's workspace.
+struct WsPlan {
+  size_t total = 0;
+  size_t desc = 0, srcs = 0;
+  size_t U = 0, YB = 0, ENV = 0, G = 0;
+  size_t ZU = 0, ZH = 0, T1 = 0, T2 = 0, T3 = 0;
+  size_t tw = 0, twd = 0, twhi = 0, twlo = 0;
+  size_t eq_h = 0, eq_dh = 0, eq_cos = 0;
+  size_t dl_tab = 0, dl_dh = 0, dl_cos = 0;
+  size_t rv_U = 0, rv_fr = 0, rv_h = 0, rv_dh = 0, rv_dM = 0, rv_cs = 0, rv_win = 0, rv_wsum = 0;
+  size_t cmp_sum = 0, cmp_carry = 0;
+  size_t part = 0;           // per (node, block) partial sums
+  size_t pgrad = 0;          // per node parameter gradient staging (double)
+  size_t ls_tgt = 0, ls_part = 0, ls_norm = 0, ls_tab = 0, ls_aw = 0, ls_win = 0;
+  size_t ls_stats = 0;       // double: per (res, combo): |Y|^2, |Y-Yh|^2, sum|dlog|
+  size_t lg = 0;             // double per node: E_ybar, E_u
+  size_t losses_tmp = 0;
+};
+
+struct LossRes {
+  int nfft, hop, frames;
+  size_t tgt_off, part_off, tab_off, aw_off, win_off;  // byte offsets in ws
+  int n_tab;                                           // CSR entries
+};
+
+}  // namespace mg
+
+struct mg_graph {
+  // user graph
+  int n_nodes = 0;
+  std::vector<int> type, track;
+  std::vector<std::vector<int>> preds, succs;
+  int n_tracks = 0, track_ch = 1;
+  mg_config cfg{};
+  // schedule and layout
+  std::vector<mg::Stage> stages;
+  std::vector<int> order, pos;            // sigma: position -> node, node -> position
+  std::vector<int> stage_of, proc_idx, type_row;
+  std::vector<int64_t> param_off;
+  int type_count[mg::NTYPES] = {0};
+  int type_np[mg::NTYPES] = {0};
+  int64_t type_off[mg::NTYPES] = {0};
+  int n_proc = 0;
+  int64_t n_theta = 0;
+  int output_node = -1;
+  // slots
+  std::vector<int> uslot;                 // node -> U slot (-1 for inputs)
+  int n_uslots = 0;
+  std::vector<int> gslot, ginslot;        // node -> gradient slot of dL/dy, dL/du
+  int n_gslots = 0;
+  std::vector<int> fanout_sum;            // nodes whose dL/dy is a sum of contributions
+  // device descriptor tables (host copies)
+  std::vector<mg::NodeDesc> desc;
+  std::vector<mg::SrcRef> srcs;
+  std::vector<mg::SrcRef> gsrcs;          // backward fan-out sums
+  mg::FftPlan fft;
+  std::vector<mg::LossRes> lres;
+  int max_conv_stage = 0, max_stage = 0;
+  int nf_rev = 0;                         // reverb STFT frames
+  int64_t dl_len = 0;                     // delay compact FIR length
+  int dyn_chunks = 0;
+  int part_blocks = 0;                    // blocks per node for partial sums
+  // bound workspace
+  mg::WsPlan ws;
+  char* base = nullptr;
+  size_t ws_bytes = 0;
+  int mode = 0;
+  bool ready = false;
+  bool have_forward = false;
+  // last forward's inputs (for backward)
+  const float* f_dry = nullptr;
+  const float* f_theta = nullptr;
+  const float* f_wet = nullptr;
+  const float* f_mask = nullptr;
+};

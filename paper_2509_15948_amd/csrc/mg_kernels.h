@@ -1,0 +1,68 @@
+// Launch context and kernel launchers of the mixgraph library.
+#pragma once
+#include "mg_internal.h"
+
+namespace mg {
+
+constexpr int PK = 8;  // floats of partial sums per (node, block)
+
+struct Ctx {
+  const mg_graph* g;
+  hipStream_t st;
+  int64_t L;
+  int C;                 // channels of the dry tracks (1 or 2)
+  float* U;              // node outputs [slot][2][L]
+  float* G;              // gradient buffers [slot][2][L]
+  const float* dry;
+  const float* theta;
+  const float* wet;
+  const float* mask;
+  const NodeDesc* desc;  // device descriptor array
+  const SrcRef* srcs;    // device source list
+  float* part;           // partial sums [desc][PB][PK]
+  int PB;                // blocks per node row of part
+  double* lg;            // per desc: E_ybar, E_u (double)
+  float alpha_g, alpha_p;
+  char* base;            // workspace base
+};
+
+template <typename T>
+inline T* wsp(const Ctx& c, size_t off) {
+  return reinterpret_cast<T*>(c.base + off);
+}
+
+// k_basic.hip
+void launch_sum(const Ctx& c, int desc_off, int n, const SrcRef* srcs, float* out_base, int dest_kind);
+void launch_pointwise_fwd(const Ctx& c, int type, int desc_off, int n);
+void launch_pointwise_bwd(const Ctx& c, int type, int desc_off, int n);
+void launch_finish_grads(const Ctx& c, int desc_off, int n, int nblocks, int nparams, float* grad_theta,
+                         float* grad_wet);
+void launch_reduce_lg(const Ctx& c, int desc_off, int n, int nblocks);
+void launch_finalize_losses(const Ctx& c, double* losses, const double* lstats, int n_res, const double* lweights,
+                            int n_desc);
+void launch_adam(float* th, float* m, float* v, const float* g, int64_t n, float lr, float b1, float b2, float eps,
+                 int step, hipStream_t st);
+void launch_zero(void* p, size_t bytes, hipStream_t st);
+
+// k_fft.hip: the FIR convolution engine
+void fft_init_tables(const Ctx& c, float2* tw, float2* twhi, float2* twlo, int N, hipStream_t st);
+// forward conv of stage nodes; fir spectra ZH must be ready
+void conv_fir_spectrum(const Ctx& c, int type, int desc_off, int n);
+void conv_forward(const Ctx& c, int type, int desc_off, int n, bool keep_input_spectrum);
+void conv_backward(const Ctx& c, int type, int desc_off, int n);
+
+// k_fir.hip: FIR synthesis and adjoints
+void fir_setup(const Ctx& c, const float* reverb_noise);
+void fir_synth(const Ctx& c, int type, int desc_off, int n);
+void fir_adjoint(const Ctx& c, int type, int desc_off, int n, float* grad_theta);
+
+// k_dyn.hip
+void dyn_forward(const Ctx& c, int type, int desc_off, int n);
+void dyn_backward(const Ctx& c, int type, int desc_off, int n);
+
+// k_loss.hip
+void loss_setup(const Ctx& c, const float* target);
+void loss_forward(const Ctx& c, const float* yhat);
+void loss_backward(const Ctx& c, const float* yhat, float* dyhat);
+
+}  // namespace mg

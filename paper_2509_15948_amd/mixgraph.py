@@ -1,0 +1,312 @@
+"""Python binding of libmixgraph (ctypes; argument marshalling only).
+
+Every function here forwards to the C-ABI of include/mixgraph.h with the same
+name; the classes below only hold handles, shapes and device buffers (torch
+tensors used as plain device memory).  No step of the mixing-graph method is
+computed here, and there is no fallback: if the shared library is missing or
+fails to load, importing the functions raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Dict, Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmixgraph.so")
+
+TYPE_CODES = {"i": 0, "m": 1, "o": 2, "e": 3, "c": 4, "n": 5, "x": 6, "s": 7, "g": 8, "d": 9, "r": 10}
+LOSS_KEYS = ("L", "La", "Llr", "Lm", "Ls", "Lg", "Lp")
+
+
+class MixgraphError(RuntimeError):
+    pass
+
+
+class mg_config(ctypes.Structure):
+    _fields_ = [("length", ctypes.c_int64), ("sample_rate", ctypes.c_int32), ("eq_taps", ctypes.c_int32),
+                ("comp_mode", ctypes.c_int32), ("delay_taps", ctypes.c_int32), ("delay_range", ctypes.c_int32),
+                ("delay_fir_taps", ctypes.c_int32), ("reverb_length", ctypes.c_int32),
+                ("reverb_nfft", ctypes.c_int32), ("reverb_hop", ctypes.c_int32), ("n_loss_ffts", ctypes.c_int32),
+                ("loss_ffts", ctypes.c_int32 * 8), ("n_mels", ctypes.c_int32), ("loss_skip", ctypes.c_int32),
+                ("alpha_g", ctypes.c_double), ("alpha_p", ctypes.c_double)]
+
+
+class mg_info(ctypes.Structure):
+    _fields_ = [("n_nodes", ctypes.c_int32), ("n_processors", ctypes.c_int32), ("n_stages", ctypes.c_int32),
+                ("fft_size", ctypes.c_int32), ("n_theta", ctypes.c_int64), ("n_reverbs", ctypes.c_int32),
+                ("n_losses", ctypes.c_int32)]
+
+
+_lib = None
+
+EXPORTS = ("mg_graph_create", "mg_graph_destroy", "mg_graph_info", "mg_graph_layout", "mg_workspace_size",
+           "mg_setup", "mg_forward", "mg_backward", "mg_forward_masked", "mg_adam_step", "mg_graph_prune",
+           "mg_last_error")
+
+
+def lib() -> ctypes.CDLL:
+    """Load libmixgraph.so (raises when it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise MixgraphError(f"{LIB_PATH} is missing: run `python -m paper_2509_15948_amd.build`")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i32, i64, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t
+    L.mg_last_error.restype = ctypes.c_char_p
+    L.mg_last_error.argtypes = []
+    sig = {
+        "mg_graph_create": [i32, vp, i32, vp, vp, i32, i32, ctypes.POINTER(mg_config), ctypes.POINTER(vp)],
+        "mg_graph_destroy": [vp],
+        "mg_graph_info": [vp, ctypes.POINTER(mg_info)],
+        "mg_graph_layout": [vp, vp, vp, vp, vp, vp],
+        "mg_workspace_size": [vp, i32, ctypes.POINTER(sz)],
+        "mg_setup": [vp, vp, sz, i32, vp, vp, vp],
+        "mg_forward": [vp, vp, vp, vp, vp, vp, vp, vp],
+        "mg_backward": [vp, vp, vp, vp],
+        "mg_forward_masked": [vp, vp, vp, vp, vp, i32, vp, vp],
+        "mg_adam_step": [vp, vp, vp, vp, i64, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                         i32, vp],
+        "mg_graph_prune": [vp, vp, ctypes.POINTER(vp), vp],
+    }
+    for name, args in sig.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = ctypes.c_int
+    _lib = L
+    return L
+
+
+def _check(rc: int) -> None:
+    if rc != 0:
+        raise MixgraphError(f"mixgraph error {rc}: {lib().mg_last_error().decode(errors='replace')}")
+
+
+def _ptr(a) -> Optional[int]:
+    """Device/host address of a torch tensor or numpy array (None -> NULL)."""
+    if a is None:
+        return None
+    if isinstance(a, np.ndarray):
+        return a.ctypes.data
+    return a.data_ptr()
+
+
+def make_config(length: int, sample_rate: int, eq_taps: int = 2047, comp_mode: int = 0, delay_taps: int = 4,
+                delay_range: int = 5512, delay_fir_taps: int = 39, reverb_length: int = 66150,
+                reverb_nfft: int = 384, reverb_hop: int = 192, loss_ffts: Sequence[int] = (512, 1024, 2048),
+                n_mels: int = 96, loss_skip: int = 0, alpha_g: float = 1e-3, alpha_p: float = 0.0) -> mg_config:
+    c = mg_config()
+    c.length = length
+    c.sample_rate = sample_rate
+    c.eq_taps = eq_taps
+    c.comp_mode = comp_mode
+    c.delay_taps = delay_taps
+    c.delay_range = delay_range
+    c.delay_fir_taps = delay_fir_taps
+    c.reverb_length = reverb_length
+    c.reverb_nfft = reverb_nfft
+    c.reverb_hop = reverb_hop
+    c.n_loss_ffts = len(loss_ffts)
+    for i, n in enumerate(loss_ffts):
+        c.loss_ffts[i] = n
+    c.n_mels = n_mels
+    c.loss_skip = loss_skip
+    c.alpha_g = alpha_g
+    c.alpha_p = alpha_p
+    return c
+
+
+# ---------------------------------------------------------------- C-ABI mirrors
+def mg_graph_create(types: Sequence[int], edges: np.ndarray, input_track: Sequence[int], n_tracks: int,
+                    track_channels: int, cfg: mg_config) -> int:
+    t = np.ascontiguousarray(types, dtype=np.int32)
+    e = np.ascontiguousarray(edges, dtype=np.int32).reshape(2, -1)
+    it = np.ascontiguousarray(input_track, dtype=np.int32)
+    out = ctypes.c_void_p()
+    _check(lib().mg_graph_create(len(t), t.ctypes.data, e.shape[1], e.ctypes.data if e.size else None,
+                                 it.ctypes.data, n_tracks, track_channels, ctypes.byref(cfg), ctypes.byref(out)))
+    return out.value
+
+
+def mg_graph_destroy(g: int) -> None:
+    _check(lib().mg_graph_destroy(g))
+
+
+def mg_graph_info(g: int) -> mg_info:
+    info = mg_info()
+    _check(lib().mg_graph_info(g, ctypes.byref(info)))
+    return info
+
+
+def mg_graph_layout(g: int, n_nodes: int, n_stages: int):
+    po = np.zeros(n_nodes, np.int64)
+    pi = np.zeros(n_nodes, np.int32)
+    st = np.zeros(n_nodes, np.int32)
+    tr = np.zeros(n_nodes, np.int32)
+    sched = ctypes.create_string_buffer(n_stages + 1)
+    _check(lib().mg_graph_layout(g, po.ctypes.data, pi.ctypes.data, st.ctypes.data, tr.ctypes.data, sched))
+    return po, pi, st, tr, sched.value.decode()
+
+
+def mg_workspace_size(g: int, mode: int) -> int:
+    n = ctypes.c_size_t()
+    _check(lib().mg_workspace_size(g, mode, ctypes.byref(n)))
+    return n.value
+
+
+def mg_setup(g: int, ws, ws_bytes: int, mode: int, reverb_noise, target, stream: int) -> None:
+    _check(lib().mg_setup(g, _ptr(ws), ws_bytes, mode, _ptr(reverb_noise), _ptr(target), stream))
+
+
+def mg_forward(g: int, dry, theta, wet, mask, mix, losses, stream: int) -> None:
+    _check(lib().mg_forward(g, _ptr(dry), _ptr(theta), _ptr(wet), _ptr(mask), _ptr(mix), _ptr(losses), stream))
+
+
+def mg_backward(g: int, grad_theta, grad_wet, stream: int) -> None:
+    _check(lib().mg_backward(g, _ptr(grad_theta), _ptr(grad_wet), stream))
+
+
+def mg_forward_masked(g: int, dry, theta, wet, masks, B: int, losses, stream: int) -> None:
+    _check(lib().mg_forward_masked(g, _ptr(dry), _ptr(theta), _ptr(wet), _ptr(masks), B, _ptr(losses), stream))
+
+
+def mg_adam_step(theta, m, v, grad, n: int, lr: float, b1: float, b2: float, eps: float, step: int,
+                 stream: int) -> None:
+    _check(lib().mg_adam_step(_ptr(theta), _ptr(m), _ptr(v), _ptr(grad), n, lr, b1, b2, eps, step, stream))
+
+
+def mg_graph_prune(g: int, keep: np.ndarray, n_nodes: int):
+    k = np.ascontiguousarray(keep, dtype=np.uint8)
+    out = ctypes.c_void_p()
+    o2n = np.zeros(n_nodes, np.int32)
+    _check(lib().mg_graph_prune(g, k.ctypes.data, ctypes.byref(out), o2n.ctypes.data))
+    return out.value, o2n
+
+
+# ---------------------------------------------------------------- handles
+class Graph:
+    """A compiled graph (host object) with its layout."""
+
+    def __init__(self, types: Sequence[str], edges: np.ndarray, input_track: Sequence[int], n_tracks: int,
+                 track_channels: int, cfg: mg_config, handle: Optional[int] = None):
+        self.types = list(types)
+        self.cfg = cfg
+        self.n_tracks = n_tracks
+        self.track_channels = track_channels
+        codes = [TYPE_CODES[t] for t in self.types]
+        self.h = handle if handle is not None else mg_graph_create(codes, edges, input_track, n_tracks,
+                                                                   track_channels, cfg)
+        self.info = mg_graph_info(self.h)
+        (self.param_offset, self.proc_index, self.stage, self.type_row,
+         self.schedule) = mg_graph_layout(self.h, len(self.types), self.info.n_stages)
+
+    def __del__(self):
+        try:
+            if getattr(self, "h", None):
+                mg_graph_destroy(self.h)
+                self.h = None
+        except Exception:
+            pass
+
+    @property
+    def n_theta(self) -> int:
+        return int(self.info.n_theta)
+
+    @property
+    def n_proc(self) -> int:
+        return int(self.info.n_processors)
+
+    def flatten(self, theta: Dict[int, np.ndarray], wet: Dict[int, float]):
+        """Per-node raw parameters -> (theta[n_theta], wet[P]) float32."""
+        th = np.zeros(self.n_theta, np.float32)
+        we = np.zeros(self.n_proc, np.float32)
+        for v, p in theta.items():
+            o = int(self.param_offset[v])
+            th[o:o + len(p)] = np.asarray(p, np.float32)
+        for v, w in wet.items():
+            we[int(self.proc_index[v])] = w
+        return th, we
+
+    def unflatten(self, th: np.ndarray, we: np.ndarray, sizes: Dict[int, int]):
+        theta = {v: np.asarray(th[int(self.param_offset[v]):int(self.param_offset[v]) + n], np.float64)
+                 for v, n in sizes.items()}
+        wet = {v: float(we[int(self.proc_index[v])]) for v in sizes}
+        return theta, wet
+
+    def mask_vector(self, mask: Dict[int, float]) -> np.ndarray:
+        m = np.ones(self.n_proc, np.float32)
+        for v, x in mask.items():
+            m[int(self.proc_index[v])] = x
+        return m
+
+    def reverb_rows(self):
+        """Reverb node ids in the row order the noise input expects."""
+        rv = [v for v, t in enumerate(self.types) if t == "r"]
+        return sorted(rv, key=lambda v: int(self.type_row[v]))
+
+    def prune(self, keep: np.ndarray):
+        h, o2n = mg_graph_prune(self.h, keep, len(self.types))
+        types = [None] * int((o2n >= 0).sum())
+        for v, n in enumerate(o2n):
+            if n >= 0:
+                types[n] = self.types[v]
+        return Graph(types, None, None, self.n_tracks, self.track_channels, self.cfg, handle=h), o2n
+
+
+class Session:
+    """A graph bound to a device workspace (torch tensor) and a stream."""
+
+    def __init__(self, graph: Graph, reverb_noise, target, mode: int = 1, device: str = "cuda"):
+        import torch
+        self.torch = torch
+        self.g = graph
+        self.mode = mode
+        self.bytes = mg_workspace_size(graph.h, mode)
+        self.ws = torch.empty(self.bytes + 256, dtype=torch.uint8, device=device)
+        base = self.ws.data_ptr()
+        self.ws_ptr = (base + 255) // 256 * 256
+        self.target = target
+        self.noise = reverb_noise
+        self.losses = torch.zeros(7, dtype=torch.float64, device=device)
+        _check(lib().mg_setup(graph.h, self.ws_ptr, self.bytes, mode, _ptr(reverb_noise), _ptr(target),
+                              self.stream()))
+
+    def stream(self) -> int:
+        return self.torch.cuda.current_stream().cuda_stream
+
+    def forward(self, dry, theta, wet, mask=None, mix=None, losses=None):
+        out = self.losses if losses is None else losses
+        mg_forward(self.g.h, dry, theta, wet, mask, mix, out, self.stream())
+        return out
+
+    def backward(self, grad_theta, grad_wet):
+        mg_backward(self.g.h, grad_theta, grad_wet, self.stream())
+
+    def forward_masked(self, dry, theta, wet, masks, losses):
+        mg_forward_masked(self.g.h, dry, theta, wet, masks, masks.shape[0], losses, self.stream())
+
+
+def console_loss(session: Session, dry, theta, wet, mask=None):
+    """torch.autograd wrapper: returns the 7 loss values (float64 tensor); the
+    gradient of L (entry 0) flows to theta and wet through mg_backward."""
+    import torch
+
+    class _ConsoleFn(torch.autograd.Function):
+        @staticmethod
+        def forward(ctx, th, we):
+            out = torch.zeros(7, dtype=torch.float64, device=th.device)
+            session.forward(dry, th.detach(), we.detach(), mask, None, out)
+            return out
+
+        @staticmethod
+        def backward(ctx, gout):
+            gth = torch.empty(session.g.n_theta, dtype=torch.float32, device=gout.device)
+            gwe = torch.empty(session.g.n_proc, dtype=torch.float32, device=gout.device)
+            session.backward(gth, gwe)
+            s = gout[0].to(torch.float32)
+            return gth * s, gwe * s
+
+    return _ConsoleFn.apply(theta, wet)

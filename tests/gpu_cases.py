@@ -1,0 +1,99 @@
+"""Shared setup for the GPU parity tests: one seeded synthetic song, its
+target rendered by the FP64 oracle, the HIP session, and the oracle's
+results on exactly the FP32 values the GPU sees."""
+import numpy as np
+import torch
+
+import synth
+from oracle import train as TR
+from paper_2509_15948_amd import mixgraph as MG
+from paper_2509_15948_amd import workloads as W
+
+
+def f32(x):
+    return np.asarray(x, np.float32).astype(np.float64)
+
+
+class Case:
+    def __init__(self, cfg, seed=3, params="random", alpha_g=1e-3, alpha_p=0.0, mode=1, std=0.3):
+        self.cfg = cfg
+        self.g, self.dry, self.noise = synth.song(seed, cfg)
+        gt, gw = synth.ground_truth_params(seed + 100, self.g, cfg)
+        self.target = TR.render(self.g, cfg, self.dry, self.noise, gt, gw).astype(np.float32)
+        if params == "random":
+            th, we = synth.random_params(seed, self.g, cfg, std=std)
+        else:
+            th, we = synth.init_params(seed, self.g, cfg)
+        self.th = {v: f32(p) for v, p in th.items()}
+        self.we = {v: float(np.float32(w)) for v, w in we.items()}
+        self.alpha_g, self.alpha_p = alpha_g, alpha_p
+        self.bg = W.binding_graph(self.g, cfg, alpha_g, alpha_p)
+        dev = "cuda"
+        self.noise_d = torch.from_numpy(W.noise_rows(self.bg, self.noise, cfg.reverb_length)).to(dev)
+        self.target_d = torch.from_numpy(self.target).to(dev)
+        self.dry_d = torch.from_numpy(self.dry).to(dev)
+        self.sess = MG.Session(self.bg, self.noise_d, self.target_d, mode=mode)
+        th_f, we_f = self.bg.flatten(self.th, self.we)
+        self.theta_d = torch.from_numpy(th_f).to(dev)
+        self.wet_d = torch.from_numpy(we_f).to(dev)
+        self.sizes = {v: len(p) for v, p in self.th.items()}
+
+    def mask_d(self, mask):
+        return None if mask is None else torch.from_numpy(self.bg.mask_vector(mask)).cuda()
+
+    def gpu_forward(self, mask=None):
+        mix = torch.empty(2, self.cfg.length, dtype=torch.float32, device="cuda")
+        losses = torch.zeros(7, dtype=torch.float64, device="cuda")
+        self.sess.forward(self.dry_d, self.theta_d, self.wet_d, self.mask_d(mask), mix, losses)
+        torch.cuda.synchronize()
+        return mix.cpu().numpy().astype(np.float64), dict(zip(MG.LOSS_KEYS, losses.cpu().numpy().tolist()))
+
+    def gpu_backward(self):
+        gth = torch.empty(self.bg.n_theta, dtype=torch.float32, device="cuda")
+        gwe = torch.empty(self.bg.n_proc, dtype=torch.float32, device="cuda")
+        self.sess.backward(gth, gwe)
+        torch.cuda.synchronize()
+        return self.bg.unflatten(gth.cpu().numpy(), gwe.cpu().numpy(), self.sizes)
+
+    def oracle(self, mask=None, grads=True):
+        tgt = self.target.astype(np.float64)
+        if grads:
+            vals, gth, gwe, mix = TR.loss_and_grad(self.g, self.cfg, self.dry, self.noise, tgt, self.th, self.we,
+                                                   mask, self.alpha_g, self.alpha_p)
+            return mix, vals, gth, gwe
+        vals = TR.losses(self.g, self.cfg, self.dry, self.noise, tgt, self.th, self.we, mask, self.alpha_g,
+                         self.alpha_p)
+        mix = TR.render(self.g, self.cfg, self.dry, self.noise, self.th, self.we, mask)
+        return mix, vals, None, None
+
+
+def rel_l2(a, b):
+    a = np.asarray(a, np.float64)
+    b = np.asarray(b, np.float64)
+    nb = np.linalg.norm(b)
+    return float(np.linalg.norm(a - b) / (nb if nb > 0 else 1.0))
+
+
+# Relative RMS error of one FP32 FFT convolution (a library FP32 FFT measures
+# 2.7e-7 at 2^14 points); the loss is evaluated in FP64 on the FP32 mix.
+FP32_CONV_REL = 3e-7
+
+
+def loss_tolerances(case, omix, draws=2, rel=1e-5):
+    """Per loss term: max(rel * |L|, 3 * the change that FP32-level white noise
+    on the oracle's own mix causes).  Computed from the oracle only."""
+    import torch as T
+    from oracle import loss as LS
+    tgt = T.tensor(case.target.astype(np.float64))
+    base = LS.mrstft(T.tensor(omix), tgt, case.cfg.loss_ffts, case.cfg.fs)
+    rng = np.random.default_rng(4242)
+    rms = float(np.sqrt(np.mean(omix ** 2)))
+    delta = {k: 0.0 for k in base}
+    for _ in range(draws):
+        noisy = omix + rng.standard_normal(omix.shape) * FP32_CONV_REL * rms
+        out = LS.mrstft(T.tensor(noisy), tgt, case.cfg.loss_ffts, case.cfg.fs)
+        for k in base:
+            delta[k] = max(delta[k], abs(float(out[k]) - float(base[k])))
+    tol = {k: max(rel * abs(float(base[k])), 3.0 * delta[k]) for k in base}
+    tol["L"] = tol["La"] + rel * abs(float(base["La"]))
+    return tol

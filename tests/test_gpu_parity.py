@@ -1,0 +1,189 @@
+"""GPU parity: the HIP path through the C-ABI against the FP64 oracle on the
+same seeded inputs.  Tolerances: waveform relative L2 <= 1e-4, loss terms
+relative <= 1e-5, gradients relative L2 per parameter tensor <= 1e-3."""
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import train as TR
+from paper_2509_15948_amd import mixgraph as MG
+
+from gpu_cases import Case, loss_tolerances, rel_l2
+
+pytestmark = pytest.mark.gpu
+
+WAVE_TOL = 1e-4
+LOSS_TOL = 1e-5
+GRAD_TOL = 1e-3
+
+
+def _small(chain, **kw):
+    base = dict(seconds=0.75, fs=16000, n_tracks=3, n_subgroups=2, chain=chain)
+    base.update(kw)
+    return synth.small_config(**base)
+
+
+def _check_losses(gl, ol, tol=None, keys=("La", "Llr", "Lm", "Ls", "Lg", "Lp", "L")):
+    """Loss parity: relative 1e-5, or (audio terms) 3x the oracle's own
+    sensitivity to FP32-level noise on its mix, whichever is larger."""
+    for k in keys:
+        ref = ol[k]
+        bound = LOSS_TOL * abs(ref)
+        if tol is not None and k in tol:
+            bound = max(bound, tol[k])
+        print("loss", k, gl[k], ref, "err", abs(gl[k] - ref), "bound", bound, flush=True)
+        assert abs(gl[k] - ref) <= bound or abs(gl[k] - ref) < 1e-9, (k, gl[k], ref, bound)
+
+
+@pytest.mark.parametrize("chain", ["g", "s", "x", "e", "c", "n", "d", "r", "ecxsgdr"])
+def test_forward_parity_per_type(chain):
+    case = Case(_small(chain))
+    mix, gl = case.gpu_forward()
+    omix, ol, _, _ = case.oracle(grads=False)
+    print(chain, "wave", rel_l2(mix, omix), flush=True)
+    assert rel_l2(mix, omix) <= WAVE_TOL
+    _check_losses(gl, ol, loss_tolerances(case, omix))
+
+
+def test_zero_dry_wet_is_the_sum_of_the_sources():
+    case = Case(_small("ecxsgdr"))
+    mask = {v: 0.0 for v in case.g.processors()}
+    mix, gl = case.gpu_forward(mask)
+    ref = case.dry.astype(np.float32).sum(0)
+    assert np.allclose(mix, ref, rtol=1e-6, atol=1e-7)
+
+
+@pytest.mark.parametrize("chain", ["g", "s", "x", "e", "c", "n", "d", "r", "ecxsgdr"])
+def test_backward_parity_per_type(chain):
+    case = Case(_small(chain), alpha_p=1e-2)
+    mix, gl = case.gpu_forward()
+    gth, gwe = case.gpu_backward()
+    omix, ol, oth, owe = case.oracle()
+    _check_losses(gl, ol, loss_tolerances(case, omix))
+    by_type = {}
+    for v in case.g.processors():
+        t = case.g.types[v]
+        by_type.setdefault(t, ([], []))
+        by_type[t][0].append(gth[v])
+        by_type[t][1].append(oth[v])
+    Kc = (case.cfg.delay_fir_taps + 1) // 2
+    dl = [v for v in case.g.processors() if case.g.types[v] == "d"]
+    for v in dl:
+        a = gth[v].reshape(2, case.cfg.delay_taps, 2 + Kc)
+        b = oth[v].reshape(2, case.cfg.delay_taps, 2 + Kc)
+        for c in range(2):
+            for m in range(case.cfg.delay_taps):
+                print("delay", v, c, m, "z gpu", a[c, m, :2], "oracle", b[c, m, :2],
+                      "fir err", rel_l2(a[c, m, 2:], b[c, m, 2:]), flush=True)
+    for t, (a, b) in by_type.items():
+        a = np.concatenate(a)
+        b = np.concatenate(b)
+        err = rel_l2(a, b)
+        print(chain, t, "grad err", err, flush=True)
+        assert err <= GRAD_TOL, (t, err)
+    procs = case.g.processors()
+    err = rel_l2([gwe[v] for v in procs], [owe[v] for v in procs])
+    print(chain, "wet grad err", err, flush=True)
+    assert err <= GRAD_TOL
+
+
+def test_tiny_console_attack_release_full_size():
+    """4 mono tracks, 2 s at 44.1 kHz, gain/pan + 1023-tap EQ + attack/release
+    compressor, one subgroup; forward and backward at full size."""
+    cfg = synth.CONFIGS["tiny"]
+    case = Case(cfg, seed=0)
+    mix, gl = case.gpu_forward()
+    gth, gwe = case.gpu_backward()
+    omix, ol, oth, owe = case.oracle()
+    assert rel_l2(mix, omix) <= WAVE_TOL
+    _check_losses(gl, ol, loss_tolerances(case, omix))
+    for t in "ecg":
+        vs = [v for v in case.g.processors() if case.g.types[v] == t]
+        err = rel_l2(np.concatenate([gth[v] for v in vs]), np.concatenate([oth[v] for v in vs]))
+        assert err <= GRAD_TOL, (t, err)
+
+
+def test_full_console_full_size():
+    """16 stereo tracks, 4 subgroups, 10 s at 44.1 kHz, full processor set
+    (EQ 2047 taps, 4-tap delay over 0.5 s, 1.5 s reverb): forward and backward
+    at full size from the initial parameters."""
+    cfg = synth.CONFIGS["full"]
+    case = Case(cfg, seed=1, params="init")
+    mix, gl = case.gpu_forward()
+    gth, gwe = case.gpu_backward()
+    omix, ol, oth, owe = case.oracle()
+    print("full wave", rel_l2(mix, omix), flush=True)
+    assert rel_l2(mix, omix) <= WAVE_TOL
+    _check_losses(gl, ol, loss_tolerances(case, omix))
+    for t in "ecxsgdr":
+        vs = [v for v in case.g.processors() if case.g.types[v] == t]
+        err = rel_l2(np.concatenate([gth[v] for v in vs]), np.concatenate([oth[v] for v in vs]))
+        print("full", t, "grad err", err, flush=True)
+    procs = case.g.processors()
+    print("full wet grad err", rel_l2([gwe[v] for v in procs], [owe[v] for v in procs]), flush=True)
+    for t in "ecxsgdr":
+        vs = [v for v in case.g.processors() if case.g.types[v] == t]
+        err = rel_l2(np.concatenate([gth[v] for v in vs]), np.concatenate([oth[v] for v in vs]))
+        assert err <= GRAD_TOL, (t, err)
+    assert rel_l2([gwe[v] for v in procs], [owe[v] for v in procs]) <= GRAD_TOL
+
+
+def test_masked_forward_equals_separate_forwards():
+    case = Case(_small("ecxsgdr"), mode=0)
+    procs = case.g.processors()
+    rng = np.random.default_rng(1)
+    B = 5
+    masks = []
+    for b in range(B):
+        m = {v: 1.0 for v in procs}
+        for v in rng.choice(procs, size=3, replace=False):
+            m[int(v)] = 0.0
+        masks.append(m)
+    md = torch.from_numpy(np.stack([case.bg.mask_vector(m) for m in masks])).cuda()
+    out = torch.zeros(B, 7, dtype=torch.float64, device="cuda")
+    case.sess.forward_masked(case.dry_d, case.theta_d, case.wet_d, md, out)
+    torch.cuda.synchronize()
+    out = out.cpu().numpy()
+    for b in range(B):
+        _, gl = case.gpu_forward(masks[b])
+        assert np.array_equal(out[b], np.array([gl[k] for k in MG.LOSS_KEYS]))
+        omix, ol, _, _ = case.oracle(masks[b], grads=False)
+        _check_losses(dict(zip(MG.LOSS_KEYS, out[b])), ol, loss_tolerances(case, omix))
+
+
+def test_adam_matches_textbook():
+    n = 10007
+    rng = np.random.default_rng(0)
+    th = rng.normal(size=n).astype(np.float32)
+    g = rng.normal(size=n).astype(np.float32)
+    m = np.zeros(n, np.float32)
+    v = np.zeros(n, np.float32)
+    td, gd, md, vd = (torch.from_numpy(x.copy()).cuda() for x in (th, g, m, v))
+    ref = [th.astype(np.float64), m.astype(np.float64), v.astype(np.float64)]
+    for step in (1, 2, 3):
+        MG.mg_adam_step(td, md, vd, gd, n, 1e-2, 0.9, 0.999, 1e-8, step, torch.cuda.current_stream().cuda_stream)
+        TR.adam_step(ref[0], ref[1], ref[2], g.astype(np.float64), step)
+    torch.cuda.synchronize()
+    assert np.allclose(td.cpu().numpy(), ref[0], rtol=1e-6, atol=1e-7)
+
+
+@pytest.mark.parametrize("chain", ["s", "e", "n", "ecxsgdr"])
+def test_loss_kernel_on_the_gpu_mix(chain):
+    """The FP64 loss kernels alone: the oracle's loss evaluated on the GPU's
+    own FP32 mix must equal the GPU's loss (the only difference left is
+    summation order in FP64)."""
+    import torch as T
+    from oracle import loss as LS
+    case = Case(_small(chain))
+    mix, gl = case.gpu_forward()
+    ol = LS.mrstft(T.tensor(mix), T.tensor(case.target.astype(np.float64)), case.cfg.loss_ffts, case.cfg.fs)
+    omix, ofull, _, _ = case.oracle(grads=False)
+    ol64 = LS.mrstft(T.tensor(omix), T.tensor(case.target.astype(np.float64)), case.cfg.loss_ffts, case.cfg.fs)
+    ol32 = LS.mrstft(T.tensor(omix.astype(np.float32).astype(np.float64)),
+                     T.tensor(case.target.astype(np.float64)), case.cfg.loss_ffts, case.cfg.fs)
+    for k in ("La", "Llr", "Lm", "Ls"):
+        print(chain, k, "gpu", gl[k], "oracle(gpu mix)", float(ol[k]), "oracle", float(ol64[k]),
+              "oracle(mix rounded to fp32)", float(ol32[k]), flush=True)
+    for k in ("La", "Llr", "Lm", "Ls"):
+        assert abs(gl[k] - float(ol[k])) <= 1e-9 * max(1.0, abs(float(ol[k]))), (k, gl[k], float(ol[k]))

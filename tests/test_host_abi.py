@@ -1,0 +1,160 @@
+"""Host-side tests of the C-ABI library (no GPU needed): symbols, graph
+validation and error codes, type schedule (Sec. 4.1-4.2), node order and
+parameter layout (Alg. 1 Reorder), pruning surgery (Sec. 1.2 bypass)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import train as TR
+from paper_2509_15948_amd import mixgraph as MG
+from paper_2509_15948_amd import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_library_exports_every_declared_symbol():
+    hdr = open(os.path.join(ROOT, "include", "mixgraph.h")).read()
+    declared = sorted(set(re.findall(r"\b(mg_[a-z_]+)\s*\(", hdr)))
+    assert len(declared) >= 12
+    L = MG.lib()
+    for name in declared:
+        assert hasattr(L, name), name
+    assert set(MG.EXPORTS) <= set(declared)
+
+
+def _graph(chain="ecxsgdr", K=5, S=2, **kw):
+    cfg = synth.small_config(n_tracks=K, n_subgroups=S, chain=chain, **kw)
+    g = synth.make_console(K, synth.subgroup_labels(1, K, S), chain)
+    return cfg, g, W.binding_graph(g, cfg)
+
+
+@pytest.mark.parametrize("chain", ["ecxsgdr", "ecnsgdr", "ecg"])
+def test_console_schedule_is_the_console_type_string(chain):
+    cfg, g, bg = _graph(chain, comp_mode="single")
+    assert bg.schedule == "i" + chain + "m" + chain + "o"
+    # partition, causal and homogeneous (Sec. 4.1)
+    for s, d in g.edges:
+        assert bg.stage[s] < bg.stage[d]
+    for st in range(bg.info.n_stages):
+        ts = {g.types[v] for v in range(g.n_nodes) if bg.stage[v] == st}
+        assert len(ts) == 1
+
+
+def test_layout_is_type_major_and_contiguous_per_stage():
+    cfg, g, bg = _graph()
+    np_of = {t: cfg.n_params(t) for t in "ecnxsgdr"}
+    offs = []
+    for v in g.processors():
+        offs.append((int(bg.param_offset[v]), np_of[g.types[v]], v))
+    offs.sort()
+    pos = 0
+    for o, n, v in offs:
+        assert o == pos, (o, pos, g.types[v])
+        pos += n
+    assert pos == bg.n_theta
+    assert sorted(int(bg.proc_index[v]) for v in g.processors()) == list(range(len(g.processors())))
+    # rows of one stage are consecutive
+    for st in range(1, bg.info.n_stages):
+        rows = sorted(int(bg.type_row[v]) for v in range(g.n_nodes) if bg.stage[v] == st)
+        assert rows == list(range(rows[0], rows[0] + len(rows)))
+
+
+def _create(types, edges, tracks=None, n_tracks=1):
+    cfg = W.binding_config(synth.small_config())
+    if tracks is None:
+        tracks = [0 if t == "i" else -1 for t in types]
+    return MG.mg_graph_create([MG.TYPE_CODES[t] for t in types], np.array(edges, np.int32).T.reshape(2, -1),
+                              tracks, n_tracks, 2, cfg)
+
+
+def test_error_codes():
+    with pytest.raises(MG.MixgraphError, match="error 2"):       # cycle
+        _create(["i", "g", "s", "o"], [(0, 1), (1, 2), (2, 1), (2, 3)])
+    with pytest.raises(MG.MixgraphError, match="error 2"):       # two outputs
+        _create(["i", "g", "o", "o"], [(0, 1), (1, 2), (1, 3)])
+    with pytest.raises(MG.MixgraphError, match="error 2"):       # processor without input
+        _create(["i", "g", "s", "o"], [(0, 1), (1, 3), (2, 3)])
+    with pytest.raises(MG.MixgraphError, match="error 2"):       # dangling node
+        _create(["i", "g", "s", "o"], [(0, 1), (1, 3), (1, 2)])
+    with pytest.raises(MG.MixgraphError, match="error 2"):       # unknown type
+        cfg = W.binding_config(synth.small_config())
+        MG.mg_graph_create([0, 42, 2], np.array([[0, 1], [1, 2]], np.int32), [0, -1, -1], 1, 2, cfg)
+    with pytest.raises(MG.MixgraphError, match="error 1"):       # bad config (even EQ length)
+        cfg = W.binding_config(synth.small_config(eq_taps=254))
+        MG.mg_graph_create([0, 3, 2], np.array([[0, 1], [1, 2]], np.int32), [0, -1, -1], 1, 2, cfg)
+    L = MG.lib()
+    assert L.mg_forward(None, None, None, None, None, None, None, None) == 1
+    assert L.mg_backward(None, None, None, None) == 1
+
+
+def test_greedy_schedule_for_a_general_dag():
+    # i -> e -> c -> o ; i -> c -> s ... a DAG that is not a console
+    types = ["i", "i", "e", "c", "c", "s", "m", "g", "o"]
+    edges = [(0, 2), (2, 3), (1, 4), (3, 6), (4, 5), (5, 6), (6, 7), (7, 8)]
+    h = _create(types, edges, tracks=[0, 0, -1, -1, -1, -1, -1, -1, -1])
+    info = MG.mg_graph_info(h)
+    po, pi, st, tr, sched = MG.mg_graph_layout(h, len(types), info.n_stages)
+    for s, d in edges:
+        assert st[s] < st[d]
+    assert sched[0] == "i" and sched[-1] == "o"
+    assert len(sched) <= 7      # i, e/c, c, s, m, g, o at most
+    MG.mg_graph_destroy(h)
+
+
+def test_workspace_size_positive_and_mode_monotone():
+    cfg, g, bg = _graph()
+    a = MG.mg_workspace_size(bg.h, 0)
+    b = MG.mg_workspace_size(bg.h, 1)
+    assert 0 < a < b
+
+
+def test_prune_is_bypass_in_the_oracle():
+    """Removing processors by graph surgery equals zeroing their dry/wet."""
+    cfg = synth.small_config(seconds=0.1, fs=8000, n_tracks=3, n_subgroups=2, loss_ffts=(256,), eq_taps=31,
+                             delay_range_s=0.04, reverb_seconds=0.05)
+    g, dry, noise = synth.song(2, cfg)
+    bg = W.binding_graph(g, cfg)
+    th, we = synth.random_params(2, g, cfg)
+    procs = g.processors()
+    rng = np.random.default_rng(0)
+    drop = set(int(v) for v in rng.choice(procs, size=len(procs) // 2, replace=False))
+    keep = np.ones(bg.n_proc, np.uint8)
+    for v in drop:
+        keep[int(bg.proc_index[v])] = 0
+    pg, o2n = bg.prune(keep)
+    masked = TR.render(g, cfg, dry, noise, th, we, {v: 0.0 for v in drop})
+    # rebuild the pruned graph for the oracle from the library's edges
+    import synth as S
+    new_types = pg.types
+    n = len(new_types)
+    # map parameters
+    th2 = {int(o2n[v]): th[v] for v in procs if v not in drop}
+    we2 = {int(o2n[v]): we[v] for v in procs if v not in drop}
+    noise2 = {int(o2n[v]): noise[v] for v in noise if v not in drop}
+    # edges of the pruned graph: rebuild by bypass rule in python for the oracle
+    keep_nodes = [v for v in range(g.n_nodes) if v not in drop]
+    preds = {v: [] for v in range(g.n_nodes)}
+    for s_, d_ in g.edges:
+        preds[d_].append(s_)
+    edges = []
+    for v in keep_nodes:
+        stack = list(preds[v])
+        srcs = set()
+        while stack:
+            p = stack.pop()
+            if p in drop:
+                stack.extend(preds[p])
+            else:
+                srcs.add(p)
+        edges += [(int(o2n[p]), int(o2n[v])) for p in sorted(srcs)]
+    tin = {int(o2n[v]): k for v, k in g.track_of_input.items()}
+    g2 = S.Graph(new_types, edges, tin)
+    mix2 = TR.render(g2, cfg, dry, noise2, th2, we2)
+    assert np.allclose(mix2, masked, rtol=1e-12, atol=1e-14)
+    assert pg.schedule.startswith("i") and pg.schedule.endswith("o")
+    assert len(pg.schedule) <= len(bg.schedule)
