@@ -174,6 +174,17 @@ int mg_adam_step(float* theta, float* m, float* v, const float* grad, int64_t n,
 int mg_graph_prune(const mg_graph* g, const uint8_t* keep, mg_graph** out,
                    int32_t* old_to_new);
 
+/* Measurement of one kernel class (for roofline reporting, not part of the
+ * method): after mg_profile_enable(g, cls), HIP events are recorded on the
+ * caller's stream around every launch of that class ("conv_cols",
+ * "conv_rows", "conv_icols", "dyn", "pointwise", "sum", "loss", "fir"; NULL
+ * disables; at most 4096 launches between reads).  mg_profile_read
+ * synchronises on the recorded events and returns the summed device time in
+ * ms, the number of timed launches and the algorithmic bytes they move (the
+ * reads and writes each kernel is designed to make), then resets. */
+int mg_profile_enable(mg_graph* g, const char* kernel_class);
+int mg_profile_read(mg_graph* g, double* ms, int64_t* launches, double* bytes);
+
 const char* mg_last_error(void);
 
 #ifdef __cplusplus

@@ -61,6 +61,7 @@ __global__ __launch_bounds__(MG_BLOCK) void k_sum(const NodeDesc* __restrict__ d
 void launch_sum(const Ctx& c, int desc_off, int n, const SrcRef* srcs, float* out_base, int dest_kind) {
   if (n <= 0) return;
   dim3 grid(256, n);
+  ProfScope ps(c, "sum", (double)n * 8.0 * c.L * 2);
   hipLaunchKernelGGL(k_sum, grid, dim3(MG_BLOCK), 0, c.st, c.desc + desc_off, srcs, c.dry, c.U, c.G, out_base, c.L,
                      c.C, dest_kind);
 }
@@ -197,6 +198,7 @@ __global__ __launch_bounds__(MG_BLOCK) void k_pointwise_bwd(const NodeDesc* __re
 
 void launch_pointwise_fwd(const Ctx& c, int type, int desc_off, int n) {
   dim3 grid(128, n), blk(MG_BLOCK);
+  ProfScope ps(c, "pointwise", (double)n * 16.0 * c.L);
   const NodeDesc* d = c.desc + desc_off;
   switch (type) {
     case MG_GAINPAN:
@@ -213,6 +215,7 @@ void launch_pointwise_fwd(const Ctx& c, int type, int desc_off, int n) {
 
 void launch_pointwise_bwd(const Ctx& c, int type, int desc_off, int n) {
   dim3 grid(128, n), blk(MG_BLOCK);
+  ProfScope ps(c, "pointwise", (double)n * 24.0 * c.L);
   const NodeDesc* d = c.desc + desc_off;
   float* part = c.part + (int64_t)desc_off * c.PB * PK;
   switch (type) {

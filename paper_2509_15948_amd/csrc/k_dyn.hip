@@ -545,6 +545,7 @@ static DynView dyn_view(const Ctx& c, int type, int desc_off) {
 void dyn_forward(const Ctx& c, int type, int desc_off, int n) {
   const mg_graph* g = c.g;
   DynView v = dyn_view(c, type, desc_off);
+  ProfScope ps(c, "dyn", (double)n * 20.0 * c.L);
   const bool ar = (type == MG_COMP && g->cfg.comp_mode == 1);
   if (ar) {
     if (type == MG_COMP) hipLaunchKernelGGL(k_dyn_ar_fwd<0>, dim3(n), dim3(64), 0, c.st, v);
@@ -562,6 +563,7 @@ void dyn_forward(const Ctx& c, int type, int desc_off, int n) {
 void dyn_backward(const Ctx& c, int type, int desc_off, int n) {
   const mg_graph* g = c.g;
   DynView v = dyn_view(c, type, desc_off);
+  ProfScope ps(c, "dyn", (double)n * 28.0 * c.L);
   const bool ar = (type == MG_COMP && g->cfg.comp_mode == 1);
   if (ar) {
     hipLaunchKernelGGL(k_dyn_ar_bwd<0>, dim3(n), dim3(64), 0, c.st, v);

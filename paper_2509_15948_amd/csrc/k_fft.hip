@@ -490,10 +490,11 @@ __global__ __launch_bounds__(MG_BLOCK) void k_rows_bwd(const float2* __restrict_
 
 // ---------------------------------------------------------------- dispatch
 template <typename LD>
-void run_cols(const Ctx& c, const LD& ld, float2* T, int n, const EngineArgs& ea) {
+void run_cols(const Ctx& c, const LD& ld, float2* T, int n, const EngineArgs& ea, double in_bytes) {
   const int N2 = ea.N2;
   const int TC = 8192 / N2;
   dim3 grid(ea.N1 / TC, n), blk(MG_BLOCK);
+  ProfScope ps(c, "conv_cols", (double)n * (in_bytes + 8.0 * ea.N));
   switch (N2) {
 #define MG_CASE(NN)                                                                   \
   case NN:                                                                            \
@@ -505,10 +506,11 @@ void run_cols(const Ctx& c, const LD& ld, float2* T, int n, const EngineArgs& ea
 }
 
 template <typename ST>
-void run_icols(const Ctx& c, const ST& st, const float2* T, int n, const EngineArgs& ea) {
+void run_icols(const Ctx& c, const ST& st, const float2* T, int n, const EngineArgs& ea, double out_bytes) {
   const int N2 = ea.N2;
   const int TC = 8192 / N2;
   dim3 grid(ea.N1 / TC, n), blk(MG_BLOCK);
+  ProfScope ps(c, "conv_icols", (double)n * (out_bytes + 8.0 * ea.N));
   switch (N2) {
 #define MG_CASE(NN)                                                                    \
   case NN:                                                                             \
@@ -551,17 +553,20 @@ static NodeView node_view(const Ctx& c, int desc_off) {
 
 template <int N1>
 static void rows_spec_n(const Ctx& c, const float2* T, float2* Z, int z0, int desc_off, int n, const EngineArgs& ea) {
+  ProfScope ps(c, "conv_rows", (double)n * 16.0 * ea.N);
   hipLaunchKernelGGL(k_rows_spec<N1>, dim3(ea.N2 / 2, n), dim3(MG_BLOCK), 0, c.st, T, Z, z0, c.desc + desc_off, ea);
 }
 template <int N1>
 static void rows_conv_n(const Ctx& c, const float2* Tin, float2* Tout, const float2* ZH, float2* ZU, int z0,
                         int desc_off, int n, const EngineArgs& ea) {
+  ProfScope ps(c, "conv_rows", (double)n * (ZU ? 32.0 : 24.0) * ea.N);
   hipLaunchKernelGGL(k_rows_conv<N1>, dim3(ea.N2 / 2, n), dim3(MG_BLOCK), 0, c.st, Tin, Tout, ZH, ZU, z0,
                      c.desc + desc_off, ea);
 }
 template <int N1>
 static void rows_bwd_n(const Ctx& c, const float2* Tin, float2* Tu, float2* Th, const float2* ZH, const float2* ZU,
                        int z0, int desc_off, int n, int want_u, const EngineArgs& ea) {
+  ProfScope ps(c, "conv_rows", (double)n * (want_u ? 40.0 : 32.0) * ea.N);
   hipLaunchKernelGGL(k_rows_bwd<N1>, dim3(ea.N2 / 2, n), dim3(MG_BLOCK), 0, c.st, Tin, Tu, Th, ZH, ZU, z0,
                      c.desc + desc_off, want_u, ea);
 }
@@ -591,7 +596,7 @@ void conv_fir_spectrum(const Ctx& c, int type, int desc_off, int n) {
     ld.N = ea.N;
     ld.stride = cf.eq_taps;
     ld.shared = 1;
-    run_cols(c, ld, T1, n, ea);
+    run_cols(c, ld, T1, n, ea, 4.0 * cf.eq_taps);
   } else if (type == MG_REVERB) {
     LdFir ld;
     ld.desc = c.desc + desc_off;
@@ -601,7 +606,7 @@ void conv_fir_spectrum(const Ctx& c, int type, int desc_off, int n) {
     ld.N = ea.N;
     ld.stride = 2 * (int64_t)cf.reverb_length;
     ld.shared = 0;
-    run_cols(c, ld, T1, n, ea);
+    run_cols(c, ld, T1, n, ea, 8.0 * cf.reverb_length);
   } else {
     LdDelay ld;
     ld.desc = c.desc + desc_off;
@@ -611,7 +616,7 @@ void conv_fir_spectrum(const Ctx& c, int type, int desc_off, int n) {
     ld.half = (cf.delay_fir_taps - 1) / 2;
     ld.N = ea.N;
     ld.stride = 2 * (int64_t)cf.delay_taps * (1 + cf.delay_fir_taps);
-    run_cols(c, ld, T1, n, ea);
+    run_cols(c, ld, T1, n, ea, 8.0 * cf.delay_taps * (1 + cf.delay_fir_taps));
   }
   MG_N1_SWITCH(rows_spec_n, c, T1, ZH, z0, desc_off, n, ea);
 }
@@ -626,7 +631,7 @@ void conv_forward(const Ctx& c, int type, int desc_off, int n, bool keep_input_s
   const int z0 = conv_base(g, type);
   LdSignal ld;
   ld.v = node_view(c, desc_off);
-  run_cols(c, ld, T1, n, ea);
+  run_cols(c, ld, T1, n, ea, 8.0 * c.L);
   MG_N1_SWITCH(rows_conv_n, c, T1, T2, ZH, ZU, z0, desc_off, n, ea);
   StFwd st;
   st.v = node_view(c, desc_off);
@@ -640,7 +645,7 @@ void conv_forward(const Ctx& c, int type, int desc_off, int n, bool keep_input_s
     // forward-only: no ybar buffer; StFwd skips the ybar store
     st.ybar_base = nullptr;
   }
-  run_icols(c, st, T2, n, ea);
+  run_icols(c, st, T2, n, ea, (keep_input_spectrum ? 24.0 : 16.0) * c.L);
   launch_reduce_lg(c, desc_off, n, ea.N1 / (8192 / ea.N2));
 }
 
@@ -664,7 +669,7 @@ void conv_backward(const Ctx& c, int type, int desc_off, int n) {
   ld.yb0 = z0;
   ld.part = c.part + (int64_t)desc_off * c.PB * PK;
   ld.PB = c.PB;
-  run_cols(c, ld, T1, n, ea);
+  run_cols(c, ld, T1, n, ea, 24.0 * c.L);
   int want_u = 0;
   for (int j = 0; j < n; ++j)
     if (g->desc[desc_off + j].gin >= 0) want_u = 1;
@@ -676,7 +681,7 @@ void conv_backward(const Ctx& c, int type, int desc_off, int n) {
     su.wet = c.wet;
     su.mask = c.mask;
     su.alpha_g = c.alpha_g;
-    run_icols(c, su, T2, n, ea);
+    run_icols(c, su, T2, n, ea, 24.0 * c.L);
   }
   StGradH sh;
   sh.desc = c.desc + desc_off;
@@ -700,7 +705,7 @@ void conv_backward(const Ctx& c, int type, int desc_off, int n) {
     sh.stride = 2 * g->dl_len;
     sh.shared = 0;
   }
-  run_icols(c, sh, T3, n, ea);
+  run_icols(c, sh, T3, n, ea, (sh.shared ? 4.0 : 8.0) * sh.Nh);
 }
 
 // tables for the LDS FFT (size MG_TWN) and for the big twiddles of N

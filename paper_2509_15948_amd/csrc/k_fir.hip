@@ -442,6 +442,7 @@ void fir_setup(const Ctx& c, const float* reverb_noise) {
 void fir_synth(const Ctx& c, int type, int desc_off, int n) {
   const mg_graph* g = c.g;
   const mg_config& cf = g->cfg;
+  ProfScope ps(c, "fir", 0.0);
   const NodeDesc* d = c.desc + desc_off;
   if (type == MG_EQ) {
     hipLaunchKernelGGL(k_eq_synth, dim3((cf.eq_taps + MG_BLOCK - 1) / MG_BLOCK, n), dim3(MG_BLOCK), 0, c.st, d,
@@ -464,6 +465,7 @@ void fir_synth(const Ctx& c, int type, int desc_off, int n) {
 void fir_adjoint(const Ctx& c, int type, int desc_off, int n, float* grad_theta) {
   const mg_graph* g = c.g;
   const mg_config& cf = g->cfg;
+  ProfScope ps(c, "fir", 0.0);
   const NodeDesc* d = c.desc + desc_off;
   if (type == MG_EQ) {
     const int K = (cf.eq_taps + 1) / 2;

@@ -445,10 +445,14 @@ void loss_setup(const Ctx& c, const float* target) {
   run_loss_fwd(c, target, 0);
 }
 
-void loss_forward(const Ctx& c, const float* yhat) { run_loss_fwd(c, yhat, 1); }
+void loss_forward(const Ctx& c, const float* yhat) {
+  ProfScope ps(c, "loss", 8.0 * c.L);
+  run_loss_fwd(c, yhat, 1);
+}
 
 void loss_backward(const Ctx& c, const float* yhat, float* dyhat) {
   const mg_graph* g = c.g;
+  ProfScope ps(c, "loss", 16.0 * c.L);
   GatherArgs ga;
   ga.nres = (int)g->lres.size();
   ga.skip = g->cfg.loss_skip;

@@ -298,6 +298,44 @@ extern "C" int mg_backward(mg_graph* g, float* grad_theta, float* grad_wet, void
   return hip_check(hipGetLastError(), "backward launch");
 }
 
+extern "C" int mg_profile_enable(mg_graph* g, const char* kernel_class) {
+  if (!g) return fail(MG_ERR_INVALID_ARG, "NULL graph");
+  Profiler& p = g->prof;
+  p.cls = kernel_class ? kernel_class : "";
+  p.used = 0;
+  p.bytes = 0.0;
+  p.launches = 0;
+  if (!p.cls.empty() && p.ev.empty()) {
+    p.ev.resize(8192);
+    for (auto& e : p.ev) {
+      int rc = hip_check(hipEventCreate(&e), "event create");
+      if (rc) return rc;
+    }
+  }
+  return MG_OK;
+}
+
+extern "C" int mg_profile_read(mg_graph* g, double* ms, int64_t* launches, double* bytes) {
+  if (!g || !ms || !launches || !bytes) return fail(MG_ERR_INVALID_ARG, "NULL argument");
+  Profiler& p = g->prof;
+  double total = 0.0;
+  for (int i = 0; i + 1 < p.used; i += 2) {
+    int rc = hip_check(hipEventSynchronize(p.ev[i + 1]), "event sync");
+    if (rc) return rc;
+    float t = 0.f;
+    rc = hip_check(hipEventElapsedTime(&t, p.ev[i], p.ev[i + 1]), "event time");
+    if (rc) return rc;
+    total += t;
+  }
+  *ms = total;
+  *launches = p.launches;
+  *bytes = p.bytes;
+  p.used = 0;
+  p.bytes = 0.0;
+  p.launches = 0;
+  return MG_OK;
+}
+
 extern "C" int mg_adam_step(float* theta, float* m, float* v, const float* grad, int64_t n, float lr, float beta1,
                             float beta2, float eps, int32_t step, void* stream) {
   if (!theta || !m || !v || !grad || n < 0 || step < 1) return fail(MG_ERR_INVALID_ARG, "bad arguments");

@@ -426,6 +426,8 @@ extern "C" int mg_graph_create(int32_t n_nodes, const int32_t* types, int32_t n_
 }
 
 extern "C" int mg_graph_destroy(mg_graph* g) {
+  if (g)
+    for (auto& e : g->prof.ev) (void)hipEventDestroy(e);
   delete g;
   return MG_OK;
 }

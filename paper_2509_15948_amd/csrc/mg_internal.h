@@ -73,6 +73,16 @@ struct WsPlan {
   size_t losses_tmp = 0;
 };
 
+// Optional timing of one kernel class (measurement only): HIP events are
+// recorded on the caller's stream around every launch of that class.
+struct Profiler {
+  std::string cls;                       // empty: disabled
+  std::vector<hipEvent_t> ev;            // pool of start/stop pairs
+  int used = 0;                          // events used since the last read
+  double bytes = 0.0;                    // algorithmic bytes of the timed launches
+  int64_t launches = 0;
+};
+
 struct LossRes {
   int nfft, hop, frames;
   size_t tgt_off, part_off, tab_off, aw_off, win_off;  // byte offsets in ws
@@ -123,6 +133,7 @@ struct mg_graph {
   int mode = 0;
   bool ready = false;
   bool have_forward = false;
+  mg::Profiler prof;
   // last forward's inputs (for backward)
   const float* f_dry = nullptr;
   const float* f_theta = nullptr;

@@ -31,6 +31,26 @@ inline T* wsp(const Ctx& c, size_t off) {
   return reinterpret_cast<T*>(c.base + off);
 }
 
+// Measurement scope around a launch of kernel class cls moving `bytes`
+// algorithmic bytes; a no-op unless the graph's profiler targets cls.
+struct ProfScope {
+  Profiler* p = nullptr;
+  hipStream_t st;
+  ProfScope(const Ctx& c, const char* cls, double bytes) : st(c.st) {
+    Profiler* q = const_cast<Profiler*>(&c.g->prof);
+    if (q->cls.empty() || q->cls != cls || q->used + 2 > (int)q->ev.size()) return;
+    p = q;
+    hipEventRecord(p->ev[p->used], st);
+    p->bytes += bytes;
+    p->launches += 1;
+  }
+  ~ProfScope() {
+    if (!p) return;
+    hipEventRecord(p->ev[p->used + 1], st);
+    p->used += 2;
+  }
+};
+
 // k_basic.hip
 void launch_sum(const Ctx& c, int desc_off, int n, const SrcRef* srcs, float* out_base, int dest_kind);
 void launch_pointwise_fwd(const Ctx& c, int type, int desc_off, int n);

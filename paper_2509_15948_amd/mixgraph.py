@@ -44,7 +44,7 @@ _lib = None
 
 EXPORTS = ("mg_graph_create", "mg_graph_destroy", "mg_graph_info", "mg_graph_layout", "mg_workspace_size",
            "mg_setup", "mg_forward", "mg_backward", "mg_forward_masked", "mg_adam_step", "mg_graph_prune",
-           "mg_last_error")
+           "mg_last_error", "mg_profile_enable", "mg_profile_read")
 
 
 def lib() -> ctypes.CDLL:
@@ -71,6 +71,9 @@ def lib() -> ctypes.CDLL:
         "mg_adam_step": [vp, vp, vp, vp, i64, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float,
                          i32, vp],
         "mg_graph_prune": [vp, vp, ctypes.POINTER(vp), vp],
+        "mg_profile_enable": [vp, ctypes.c_char_p],
+        "mg_profile_read": [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64),
+                            ctypes.POINTER(ctypes.c_double)],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -184,6 +187,18 @@ def mg_graph_prune(g: int, keep: np.ndarray, n_nodes: int):
     o2n = np.zeros(n_nodes, np.int32)
     _check(lib().mg_graph_prune(g, k.ctypes.data, ctypes.byref(out), o2n.ctypes.data))
     return out.value, o2n
+
+
+def mg_profile_enable(g: int, kernel_class: Optional[str]) -> None:
+    _check(lib().mg_profile_enable(g, kernel_class.encode() if kernel_class else None))
+
+
+def mg_profile_read(g: int):
+    ms = ctypes.c_double()
+    n = ctypes.c_int64()
+    b = ctypes.c_double()
+    _check(lib().mg_profile_read(g, ctypes.byref(ms), ctypes.byref(n), ctypes.byref(b)))
+    return ms.value, n.value, b.value
 
 
 # ---------------------------------------------------------------- handles
