@@ -32,7 +32,8 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-KERNEL_CLASSES = ("conv_cols", "conv_rows", "conv_icols", "dyn", "pointwise", "sum", "loss", "fir")
+KERNEL_CLASSES = ("conv_cols", "conv_rows", "conv_icols", "eq_conv", "eq_spec", "dyn", "pointwise", "sum", "loss",
+                  "reverb_fir", "fir")
 
 
 def log(msg):

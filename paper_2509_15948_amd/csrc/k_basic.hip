@@ -235,62 +235,86 @@ void launch_pointwise_bwd(const Ctx& c, int type, int desc_off, int n) {
 }
 
 // ---------------------------------------------------------------- reductions
-// One workgroup per node: sums partial k over nblocks in FP64 (fixed order),
-// then writes dL/d(wet logit) (with the sigmoid chain, the mask and the
-// l1 regulariser of Sec. 6.3) and nparams direct parameter gradients.
-__global__ __launch_bounds__(64) void k_finish_grads(const NodeDesc* __restrict__ desc, const float* __restrict__ part,
-                                                      int PB, int nblocks, int nparams,
-                                                      const float* __restrict__ wet, const float* __restrict__ mask,
-                                                      float alpha_p, float* __restrict__ grad_theta,
-                                                      float* __restrict__ grad_wet) {
+// One workgroup per node: sums partial k over nblocks in FP64 (fixed order:
+// strided per thread, then a tree), then writes dL/d(wet logit) (with the
+// sigmoid chain, the mask and the l1 regulariser of Sec. 6.3) and nparams
+// direct parameter gradients.
+__global__ __launch_bounds__(MG_BLOCK) void k_finish_grads(const NodeDesc* __restrict__ desc,
+                                                            const float* __restrict__ part, int PB, int nblocks,
+                                                            int nparams, const float* __restrict__ wet,
+                                                            const float* __restrict__ mask, float alpha_p,
+                                                            float* __restrict__ grad_theta,
+                                                            float* __restrict__ grad_wet) {
+  __shared__ double red[MG_BLOCK];
   const NodeDesc d = desc[blockIdx.x];
   const float* pr = part + (int64_t)blockIdx.x * PB * PK;
-  const int k = threadIdx.x;
-  if (k >= 1 + nparams) return;
-  const int kk = (k == 0) ? 2 : 2 + k;
-  double s = 0.0;
-  for (int b = 0; b < nblocks; ++b) s += (double)pr[b * PK + kk];
-  if (k == 0) {
-    const double sg = 1.0 / (1.0 + exp(-(double)wet[d.proc]));
-    const double m = mask ? (double)mask[d.proc] : 1.0;
-    grad_wet[d.proc] = (float)((s + (double)alpha_p) * sg * (1.0 - sg) * m);
-  } else {
-    grad_theta[d.theta_off + (k - 1)] = (float)s;
+  for (int q = 0; q < 1 + nparams; ++q) {
+    const int kk = (q == 0) ? 2 : 2 + q;
+    double s = 0.0;
+    for (int b = threadIdx.x; b < nblocks; b += MG_BLOCK) s += (double)pr[b * PK + kk];
+    s = block_sum<MG_BLOCK>(s, red);
+    if (threadIdx.x == 0) {
+      if (q == 0) {
+        const double sg = 1.0 / (1.0 + exp(-(double)wet[d.proc]));
+        const double m = mask ? (double)mask[d.proc] : 1.0;
+        grad_wet[d.proc] = (float)((s + (double)alpha_p) * sg * (1.0 - sg) * m);
+      } else {
+        grad_theta[d.theta_off + (q - 1)] = (float)s;
+      }
+    }
   }
 }
 
 void launch_finish_grads(const Ctx& c, int desc_off, int n, int nblocks, int nparams, float* grad_theta,
                          float* grad_wet) {
   if (n <= 0) return;
-  hipLaunchKernelGGL(k_finish_grads, dim3(n), dim3(64), 0, c.st, c.desc + desc_off,
+  hipLaunchKernelGGL(k_finish_grads, dim3(n), dim3(MG_BLOCK), 0, c.st, c.desc + desc_off,
                      c.part + (int64_t)desc_off * c.PB * PK, c.PB, nblocks, nparams, c.wet, c.mask, c.alpha_p,
                      grad_theta, grad_wet);
 }
 
 // L_g energies: lg[desc] = (sum over blocks of partial 0, of partial 1)
-__global__ void k_reduce_lg(const float* __restrict__ part, int PB, int nblocks, double* __restrict__ lg) {
+__global__ __launch_bounds__(MG_BLOCK) void k_reduce_lg(const float* __restrict__ part, int PB, int nblocks,
+                                                         double* __restrict__ lg) {
+  __shared__ double red[MG_BLOCK];
   const float* pr = part + (int64_t)blockIdx.x * PB * PK;
-  const int k = threadIdx.x;
-  if (k >= 2) return;
-  double s = 0.0;
-  for (int b = 0; b < nblocks; ++b) s += (double)pr[b * PK + k];
-  lg[2 * blockIdx.x + k] = s;
+  for (int k = 0; k < 2; ++k) {
+    double s = 0.0;
+    for (int b = threadIdx.x; b < nblocks; b += MG_BLOCK) s += (double)pr[b * PK + k];
+    s = block_sum<MG_BLOCK>(s, red);
+    if (threadIdx.x == 0) lg[2 * blockIdx.x + k] = s;
+  }
 }
 
 void launch_reduce_lg(const Ctx& c, int desc_off, int n, int nblocks) {
   if (n <= 0) return;
-  hipLaunchKernelGGL(k_reduce_lg, dim3(n), dim3(64), 0, c.st, c.part + (int64_t)desc_off * c.PB * PK, c.PB, nblocks,
-                     c.lg + 2 * desc_off);
+  hipLaunchKernelGGL(k_reduce_lg, dim3(n), dim3(MG_BLOCK), 0, c.st, c.part + (int64_t)desc_off * c.PB * PK, c.PB,
+                     nblocks, c.lg + 2 * desc_off);
 }
 
 // losses[7] = L, La, Llr, Lm, Ls, Lg, Lp.
 // lstats per (resolution, combo): [0] sum |Y|^2, [1] sum |Y - Yh|^2,
-// [2] sum |log diff| / cells.  lweights per combo (l, r, m, s).
-__global__ void k_finalize_losses(double* __restrict__ losses, const double* __restrict__ lstats, int n_res,
-                                  const NodeDesc* __restrict__ desc, int n_desc, const double* __restrict__ lg,
-                                  const float* __restrict__ wet, const float* __restrict__ mask, float alpha_g,
-                                  float alpha_p, const int* __restrict__ lg_flag) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+// [2] sum |log diff| / cells.
+__global__ __launch_bounds__(MG_BLOCK) void k_finalize_losses(double* __restrict__ losses,
+                                                               const double* __restrict__ lstats, int n_res,
+                                                               const NodeDesc* __restrict__ desc, int n_desc,
+                                                               const double* __restrict__ lg,
+                                                               const float* __restrict__ wet,
+                                                               const float* __restrict__ mask, float alpha_g,
+                                                               float alpha_p, const int* __restrict__ lg_flag) {
+  __shared__ double red[MG_BLOCK];
+  double lgs = 0.0, lps = 0.0;
+  for (int j = threadIdx.x; j < n_desc; j += MG_BLOCK) {
+    const NodeDesc d = desc[j];
+    if (d.proc < 0) continue;
+    double w = 1.0 / (1.0 + exp(-(double)wet[d.proc]));
+    if (mask) w *= (double)mask[d.proc];
+    lps += w;
+    if (lg_flag[j]) lgs += fabs(0.5 * log(lg[2 * j] + 1e-12) - 0.5 * log(lg[2 * j + 1] + 1e-12));
+  }
+  const double Lg = block_sum<MG_BLOCK>(lgs, red);
+  const double Lp = block_sum<MG_BLOCK>(lps, red);
+  if (threadIdx.x != 0) return;
   double term[4] = {0, 0, 0, 0};
   for (int i = 0; i < n_res; ++i)
     for (int x = 0; x < 4; ++x) {
@@ -300,15 +324,6 @@ __global__ void k_finalize_losses(double* __restrict__ losses, const double* __r
     }
   const double Llr = 0.5 * (term[0] + term[1]);
   const double La = 0.5 * Llr + 0.25 * term[2] + 0.25 * term[3];
-  double Lg = 0.0, Lp = 0.0;
-  for (int j = 0; j < n_desc; ++j) {
-    const NodeDesc d = desc[j];
-    if (d.proc < 0) continue;
-    double w = 1.0 / (1.0 + exp(-(double)wet[d.proc]));
-    if (mask) w *= (double)mask[d.proc];
-    Lp += w;
-    if (lg_flag[j]) Lg += fabs(0.5 * log(lg[2 * j] + 1e-12) - 0.5 * log(lg[2 * j + 1] + 1e-12));
-  }
   losses[0] = La + (double)alpha_g * Lg + (double)alpha_p * Lp;
   losses[1] = La;
   losses[2] = Llr;
@@ -322,8 +337,8 @@ void launch_finalize_losses(const Ctx& c, double* losses, const double* lstats, 
                             int n_desc) {
   (void)lweights;
   const int* flag = reinterpret_cast<const int*>(c.base + c.g->ws.losses_tmp);
-  hipLaunchKernelGGL(k_finalize_losses, dim3(1), dim3(64), 0, c.st, losses, lstats, n_res, c.desc, n_desc, c.lg,
-                     c.wet, c.mask, c.alpha_g, c.alpha_p, flag);
+  hipLaunchKernelGGL(k_finalize_losses, dim3(1), dim3(MG_BLOCK), 0, c.st, losses, lstats, n_res, c.desc, n_desc,
+                     c.lg, c.wet, c.mask, c.alpha_g, c.alpha_p, flag);
 }
 
 // ---------------------------------------------------------------- Adam

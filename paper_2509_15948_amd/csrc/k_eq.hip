@@ -1,0 +1,258 @@
+// Equalizer convolution by overlap-save in LDS (Sec. 3.3).
+//
+// The zero-phase FIR h (N taps, centred) is short next to the signal, so each
+// workgroup owns V = P - (N - 1) consecutive output samples and transforms
+// one P = 8192-point window of the packed stereo input (l + i r) entirely in
+// LDS: HBM traffic is the input window (P / V x 8 bytes per stereo sample)
+// plus the outputs.  The filter spectrum H_P = FFT_P(h placed circularly) is
+// real (h is real and even) and is built once per node and step.
+//   forward : y = IFFT(FFT(x) H_P) on the valid part; dry/wet; L_g energies
+//   backward: dL/du = (1 - w) dL/dy + (dL/dybar correlated with h) - L_g term;
+//             dL/dh[m] = Re sum_n Zg[n] conj(Zu[n - m]) per block (valid n
+//             only), reduced over blocks in a fixed order; dry/wet partials.
+#include "mg_device.h"
+#include "mg_kernels.h"
+
+namespace mg {
+
+constexpr int EQ_P = 8192;
+
+struct EqArgs {
+  const NodeDesc* desc;
+  const float* dry;
+  const float* U;
+  float* G;
+  float* Uo;            // node outputs (written)
+  float* ybar;          // YB rows of EQ nodes (row = aux), or null
+  const float* h;       // compact FIRs [row][N]
+  float* HP;            // [row][P] real spectra
+  float* dhp;           // [row][nblk][N] per-block FIR gradients
+  float* dh;            // [row][N]
+  const float* wet;
+  const float* mask;
+  const double* lg;     // per stage node: E_ybar, E_u
+  float* part;          // per stage node partial rows
+  int PB;
+  int64_t L;
+  int C, N, V, nblk;
+  float alpha_g;
+  const float2* tw;
+};
+
+__device__ __forceinline__ const float* eq_input(const EqArgs& a, const NodeDesc& d, int64_t& cs) {
+  if (d.in_kind == 0) {
+    cs = (a.C == 1) ? 0 : a.L;
+    return a.dry + (int64_t)d.in_slot * a.C * a.L;
+  }
+  cs = a.L;
+  return a.U + (int64_t)d.in_slot * 2 * a.L;
+}
+
+// H_P of every node of the stage: grid (nodes)
+__global__ __launch_bounds__(MG_BLOCK) void k_eq_spec(EqArgs a) {
+  __shared__ float2 buf[EQ_P];
+  const NodeDesc d = a.desc[blockIdx.x];
+  const float* h = a.h + (int64_t)d.aux * a.N;
+  const int half = (a.N - 1) / 2;
+  for (int i = threadIdx.x; i < EQ_P; i += MG_BLOCK) {
+    // circular position i holds tap m = i (i <= half) or m = i - P (i >= P - half)
+    float v = 0.f;
+    if (i <= half) v = h[half + i];
+    else if (i >= EQ_P - half) v = h[half + i - EQ_P];
+    buf[i] = make_float2(v, 0.f);
+  }
+  __syncthreads();
+  fft_lds<EQ_P, 1, EQ_P, MG_BLOCK, -1>(buf, a.tw);
+  float* o = a.HP + (int64_t)d.aux * EQ_P;
+  for (int i = threadIdx.x; i < EQ_P; i += MG_BLOCK) o[i] = buf[i].x;
+}
+
+// forward: grid (nblk, nodes)
+__global__ __launch_bounds__(MG_BLOCK) void k_eq_fwd(EqArgs a) {
+  __shared__ float2 buf[EQ_P];
+  __shared__ float red[MG_BLOCK];
+  const int j = blockIdx.y, blk = blockIdx.x;
+  const NodeDesc d = a.desc[j];
+  int64_t cs;
+  const float* u = eq_input(a, d, cs);
+  const int half = (a.N - 1) / 2;
+  const int64_t s0 = (int64_t)blk * a.V - half;   // window start
+  for (int i = threadIdx.x; i < EQ_P; i += MG_BLOCK) {
+    const int64_t n = s0 + i;
+    buf[i] = (n >= 0 && n < a.L) ? make_float2(u[n], u[cs + n]) : make_float2(0.f, 0.f);
+  }
+  __syncthreads();
+  fft_lds<EQ_P, 1, EQ_P, MG_BLOCK, -1>(buf, a.tw);
+  const float* H = a.HP + (int64_t)d.aux * EQ_P;
+  for (int i = threadIdx.x; i < EQ_P; i += MG_BLOCK) buf[i] = c_scale(buf[i], H[i] * (1.0f / EQ_P));
+  __syncthreads();
+  fft_lds<EQ_P, 1, EQ_P, MG_BLOCK, +1>(buf, a.tw);
+  float w = 1.0f / (1.0f + expf(-a.wet[d.proc]));
+  if (a.mask) w *= a.mask[d.proc];
+  float* y = a.Uo + (int64_t)d.out_slot * 2 * a.L;
+  float* yb = a.ybar ? a.ybar + (int64_t)d.aux * 2 * a.L : nullptr;
+  float ey = 0.f, eu = 0.f;
+  for (int i = half + threadIdx.x; i < half + a.V; i += MG_BLOCK) {
+    const int64_t n = s0 + i;
+    if (n >= a.L) break;
+    const float2 v = buf[i];
+    const float l = u[n], r = u[cs + n];
+    if (yb) {
+      yb[n] = v.x;
+      yb[a.L + n] = v.y;
+    }
+    y[n] = w * v.x + (1.0f - w) * l;
+    y[a.L + n] = w * v.y + (1.0f - w) * r;
+    const float m = v.x + v.y, um = l + r;
+    ey += m * m;
+    eu += um * um;
+  }
+  const float sa = block_sum<MG_BLOCK>(ey, red);
+  const float sb = block_sum<MG_BLOCK>(eu, red);
+  if (threadIdx.x == 0) {
+    float* pr = a.part + ((int64_t)j * a.PB + blk) * PK;
+    pr[0] = sa;
+    pr[1] = sb;
+  }
+}
+
+// backward: grid (nblk, nodes); LDS holds two P-point windows (128 KB)
+__global__ __launch_bounds__(MG_BLOCK) void k_eq_bwd(EqArgs a) {
+  __shared__ float2 A[EQ_P];
+  __shared__ float2 B[EQ_P];
+  __shared__ float red[MG_BLOCK];
+  const int j = blockIdx.y, blk = blockIdx.x;
+  const NodeDesc d = a.desc[j];
+  int64_t cs;
+  const float* u = eq_input(a, d, cs);
+  const int half = (a.N - 1) / 2;
+  const int64_t s0 = (int64_t)blk * a.V - half;
+  const float* dy = a.G + (int64_t)d.gout * 2 * a.L;
+  const float* yb = a.ybar + (int64_t)d.aux * 2 * a.L;
+  float w = 1.0f / (1.0f + expf(-a.wet[d.proc]));
+  if (a.mask) w *= a.mask[d.proc];
+  const double Ey = a.lg[2 * j] + 1e-12, Eu = a.lg[2 * j + 1] + 1e-12;
+  const double diff = 0.5 * log(Ey) - 0.5 * log(Eu);
+  const double sgn = diff > 0 ? 1.0 : (diff < 0 ? -1.0 : 0.0);
+  const float ky = (float)((double)a.alpha_g * sgn / Ey), ku = (float)((double)a.alpha_g * sgn / Eu);
+  // dL/dybar over the whole window (A) and over the valid part only (B)
+  float dw = 0.f;
+  for (int i = threadIdx.x; i < EQ_P; i += MG_BLOCK) {
+    const int64_t n = s0 + i;
+    float2 g = make_float2(0.f, 0.f);
+    if (n >= 0 && n < a.L) {
+      const float bl = yb[n], br = yb[a.L + n];
+      const float rm = ky * (bl + br);
+      const float gl = dy[n], gr = dy[a.L + n];
+      g = make_float2(w * gl + rm, w * gr + rm);
+      if (i >= half && i < half + a.V) dw += gl * (bl - u[n]) + gr * (br - u[cs + n]);
+    }
+    A[i] = g;
+    B[i] = (i >= half && i < half + a.V) ? g : make_float2(0.f, 0.f);
+  }
+  __syncthreads();
+  const float* H = a.HP + (int64_t)d.aux * EQ_P;
+  float* gin = d.gin >= 0 ? a.G + (int64_t)d.gin * 2 * a.L : nullptr;
+  if (gin) {
+    fft_lds<EQ_P, 1, EQ_P, MG_BLOCK, -1>(A, a.tw);
+    for (int i = threadIdx.x; i < EQ_P; i += MG_BLOCK) A[i] = c_scale(A[i], H[i] * (1.0f / EQ_P));
+    __syncthreads();
+    fft_lds<EQ_P, 1, EQ_P, MG_BLOCK, +1>(A, a.tw);
+    for (int i = half + threadIdx.x; i < half + a.V; i += MG_BLOCK) {
+      const int64_t n = s0 + i;
+      if (n >= a.L) break;
+      const float um = u[n] + u[cs + n];
+      gin[n] = (1.0f - w) * dy[n] + A[i].x - ku * um;
+      gin[a.L + n] = (1.0f - w) * dy[a.L + n] + A[i].y - ku * um;
+    }
+    __syncthreads();
+  }
+  // FIR gradient: correlate the valid-part gradient (B) with the input window (A)
+  for (int i = threadIdx.x; i < EQ_P; i += MG_BLOCK) {
+    const int64_t n = s0 + i;
+    A[i] = (n >= 0 && n < a.L) ? make_float2(u[n], u[cs + n]) : make_float2(0.f, 0.f);
+  }
+  __syncthreads();
+  fft_lds<EQ_P, 1, EQ_P, MG_BLOCK, -1>(A, a.tw);
+  fft_lds<EQ_P, 1, EQ_P, MG_BLOCK, -1>(B, a.tw);
+  for (int i = threadIdx.x; i < EQ_P; i += MG_BLOCK) B[i] = c_scale(c_mulc(B[i], A[i]), 1.0f / EQ_P);
+  __syncthreads();
+  fft_lds<EQ_P, 1, EQ_P, MG_BLOCK, +1>(B, a.tw);
+  // lag m sits at circular index m mod P; dh index = m + half
+  float* o = a.dhp + ((int64_t)d.aux * a.nblk + blk) * a.N;
+  for (int t = threadIdx.x; t < a.N; t += MG_BLOCK) {
+    const int m = t - half;
+    o[t] = B[m >= 0 ? m : m + EQ_P].x;
+  }
+  const float s = block_sum<MG_BLOCK>(dw, red);
+  if (threadIdx.x == 0) a.part[((int64_t)j * a.PB + blk) * PK + 2] = s;
+}
+
+// dh[row][t] = sum over blocks (fixed order, FP64); grid (ceil(N/256), nodes)
+__global__ __launch_bounds__(MG_BLOCK) void k_eq_dh_reduce(EqArgs a) {
+  const NodeDesc d = a.desc[blockIdx.y];
+  const int t = blockIdx.x * MG_BLOCK + threadIdx.x;
+  if (t >= a.N) return;
+  const float* src = a.dhp + (int64_t)d.aux * a.nblk * a.N + t;
+  double s = 0.0;
+  for (int b = 0; b < a.nblk; ++b) s += (double)src[(int64_t)b * a.N];
+  a.dh[(int64_t)d.aux * a.N + t] = (float)s;
+}
+
+static EqArgs eq_args(const Ctx& c, int desc_off, bool keep) {
+  const mg_graph* g = c.g;
+  EqArgs a;
+  a.desc = c.desc + desc_off;
+  a.dry = c.dry;
+  a.U = c.U;
+  a.G = c.G;
+  a.Uo = c.U;
+  a.ybar = keep ? wsp<float>(c, g->ws.YB) : nullptr;  // EQ rows come first in YB
+  a.h = wsp<float>(c, g->ws.eq_h);
+  a.HP = wsp<float>(c, g->ws.eq_HP);
+  a.dhp = g->mode ? wsp<float>(c, g->ws.eq_dhp) : nullptr;
+  a.dh = g->mode ? wsp<float>(c, g->ws.eq_dh) : nullptr;
+  a.wet = c.wet;
+  a.mask = c.mask;
+  a.lg = c.lg + 2 * desc_off;
+  a.part = c.part + (int64_t)desc_off * c.PB * PK;
+  a.PB = c.PB;
+  a.L = c.L;
+  a.C = c.C;
+  a.N = g->cfg.eq_taps;
+  a.V = EQ_P - (a.N - 1);
+  a.nblk = (int)((c.L + a.V - 1) / a.V);
+  a.alpha_g = c.alpha_g;
+  a.tw = wsp<float2>(c, g->ws.tw);
+  return a;
+}
+
+int eq_blocks(const mg_graph* g) {
+  const int V = EQ_P - (g->cfg.eq_taps - 1);
+  return (int)((g->cfg.length + V - 1) / V);
+}
+
+void eq_forward(const Ctx& c, int desc_off, int n, bool keep) {
+  EqArgs a = eq_args(c, desc_off, keep);
+  {
+    ProfScope ps(c, "eq_spec", (double)n * (4.0 * a.N + 4.0 * EQ_P));
+    hipLaunchKernelGGL(k_eq_spec, dim3(n), dim3(MG_BLOCK), 0, c.st, a);
+  }
+  {
+    ProfScope ps(c, "eq_conv", (double)n * ((8.0 * EQ_P) * a.nblk + (keep ? 16.0 : 8.0) * c.L + 8.0 * c.L));
+    hipLaunchKernelGGL(k_eq_fwd, dim3(a.nblk, n), dim3(MG_BLOCK), 0, c.st, a);
+  }
+  launch_reduce_lg(c, desc_off, n, a.nblk);
+}
+
+void eq_backward(const Ctx& c, int desc_off, int n) {
+  EqArgs a = eq_args(c, desc_off, true);
+  {
+    // reads dL/dy, ybar, u (window each) and u again; writes dL/du and the block FIR gradients
+    ProfScope ps(c, "eq_conv", (double)n * ((24.0 * EQ_P) * a.nblk + 16.0 * c.L + 4.0 * a.N * a.nblk));
+    hipLaunchKernelGGL(k_eq_bwd, dim3(a.nblk, n), dim3(MG_BLOCK), 0, c.st, a);
+  }
+  hipLaunchKernelGGL(k_eq_dh_reduce, dim3((a.N + MG_BLOCK - 1) / MG_BLOCK, n), dim3(MG_BLOCK), 0, c.st, a);
+}
+
+}  // namespace mg

@@ -533,8 +533,13 @@ static EngineArgs engine_args(const Ctx& c) {
   return ea;
 }
 
-// slot of row 0 of each FIR type in the ybar / spectrum arrays
+// row 0 of each long-FIR type in the spectrum arrays (delay, then reverb)
 static int conv_base(const mg_graph* g, int type) {
+  return type == MG_DELAY ? 0 : g->type_count[MG_DELAY];
+}
+
+// row 0 of each FIR type in the stored wet outputs (EQ, delay, reverb)
+static int ybar_base(const mg_graph* g, int type) {
   if (type == MG_EQ) return 0;
   if (type == MG_DELAY) return g->type_count[MG_EQ];
   return g->type_count[MG_EQ] + g->type_count[MG_DELAY];
@@ -638,7 +643,7 @@ void conv_forward(const Ctx& c, int type, int desc_off, int n, bool keep_input_s
   st.ybar_base = keep_input_spectrum ? wsp<float>(c, g->ws.YB) : nullptr;
   st.wet = c.wet;
   st.mask = c.mask;
-  st.yb0 = z0;
+  st.yb0 = ybar_base(g, type);
   st.part = c.part + (int64_t)desc_off * c.PB * PK;
   st.PB = c.PB;
   if (!keep_input_spectrum) {
@@ -666,7 +671,7 @@ void conv_backward(const Ctx& c, int type, int desc_off, int n) {
   ld.wet = c.wet;
   ld.mask = c.mask;
   ld.alpha_g = c.alpha_g;
-  ld.yb0 = z0;
+  ld.yb0 = ybar_base(g, type);
   ld.part = c.part + (int64_t)desc_off * c.PB * PK;
   ld.PB = c.PB;
   run_cols(c, ld, T1, n, ea, 24.0 * c.L);

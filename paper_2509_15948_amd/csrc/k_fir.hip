@@ -248,65 +248,156 @@ __global__ __launch_bounds__(MG_BLOCK) void k_delay_adjoint(const NodeDesc* __re
 }
 
 // ---------------------------------------------------------------- reverb
-// noise STFT (setup): U[row][x][m][k] = sum_t w[t] noise_x[m hop - nfft/2 + t] e^{-2 pi i k t / nfft}
-__global__ __launch_bounds__(MG_BLOCK) void k_rv_noise_stft(const float* __restrict__ noise, int Lr, int nf,
-                                                             const float2* __restrict__ cs384,
-                                                             const float* __restrict__ win,
-                                                             float2* __restrict__ Uout) {
-  __shared__ float fr[384];
-  const int m = blockIdx.x, x = blockIdx.y, row = blockIdx.z;
-  const float* nz = noise + ((int64_t)row * 2 + x) * Lr;
-  for (int t = threadIdx.x; t < 384; t += MG_BLOCK) {
-    const int64_t n = (int64_t)m * 192 - 192 + t;
-    fr[t] = (n >= 0 && n < Lr) ? win[t] * nz[n] : 0.0f;
+// The reverb's STFT frames are 384 = 3 * 4 * 4 * 4 * 2 points: a mixed-radix
+// Stockham FFT in LDS (table tw384[m] = exp(-2 pi i m / 384), FP64-rounded),
+// with two real frames packed into one complex transform.
+constexpr int RV_N = 384;
+constexpr int RV_FPB = 16;            // frames per workgroup (8 packed transforms)
+constexpr int RV_SEQ = RV_FPB / 2;
+
+template <int R, int DIR>
+__device__ __forceinline__ void rv_pass(float2* buf, const float2* __restrict__ tw, int Ns) {
+  constexpr int Q = RV_N / R;
+  constexpr int NB = RV_SEQ * Q;
+  constexpr int PER = NB / MG_BLOCK;
+  static_assert(NB % MG_BLOCK == 0, "even split");
+  float2 v[PER][R];
+  const int tid = threadIdx.x;
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const int g = tid + q * MG_BLOCK;
+    const int b = g / Q, j = g % Q;
+#pragma unroll
+    for (int r = 0; r < R; ++r) v[q][r] = buf[b * RV_N + j + r * Q];
   }
   __syncthreads();
-  for (int k = threadIdx.x; k < 192; k += MG_BLOCK) {
-    double ar = 0.0, ai = 0.0;
-    int idx = 0;
-    for (int t = 0; t < 384; ++t) {
-      const float2 e = cs384[idx];  // (cos, sin) of 2 pi idx / 384
-      ar += (double)fr[t] * (double)e.x;
-      ai -= (double)fr[t] * (double)e.y;
-      idx += k;
-      if (idx >= 384) idx -= 384;
+  const int stride = RV_N / (Ns * R);
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const int g = tid + q * MG_BLOCK;
+    const int b = g / Q, j = g % Q;
+    const int k = j % Ns;
+#pragma unroll
+    for (int r = 1; r < R; ++r) v[q][r] = c_mul(v[q][r], tw_get<DIR>(tw, r * k * stride));
+    float2 y[R];
+    if (R == 2) {
+      y[0] = c_add(v[q][0], v[q][1]);
+      y[1] = c_sub(v[q][0], v[q][1]);
+    } else if (R == 3) {
+      const float s3 = 0.86602540378443864676f * (DIR < 0 ? -1.0f : 1.0f);
+      const float2 t1 = c_add(v[q][1], v[q][2]);
+      const float2 t2 = make_float2(v[q][0].x - 0.5f * t1.x, v[q][0].y - 0.5f * t1.y);
+      const float2 d = c_sub(v[q][1], v[q][2]);
+      const float2 t3 = make_float2(-s3 * d.y, s3 * d.x);  // i * s3 * (a1 - a2)
+      y[0] = c_add(v[q][0], t1);
+      y[1] = c_add(t2, t3);
+      y[2] = c_sub(t2, t3);
+    } else {
+      const float2 t0 = c_add(v[q][0], v[q][2]), t1 = c_sub(v[q][0], v[q][2]);
+      const float2 t2 = c_add(v[q][1], v[q][3]), t3 = c_rot<DIR>(c_sub(v[q][1], v[q][3]));
+      y[0] = c_add(t0, t2);
+      y[1] = c_add(t1, t3);
+      y[2] = c_sub(t0, t2);
+      y[3] = c_sub(t1, t3);
     }
-    Uout[(((int64_t)row * 2 + x) * nf + m) * 192 + k] = make_float2((float)ar, (float)ai);
+    const int idx = (j - k) * R + k;
+#pragma unroll
+    for (int r = 0; r < R; ++r) buf[b * RV_N + idx + r * Ns] = y[r];
+  }
+  __syncthreads();
+}
+
+// RV_SEQ unnormalised 384-point transforms in LDS (caller syncs after filling)
+template <int DIR>
+__device__ __forceinline__ void rv_fft(float2* buf, const float2* __restrict__ tw) {
+  rv_pass<3, DIR>(buf, tw, 1);
+  rv_pass<4, DIR>(buf, tw, 3);
+  rv_pass<4, DIR>(buf, tw, 12);
+  rv_pass<4, DIR>(buf, tw, 48);
+  rv_pass<2, DIR>(buf, tw, 192);
+}
+
+// noise STFT (setup): U[row][x][m][k] = sum_t w[t] noise_x[m hop - nfft/2 + t] e^{-2 pi i k t / nfft}
+// grid (ceil(nf / 16), 2, rows)
+__global__ __launch_bounds__(MG_BLOCK) void k_rv_noise_stft(const float* __restrict__ noise, int Lr, int nf,
+                                                             const float2* __restrict__ tw,
+                                                             const float* __restrict__ win,
+                                                             float2* __restrict__ Uout) {
+  __shared__ float2 buf[RV_SEQ * RV_N];
+  const int m0 = blockIdx.x * RV_FPB, x = blockIdx.y, row = blockIdx.z;
+  const float* nz = noise + ((int64_t)row * 2 + x) * Lr;
+  for (int i = threadIdx.x; i < RV_SEQ * RV_N; i += MG_BLOCK) {
+    const int p = i / RV_N, t = i % RV_N;
+    float v[2];
+    for (int h = 0; h < 2; ++h) {
+      const int m = m0 + 2 * p + h;
+      const int64_t n = (int64_t)m * 192 - 192 + t;
+      v[h] = (m < nf && n >= 0 && n < Lr) ? win[t] * nz[n] : 0.0f;
+    }
+    buf[i] = make_float2(v[0], v[1]);
+  }
+  __syncthreads();
+  rv_fft<-1>(buf, tw);
+  for (int i = threadIdx.x; i < RV_SEQ * 192; i += MG_BLOCK) {
+    const int p = i / 192, k = i % 192;
+    const float2 z = buf[p * RV_N + k], zm = buf[p * RV_N + ((RV_N - k) % RV_N)];
+    const float2 a = make_float2(0.5f * (z.x + zm.x), 0.5f * (z.y - zm.y));
+    const float2 b = make_float2(0.5f * (z.y + zm.y), -0.5f * (z.x - zm.x));
+    for (int h = 0; h < 2; ++h) {
+      const int m = m0 + 2 * p + h;
+      if (m < nf) Uout[(((int64_t)row * 2 + x) * nf + m) * 192 + k] = h ? b : a;
+    }
   }
 }
 
-// frames: fr[row][x][m][t] = w[t] (1/384) sum_{k<192} c_k Re(U M e^{+2 pi i k t/384})
-// grid (nf, 2, nodes), block 128 (3 samples per thread)
-__global__ __launch_bounds__(128) void k_rv_frames(const NodeDesc* __restrict__ desc, const float* __restrict__ theta,
-                                                    const float2* __restrict__ Unz, int nf,
-                                                    const float2* __restrict__ cs384,
-                                                    const float* __restrict__ win, float gbias, float beta,
-                                                    float* __restrict__ frames) {
-  __shared__ float2 Hm[192];
-  const int m = blockIdx.x, x = blockIdx.y;
+// frames: fr[row][x][m][t] = w[t] (1/384) sum_{k<192} c_k Re(U M e^{+2 pi i k t/384}),
+// M = exp(H0 + g0 + m d), d = -softplus(Hd + beta).  grid (ceil(nf / 16), 2, nodes)
+__global__ __launch_bounds__(MG_BLOCK) void k_rv_frames(const NodeDesc* __restrict__ desc,
+                                                         const float* __restrict__ theta,
+                                                         const float2* __restrict__ Unz, int nf,
+                                                         const float2* __restrict__ tw,
+                                                         const float* __restrict__ win, float gbias, float beta,
+                                                         float* __restrict__ frames) {
+  __shared__ float2 buf[RV_SEQ * RV_N];
+  __shared__ float h0[192], dk[192];
+  const int m0 = blockIdx.x * RV_FPB, x = blockIdx.y;
   const NodeDesc d = desc[blockIdx.z];
   const float* p = theta + d.theta_off + x * 384;  // [H0 (192), Hd (192)]
-  const float2* U = Unz + (((int64_t)d.aux * 2 + x) * nf + m) * 192;
-  for (int k = threadIdx.x; k < 192; k += 128) {
-    // decay per frame -softplus(theta + beta) (FP64 for the small argument range)
-    const double dk = -log1p(exp((double)p[192 + k] + (double)beta));
-    const float mk = (float)exp((double)p[k] + (double)gbias + (double)m * dk);
-    const float sc = (k == 0 ? 1.0f : 2.0f) / 384.0f * mk;
-    const float2 u = U[k];
-    Hm[k] = make_float2(u.x * sc, u.y * sc);
+  for (int k = threadIdx.x; k < 192; k += MG_BLOCK) {
+    h0[k] = p[k] + gbias;
+    dk[k] = (float)(-log1p(exp((double)p[192 + k] + (double)beta)));
   }
   __syncthreads();
-  float* out = frames + (((int64_t)d.aux * 2 + x) * nf + m) * 384;
-  for (int t = threadIdx.x; t < 384; t += 128) {
-    double acc = 0.0;
-    int idx = 0;
-    for (int k = 0; k < 192; ++k) {
-      const float2 e = cs384[idx];
-      acc += (double)Hm[k].x * (double)e.x - (double)Hm[k].y * (double)e.y;
-      idx += t;
-      if (idx >= 384) idx -= 384;
+  const float2* U = Unz + ((int64_t)d.aux * 2 + x) * nf * 192;
+  // Hermitian spectra of frame pairs: Z = A + i B
+  for (int i = threadIdx.x; i < RV_SEQ * RV_N; i += MG_BLOCK) {
+    const int pr = i / RV_N, k = i % RV_N;
+    float2 s[2];
+    for (int h = 0; h < 2; ++h) {
+      const int m = m0 + 2 * pr + h;
+      float2 v = make_float2(0.f, 0.f);
+      if (m < nf && k != 192) {
+        const int kk = k < 192 ? k : RV_N - k;
+        const float mk = expf(h0[kk] + (float)m * dk[kk]);
+        const float2 u = U[(int64_t)m * 192 + kk];
+        v = make_float2(u.x * mk, u.y * mk);
+        if (kk == 0) v.y = 0.f;
+        if (k > 192) v.y = -v.y;
+      }
+      s[h] = v;
     }
-    out[t] = (float)(acc * (double)win[t]);
+    buf[i] = make_float2(s[0].x - s[1].y, s[0].y + s[1].x);
+  }
+  __syncthreads();
+  rv_fft<+1>(buf, tw);
+  for (int i = threadIdx.x; i < RV_SEQ * RV_N; i += MG_BLOCK) {
+    const int pr = i / RV_N, t = i % RV_N;
+    const float2 z = buf[i];
+    const float wt = win[t] * (1.0f / RV_N);
+    for (int h = 0; h < 2; ++h) {
+      const int m = m0 + 2 * pr + h;
+      if (m < nf) frames[(((int64_t)d.aux * 2 + x) * nf + m) * RV_N + t] = (h ? z.y : z.x) * wt;
+    }
   }
 }
 
@@ -328,71 +419,95 @@ __global__ __launch_bounds__(MG_BLOCK) void k_rv_ola(const NodeDesc* __restrict_
   o[Lr + n] = hx[0] - hx[1];
 }
 
-// adjoint per (frame, x, node): dM[k] M[k] (for H0) and m dM[k] M[k] (for Hd)
+// adjoint per frame: dMM[k] = dM[k] M[k] with dM = Re(dH conj(U)),
+// dH[k] = (c_k / 384) DFT(w dh / wsum)[k].  grid (ceil(nf / 16), 2, nodes)
 __global__ __launch_bounds__(MG_BLOCK) void k_rv_adj_frames(const NodeDesc* __restrict__ desc,
                                                              const float* __restrict__ theta,
                                                              const float2* __restrict__ Unz, int nf, int Lr,
-                                                             const float2* __restrict__ cs384,
+                                                             const float2* __restrict__ tw,
                                                              const float* __restrict__ win,
                                                              const float* __restrict__ wsum, float gbias,
                                                              float beta, const float* __restrict__ dh,
                                                              float* __restrict__ dMout) {
-  __shared__ float df[384];
-  const int m = blockIdx.x, x = blockIdx.y;
+  __shared__ float2 buf[RV_SEQ * RV_N];
+  __shared__ float h0[192], dk[192];
+  const int m0 = blockIdx.x * RV_FPB, x = blockIdx.y;
   const NodeDesc d = desc[blockIdx.z];
+  const float* p = theta + d.theta_off + x * 384;
+  for (int k = threadIdx.x; k < 192; k += MG_BLOCK) {
+    h0[k] = p[k] + gbias;
+    dk[k] = (float)(-log1p(exp((double)p[192 + k] + (double)beta)));
+  }
   const float* dhn = dh + (int64_t)d.aux * 2 * Lr;
-  for (int t = threadIdx.x; t < 384; t += MG_BLOCK) {
-    const int64_t n = (int64_t)m * 192 - 192 + t;
-    float v = 0.0f;
-    if (n >= 0 && n < Lr) {
-      const float g = x == 0 ? dhn[n] + dhn[Lr + n] : dhn[n] - dhn[Lr + n];
-      v = win[t] * g / wsum[t % 192];
+  for (int i = threadIdx.x; i < RV_SEQ * RV_N; i += MG_BLOCK) {
+    const int pr = i / RV_N, t = i % RV_N;
+    float v[2];
+    for (int h = 0; h < 2; ++h) {
+      const int m = m0 + 2 * pr + h;
+      const int64_t n = (int64_t)m * 192 - 192 + t;
+      float a = 0.f;
+      if (m < nf && n >= 0 && n < Lr) {
+        const float gx = x == 0 ? dhn[n] + dhn[Lr + n] : dhn[n] - dhn[Lr + n];
+        a = win[t] * gx / wsum[t % 192];
+      }
+      v[h] = a;
     }
-    df[t] = v;
+    buf[i] = make_float2(v[0], v[1]);
   }
   __syncthreads();
-  const float* p = theta + d.theta_off + x * 384;
-  const float2* U = Unz + (((int64_t)d.aux * 2 + x) * nf + m) * 192;
-  float* o = dMout + (((int64_t)d.aux * 2 + x) * nf + m) * 192;
-  for (int k = threadIdx.x; k < 192; k += MG_BLOCK) {
-    double cr = 0.0, ci = 0.0;
-    int idx = 0;
-    for (int t = 0; t < 384; ++t) {
-      const float2 e = cs384[idx];
-      cr += (double)df[t] * (double)e.x;
-      ci += (double)df[t] * (double)e.y;
-      idx += k;
-      if (idx >= 384) idx -= 384;
+  rv_fft<-1>(buf, tw);
+  const float2* U = Unz + ((int64_t)d.aux * 2 + x) * nf * 192;
+  float* o = dMout + ((int64_t)d.aux * 2 + x) * nf * 192;
+  for (int i = threadIdx.x; i < RV_SEQ * 192; i += MG_BLOCK) {
+    const int pr = i / 192, k = i % 192;
+    const float2 z = buf[pr * RV_N + k], zm = buf[pr * RV_N + ((RV_N - k) % RV_N)];
+    const float2 Da = make_float2(0.5f * (z.x + zm.x), 0.5f * (z.y - zm.y));
+    const float2 Db = make_float2(0.5f * (z.y + zm.y), -0.5f * (z.x - zm.x));
+    const float ck = (k == 0 ? 1.0f : 2.0f) / RV_N;
+    for (int h = 0; h < 2; ++h) {
+      const int m = m0 + 2 * pr + h;
+      if (m >= nf) continue;
+      const float2 D = h ? Db : Da;
+      const float2 u = U[(int64_t)m * 192 + k];
+      const float dM = ck * (D.x * u.x + D.y * u.y);
+      o[(int64_t)m * 192 + k] = dM * expf(h0[k] + (float)m * dk[k]);
     }
-    const double ck = (k == 0 ? 1.0 : 2.0) / 384.0;
-    const double dRe = ck * cr, dIm = -ck * ci;
-    const float2 u = U[k];
-    const double dM = dRe * (double)u.x + dIm * (double)u.y;
-    const double dk = -log1p(exp((double)p[192 + k] + (double)beta));
-    const double mk = exp((double)p[k] + gbias + (double)m * dk);
-    o[k] = (float)(dM * mk);
   }
 }
 
 // reduce over frames: dH0[k] = sum_m dMM[m][k];
-// dtheta_d[k] = -sigmoid(theta_d[k] + beta) sum_m m dMM[m][k]
+// dtheta_d[k] = -sigmoid(theta_d[k] + beta) sum_m m dMM[m][k].
+// grid (192 / 16, 2, nodes), block 256 = 16 bins x 16 frame lanes
 __global__ __launch_bounds__(MG_BLOCK) void k_rv_adj_reduce(const NodeDesc* __restrict__ desc, int nf,
                                                              const float* __restrict__ dM,
                                                              const float* __restrict__ theta, float beta,
                                                              float* __restrict__ grad_theta) {
-  const int x = blockIdx.x;
-  const NodeDesc d = desc[blockIdx.y];
+  __shared__ double ra[MG_BLOCK], rb[MG_BLOCK];
+  const int x = blockIdx.y;
+  const NodeDesc d = desc[blockIdx.z];
+  const int kl = threadIdx.x % 16, lane = threadIdx.x / 16;
+  const int k = blockIdx.x * 16 + kl;
   const float* src = dM + ((int64_t)d.aux * 2 + x) * nf * 192;
-  for (int k = threadIdx.x; k < 192; k += MG_BLOCK) {
-    double a = 0.0, b = 0.0;
-    for (int m = 0; m < nf; ++m) {
-      const double v = src[(int64_t)m * 192 + k];
-      a += v;
-      b += (double)m * v;
+  double a = 0.0, b = 0.0;
+  for (int m = lane; m < nf; m += 16) {
+    const double v = src[(int64_t)m * 192 + k];
+    a += v;
+    b += (double)m * v;
+  }
+  ra[threadIdx.x] = a;
+  rb[threadIdx.x] = b;
+  __syncthreads();
+  for (int s = 8; s > 0; s >>= 1) {
+    if (lane < s) {
+      ra[threadIdx.x] += ra[threadIdx.x + s * 16];
+      rb[threadIdx.x] += rb[threadIdx.x + s * 16];
     }
+    __syncthreads();
+  }
+  if (lane == 0) {
     const double sg = 1.0 / (1.0 + exp(-((double)theta[d.theta_off + x * 384 + 192 + k] + (double)beta)));
-    grad_theta[d.theta_off + x * 384 + k] = (float)a;
-    grad_theta[d.theta_off + x * 384 + 192 + k] = (float)(-sg * b);
+    grad_theta[d.theta_off + x * 384 + k] = (float)ra[kl];
+    grad_theta[d.theta_off + x * 384 + 192 + k] = (float)(-sg * rb[kl]);
   }
 }
 
@@ -421,7 +536,7 @@ void fir_setup(const Ctx& c, const float* reverb_noise) {
     std::vector<float2> cs(384);
     std::vector<float> win(384), ws(192);
     for (int m = 0; m < 384; ++m) {
-      cs[m] = make_float2((float)cos(2.0 * pi * m / 384), (float)sin(2.0 * pi * m / 384));
+      cs[m] = make_float2((float)cos(2.0 * pi * m / 384), (float)-sin(2.0 * pi * m / 384));
       win[m] = (float)(0.5 - 0.5 * cos(2.0 * pi * m / 384));
     }
     for (int r = 0; r < 192; ++r) {
@@ -432,7 +547,8 @@ void fir_setup(const Ctx& c, const float* reverb_noise) {
     hipMemcpyAsync(wsp<float>(c, g->ws.rv_win), win.data(), win.size() * 4, hipMemcpyHostToDevice, c.st);
     hipMemcpyAsync(wsp<float>(c, g->ws.rv_wsum), ws.data(), ws.size() * 4, hipMemcpyHostToDevice, c.st);
     const int nrv = g->type_count[MG_REVERB];
-    hipLaunchKernelGGL(k_rv_noise_stft, dim3(g->nf_rev, 2, nrv), dim3(MG_BLOCK), 0, c.st, reverb_noise,
+    hipLaunchKernelGGL(k_rv_noise_stft, dim3((g->nf_rev + RV_FPB - 1) / RV_FPB, 2, nrv), dim3(MG_BLOCK), 0, c.st,
+                       reverb_noise,
                        cf.reverb_length, g->nf_rev, wsp<float2>(c, g->ws.rv_cs), wsp<float>(c, g->ws.rv_win),
                        wsp<float2>(c, g->ws.rv_U));
     hipStreamSynchronize(c.st);
@@ -453,7 +569,9 @@ void fir_synth(const Ctx& c, int type, int desc_off, int n) {
   } else if (type == MG_REVERB) {
     const float gb = (float)reverb_gain_bias(cf.sample_rate);
     const float db = (float)reverb_decay_offset(cf.sample_rate, cf.reverb_hop);
-    hipLaunchKernelGGL(k_rv_frames, dim3(g->nf_rev, 2, n), dim3(128), 0, c.st, d, c.theta,
+    ProfScope pr(c, "reverb_fir", (double)n * 2 * g->nf_rev * (192 * 8 + 384 * 4));
+    hipLaunchKernelGGL(k_rv_frames, dim3((g->nf_rev + RV_FPB - 1) / RV_FPB, 2, n), dim3(MG_BLOCK), 0, c.st, d,
+                       c.theta,
                        wsp<float2>(c, g->ws.rv_U), g->nf_rev, wsp<float2>(c, g->ws.rv_cs),
                        wsp<float>(c, g->ws.rv_win), gb, db, wsp<float>(c, g->ws.rv_fr));
     hipLaunchKernelGGL(k_rv_ola, dim3((cf.reverb_length + MG_BLOCK - 1) / MG_BLOCK, n), dim3(MG_BLOCK), 0, c.st, d,
@@ -478,11 +596,13 @@ void fir_adjoint(const Ctx& c, int type, int desc_off, int n, float* grad_theta)
   } else if (type == MG_REVERB) {
     const float gb = (float)reverb_gain_bias(cf.sample_rate);
     const float db = (float)reverb_decay_offset(cf.sample_rate, cf.reverb_hop);
-    hipLaunchKernelGGL(k_rv_adj_frames, dim3(g->nf_rev, 2, n), dim3(MG_BLOCK), 0, c.st, d, c.theta,
+    ProfScope pr(c, "reverb_fir", (double)n * 2 * g->nf_rev * (192 * 8 + 384 * 4 + 192 * 4));
+    hipLaunchKernelGGL(k_rv_adj_frames, dim3((g->nf_rev + RV_FPB - 1) / RV_FPB, 2, n), dim3(MG_BLOCK), 0, c.st, d,
+                       c.theta,
                        wsp<float2>(c, g->ws.rv_U), g->nf_rev, cf.reverb_length, wsp<float2>(c, g->ws.rv_cs),
                        wsp<float>(c, g->ws.rv_win), wsp<float>(c, g->ws.rv_wsum), gb, db,
                        wsp<float>(c, g->ws.rv_dh), wsp<float>(c, g->ws.rv_dM));
-    hipLaunchKernelGGL(k_rv_adj_reduce, dim3(2, n), dim3(MG_BLOCK), 0, c.st, d, g->nf_rev,
+    hipLaunchKernelGGL(k_rv_adj_reduce, dim3(192 / 16, 2, n), dim3(MG_BLOCK), 0, c.st, d, g->nf_rev,
                        wsp<float>(c, g->ws.rv_dM), c.theta, db, grad_theta);
   }
 }

@@ -138,20 +138,24 @@ __global__ __launch_bounds__(MG_BLOCK) void k_loss_fwd(LossArgs a) {
 }
 
 // stats[x][0] = sum Y^2 (MODE 0), [1] = sum (Y - Yh)^2, [2] = sum|dlog| / cells
-__global__ void k_loss_reduce(const double* __restrict__ part, int nblocks, int cells, int mode,
-                              double* __restrict__ stats) {
-  const int x = threadIdx.x;
-  if (x >= 4) return;
-  double s0 = 0.0, s1 = 0.0;
-  for (int b = 0; b < nblocks; ++b) {
-    s0 += part[(int64_t)b * 8 + x];
-    s1 += part[(int64_t)b * 8 + 4 + x];
-  }
-  if (mode == 0) {
-    stats[x * 4 + 0] = s0;
-  } else {
-    stats[x * 4 + 2] = s0 / (double)cells;
-    stats[x * 4 + 1] = s1;
+// (fixed order: strided per thread, then a tree)
+__global__ __launch_bounds__(MG_BLOCK) void k_loss_reduce(const double* __restrict__ part, int nblocks, int cells,
+                                                           int mode, double* __restrict__ stats) {
+  __shared__ double red[MG_BLOCK];
+  for (int q = 0; q < 8; ++q) {
+    double s = 0.0;
+    for (int b = threadIdx.x; b < nblocks; b += MG_BLOCK) s += part[(int64_t)b * 8 + q];
+    s = block_sum<MG_BLOCK>(s, red);
+    if (threadIdx.x == 0) {
+      const int x = q % 4;
+      if (mode == 0) {
+        if (q < 4) stats[x * 4 + 0] = s;
+      } else if (q < 4) {
+        stats[x * 4 + 2] = s / (double)cells;
+      } else {
+        stats[x * 4 + 1] = s;
+      }
+    }
   }
 }
 
@@ -428,7 +432,7 @@ static void run_loss_fwd(const Ctx& c, const float* y, int mode) {
     }
 #undef MG_F0
 #undef MG_F1
-    hipLaunchKernelGGL(k_loss_reduce, dim3(1), dim3(64), 0, c.st, a.part, blocks, r.frames * g->cfg.n_mels, mode,
+    hipLaunchKernelGGL(k_loss_reduce, dim3(1), dim3(MG_BLOCK), 0, c.st, a.part, blocks, r.frames * g->cfg.n_mels, mode,
                        stats + i * 16);
   }
 }

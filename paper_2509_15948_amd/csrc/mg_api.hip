@@ -46,8 +46,8 @@ static size_t plan_ws(mg_graph& g, int mode, bool commit) {
     take(w.G, (size_t)g.n_gslots * 2 * L * 4);
   }
   if (N > 0) {
-    take(w.ZH, (size_t)n_conv * N * 8);
-    if (mode) take(w.ZU, (size_t)n_conv * N * 8);
+    take(w.ZH, (size_t)(n_dl + n_rv) * N * 8);
+    if (mode) take(w.ZU, (size_t)(n_dl + n_rv) * N * 8);
     take(w.T1, (size_t)g.max_conv_stage * N * 8);
     take(w.T2, (size_t)g.max_conv_stage * N * 8);
     if (mode) take(w.T3, (size_t)g.max_conv_stage * N * 8);
@@ -58,7 +58,11 @@ static size_t plan_ws(mg_graph& g, int mode, bool commit) {
   take(w.twd, MG_TWN * 16);
   if (n_eq) {
     take(w.eq_h, (size_t)n_eq * c.eq_taps * 4);
-    if (mode) take(w.eq_dh, (size_t)n_eq * c.eq_taps * 4);
+    take(w.eq_HP, (size_t)n_eq * 8192 * 4);
+    if (mode) {
+      take(w.eq_dh, (size_t)n_eq * c.eq_taps * 4);
+      take(w.eq_dhp, (size_t)n_eq * eq_blocks(&g) * c.eq_taps * 4);
+    }
     take(w.eq_cos, (size_t)c.eq_taps * 4);
   }
   if (n_dl) {
@@ -113,6 +117,7 @@ static void finish_compile(mg_graph& g) {
   int pb = 128;
   if (g.fft.N > 0) pb = std::max(pb, g.fft.N / 8192);
   pb = std::max(pb, g.dyn_chunks);
+  if (g.type_count[MG_EQ] > 0) pb = std::max(pb, eq_blocks(&g));
   g.part_blocks = pb;
 }
 
@@ -160,6 +165,9 @@ static void run_forward(mg_graph* g, hipStream_t st, bool keep, double* losses, 
       launch_pointwise_fwd(c, t, off, n);
     } else if (t == MG_COMP || t == MG_GATE) {
       dyn_forward(c, t, off, n);
+    } else if (t == MG_EQ) {
+      fir_synth(c, t, off, n);
+      eq_forward(c, off, n, keep);
     } else if (is_conv(t)) {
       fir_synth(c, t, off, n);
       conv_fir_spectrum(c, t, off, n);
@@ -286,6 +294,10 @@ extern "C" int mg_backward(mg_graph* g, float* grad_theta, float* grad_wet, void
       dyn_backward(c, t, off, n);
       const bool ar = (t == MG_COMP && cf.comp_mode == 1);
       launch_finish_grads(c, off, n, ar ? 1 : g->dyn_chunks, g->type_np[t], grad_theta, grad_wet);
+    } else if (t == MG_EQ) {
+      eq_backward(c, off, n);
+      fir_adjoint(c, t, off, n, grad_theta);
+      launch_finish_grads(c, off, n, eq_blocks(g), 0, grad_theta, grad_wet);
     } else if (is_conv(t)) {
       conv_backward(c, t, off, n);
       fir_adjoint(c, t, off, n, grad_theta);

@@ -214,7 +214,8 @@ int compile(mg_graph& g) {
     Stage& S = g.stages[s];
     S.desc_off = (int)g.desc.size();
     g.max_stage = std::max(g.max_stage, (int)S.nodes.size());
-    if (is_conv(S.type)) g.max_conv_stage = std::max(g.max_conv_stage, (int)S.nodes.size());
+    if (S.type == MG_DELAY || S.type == MG_REVERB)
+      g.max_conv_stage = std::max(g.max_conv_stage, (int)S.nodes.size());
     for (int v : S.nodes) {
       NodeDesc d{};
       d.node = v;
@@ -276,7 +277,6 @@ int compile(mg_graph& g) {
   bool any_conv = false;
   for (int v = 0; v < g.n_nodes; ++v) {
     int t = g.type[v];
-    if (t == MG_EQ) ext = std::max<int64_t>(ext, (c.eq_taps - 1) / 2), any_conv = true;
     if (t == MG_DELAY)
       ext = std::max<int64_t>(ext, (int64_t)c.delay_taps * c.delay_range + (c.delay_fir_taps - 1) / 2), any_conv = true;
     if (t == MG_REVERB) ext = std::max<int64_t>(ext, c.reverb_length), any_conv = true;
@@ -312,8 +312,8 @@ int validate_config(const mg_config& c, const std::vector<int>& type) {
   for (int t : type) has[t] = true;
   if (c.length < 64) return fail(MG_ERR_INVALID_ARG, "length must be >= 64");
   if (c.sample_rate <= 0) return fail(MG_ERR_INVALID_ARG, "sample_rate must be > 0");
-  if (has[MG_EQ] && (c.eq_taps < 3 || (c.eq_taps & 1) == 0 || c.eq_taps > 8191))
-    return fail(MG_ERR_INVALID_ARG, "eq_taps must be odd in [3, 8191]");
+  if (has[MG_EQ] && (c.eq_taps < 3 || (c.eq_taps & 1) == 0 || c.eq_taps > 4095))
+    return fail(MG_ERR_INVALID_ARG, "eq_taps must be odd in [3, 4095]");
   if (has[MG_COMP] && c.comp_mode != 0 && c.comp_mode != 1)
     return fail(MG_ERR_INVALID_ARG, "comp_mode must be 0 or 1");
   if (has[MG_DELAY]) {

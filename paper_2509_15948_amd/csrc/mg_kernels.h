@@ -71,6 +71,11 @@ void conv_fir_spectrum(const Ctx& c, int type, int desc_off, int n);
 void conv_forward(const Ctx& c, int type, int desc_off, int n, bool keep_input_spectrum);
 void conv_backward(const Ctx& c, int type, int desc_off, int n);
 
+// k_eq.hip: equalizer by overlap-save in LDS
+int eq_blocks(const mg_graph* g);
+void eq_forward(const Ctx& c, int desc_off, int n, bool keep);
+void eq_backward(const Ctx& c, int desc_off, int n);
+
 // k_fir.hip: FIR synthesis and adjoints
 void fir_setup(const Ctx& c, const float* reverb_noise);
 void fir_synth(const Ctx& c, int type, int desc_off, int n);

@@ -120,6 +120,15 @@ def test_full_console_full_size():
         vs = [v for v in case.g.processors() if case.g.types[v] == t]
         err = rel_l2(np.concatenate([gth[v] for v in vs]), np.concatenate([oth[v] for v in vs]))
         print("full", t, "grad err", err, flush=True)
+    Kc = (cfg.delay_fir_taps + 1) // 2
+    for v in [v for v in case.g.processors() if case.g.types[v] == "d"][:3]:
+        a = gth[v].reshape(2, cfg.delay_taps, 2 + Kc)
+        b = oth[v].reshape(2, cfg.delay_taps, 2 + Kc)
+        for c in range(2):
+            for m in range(cfg.delay_taps):
+                print("full delay", v, c, m, "z gpu", a[c, m, :2], "oracle", b[c, m, :2], "theta",
+                      case.th[v].reshape(2, cfg.delay_taps, 2 + Kc)[c, m, :2],
+                      "fir err", rel_l2(a[c, m, 2:], b[c, m, 2:]), flush=True)
     procs = case.g.processors()
     print("full wet grad err", rel_l2([gwe[v] for v in procs], [owe[v] for v in procs]), flush=True)
     for t in "ecxsgdr":
@@ -187,3 +196,17 @@ def test_loss_kernel_on_the_gpu_mix(chain):
               "oracle(mix rounded to fp32)", float(ol32[k]), flush=True)
     for k in ("La", "Llr", "Lm", "Ls"):
         assert abs(gl[k] - float(ol[k])) <= 1e-9 * max(1.0, abs(float(ol[k]))), (k, gl[k], float(ol[k]))
+
+
+def test_forward_backward_is_bitwise_reproducible():
+    """No floating-point atomics: two identical fwd+bwd passes give identical bits."""
+    case = Case(_small("ecxsgdr"), seed=5)
+    m1, l1 = case.gpu_forward()
+    g1, w1 = case.gpu_backward()
+    m2, l2 = case.gpu_forward()
+    g2, w2 = case.gpu_backward()
+    assert np.array_equal(m1, m2)
+    assert l1 == l2
+    for v in g1:
+        assert np.array_equal(g1[v], g2[v]), v
+    assert w1 == w2
