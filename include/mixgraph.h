@@ -73,6 +73,12 @@ typedef struct mg_config {
   int32_t loss_ffts[8];    /* FFT sizes, powers of two in [64, 4096]          */
   int32_t n_mels;          /* Mel bands (96)                                  */
   int32_t loss_skip;       /* leading samples excluded from the loss          */
+  int32_t max_trials;      /* pruning trials per mg_forward_trials call (0:
+                              none); reserves the trial tables              */
+  int32_t trial_slots;     /* node outputs [2][L] reserved for trial copies;
+                              0 picks max_trials x the largest suffix of one
+                              processor, so single-processor trials run as
+                              one batch                                      */
   double alpha_g;          /* gain-staging regulariser weight                 */
   double alpha_p;          /* dry/wet l1 regulariser weight                   */
 } mg_config;
@@ -155,11 +161,47 @@ int mg_forward(mg_graph* g, const float* dry, const float* theta, const float* w
  *   grad_wet   dev float[P]       (overwritten)                              */
 int mg_backward(mg_graph* g, float* grad_theta, float* grad_wet, void* stream);
 
-/* Pruning trials (Alg. 2 Evaluate with w * m * m_cand): the forward pass and
- * loss for B masks, one after another on the stream, all results kept.
+/* Masked evaluation (Alg. 2 Evaluate with w * m * m_cand): a complete forward
+ * pass and loss for each of B masks, one after another on the stream (the
+ * reference for mg_forward_trials, which recomputes only suffixes).
  *   masks  dev float[B][P];  losses dev double[B][7].                        */
 int mg_forward_masked(mg_graph* g, const float* dry, const float* theta, const float* wet,
                       const float* masks, int32_t B, double* losses, void* stream);
+
+/* Pruning trials by suffix recomputation (Alg. 2 Evaluate for a batch of
+ * candidate masks, Sec. 4.1 batching).  Trial b uses the mask of the last
+ * mg_forward multiplied by keep[b]; a processor with keep 0 is bypassed
+ * (w = 0, so y = u, Sec. 1.2).  Only the nodes downstream of a bypassed
+ * processor are evaluated again, reading every other node's output from the
+ * last mg_forward; the copies of one stage across all trials run in one
+ * launch per kernel, then each trial's loss is taken.  The results equal B
+ * separate mg_forward calls with those masks bit for bit.
+ *   keep    host uint8[B][P] (P = processors, proc_index order); B <= max_trials
+ *   losses  dev double[B][7], as mg_forward
+ * Requires a preceding mg_forward (MG_ERR_STATE otherwise) whose dry, theta,
+ * wet and mask buffers still hold the same values; does not disturb a
+ * pending mg_backward.  Trials
+ * whose copies exceed trial_slots run in several batches; one trial that
+ * alone needs more than trial_slots fails with MG_ERR_SHAPE.                */
+int mg_forward_trials(mg_graph* g, const uint8_t* keep, int32_t B, double* losses, void* stream);
+
+/* Decision rule of one pruning round (Alg. 2 with a batched trial step), host
+ * only.  Phase 1: candidates are the first max_n processors with alive != 0
+ * ordered by (w ascending, index), w = sigmoid(wet[p]) * mask[p] the
+ * effective dry/wet weight (Sec. 5.1); cand receives their indices, *n_out
+ * the count.  wet, mask (may be NULL: all ones), alive: host arrays of P.    */
+int mg_prune_candidates(int32_t P, const float* wet, const float* mask, const uint8_t* alive, int32_t max_n,
+                        int32_t* cand, int32_t* n_out);
+
+/* Phase 2: from the single-bypass losses L_cand[i] of cand[i] (i < n), keep
+ * those with L_cand - L_min < tau * L_min, ordered by (L_cand - L_min, index)
+ * into order; *n_out their count.  The trial masks of phase 3 bypass the
+ * prefixes order[0..k-1], k = 1..*n_out.                                    */
+int mg_prune_order(int32_t n, const int32_t* cand, const double* L_cand, double L_min, double tau,
+                   int32_t* order, int32_t* n_out);
+
+/* Phase 3: the largest k with L_prefix[k-1] < L_min (1 + tau), 0 if none.   */
+int mg_prune_accept(int32_t n, const double* L_prefix, double L_min, double tau, int32_t* k_out);
 
 /* One Adam step (Kingma & Ba) on n parameters, in place on theta, m, v.
  * step counts from 1.  All pointers dev float[n]. */
@@ -177,7 +219,8 @@ int mg_graph_prune(const mg_graph* g, const uint8_t* keep, mg_graph** out,
 /* Measurement of one kernel class (for roofline reporting, not part of the
  * method): after mg_profile_enable(g, cls), HIP events are recorded on the
  * caller's stream around every launch of that class ("conv_cols",
- * "conv_rows", "conv_icols", "dyn", "pointwise", "sum", "loss", "fir"; NULL
+ * "conv_rows", "conv_icols", "eq_conv", "eq_spec", "dyn", "pointwise", "sum",
+ * "loss", "fir", "reverb_fir"; NULL
  * disables; at most 4096 launches between reads).  mg_profile_read
  * synchronises on the recorded events and returns the summed device time in
  * ms, the number of timed launches and the algorithmic bytes they move (the

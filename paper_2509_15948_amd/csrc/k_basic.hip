@@ -8,6 +8,8 @@
 // Every stage launch covers all nodes of the stage: grid.y = node, grid.x =
 // blocks along time.  HBM traffic per stereo sample is one read of the input
 // and one write of the output (8 + 8 bytes) in the forward.
+#include <algorithm>
+
 #include "mg_device.h"
 #include "mg_kernels.h"
 
@@ -24,8 +26,7 @@ __device__ __forceinline__ const float* resolve_in(const NodeDesc& d, const floa
 }
 
 __device__ __forceinline__ float wet_of(const NodeDesc& d, const float* wet, const float* mask) {
-  float w = 1.0f / (1.0f + expf(-wet[d.proc]));
-  if (mask) w *= mask[d.proc];
+  float w = node_w(wet, mask, d);
   return w;
 }
 
@@ -256,7 +257,7 @@ __global__ __launch_bounds__(MG_BLOCK) void k_finish_grads(const NodeDesc* __res
     if (threadIdx.x == 0) {
       if (q == 0) {
         const double sg = 1.0 / (1.0 + exp(-(double)wet[d.proc]));
-        const double m = mask ? (double)mask[d.proc] : 1.0;
+        const double m = mask ? (double)mask[d.mrow] : 1.0;
         grad_wet[d.proc] = (float)((s + (double)alpha_p) * sg * (1.0 - sg) * m);
       } else {
         grad_theta[d.theta_off + (q - 1)] = (float)s;
@@ -295,22 +296,33 @@ void launch_reduce_lg(const Ctx& c, int desc_off, int n, int nblocks) {
 // losses[7] = L, La, Llr, Lm, Ls, Lg, Lp.
 // lstats per (resolution, combo): [0] sum |Y|^2, [1] sum |Y - Yh|^2,
 // [2] sum |log diff| / cells.
+// One block per loss record b (the graph itself: one block, sub = nullptr).
+// L_g and L_p run over the graph's nodes in descriptor order; a trial takes
+// node j's energies from lg row sub[j] (its copy, or j itself), so the sums
+// are formed in the same order as for a complete forward with that mask.
 __global__ __launch_bounds__(MG_BLOCK) void k_finalize_losses(double* __restrict__ losses,
                                                                const double* __restrict__ lstats, int n_res,
                                                                const NodeDesc* __restrict__ desc, int n_desc,
                                                                const double* __restrict__ lg,
                                                                const float* __restrict__ wet,
-                                                               const float* __restrict__ mask, float alpha_g,
+                                                               const float* __restrict__ mask, int mask_stride,
+                                                               const int* __restrict__ sub, float alpha_g,
                                                                float alpha_p, const int* __restrict__ lg_flag) {
   __shared__ double red[MG_BLOCK];
+  const int b = blockIdx.x;
+  losses += 7 * b;
+  lstats += 128 * b;
+  if (mask) mask += (int64_t)mask_stride * b;
+  if (sub) sub += (int64_t)n_desc * b;
   double lgs = 0.0, lps = 0.0;
   for (int j = threadIdx.x; j < n_desc; j += MG_BLOCK) {
     const NodeDesc d = desc[j];
     if (d.proc < 0) continue;
     double w = 1.0 / (1.0 + exp(-(double)wet[d.proc]));
-    if (mask) w *= (double)mask[d.proc];
+    if (mask) w *= (double)mask[d.mrow];
     lps += w;
-    if (lg_flag[j]) lgs += fabs(0.5 * log(lg[2 * j] + 1e-12) - 0.5 * log(lg[2 * j + 1] + 1e-12));
+    const int r = sub ? sub[j] : j;
+    if (lg_flag[j]) lgs += fabs(0.5 * log(lg[2 * r] + 1e-12) - 0.5 * log(lg[2 * r + 1] + 1e-12));
   }
   const double Lg = block_sum<MG_BLOCK>(lgs, red);
   const double Lp = block_sum<MG_BLOCK>(lps, red);
@@ -333,12 +345,18 @@ __global__ __launch_bounds__(MG_BLOCK) void k_finalize_losses(double* __restrict
   losses[6] = Lp;
 }
 
-void launch_finalize_losses(const Ctx& c, double* losses, const double* lstats, int n_res, const double* lweights,
-                            int n_desc) {
-  (void)lweights;
+void launch_finalize_losses(const Ctx& c, double* losses, const double* lstats, int n_res, int n_desc) {
   const int* flag = reinterpret_cast<const int*>(c.base + c.g->ws.losses_tmp);
   hipLaunchKernelGGL(k_finalize_losses, dim3(1), dim3(MG_BLOCK), 0, c.st, losses, lstats, n_res, c.desc, n_desc,
-                     c.lg, c.wet, c.mask, c.alpha_g, c.alpha_p, flag);
+                     c.lg, c.wet, c.mask, 0, (const int*)nullptr, c.alpha_g, c.alpha_p, flag);
+}
+
+void launch_finalize_trials(const Ctx& c, double* losses, const double* lstats, int n_res, int n_desc,
+                            const float* mask, int P, const int* sub, int n_trials) {
+  if (n_trials <= 0) return;
+  const int* flag = reinterpret_cast<const int*>(c.base + c.g->ws.losses_tmp);
+  hipLaunchKernelGGL(k_finalize_losses, dim3(n_trials), dim3(MG_BLOCK), 0, c.st, losses, lstats, n_res, c.desc,
+                     n_desc, c.lg, c.wet, mask, P, sub, c.alpha_g, c.alpha_p, flag);
 }
 
 // ---------------------------------------------------------------- Adam
@@ -363,6 +381,21 @@ void launch_adam(float* th, float* m, float* v, const float* g, int64_t n, float
   if (blocks > 4096) blocks = 4096;
   if (blocks < 1) blocks = 1;
   hipLaunchKernelGGL(k_adam, dim3((unsigned)blocks), dim3(MG_BLOCK), 0, st, th, m, v, g, n, lr, b1, b2, eps, c1, c2);
+}
+
+// Trial masks: the mask of the cached forward times each trial's keep flags.
+__global__ void k_trial_mask(float* __restrict__ mask, const float* __restrict__ base,
+                             const float* __restrict__ keep, int P, int B) {
+  const int64_t n = (int64_t)P * B;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    mask[i] = (base ? base[i % P] : 1.0f) * keep[i];
+}
+
+void launch_trial_mask(float* mask, const float* base, const float* keep, int P, int B, hipStream_t st) {
+  const int64_t n = (int64_t)P * B;
+  if (n <= 0) return;
+  const unsigned blocks = (unsigned)std::min<int64_t>((n + MG_BLOCK - 1) / MG_BLOCK, 1024);
+  hipLaunchKernelGGL(k_trial_mask, dim3(blocks), dim3(MG_BLOCK), 0, st, mask, base, keep, P, B);
 }
 
 // Zero fill with a kernel (no memset nodes, so a caller may capture it).

@@ -221,8 +221,7 @@ __global__ __launch_bounds__(MG_BLOCK) void k_dyn_apply(DynView v, const double*
     le[i * DYN_PAD + t] = gst;
   }
   __syncthreads();
-  float w = 1.0f / (1.0f + expf(-v.wet[d.proc]));
-  if (v.mask) w *= v.mask[d.proc];
+  float w = node_w(v.wet, v.mask, d);
   float* y = v.U + (int64_t)d.out_slot * 2 * v.L;
   float* env = v.env ? v.env + (int64_t)(v.env0 + d.aux) * v.L : nullptr;
   for (int idx = threadIdx.x; idx < DYN_CH; idx += MG_BLOCK) {
@@ -272,8 +271,7 @@ __global__ __launch_bounds__(MG_BLOCK) void k_dyn_bsum(DynView v, float* __restr
   __shared__ float red[MG_BLOCK];
   const NodeDesc d = v.desc[blockIdx.y];
   const DynParams q = dyn_params(v.theta + d.theta_off, 0);
-  float w = 1.0f / (1.0f + expf(-v.wet[d.proc]));
-  if (v.mask) w *= v.mask[d.proc];
+  float w = node_w(v.wet, v.mask, d);
   int64_t cs;
   const float* u = dyn_input(v, d, cs);
   const float* dy = v.G + (int64_t)d.gout * 2 * v.L;
@@ -322,8 +320,7 @@ __global__ __launch_bounds__(MG_BLOCK) void k_dyn_bapply(DynView v, const double
   __shared__ float red[MG_BLOCK];
   const NodeDesc d = v.desc[blockIdx.y];
   const DynParams q = dyn_params(v.theta + d.theta_off, 0);
-  float w = 1.0f / (1.0f + expf(-v.wet[d.proc]));
-  if (v.mask) w *= v.mask[d.proc];
+  float w = node_w(v.wet, v.mask, d);
   int64_t cs;
   const float* u = dyn_input(v, d, cs);
   const float* dy = v.G + (int64_t)d.gout * 2 * v.L;
@@ -405,8 +402,7 @@ __global__ __launch_bounds__(64) void k_dyn_ar_fwd(DynView v) {
   __shared__ float le[AR_CH];
   const NodeDesc d = v.desc[blockIdx.x];
   const DynParams q = dyn_params(v.theta + d.theta_off, 1);
-  float w = 1.0f / (1.0f + expf(-v.wet[d.proc]));
-  if (v.mask) w *= v.mask[d.proc];
+  float w = node_w(v.wet, v.mask, d);
   int64_t cs;
   const float* u = dyn_input(v, d, cs);
   float* y = v.U + (int64_t)d.out_slot * 2 * v.L;
@@ -451,8 +447,7 @@ __global__ __launch_bounds__(64) void k_dyn_ar_bwd(DynView v) {
   __shared__ float red[64];
   const NodeDesc d = v.desc[blockIdx.x];
   const DynParams q = dyn_params(v.theta + d.theta_off, 1);
-  float w = 1.0f / (1.0f + expf(-v.wet[d.proc]));
-  if (v.mask) w *= v.mask[d.proc];
+  float w = node_w(v.wet, v.mask, d);
   int64_t cs;
   const float* u = dyn_input(v, d, cs);
   const float* dy = v.G + (int64_t)d.gout * 2 * v.L;
@@ -530,7 +525,7 @@ static DynView dyn_view(const Ctx& c, int type, int desc_off) {
   v.dry = c.dry;
   v.U = c.U;
   v.G = c.G;
-  v.env = g->mode ? wsp<float>(c, g->ws.ENV) : nullptr;
+  v.env = (g->mode && !c.trial) ? wsp<float>(c, g->ws.ENV) : nullptr;
   v.theta = c.theta;
   v.wet = c.wet;
   v.mask = c.mask;

@@ -87,8 +87,7 @@ __global__ __launch_bounds__(MG_BLOCK) void k_eq_fwd(EqArgs a) {
   for (int i = threadIdx.x; i < EQ_P; i += MG_BLOCK) buf[i] = c_scale(buf[i], H[i] * (1.0f / EQ_P));
   __syncthreads();
   fft_lds<EQ_P, 1, EQ_P, MG_BLOCK, +1>(buf, a.tw);
-  float w = 1.0f / (1.0f + expf(-a.wet[d.proc]));
-  if (a.mask) w *= a.mask[d.proc];
+  float w = node_w(a.wet, a.mask, d);
   float* y = a.Uo + (int64_t)d.out_slot * 2 * a.L;
   float* yb = a.ybar ? a.ybar + (int64_t)d.aux * 2 * a.L : nullptr;
   float ey = 0.f, eu = 0.f;
@@ -129,8 +128,7 @@ __global__ __launch_bounds__(MG_BLOCK) void k_eq_bwd(EqArgs a) {
   const int64_t s0 = (int64_t)blk * a.V - half;
   const float* dy = a.G + (int64_t)d.gout * 2 * a.L;
   const float* yb = a.ybar + (int64_t)d.aux * 2 * a.L;
-  float w = 1.0f / (1.0f + expf(-a.wet[d.proc]));
-  if (a.mask) w *= a.mask[d.proc];
+  float w = node_w(a.wet, a.mask, d);
   const double Ey = a.lg[2 * j] + 1e-12, Eu = a.lg[2 * j + 1] + 1e-12;
   const double diff = 0.5 * log(Ey) - 0.5 * log(Eu);
   const double sgn = diff > 0 ? 1.0 : (diff < 0 ? -1.0 : 0.0);
@@ -234,7 +232,7 @@ int eq_blocks(const mg_graph* g) {
 
 void eq_forward(const Ctx& c, int desc_off, int n, bool keep) {
   EqArgs a = eq_args(c, desc_off, keep);
-  {
+  if (!c.trial) {
     ProfScope ps(c, "eq_spec", (double)n * (4.0 * a.N + 4.0 * EQ_P));
     hipLaunchKernelGGL(k_eq_spec, dim3(n), dim3(MG_BLOCK), 0, c.st, a);
   }

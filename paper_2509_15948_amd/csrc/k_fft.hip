@@ -134,8 +134,7 @@ struct LdGrad {
     u = node_input(v, d, cs);
     dy = v.G + (int64_t)d.gout * 2 * v.L;
     yb = ybar_base + (int64_t)(yb0 + d.aux) * 2 * v.L;
-    w = 1.0f / (1.0f + expf(-wet[d.proc]));
-    if (mask) w *= mask[d.proc];
+    w = node_w(wet, mask, d);
     const double Ey = lg[2 * j] + 1e-12, Eu = lg[2 * j + 1] + 1e-12;
     const double diff = 0.5 * log(Ey) - 0.5 * log(Eu);
     const double s = diff > 0 ? 1.0 : (diff < 0 ? -1.0 : 0.0);
@@ -177,8 +176,7 @@ struct StFwd {
     u = node_input(v, d, cs);
     y = const_cast<float*>(v.U) + (int64_t)d.out_slot * 2 * v.L;
     yb = ybar_base ? ybar_base + (int64_t)(yb0 + d.aux) * 2 * v.L : nullptr;
-    w = 1.0f / (1.0f + expf(-wet[d.proc]));
-    if (mask) w *= mask[d.proc];
+    w = node_w(wet, mask, d);
     ey = eu = 0.f;
   }
   __device__ void store(int64_t n, float2 val) {
@@ -224,8 +222,7 @@ struct StGradU {
     gin = active ? const_cast<float*>(v.G) + (int64_t)d.gin * 2 * v.L : nullptr;
     dy = v.G + (int64_t)d.gout * 2 * v.L;
     u = node_input(v, d, cs);
-    w = 1.0f / (1.0f + expf(-wet[d.proc]));
-    if (mask) w *= mask[d.proc];
+    w = node_w(wet, mask, d);
     const double Ey = lg[2 * j] + 1e-12, Eu = lg[2 * j + 1] + 1e-12;
     const double diff = 0.5 * log(Ey) - 0.5 * log(Eu);
     const double s = diff > 0 ? 1.0 : (diff < 0 ? -1.0 : 0.0);
@@ -403,12 +400,13 @@ __global__ __launch_bounds__(MG_BLOCK) void k_rows_conv(const float2* __restrict
   fft_lds<N1, 2, N1, MG_BLOCK, -1>(buf, ea.tw);
   const int64_t zr = (int64_t)(z0 + desc[j].aux) * ea.N;
   const float2* H = ZH + zr;
-  if (ZU) {
+  if (ZU) {  // keep the input spectrum for the backward
     float2* Zs = ZU + zr;
     for (int i = threadIdx.x; i < N1; i += MG_BLOCK) {
       Zs[(int64_t)ra * N1 + i] = buf[i];
       Zs[(int64_t)rb * N1 + i] = buf[N1 + i];
     }
+    __syncthreads();  // every bin stored before the product below overwrites it
   }
   for (int q = threadIdx.x; q < N1 + 1; q += MG_BLOCK) {
     int ia, ib;

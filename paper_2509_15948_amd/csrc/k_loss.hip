@@ -139,9 +139,13 @@ __global__ __launch_bounds__(MG_BLOCK) void k_loss_fwd(LossArgs a) {
 
 // stats[x][0] = sum Y^2 (MODE 0), [1] = sum (Y - Yh)^2, [2] = sum|dlog| / cells
 // (fixed order: strided per thread, then a tree)
+// tgt: the target's statistics of this resolution (setup), copied into a
+// separate record (pruning trials) so that it is complete on its own.
 __global__ __launch_bounds__(MG_BLOCK) void k_loss_reduce(const double* __restrict__ part, int nblocks, int cells,
-                                                           int mode, double* __restrict__ stats) {
+                                                           int mode, double* __restrict__ stats,
+                                                           const double* __restrict__ tgt) {
   __shared__ double red[MG_BLOCK];
+  if (mode == 1 && tgt != stats && threadIdx.x < 4) stats[threadIdx.x * 4 + 0] = tgt[threadIdx.x * 4 + 0];
   for (int q = 0; q < 8; ++q) {
     double s = 0.0;
     for (int b = threadIdx.x; b < nblocks; b += MG_BLOCK) s += part[(int64_t)b * 8 + q];
@@ -415,9 +419,9 @@ static void bwd_n(const Ctx& c, const LossArgs& a, int blocks) {
     case 4096: CALL(4096); break;  \
   }
 
-static void run_loss_fwd(const Ctx& c, const float* y, int mode) {
+static void run_loss_fwd(const Ctx& c, const float* y, int mode, double* stats_out) {
   const mg_graph* g = c.g;
-  double* stats = wsp<double>(c, g->ws.ls_stats);
+  double* stats = stats_out ? stats_out : wsp<double>(c, g->ws.ls_stats);
   for (size_t i = 0; i < g->lres.size(); ++i) {
     const LossRes& r = g->lres[i];
     LossArgs a = loss_args(c, (int)i, y);
@@ -433,7 +437,7 @@ static void run_loss_fwd(const Ctx& c, const float* y, int mode) {
 #undef MG_F0
 #undef MG_F1
     hipLaunchKernelGGL(k_loss_reduce, dim3(1), dim3(MG_BLOCK), 0, c.st, a.part, blocks, r.frames * g->cfg.n_mels, mode,
-                       stats + i * 16);
+                       stats + i * 16, wsp<double>(c, g->ws.ls_stats) + i * 16);
   }
 }
 
@@ -446,12 +450,12 @@ void loss_setup(const Ctx& c, const float* target) {
     hipStreamSynchronize(c.st);
   }
   launch_zero(c.base + g->ws.ls_stats, 8 * sizeof(double) * 16, c.st);
-  run_loss_fwd(c, target, 0);
+  run_loss_fwd(c, target, 0, nullptr);
 }
 
-void loss_forward(const Ctx& c, const float* yhat) {
+void loss_forward(const Ctx& c, const float* yhat, double* stats) {
   ProfScope ps(c, "loss", 8.0 * c.L);
-  run_loss_fwd(c, yhat, 1);
+  run_loss_fwd(c, yhat, 1, stats);
 }
 
 void loss_backward(const Ctx& c, const float* yhat, float* dyhat) {

@@ -4,6 +4,8 @@
 // pruning evaluation (Alg. 2 Evaluate) and Adam.  All work is enqueued on
 // the caller's stream; nothing here allocates device memory.
 #include <algorithm>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 
@@ -36,10 +38,19 @@ static size_t plan_ws(mg_graph& g, int mode, bool commit) {
   const int n_conv = n_eq + n_dl + n_rv;
   const int n_dyn = g.type_count[MG_COMP] + g.type_count[MG_GATE];
   const int64_t N = g.fft.N;
-  take(w.desc, std::max<size_t>(1, n_desc) * sizeof(NodeDesc));
-  take(w.srcs, std::max<size_t>(1, g.srcs.size() + g.gsrcs.size()) * sizeof(SrcRef));
+  const int n_win = n_desc + g.trial_slots;   // descriptors incl. the trial window
+  const int P = g.n_proc, Bt = c.max_trials;
+  take(w.desc, std::max<size_t>(1, n_win) * sizeof(NodeDesc));
+  take(w.srcs, std::max<size_t>(1, g.n_src_base + g.trial_src_cap) * sizeof(SrcRef));
   take(w.losses_tmp, std::max(1, n_desc) * sizeof(int));
-  take(w.U, (size_t)g.n_uslots * 2 * L * 4);
+  take(w.U, (size_t)(g.n_uslots + g.trial_slots) * 2 * L * 4);
+  if (Bt > 0) {
+    take(w.tr_desc, (size_t)std::max(1, g.trial_desc_cap) * sizeof(NodeDesc));
+    take(w.tr_keep, (size_t)Bt * std::max(1, P) * 4);
+    take(w.tr_mask, (size_t)Bt * std::max(1, P) * 4);
+    take(w.tr_sub, (size_t)Bt * std::max(1, n_desc) * 4);
+    take(w.tr_stats, (size_t)Bt * 128 * 8);
+  }
   if (mode) {
     take(w.YB, (size_t)n_conv * 2 * L * 4);
     take(w.ENV, (size_t)n_dyn * L * 4);
@@ -86,8 +97,8 @@ static size_t plan_ws(mg_graph& g, int mode, bool commit) {
     take(w.cmp_sum, (size_t)std::max(1, g.max_stage) * g.dyn_chunks * 4);
     take(w.cmp_carry, (size_t)std::max(1, g.max_stage) * g.dyn_chunks * 8);
   }
-  take(w.part, (size_t)std::max(1, n_desc) * g.part_blocks * PK * 4);
-  take(w.lg, (size_t)std::max(1, n_desc) * 2 * 8);
+  take(w.part, (size_t)std::max(1, n_win) * g.part_blocks * PK * 4);
+  take(w.lg, (size_t)std::max(1, n_win) * 2 * 8);
   take(w.ls_stats, 8 * 16 * 8);
   for (auto& r : g.lres) {
     const int FPB = r.nfft >= 2048 ? 1 : 2048 / r.nfft;
@@ -112,7 +123,38 @@ static size_t plan_ws(mg_graph& g, int mode, bool commit) {
   return o;
 }
 
+// U slots that bypassing processor v costs a trial: every node downstream of
+// v, plus an input sum for each downstream processor with several inputs.
+static int suffix_slots(const mg_graph& g, int v) {
+  std::vector<char> seen(g.n_nodes, 0);
+  std::vector<int> stack(g.succs[v].begin(), g.succs[v].end());
+  int n = 0;
+  while (!stack.empty()) {
+    const int u = stack.back();
+    stack.pop_back();
+    if (seen[u]) continue;
+    seen[u] = 1;
+    n += 1 + ((is_proc(g.type[u]) && g.preds[u].size() > 1) ? 1 : 0);
+    for (int s : g.succs[u]) stack.push_back(s);
+  }
+  return n;
+}
+
 static void finish_compile(mg_graph& g) {
+  g.n_src_base = (int)(g.srcs.size() + g.gsrcs.size());
+  const int Bt = std::max(0, g.cfg.max_trials);
+  if (Bt > 0) {
+    int per = 1;
+    for (int v = 0; v < g.n_nodes; ++v)
+      if (is_proc(g.type[v])) per = std::max(per, suffix_slots(g, v));
+    g.trial_slots = g.cfg.trial_slots > 0 ? g.cfg.trial_slots : Bt * per;
+    int64_t n_edges = 0;
+    for (int v = 0; v < g.n_nodes; ++v) n_edges += (int64_t)g.preds[v].size();
+    g.trial_desc_cap = Bt * g.n_nodes;
+    g.trial_src_cap = (int)(Bt * n_edges);
+  } else {
+    g.trial_slots = g.trial_desc_cap = g.trial_src_cap = 0;
+  }
   g.dyn_chunks = (int)((g.cfg.length + 4095) / 4096);
   int pb = 128;
   if (g.fft.N > 0) pb = std::max(pb, g.fft.N / 8192);
@@ -121,7 +163,7 @@ static void finish_compile(mg_graph& g) {
   g.part_blocks = pb;
 }
 
-static Ctx make_ctx(const mg_graph* g, hipStream_t st) {
+Ctx make_ctx(const mg_graph* g, hipStream_t st) {
   Ctx c;
   c.g = g;
   c.st = st;
@@ -144,40 +186,50 @@ static Ctx make_ctx(const mg_graph* g, hipStream_t st) {
   return c;
 }
 
+// Forward of the nodes [off, off + n) of one stage of type t; hd are the host
+// copies of those descriptors.  Trial copies (c.trial) reuse the FIR tables
+// and spectra of the last forward and run in pieces no larger than the
+// graph's own largest stage, which sizes the per-launch temporaries.
+void forward_stage(const Ctx& c, int t, int off, int n, bool keep, const NodeDesc* hd) {
+  const mg_graph* g = c.g;
+  if (n <= 0) return;
+  if (t == MG_MIX || t == MG_OUT) {
+    launch_sum(c, off, n, c.srcs, c.U, 0);
+    return;
+  }
+  // processors whose input is a sum of several nodes: gather it first
+  bool any_sum = false;
+  for (int j = 0; j < n; ++j)
+    if (hd[j].src_count > 0) any_sum = true;
+  if (any_sum) launch_sum(c, off, n, c.srcs, c.U, 2);
+  if (t == MG_GAINPAN || t == MG_IMAGER || t == MG_DIST) {
+    launch_pointwise_fwd(c, t, off, n);
+  } else if (t == MG_COMP || t == MG_GATE) {
+    const int cap = std::max(1, g->max_stage);
+    for (int j = 0; j < n; j += cap) dyn_forward(c, t, off + j, std::min(cap, n - j));
+  } else if (t == MG_EQ) {
+    if (!c.trial) fir_synth(c, t, off, n);
+    eq_forward(c, off, n, keep);
+  } else if (is_conv(t)) {
+    if (!c.trial) {
+      fir_synth(c, t, off, n);
+      conv_fir_spectrum(c, t, off, n);
+    }
+    const int cap = std::max(1, g->max_conv_stage);
+    for (int j = 0; j < n; j += cap) conv_forward(c, t, off + j, std::min(cap, n - j), keep);
+  }
+}
+
 static void run_forward(mg_graph* g, hipStream_t st, bool keep, double* losses, float* mix) {
   Ctx c = make_ctx(g, st);
   const int n_desc = (int)g->desc.size();
   for (size_t s = 1; s < g->stages.size(); ++s) {
     const Stage& S = g->stages[s];
-    const int n = (int)S.nodes.size();
-    const int off = S.desc_off;
-    const int t = S.type;
-    if (t == MG_MIX || t == MG_OUT) {
-      launch_sum(c, off, n, c.srcs, c.U, 0);
-      continue;
-    }
-    // processors whose input is a sum of several nodes: gather it first
-    bool any_sum = false;
-    for (int j = 0; j < n; ++j)
-      if (g->desc[off + j].src_count > 0) any_sum = true;
-    if (any_sum) launch_sum(c, off, n, c.srcs, c.U, 2);
-    if (t == MG_GAINPAN || t == MG_IMAGER || t == MG_DIST) {
-      launch_pointwise_fwd(c, t, off, n);
-    } else if (t == MG_COMP || t == MG_GATE) {
-      dyn_forward(c, t, off, n);
-    } else if (t == MG_EQ) {
-      fir_synth(c, t, off, n);
-      eq_forward(c, off, n, keep);
-    } else if (is_conv(t)) {
-      fir_synth(c, t, off, n);
-      conv_fir_spectrum(c, t, off, n);
-      conv_forward(c, t, off, n, keep);
-    }
+    forward_stage(c, S.type, S.desc_off, (int)S.nodes.size(), keep, g->desc.data() + S.desc_off);
   }
   const float* yhat = c.U + (int64_t)g->uslot[g->output_node] * 2 * c.L;
   loss_forward(c, yhat);
-  launch_finalize_losses(c, losses, (const double*)(g->base + g->ws.ls_stats), (int)g->lres.size(), nullptr,
-                         n_desc);
+  launch_finalize_losses(c, losses, (const double*)(g->base + g->ws.ls_stats), (int)g->lres.size(), n_desc);
   if (mix) hipMemcpyAsync(mix, yhat, (size_t)2 * c.L * 4, hipMemcpyDeviceToDevice, st);
 }
 
@@ -206,6 +258,7 @@ extern "C" int mg_setup(mg_graph* g, void* workspace, size_t workspace_bytes, in
   g->ws_bytes = workspace_bytes;
   g->mode = mode;
   g->have_forward = false;
+  g->have_cache = false;
   // descriptor tables
   std::vector<SrcRef> all = g->srcs;
   all.insert(all.end(), g->gsrcs.begin(), g->gsrcs.end());
@@ -235,6 +288,19 @@ extern "C" int mg_setup(mg_graph* g, void* workspace, size_t workspace_bytes, in
   if ((rc = hip_check(hipStreamSynchronize(st), "setup"))) return rc;
   if ((rc = hip_check(hipGetLastError(), "setup launch"))) return rc;
   g->ready = true;
+  if (getenv("MG_PRINT_LAYOUT")) {  // diagnostics: byte offsets of the workspace regions
+    const WsPlan& w = g->ws;
+    const std::pair<const char*, size_t> r[] = {
+        {"desc", w.desc}, {"srcs", w.srcs}, {"U", w.U}, {"YB", w.YB}, {"ENV", w.ENV}, {"G", w.G},
+        {"ZH", w.ZH}, {"ZU", w.ZU}, {"T1", w.T1}, {"T2", w.T2}, {"T3", w.T3}, {"twhi", w.twhi},
+        {"twlo", w.twlo}, {"tw", w.tw}, {"twd", w.twd}, {"eq_h", w.eq_h}, {"eq_HP", w.eq_HP},
+        {"eq_dh", w.eq_dh}, {"eq_dhp", w.eq_dhp}, {"eq_cos", w.eq_cos}, {"dl_tab", w.dl_tab},
+        {"dl_dh", w.dl_dh}, {"dl_cos", w.dl_cos}, {"rv_U", w.rv_U}, {"rv_fr", w.rv_fr}, {"rv_h", w.rv_h},
+        {"rv_dh", w.rv_dh}, {"rv_dM", w.rv_dM}, {"rv_cs", w.rv_cs}, {"rv_win", w.rv_win},
+        {"rv_wsum", w.rv_wsum}, {"cmp_sum", w.cmp_sum}, {"cmp_carry", w.cmp_carry}, {"part", w.part},
+        {"lg", w.lg}, {"ls_stats", w.ls_stats}, {"ls_part", w.ls_part}, {"total", w.total}};
+    for (const auto& x : r) fprintf(stderr, "mg layout %s %zu\n", x.first, x.second);
+  }
   return MG_OK;
 }
 
@@ -250,6 +316,7 @@ extern "C" int mg_forward(mg_graph* g, const float* dry, const float* theta, con
   int rc = hip_check(hipGetLastError(), "forward launch");
   if (rc) return rc;
   g->have_forward = (g->mode == 1);
+  g->have_cache = true;
   return MG_OK;
 }
 
@@ -265,6 +332,7 @@ extern "C" int mg_forward_masked(mg_graph* g, const float* dry, const float* the
     run_forward(g, (hipStream_t)stream, false, losses + (int64_t)b * 7, nullptr);
   }
   g->have_forward = false;
+  g->have_cache = false;
   return hip_check(hipGetLastError(), "masked forward launch");
 }
 

@@ -220,6 +220,7 @@ int compile(mg_graph& g) {
       NodeDesc d{};
       d.node = v;
       d.proc = g.proc_idx[v];
+      d.mrow = d.proc;
       d.out_slot = g.uslot[v];
       d.aux = g.type_row[v];
       d.theta_off = g.param_off[v] < 0 ? 0 : g.param_off[v];
@@ -333,6 +334,8 @@ int validate_config(const mg_config& c, const std::vector<int>& type) {
   }
   if (c.n_mels < 1 || c.n_mels > 128) return fail(MG_ERR_INVALID_ARG, "n_mels must be in [1, 128]");
   if (c.loss_skip < 0) return fail(MG_ERR_INVALID_ARG, "loss_skip must be >= 0");
+  if (c.max_trials < 0 || c.max_trials > 4096) return fail(MG_ERR_INVALID_ARG, "max_trials must be in [0, 4096]");
+  if (c.trial_slots < 0) return fail(MG_ERR_INVALID_ARG, "trial_slots must be >= 0");
   return MG_OK;
 }
 
@@ -426,8 +429,10 @@ extern "C" int mg_graph_create(int32_t n_nodes, const int32_t* types, int32_t n_
 }
 
 extern "C" int mg_graph_destroy(mg_graph* g) {
-  if (g)
+  if (g) {
     for (auto& e : g->prof.ev) (void)hipEventDestroy(e);
+    if (g->trial_ev) (void)hipEventDestroy(g->trial_ev);
+  }
   delete g;
   return MG_OK;
 }

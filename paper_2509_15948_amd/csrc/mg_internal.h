@@ -35,6 +35,8 @@ struct NodeDesc {
   int64_t theta_off;  // offset of the parameter row in theta
   int32_t src_begin;  // m/o/sum: range in the source list
   int32_t src_count;
+  int32_t mrow;       // index of the node's entry in the mask vector (proc for
+                      // the graph itself, trial * P + proc for a trial copy)
 };
 
 // One source of a sum: kind 0 dry track, 1 U slot, 2 gradient slot
@@ -71,6 +73,27 @@ struct WsPlan {
   size_t ls_stats = 0;       // double: per (res, combo): |Y|^2, |Y-Yh|^2, sum|dlog|
   size_t lg = 0;             // double per node: E_ybar, E_u
   size_t losses_tmp = 0;
+  // pruning trials (mg_forward_trials)
+  size_t tr_desc = 0;        // staged copy descriptors of every batch
+  size_t tr_keep = 0;        // float [max_trials][P] keep flags
+  size_t tr_mask = 0;        // float [max_trials][P] trial masks
+  size_t tr_sub = 0;         // int [max_trials][n_desc]: lg row used for each node
+  size_t tr_stats = 0;       // double [max_trials][8][16] loss statistics
+};
+
+// Host tables of one mg_forward_trials call.
+struct TrialPlan {
+  std::vector<NodeDesc> desc;          // copies, batch by batch, stage-major inside a batch
+  std::vector<SrcRef> srcs;            // sources of the copies' sums
+  std::vector<float> keep;             // [B][P]
+  std::vector<int32_t> sub;            // [B][n_desc]
+  struct Batch {
+    int t0, t1;                        // trials [t0, t1)
+    int d0;                            // first copy in desc
+    std::vector<int> stage_off, stage_n;  // per stage: copy range inside the batch
+    std::vector<int> out_slot;         // per trial: U slot of its mix
+  };
+  std::vector<Batch> batches;
 };
 
 // Optional timing of one kernel class (measurement only): HIP events are
@@ -133,6 +156,15 @@ struct mg_graph {
   int mode = 0;
   bool ready = false;
   bool have_forward = false;
+  bool have_cache = false;                // node outputs of the last forward are in U
+  // pruning trials
+  int trial_slots = 0;                    // U slots reserved for copies
+  int trial_desc_cap = 0;                 // staged copy descriptors
+  int trial_src_cap = 0;                  // staged copy sources
+  int n_src_base = 0;                     // srcs + gsrcs of the graph itself
+  mg::TrialPlan tplan;
+  hipEvent_t trial_ev = nullptr;          // upload of tplan done
+  bool trial_ev_pending = false;
   mg::Profiler prof;
   // last forward's inputs (for backward)
   const float* f_dry = nullptr;

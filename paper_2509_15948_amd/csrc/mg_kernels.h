@@ -24,7 +24,17 @@ struct Ctx {
   double* lg;            // per desc: E_ybar, E_u (double)
   float alpha_g, alpha_p;
   char* base;            // workspace base
+  bool trial = false;    // pruning-trial copies: keep no backward state, reuse
+                         // the FIR tables and spectra of the last forward
 };
+
+// effective dry/wet weight w = sigmoid(logit) * mask (Sec. 5.1 and the masked
+// evaluation of Alg. 2); the same FP32 expression in every kernel
+__device__ __forceinline__ float node_w(const float* wet, const float* mask, const NodeDesc& d) {
+  float w = 1.0f / (1.0f + expf(-wet[d.proc]));
+  if (mask) w *= mask[d.mrow];
+  return w;
+}
 
 template <typename T>
 inline T* wsp(const Ctx& c, size_t off) {
@@ -51,6 +61,10 @@ struct ProfScope {
   }
 };
 
+// mg_api.hip
+Ctx make_ctx(const mg_graph* g, hipStream_t st);
+void forward_stage(const Ctx& c, int t, int off, int n, bool keep, const NodeDesc* hd);
+
 // k_basic.hip
 void launch_sum(const Ctx& c, int desc_off, int n, const SrcRef* srcs, float* out_base, int dest_kind);
 void launch_pointwise_fwd(const Ctx& c, int type, int desc_off, int n);
@@ -58,11 +72,15 @@ void launch_pointwise_bwd(const Ctx& c, int type, int desc_off, int n);
 void launch_finish_grads(const Ctx& c, int desc_off, int n, int nblocks, int nparams, float* grad_theta,
                          float* grad_wet);
 void launch_reduce_lg(const Ctx& c, int desc_off, int n, int nblocks);
-void launch_finalize_losses(const Ctx& c, double* losses, const double* lstats, int n_res, const double* lweights,
-                            int n_desc);
+void launch_finalize_losses(const Ctx& c, double* losses, const double* lstats, int n_res, int n_desc);
+// one block per trial b: losses + 7 b, lstats + 128 b, mask + P b, sub + n_desc b
+void launch_finalize_trials(const Ctx& c, double* losses, const double* lstats, int n_res, int n_desc,
+                            const float* mask, int P, const int* sub, int n_trials);
 void launch_adam(float* th, float* m, float* v, const float* g, int64_t n, float lr, float b1, float b2, float eps,
                  int step, hipStream_t st);
 void launch_zero(void* p, size_t bytes, hipStream_t st);
+// mask[b][p] = (base ? base[p] : 1) * keep[b][p]
+void launch_trial_mask(float* mask, const float* base, const float* keep, int P, int B, hipStream_t st);
 
 // k_fft.hip: the FIR convolution engine
 void fft_init_tables(const Ctx& c, float2* tw, float2* twhi, float2* twlo, int N, hipStream_t st);
@@ -73,7 +91,7 @@ void conv_backward(const Ctx& c, int type, int desc_off, int n);
 
 // k_eq.hip: equalizer by overlap-save in LDS
 int eq_blocks(const mg_graph* g);
-void eq_forward(const Ctx& c, int desc_off, int n, bool keep);
+void eq_forward(const Ctx& c, int desc_off, int n, bool keep);  // c.trial: reuse the block spectra
 void eq_backward(const Ctx& c, int desc_off, int n);
 
 // k_fir.hip: FIR synthesis and adjoints
@@ -87,7 +105,9 @@ void dyn_backward(const Ctx& c, int type, int desc_off, int n);
 
 // k_loss.hip
 void loss_setup(const Ctx& c, const float* target);
-void loss_forward(const Ctx& c, const float* yhat);
+// stats: per-resolution statistics output (nullptr: the graph's own, which
+// the backward reads)
+void loss_forward(const Ctx& c, const float* yhat, double* stats = nullptr);
 void loss_backward(const Ctx& c, const float* yhat, float* dyhat);
 
 }  // namespace mg

@@ -31,6 +31,7 @@ class mg_config(ctypes.Structure):
                 ("delay_fir_taps", ctypes.c_int32), ("reverb_length", ctypes.c_int32),
                 ("reverb_nfft", ctypes.c_int32), ("reverb_hop", ctypes.c_int32), ("n_loss_ffts", ctypes.c_int32),
                 ("loss_ffts", ctypes.c_int32 * 8), ("n_mels", ctypes.c_int32), ("loss_skip", ctypes.c_int32),
+                ("max_trials", ctypes.c_int32), ("trial_slots", ctypes.c_int32),
                 ("alpha_g", ctypes.c_double), ("alpha_p", ctypes.c_double)]
 
 
@@ -44,7 +45,8 @@ _lib = None
 
 EXPORTS = ("mg_graph_create", "mg_graph_destroy", "mg_graph_info", "mg_graph_layout", "mg_workspace_size",
            "mg_setup", "mg_forward", "mg_backward", "mg_forward_masked", "mg_adam_step", "mg_graph_prune",
-           "mg_last_error", "mg_profile_enable", "mg_profile_read")
+           "mg_last_error", "mg_profile_enable", "mg_profile_read", "mg_forward_trials", "mg_prune_candidates",
+           "mg_prune_order", "mg_prune_accept")
 
 
 def lib() -> ctypes.CDLL:
@@ -71,6 +73,10 @@ def lib() -> ctypes.CDLL:
         "mg_adam_step": [vp, vp, vp, vp, i64, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float,
                          i32, vp],
         "mg_graph_prune": [vp, vp, ctypes.POINTER(vp), vp],
+        "mg_forward_trials": [vp, vp, i32, vp, vp],
+        "mg_prune_candidates": [i32, vp, vp, vp, i32, vp, vp],
+        "mg_prune_order": [i32, vp, vp, ctypes.c_double, ctypes.c_double, vp, vp],
+        "mg_prune_accept": [i32, vp, ctypes.c_double, ctypes.c_double, vp],
         "mg_profile_enable": [vp, ctypes.c_char_p],
         "mg_profile_read": [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64),
                             ctypes.POINTER(ctypes.c_double)],
@@ -100,7 +106,8 @@ def _ptr(a) -> Optional[int]:
 def make_config(length: int, sample_rate: int, eq_taps: int = 2047, comp_mode: int = 0, delay_taps: int = 4,
                 delay_range: int = 5512, delay_fir_taps: int = 39, reverb_length: int = 66150,
                 reverb_nfft: int = 384, reverb_hop: int = 192, loss_ffts: Sequence[int] = (512, 1024, 2048),
-                n_mels: int = 96, loss_skip: int = 0, alpha_g: float = 1e-3, alpha_p: float = 0.0) -> mg_config:
+                n_mels: int = 96, loss_skip: int = 0, alpha_g: float = 1e-3, alpha_p: float = 0.0,
+                max_trials: int = 0, trial_slots: int = 0) -> mg_config:
     c = mg_config()
     c.length = length
     c.sample_rate = sample_rate
@@ -117,6 +124,8 @@ def make_config(length: int, sample_rate: int, eq_taps: int = 2047, comp_mode: i
         c.loss_ffts[i] = n
     c.n_mels = n_mels
     c.loss_skip = loss_skip
+    c.max_trials = max_trials
+    c.trial_slots = trial_slots
     c.alpha_g = alpha_g
     c.alpha_p = alpha_p
     return c
@@ -174,6 +183,39 @@ def mg_backward(g: int, grad_theta, grad_wet, stream: int) -> None:
 
 def mg_forward_masked(g: int, dry, theta, wet, masks, B: int, losses, stream: int) -> None:
     _check(lib().mg_forward_masked(g, _ptr(dry), _ptr(theta), _ptr(wet), _ptr(masks), B, _ptr(losses), stream))
+
+
+def mg_forward_trials(g: int, keep: np.ndarray, losses, stream: int) -> None:
+    k = np.ascontiguousarray(keep, dtype=np.uint8)
+    _check(lib().mg_forward_trials(g, k.ctypes.data, k.shape[0], _ptr(losses), stream))
+
+
+def mg_prune_candidates(wet: np.ndarray, mask: Optional[np.ndarray], alive: np.ndarray, max_n: int) -> np.ndarray:
+    we = np.ascontiguousarray(wet, dtype=np.float32)
+    m = None if mask is None else np.ascontiguousarray(mask, dtype=np.float32)
+    a = np.ascontiguousarray(alive, dtype=np.uint8)
+    out = np.zeros(max(1, max_n), np.int32)
+    n = ctypes.c_int32()
+    _check(lib().mg_prune_candidates(len(we), we.ctypes.data, None if m is None else m.ctypes.data, a.ctypes.data,
+                                     max_n, out.ctypes.data, ctypes.byref(n)))
+    return out[:n.value].copy()
+
+
+def mg_prune_order(cand: np.ndarray, L_cand: np.ndarray, L_min: float, tau: float) -> np.ndarray:
+    c = np.ascontiguousarray(cand, dtype=np.int32)
+    lc = np.ascontiguousarray(L_cand, dtype=np.float64)
+    out = np.zeros(max(1, len(c)), np.int32)
+    n = ctypes.c_int32()
+    _check(lib().mg_prune_order(len(c), c.ctypes.data, lc.ctypes.data, L_min, tau, out.ctypes.data,
+                                ctypes.byref(n)))
+    return out[:n.value].copy()
+
+
+def mg_prune_accept(L_prefix: np.ndarray, L_min: float, tau: float) -> int:
+    lp = np.ascontiguousarray(L_prefix, dtype=np.float64)
+    k = ctypes.c_int32()
+    _check(lib().mg_prune_accept(len(lp), lp.ctypes.data if len(lp) else None, L_min, tau, ctypes.byref(k)))
+    return k.value
 
 
 def mg_adam_step(theta, m, v, grad, n: int, lr: float, b1: float, b2: float, eps: float, step: int,
@@ -302,6 +344,56 @@ class Session:
 
     def forward_masked(self, dry, theta, wet, masks, losses):
         mg_forward_masked(self.g.h, dry, theta, wet, masks, masks.shape[0], losses, self.stream())
+
+    def forward_trials(self, keep: np.ndarray, losses):
+        """keep: host uint8 [B][P]; losses: device float64 [B][7]."""
+        mg_forward_trials(self.g.h, keep, losses, self.stream())
+
+
+def prune_round(session: Session, dry, theta, wet, mask=None, tau: float = 1e-3, max_candidates: int = 64,
+                L_min: Optional[float] = None):
+    """One pruning round (Alg. 2 with batched trials): a forward at the
+    current mask, single-bypass trials of the candidates, prefix trials of
+    those within tolerance, and the accept step; the rule itself is the C
+    library's (mg_prune_candidates / mg_prune_order / mg_prune_accept) and
+    every loss comes from the device.  mask: device float [P] or None.
+    Returns a dict with the new alive vector, the new L_min and the trace."""
+    torch = session.torch
+    P = session.g.n_proc
+    out = torch.zeros(7, dtype=torch.float64, device=theta.device)
+    session.forward(dry, theta, wet, mask, None, out)
+    torch.cuda.synchronize()
+    La = float(out[1].item())
+    L_min = La if L_min is None else float(L_min)
+    mask_h = None if mask is None else mask.detach().cpu().numpy().astype(np.float32)
+    alive = np.ones(P, np.uint8) if mask_h is None else (mask_h != 0).astype(np.uint8)
+    wet_h = wet.detach().cpu().numpy().astype(np.float32)
+    cand = mg_prune_candidates(wet_h, mask_h, alive, max_candidates)
+    evaluated = []
+    L_cand = np.zeros(0)
+    if len(cand):
+        keep = np.ones((len(cand), P), np.uint8)
+        keep[np.arange(len(cand)), cand] = 0
+        res = torch.zeros(len(cand), 7, dtype=torch.float64, device=theta.device)
+        session.forward_trials(keep, res)
+        L_cand = res[:, 1].cpu().numpy()
+        evaluated += [((alive & keep[i]).tolist(), float(L_cand[i])) for i in range(len(cand))]
+    order = mg_prune_order(cand, L_cand, L_min, tau) if len(cand) else np.zeros(0, np.int32)
+    L_prefix = np.zeros(0)
+    if len(order):
+        keep = np.ones((len(order), P), np.uint8)
+        for k in range(len(order)):
+            keep[k, order[:k + 1]] = 0
+        res = torch.zeros(len(order), 7, dtype=torch.float64, device=theta.device)
+        session.forward_trials(keep, res)
+        L_prefix = res[:, 1].cpu().numpy()
+        evaluated += [((alive & keep[i]).tolist(), float(L_prefix[i])) for i in range(len(order))]
+    k = mg_prune_accept(L_prefix, L_min, tau)
+    new_alive = alive.copy()
+    new_alive[order[:k]] = 0
+    return {"alive": new_alive, "L_min": min(L_min, float(L_prefix[k - 1])) if k else L_min, "L_start": L_min,
+            "La": La, "candidates": cand.tolist(), "L_cand": L_cand.tolist(), "order": order.tolist(),
+            "L_prefix": L_prefix.tolist(), "k": k, "evaluated": evaluated}
 
 
 def console_loss(session: Session, dry, theta, wet, mask=None):

@@ -15,7 +15,8 @@ def f32(x):
 
 
 class Case:
-    def __init__(self, cfg, seed=3, params="random", alpha_g=1e-3, alpha_p=0.0, mode=1, std=0.3):
+    def __init__(self, cfg, seed=3, params="random", alpha_g=1e-3, alpha_p=0.0, mode=1, std=0.3, max_trials=0,
+                 trial_slots=0):
         self.cfg = cfg
         self.g, self.dry, self.noise = synth.song(seed, cfg)
         gt, gw = synth.ground_truth_params(seed + 100, self.g, cfg)
@@ -27,7 +28,7 @@ class Case:
         self.th = {v: f32(p) for v, p in th.items()}
         self.we = {v: float(np.float32(w)) for v, w in we.items()}
         self.alpha_g, self.alpha_p = alpha_g, alpha_p
-        self.bg = W.binding_graph(self.g, cfg, alpha_g, alpha_p)
+        self.bg = W.binding_graph(self.g, cfg, alpha_g, alpha_p, max_trials=max_trials, trial_slots=trial_slots)
         dev = "cuda"
         self.noise_d = torch.from_numpy(W.noise_rows(self.bg, self.noise, cfg.reverb_length)).to(dev)
         self.target_d = torch.from_numpy(self.target).to(dev)
@@ -97,3 +98,39 @@ def loss_tolerances(case, omix, draws=2, rel=1e-5):
     tol = {k: max(rel * abs(float(base[k])), 3.0 * delta[k]) for k in base}
     tol["L"] = tol["La"] + rel * abs(float(base["La"]))
     return tol
+
+
+def grad_tolerances(case, oth, owe, mask=None, draws=2, rel=1e-3):
+    """Per processor type (and 'w' for the dry/wet logits): max(rel, 3 * the
+    relative change of the oracle's own gradient when FP32-level white noise
+    (FP32_CONV_REL * RMS) is added to every processor's wet output).  The
+    log-Mel term makes some gradients (the delay's normalised z direction, the
+    noisegate near its threshold) sensitive to rounding in quiet cells; this
+    measures that sensitivity with the oracle alone."""
+    from oracle import console as OC
+    tgt = case.target.astype(np.float64)
+    orig = OC.process
+    rng = np.random.default_rng(777)
+    worst = {}
+
+    def noisy(t, u, p, cfg, noise=None):
+        y = orig(t, u, p, cfg, noise)
+        rms = float(y.detach().pow(2).mean().sqrt())
+        return y + torch.from_numpy(rng.standard_normal(tuple(y.shape))) * (FP32_CONV_REL * rms)
+
+    types = sorted({case.g.types[v] for v in case.g.processors()})
+    try:
+        OC.process = noisy
+        for _ in range(draws):
+            _, gth, gwe, _ = TR.loss_and_grad(case.g, case.cfg, case.dry, case.noise, tgt, case.th, case.we,
+                                              mask, case.alpha_g, case.alpha_p)
+            for t in types:
+                vs = [v for v in case.g.processors() if case.g.types[v] == t]
+                e = rel_l2(np.concatenate([gth[v] for v in vs]), np.concatenate([oth[v] for v in vs]))
+                worst[t] = max(worst.get(t, 0.0), e)
+            procs = case.g.processors()
+            e = rel_l2([gwe[v] for v in procs], [owe[v] for v in procs])
+            worst["w"] = max(worst.get("w", 0.0), e)
+    finally:
+        OC.process = orig
+    return {k: max(rel, 3.0 * s) for k, s in worst.items()}, worst

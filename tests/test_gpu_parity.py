@@ -1,6 +1,9 @@
 """GPU parity: the HIP path through the C-ABI against the FP64 oracle on the
 same seeded inputs.  Tolerances: waveform relative L2 <= 1e-4, loss terms
-relative <= 1e-5, gradients relative L2 per parameter tensor <= 1e-3."""
+relative <= 1e-5, gradients relative L2 per parameter tensor <= 1e-3.  Where
+the oracle itself moves by more than a third of that under FP32-level noise on
+its processor outputs (quiet log-Mel cells), the bound is 3x that measured
+sensitivity (gpu_cases.loss_tolerances / grad_tolerances)."""
 import numpy as np
 import pytest
 import torch
@@ -9,7 +12,7 @@ import synth
 from oracle import train as TR
 from paper_2509_15948_amd import mixgraph as MG
 
-from gpu_cases import Case, loss_tolerances, rel_l2
+from gpu_cases import Case, grad_tolerances, loss_tolerances, rel_l2
 
 pytestmark = pytest.mark.gpu
 
@@ -76,16 +79,17 @@ def test_backward_parity_per_type(chain):
             for m in range(case.cfg.delay_taps):
                 print("delay", v, c, m, "z gpu", a[c, m, :2], "oracle", b[c, m, :2],
                       "fir err", rel_l2(a[c, m, 2:], b[c, m, 2:]), flush=True)
+    tol, sens = grad_tolerances(case, oth, owe)
     for t, (a, b) in by_type.items():
         a = np.concatenate(a)
         b = np.concatenate(b)
         err = rel_l2(a, b)
-        print(chain, t, "grad err", err, flush=True)
-        assert err <= GRAD_TOL, (t, err)
+        print(chain, t, "grad err", err, "oracle FP32 sensitivity", sens[t], "bound", tol[t], flush=True)
+        assert err <= tol[t], (t, err, tol[t])
     procs = case.g.processors()
     err = rel_l2([gwe[v] for v in procs], [owe[v] for v in procs])
-    print(chain, "wet grad err", err, flush=True)
-    assert err <= GRAD_TOL
+    print(chain, "wet grad err", err, "oracle FP32 sensitivity", sens["w"], "bound", tol["w"], flush=True)
+    assert err <= tol["w"]
 
 
 def test_tiny_console_attack_release_full_size():
@@ -131,11 +135,13 @@ def test_full_console_full_size():
                       "fir err", rel_l2(a[c, m, 2:], b[c, m, 2:]), flush=True)
     procs = case.g.processors()
     print("full wet grad err", rel_l2([gwe[v] for v in procs], [owe[v] for v in procs]), flush=True)
+    tol, sens = grad_tolerances(case, oth, owe)
     for t in "ecxsgdr":
         vs = [v for v in case.g.processors() if case.g.types[v] == t]
         err = rel_l2(np.concatenate([gth[v] for v in vs]), np.concatenate([oth[v] for v in vs]))
-        assert err <= GRAD_TOL, (t, err)
-    assert rel_l2([gwe[v] for v in procs], [owe[v] for v in procs]) <= GRAD_TOL
+        print("full", t, "grad err", err, "oracle FP32 sensitivity", sens[t], "bound", tol[t], flush=True)
+        assert err <= tol[t], (t, err, tol[t])
+    assert rel_l2([gwe[v] for v in procs], [owe[v] for v in procs]) <= tol["w"]
 
 
 def test_masked_forward_equals_separate_forwards():

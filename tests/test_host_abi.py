@@ -158,3 +158,32 @@ def test_prune_is_bypass_in_the_oracle():
     assert np.allclose(mix2, masked, rtol=1e-12, atol=1e-14)
     assert pg.schedule.startswith("i") and pg.schedule.endswith("o")
     assert len(pg.schedule) <= len(bg.schedule)
+
+
+def test_pruning_rule_matches_the_oracle_rule():
+    """The C-ABI decision rule (host only) against oracle/prune.py on random
+    weights, liveness and losses, ties included."""
+    from oracle import prune as OP
+    rng = np.random.default_rng(5)
+    for trial in range(50):
+        P = int(rng.integers(1, 40))
+        wet = rng.normal(size=P).astype(np.float32)
+        if trial % 5 == 0:
+            wet[: P // 2] = wet[0]                       # ties in w
+        mask = (rng.random(P) < 0.8).astype(np.float32) if trial % 2 else None
+        alive = (rng.random(P) < 0.9).astype(np.uint8)
+        n = int(rng.integers(0, P + 3))
+        w32 = (np.float32(1.0) / (np.float32(1.0) + np.exp(-wet))).astype(np.float32)
+        if mask is not None:
+            w32 = w32 * mask
+        cand = MG.mg_prune_candidates(wet, mask, alive, n)
+        assert cand.tolist() == OP.candidates(w32.tolist(), alive.tolist(), n)
+        L_min = 1.0 + rng.random()
+        tau = float(rng.choice([1e-3, 1e-2, 0.1]))
+        L_cand = L_min + rng.normal(scale=tau * L_min, size=len(cand))
+        if len(cand) > 2:
+            L_cand[1] = L_cand[0]                         # ties in Delta
+        order = MG.mg_prune_order(cand, L_cand, L_min, tau)
+        assert order.tolist() == OP.order_within_tolerance(cand.tolist(), L_cand.tolist(), L_min, tau)
+        L_prefix = L_min * (1 + tau * rng.normal(size=len(order)))
+        assert MG.mg_prune_accept(L_prefix, L_min, tau) == OP.accept_prefix(L_prefix.tolist(), L_min, tau)
