@@ -261,7 +261,7 @@ def main():
     cfg = synth.CONFIGS[args.config]
     dev = "cuda"
     g, dry, noise = synth.song(1, cfg)
-    bg = W.binding_graph(g, cfg)
+    bg = W.binding_graph(g, cfg, max_trials=max(0, args.prune_masks))
     dry_d = torch.from_numpy(dry).to(dev)
     noise_d = torch.from_numpy(W.noise_rows(bg, noise, cfg.reverb_length)).to(dev)
     log(f"workload {args.config}: {g.n_nodes} nodes, {bg.n_proc} processors, schedule {bg.schedule}, "
@@ -339,24 +339,39 @@ def main():
     hbm_model = {"bytes_per_step": int(mb), "achieved_GBs": round(mb / (ms_step / 1000.0) / 1e9, 1),
                  "frac_of_peak": round(mb / (ms_step / 1000.0) / 1e9 / HBM_PEAK_GBS, 4)}
 
-    # pruning evaluation: B candidate masks, each zeroing one processor
+    # pruning evaluation: B single-processor trials (the B lowest dry/wet
+    # weights) by suffix recomputation after one forward at the current
+    # parameters, and the same masks as complete forwards for comparison
     prune = None
     if args.prune_masks > 0:
         B = min(args.prune_masks, bg.n_proc)
-        masks = torch.ones(B, bg.n_proc, device=dev)
-        for b in range(B):
-            masks[b, b] = 0.0
+        cand = MG.mg_prune_candidates(wet.cpu().numpy(), None, np.ones(bg.n_proc, np.uint8), B)
+        keep = np.ones((B, bg.n_proc), np.uint8)
+        keep[np.arange(B), cand] = 0
         out = torch.zeros(B, 7, dtype=torch.float64, device=dev)
-        sess.forward_masked(dry_d, theta, wet, masks, out)
-        torch.cuda.synchronize()
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
+        e2 = torch.cuda.Event(enable_timing=True)
+        for rep in range(2):  # the first pass warms up
+            e0.record()
+            sess.forward(dry_d, theta, wet, None, None, losses)
+            e1.record()
+            sess.forward_trials(keep, out)
+            e2.record()
+            torch.cuda.synchronize()
+        fwd_ms, trial_ms = e0.elapsed_time(e1), e1.elapsed_time(e2)
+        masks = torch.from_numpy(keep.astype(np.float32)).to(dev)
+        ref = torch.zeros(B, 7, dtype=torch.float64, device=dev)
         e0.record()
-        sess.forward_masked(dry_d, theta, wet, masks, out)
+        sess.forward_masked(dry_d, theta, wet, masks, ref)
         e1.record()
         torch.cuda.synchronize()
-        pm = e0.elapsed_time(e1)
-        prune = {"candidates": B, "round_ms": round(pm, 3), "candidates_per_s": round(B / (pm / 1000.0), 1)}
+        full_ms = e0.elapsed_time(e1)
+        prune = {"candidates": B, "forward_ms": round(fwd_ms, 3), "trials_ms": round(trial_ms, 3),
+                 "candidates_per_s": round(B / ((fwd_ms + trial_ms) / 1000.0), 1),
+                 "complete_forwards_ms": round(full_ms, 3),
+                 "speedup_vs_complete_forwards": round(full_ms / (fwd_ms + trial_ms), 2),
+                 "bitwise_equal_to_complete_forwards": bool(torch.equal(out, ref))}
 
     plain = None
     if not args.no_plain_loop:

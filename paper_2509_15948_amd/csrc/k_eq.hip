@@ -51,6 +51,8 @@ __device__ __forceinline__ const float* eq_input(const EqArgs& a, const NodeDesc
 // H_P of every node of the stage: grid (nodes)
 __global__ __launch_bounds__(MG_BLOCK) void k_eq_spec(EqArgs a) {
   __shared__ float2 buf[EQ_P];
+  __shared__ TwTab<EQ_P, float2> tt;
+  tw_fill<EQ_P>(tt, a.tw);
   const NodeDesc d = a.desc[blockIdx.x];
   const float* h = a.h + (int64_t)d.aux * a.N;
   const int half = (a.N - 1) / 2;
@@ -62,7 +64,7 @@ __global__ __launch_bounds__(MG_BLOCK) void k_eq_spec(EqArgs a) {
     buf[i] = make_float2(v, 0.f);
   }
   __syncthreads();
-  fft_lds<EQ_P, 1, EQ_P, MG_BLOCK, -1>(buf, a.tw);
+  fft_lds<EQ_P, 1, EQ_P, MG_BLOCK, -1>(buf, tt);
   float* o = a.HP + (int64_t)d.aux * EQ_P;
   for (int i = threadIdx.x; i < EQ_P; i += MG_BLOCK) o[i] = buf[i].x;
 }
@@ -71,6 +73,8 @@ __global__ __launch_bounds__(MG_BLOCK) void k_eq_spec(EqArgs a) {
 __global__ __launch_bounds__(MG_BLOCK) void k_eq_fwd(EqArgs a) {
   __shared__ float2 buf[EQ_P];
   __shared__ float red[MG_BLOCK];
+  __shared__ TwTab<EQ_P, float2> tt;
+  tw_fill<EQ_P>(tt, a.tw);
   const int j = blockIdx.y, blk = blockIdx.x;
   const NodeDesc d = a.desc[j];
   int64_t cs;
@@ -82,11 +86,11 @@ __global__ __launch_bounds__(MG_BLOCK) void k_eq_fwd(EqArgs a) {
     buf[i] = (n >= 0 && n < a.L) ? make_float2(u[n], u[cs + n]) : make_float2(0.f, 0.f);
   }
   __syncthreads();
-  fft_lds<EQ_P, 1, EQ_P, MG_BLOCK, -1>(buf, a.tw);
+  fft_lds<EQ_P, 1, EQ_P, MG_BLOCK, -1>(buf, tt);
   const float* H = a.HP + (int64_t)d.aux * EQ_P;
   for (int i = threadIdx.x; i < EQ_P; i += MG_BLOCK) buf[i] = c_scale(buf[i], H[i] * (1.0f / EQ_P));
   __syncthreads();
-  fft_lds<EQ_P, 1, EQ_P, MG_BLOCK, +1>(buf, a.tw);
+  fft_lds<EQ_P, 1, EQ_P, MG_BLOCK, +1>(buf, tt);
   float w = node_w(a.wet, a.mask, d);
   float* y = a.Uo + (int64_t)d.out_slot * 2 * a.L;
   float* yb = a.ybar ? a.ybar + (int64_t)d.aux * 2 * a.L : nullptr;
@@ -120,6 +124,8 @@ __global__ __launch_bounds__(MG_BLOCK) void k_eq_bwd(EqArgs a) {
   __shared__ float2 A[EQ_P];
   __shared__ float2 B[EQ_P];
   __shared__ float red[MG_BLOCK];
+  __shared__ TwTab<EQ_P, float2> tt;
+  tw_fill<EQ_P>(tt, a.tw);
   const int j = blockIdx.y, blk = blockIdx.x;
   const NodeDesc d = a.desc[j];
   int64_t cs;
@@ -152,10 +158,10 @@ __global__ __launch_bounds__(MG_BLOCK) void k_eq_bwd(EqArgs a) {
   const float* H = a.HP + (int64_t)d.aux * EQ_P;
   float* gin = d.gin >= 0 ? a.G + (int64_t)d.gin * 2 * a.L : nullptr;
   if (gin) {
-    fft_lds<EQ_P, 1, EQ_P, MG_BLOCK, -1>(A, a.tw);
+    fft_lds<EQ_P, 1, EQ_P, MG_BLOCK, -1>(A, tt);
     for (int i = threadIdx.x; i < EQ_P; i += MG_BLOCK) A[i] = c_scale(A[i], H[i] * (1.0f / EQ_P));
     __syncthreads();
-    fft_lds<EQ_P, 1, EQ_P, MG_BLOCK, +1>(A, a.tw);
+    fft_lds<EQ_P, 1, EQ_P, MG_BLOCK, +1>(A, tt);
     for (int i = half + threadIdx.x; i < half + a.V; i += MG_BLOCK) {
       const int64_t n = s0 + i;
       if (n >= a.L) break;
@@ -171,11 +177,11 @@ __global__ __launch_bounds__(MG_BLOCK) void k_eq_bwd(EqArgs a) {
     A[i] = (n >= 0 && n < a.L) ? make_float2(u[n], u[cs + n]) : make_float2(0.f, 0.f);
   }
   __syncthreads();
-  fft_lds<EQ_P, 1, EQ_P, MG_BLOCK, -1>(A, a.tw);
-  fft_lds<EQ_P, 1, EQ_P, MG_BLOCK, -1>(B, a.tw);
+  fft_lds<EQ_P, 1, EQ_P, MG_BLOCK, -1>(A, tt);
+  fft_lds<EQ_P, 1, EQ_P, MG_BLOCK, -1>(B, tt);
   for (int i = threadIdx.x; i < EQ_P; i += MG_BLOCK) B[i] = c_scale(c_mulc(B[i], A[i]), 1.0f / EQ_P);
   __syncthreads();
-  fft_lds<EQ_P, 1, EQ_P, MG_BLOCK, +1>(B, a.tw);
+  fft_lds<EQ_P, 1, EQ_P, MG_BLOCK, +1>(B, tt);
   // lag m sits at circular index m mod P; dh index = m + half
   float* o = a.dhp + ((int64_t)d.aux * a.nblk + blk) * a.N;
   for (int t = threadIdx.x; t < a.N; t += MG_BLOCK) {

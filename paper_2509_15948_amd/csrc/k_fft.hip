@@ -262,6 +262,8 @@ template <int N2, int TC, typename LD>
 __global__ __launch_bounds__(MG_BLOCK) void k_cols(LD ld, float2* __restrict__ T, EngineArgs ea) {
   constexpr int BS = N2 + 1;
   __shared__ float2 buf[TC * BS];
+  __shared__ TwTab<N2, float2> tt;
+  tw_fill<N2>(tt, ea.tw);
   const int j = blockIdx.y;
   const int c0 = blockIdx.x * TC;
   const int N1 = ea.N1;
@@ -272,7 +274,7 @@ __global__ __launch_bounds__(MG_BLOCK) void k_cols(LD ld, float2* __restrict__ T
   }
   ld.end(j, blockIdx.x);
   __syncthreads();
-  fft_lds<N2, TC, BS, MG_BLOCK, -1>(buf, ea.tw);
+  fft_lds<N2, TC, BS, MG_BLOCK, -1>(buf, tt);
   float2* Tn = T + (int64_t)j * ea.N;
   const int64_t mask = ea.N - 1;
   for (int idx = threadIdx.x; idx < TC * N2; idx += MG_BLOCK) {
@@ -288,6 +290,8 @@ template <int N2, int TC, typename ST>
 __global__ __launch_bounds__(MG_BLOCK) void k_icols(ST st, const float2* __restrict__ T, EngineArgs ea) {
   constexpr int BS = N2 + 1;
   __shared__ float2 buf[TC * BS];
+  __shared__ TwTab<N2, float2> tt;
+  tw_fill<N2>(tt, ea.tw);
   const int j = blockIdx.y;
   const int c0 = blockIdx.x * TC;
   const int N1 = ea.N1;
@@ -297,7 +301,7 @@ __global__ __launch_bounds__(MG_BLOCK) void k_icols(ST st, const float2* __restr
     buf[cc * BS + k2] = Tn[(int64_t)k2 * N1 + c0 + cc];
   }
   __syncthreads();
-  fft_lds<N2, TC, BS, MG_BLOCK, +1>(buf, ea.tw);
+  fft_lds<N2, TC, BS, MG_BLOCK, +1>(buf, tt);
   const float sc = 1.0f / (float)ea.N;
   st.begin(j);
   for (int idx = threadIdx.x; idx < TC * N2; idx += MG_BLOCK) {
@@ -372,12 +376,14 @@ template <int N1>
 __global__ __launch_bounds__(MG_BLOCK) void k_rows_spec(const float2* __restrict__ T, float2* __restrict__ Z,
                                                          int z0, const NodeDesc* __restrict__ desc, EngineArgs ea) {
   __shared__ float2 buf[2 * N1];
+  __shared__ TwTab<N1, float2> tt;
+  tw_fill<N1>(tt, ea.tw);
   const int j = blockIdx.y;
   int ra, rb;
   row_pair(blockIdx.x, ea.N2, ra, rb);
   load_rows<N1>(buf, T + (int64_t)j * ea.N, ra, rb);
   __syncthreads();
-  fft_lds<N1, 2, N1, MG_BLOCK, -1>(buf, ea.tw);
+  fft_lds<N1, 2, N1, MG_BLOCK, -1>(buf, tt);
   float2* Zn = Z + (int64_t)(z0 + desc[j].aux) * ea.N;
   for (int i = threadIdx.x; i < N1; i += MG_BLOCK) {
     Zn[(int64_t)ra * N1 + i] = buf[i];
@@ -391,13 +397,15 @@ __global__ __launch_bounds__(MG_BLOCK) void k_rows_conv(const float2* __restrict
                                                          const float2* __restrict__ ZH, float2* __restrict__ ZU,
                                                          int z0, const NodeDesc* __restrict__ desc, EngineArgs ea) {
   __shared__ float2 buf[2 * N1];
+  __shared__ TwTab<N1, float2> tt;
+  tw_fill<N1>(tt, ea.tw);
   const int j = blockIdx.y;
   const int p = blockIdx.x;
   int ra, rb;
   row_pair(p, ea.N2, ra, rb);
   load_rows<N1>(buf, Tin + (int64_t)j * ea.N, ra, rb);
   __syncthreads();
-  fft_lds<N1, 2, N1, MG_BLOCK, -1>(buf, ea.tw);
+  fft_lds<N1, 2, N1, MG_BLOCK, -1>(buf, tt);
   const int64_t zr = (int64_t)(z0 + desc[j].aux) * ea.N;
   const float2* H = ZH + zr;
   if (ZU) {  // keep the input spectrum for the backward
@@ -426,7 +434,7 @@ __global__ __launch_bounds__(MG_BLOCK) void k_rows_conv(const float2* __restrict
     buf[ib] = yb;
   }
   __syncthreads();
-  fft_lds<N1, 2, N1, MG_BLOCK, +1>(buf, ea.tw);
+  fft_lds<N1, 2, N1, MG_BLOCK, +1>(buf, tt);
   store_rows<N1>(buf, Tout + (int64_t)j * ea.N, ra, rb, ea);
 }
 
@@ -439,6 +447,8 @@ __global__ __launch_bounds__(MG_BLOCK) void k_rows_bwd(const float2* __restrict_
                                                         const NodeDesc* __restrict__ desc, int want_u,
                                                         EngineArgs ea) {
   __shared__ float2 buf[4 * N1];
+  __shared__ TwTab<N1, float2> tt;
+  tw_fill<N1>(tt, ea.tw);
   float2* b1 = buf;
   float2* b2 = buf + 2 * N1;
   const int j = blockIdx.y;
@@ -447,7 +457,7 @@ __global__ __launch_bounds__(MG_BLOCK) void k_rows_bwd(const float2* __restrict_
   row_pair(p, ea.N2, ra, rb);
   load_rows<N1>(b1, Tin + (int64_t)j * ea.N, ra, rb);
   __syncthreads();
-  fft_lds<N1, 2, N1, MG_BLOCK, -1>(b1, ea.tw);
+  fft_lds<N1, 2, N1, MG_BLOCK, -1>(b1, tt);
   const int64_t zr = (int64_t)(z0 + desc[j].aux) * ea.N;
   const float2* H = ZH + zr;
   const float2* X = ZU + zr;
@@ -479,10 +489,10 @@ __global__ __launch_bounds__(MG_BLOCK) void k_rows_bwd(const float2* __restrict_
   }
   __syncthreads();
   if (want_u) {
-    fft_lds<N1, 2, N1, MG_BLOCK, +1>(b1, ea.tw);
+    fft_lds<N1, 2, N1, MG_BLOCK, +1>(b1, tt);
     store_rows<N1>(b1, Tu + (int64_t)j * ea.N, ra, rb, ea);
   }
-  fft_lds<N1, 2, N1, MG_BLOCK, +1>(b2, ea.tw);
+  fft_lds<N1, 2, N1, MG_BLOCK, +1>(b2, tt);
   store_rows<N1>(b2, Th + (int64_t)j * ea.N, ra, rb, ea);
 }
 

@@ -255,8 +255,21 @@ constexpr int RV_N = 384;
 constexpr int RV_FPB = 16;            // frames per workgroup (8 packed transforms)
 constexpr int RV_SEQ = RV_FPB / 2;
 
+// exp(DIR 2 pi i e / 384) from the LDS copy of the table
+template <int DIR>
+__device__ __forceinline__ float2 rv_tw(const float2* tw, int e) {
+  float2 w = tw[e];
+  if (DIR > 0) w.y = -w.y;
+  return w;
+}
+
+// copy the 384-entry table into LDS (the caller synchronises)
+__device__ __forceinline__ void rv_tw_fill(float2* tws, const float2* __restrict__ tw) {
+  for (int i = threadIdx.x; i < RV_N; i += MG_BLOCK) tws[i] = tw[i];
+}
+
 template <int R, int DIR>
-__device__ __forceinline__ void rv_pass(float2* buf, const float2* __restrict__ tw, int Ns) {
+__device__ __forceinline__ void rv_pass(float2* buf, const float2* tw, int Ns) {
   constexpr int Q = RV_N / R;
   constexpr int NB = RV_SEQ * Q;
   constexpr int PER = NB / MG_BLOCK;
@@ -278,7 +291,7 @@ __device__ __forceinline__ void rv_pass(float2* buf, const float2* __restrict__ 
     const int b = g / Q, j = g % Q;
     const int k = j % Ns;
 #pragma unroll
-    for (int r = 1; r < R; ++r) v[q][r] = c_mul(v[q][r], tw_get<DIR>(tw, r * k * stride));
+    for (int r = 1; r < R; ++r) v[q][r] = c_mul(v[q][r], rv_tw<DIR>(tw, r * k * stride));
     float2 y[R];
     if (R == 2) {
       y[0] = c_add(v[q][0], v[q][1]);
@@ -309,7 +322,7 @@ __device__ __forceinline__ void rv_pass(float2* buf, const float2* __restrict__ 
 
 // RV_SEQ unnormalised 384-point transforms in LDS (caller syncs after filling)
 template <int DIR>
-__device__ __forceinline__ void rv_fft(float2* buf, const float2* __restrict__ tw) {
+__device__ __forceinline__ void rv_fft(float2* buf, const float2* tw) {
   rv_pass<3, DIR>(buf, tw, 1);
   rv_pass<4, DIR>(buf, tw, 3);
   rv_pass<4, DIR>(buf, tw, 12);
@@ -324,6 +337,8 @@ __global__ __launch_bounds__(MG_BLOCK) void k_rv_noise_stft(const float* __restr
                                                              const float* __restrict__ win,
                                                              float2* __restrict__ Uout) {
   __shared__ float2 buf[RV_SEQ * RV_N];
+  __shared__ float2 tws[RV_N];
+  rv_tw_fill(tws, tw);
   const int m0 = blockIdx.x * RV_FPB, x = blockIdx.y, row = blockIdx.z;
   const float* nz = noise + ((int64_t)row * 2 + x) * Lr;
   for (int i = threadIdx.x; i < RV_SEQ * RV_N; i += MG_BLOCK) {
@@ -337,7 +352,7 @@ __global__ __launch_bounds__(MG_BLOCK) void k_rv_noise_stft(const float* __restr
     buf[i] = make_float2(v[0], v[1]);
   }
   __syncthreads();
-  rv_fft<-1>(buf, tw);
+  rv_fft<-1>(buf, tws);
   for (int i = threadIdx.x; i < RV_SEQ * 192; i += MG_BLOCK) {
     const int p = i / 192, k = i % 192;
     const float2 z = buf[p * RV_N + k], zm = buf[p * RV_N + ((RV_N - k) % RV_N)];
@@ -359,6 +374,8 @@ __global__ __launch_bounds__(MG_BLOCK) void k_rv_frames(const NodeDesc* __restri
                                                          const float* __restrict__ win, float gbias, float beta,
                                                          float* __restrict__ frames) {
   __shared__ float2 buf[RV_SEQ * RV_N];
+  __shared__ float2 tws[RV_N];
+  rv_tw_fill(tws, tw);
   __shared__ float h0[192], dk[192];
   const int m0 = blockIdx.x * RV_FPB, x = blockIdx.y;
   const NodeDesc d = desc[blockIdx.z];
@@ -389,7 +406,7 @@ __global__ __launch_bounds__(MG_BLOCK) void k_rv_frames(const NodeDesc* __restri
     buf[i] = make_float2(s[0].x - s[1].y, s[0].y + s[1].x);
   }
   __syncthreads();
-  rv_fft<+1>(buf, tw);
+  rv_fft<+1>(buf, tws);
   for (int i = threadIdx.x; i < RV_SEQ * RV_N; i += MG_BLOCK) {
     const int pr = i / RV_N, t = i % RV_N;
     const float2 z = buf[i];
@@ -430,6 +447,8 @@ __global__ __launch_bounds__(MG_BLOCK) void k_rv_adj_frames(const NodeDesc* __re
                                                              float beta, const float* __restrict__ dh,
                                                              float* __restrict__ dMout) {
   __shared__ float2 buf[RV_SEQ * RV_N];
+  __shared__ float2 tws[RV_N];
+  rv_tw_fill(tws, tw);
   __shared__ float h0[192], dk[192];
   const int m0 = blockIdx.x * RV_FPB, x = blockIdx.y;
   const NodeDesc d = desc[blockIdx.z];
@@ -455,7 +474,7 @@ __global__ __launch_bounds__(MG_BLOCK) void k_rv_adj_frames(const NodeDesc* __re
     buf[i] = make_float2(v[0], v[1]);
   }
   __syncthreads();
-  rv_fft<-1>(buf, tw);
+  rv_fft<-1>(buf, tws);
   const float2* U = Unz + ((int64_t)d.aux * 2 + x) * nf * 192;
   float* o = dMout + ((int64_t)d.aux * 2 + x) * nf * 192;
   for (int i = threadIdx.x; i < RV_SEQ * 192; i += MG_BLOCK) {

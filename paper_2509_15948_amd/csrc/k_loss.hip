@@ -105,12 +105,14 @@ __global__ __launch_bounds__(MG_BLOCK) void k_loss_fwd(LossArgs a) {
   constexpr int FPB = loss_fpb<N>();
   constexpr int NB = N / 2 + 1;
   __shared__ double2 buf[FPB * N];
+  __shared__ TwTab<N, double2> tt;
+  tw_fill<N>(tt, a.tw);
   __shared__ double mag[FPB * 4 * NB];
   __shared__ double red[MG_BLOCK];
   const int f0 = blockIdx.x * FPB;
   load_frames<N>(buf, a, f0);
   __syncthreads();
-  fft_lds<N, FPB, N, MG_BLOCK, -1>(buf, a.tw);
+  fft_lds<N, FPB, N, MG_BLOCK, -1>(buf, tt);
   frame_mags<N>(buf, mag, a);
   __syncthreads();
   double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
@@ -169,12 +171,14 @@ __global__ __launch_bounds__(MG_BLOCK) void k_loss_bwd(LossArgs a) {
   constexpr int FPB = loss_fpb<N>();
   constexpr int NB = N / 2 + 1;
   __shared__ double2 buf[FPB * N];
+  __shared__ TwTab<N, double2> tt;
+  tw_fill<N>(tt, a.tw);
   __shared__ double mag[FPB * 4 * NB];
   __shared__ double dyh[FPB * 4 * 128];
   const int f0 = blockIdx.x * FPB;
   load_frames<N>(buf, a, f0);
   __syncthreads();
-  fft_lds<N, FPB, N, MG_BLOCK, -1>(buf, a.tw);
+  fft_lds<N, FPB, N, MG_BLOCK, -1>(buf, tt);
   frame_mags<N>(buf, mag, a);
   __syncthreads();
   // dL/dYh per (frame, combo, band); every combo carries weight 1/4 in L_a
@@ -231,7 +235,7 @@ __global__ __launch_bounds__(MG_BLOCK) void k_loss_bwd(LossArgs a) {
     }
   }
   __syncthreads();
-  fft_lds<N, FPB, N, MG_BLOCK, +1>(buf, a.tw);
+  fft_lds<N, FPB, N, MG_BLOCK, +1>(buf, tt);
   for (int idx = threadIdx.x; idx < FPB * N; idx += MG_BLOCK) {
     const int fl = idx / N, t = idx % N;
     const int f = f0 + fl;

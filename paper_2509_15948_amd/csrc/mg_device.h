@@ -50,11 +50,34 @@ __device__ __forceinline__ V c_rot(V a) {
 
 constexpr int ilog2c(int n) { return n <= 1 ? 0 : 1 + ilog2c(n >> 1); }
 
-// Twiddle W = exp(DIR * 2 pi i * e / n) for e < n, from the table
-// tw[m] = exp(-2 pi i m / MG_TWN) (rounded from FP64 on the host).
-template <int DIR, typename V>
-__device__ __forceinline__ V tw_get(const V* __restrict__ tw, int m) {
-  V w = tw[m];
+// Twiddles of an N-point transform, staged in LDS by the calling kernel:
+// hi[j] = W_N^{64 j} (N/64 entries, at least 1) and lo[j] = W_N^j (64
+// entries), W_N = exp(-2 pi i / N), so W_N^e = hi[e >> 6] lo[e & 63].  Both
+// are copied from the global table g[m] = exp(-2 pi i m / MG_TWN) (rounded
+// from FP64 on the host), so no butterfly reads global memory.
+template <int N, typename V>
+struct TwTab {
+  static constexpr int NH = N >= 64 ? N / 64 : 1;
+  V hi[NH];
+  V lo[64];
+};
+
+// Fill t from g; the caller synchronises before the first transform.
+template <int N, typename V>
+__device__ __forceinline__ void tw_fill(TwTab<N, V>& t, const V* __restrict__ g) {
+  static_assert(N <= MG_TWN && MG_TWN % N == 0, "N must divide the table size");
+  constexpr int S = MG_TWN / N;
+  constexpr int NH = TwTab<N, V>::NH;
+  for (int i = threadIdx.x; i < NH + 64; i += blockDim.x) {
+    if (i < NH) t.hi[i] = g[(64 * i * S) & (MG_TWN - 1)];
+    else t.lo[i - NH] = g[((i - NH) * S) & (MG_TWN - 1)];
+  }
+}
+
+// W = exp(DIR * 2 pi i * e / N) for 0 <= e < N.
+template <int DIR, int N, typename V>
+__device__ __forceinline__ V tw_get(const TwTab<N, V>& t, int e) {
+  V w = c_mul(t.hi[e >> 6], t.lo[e & 63]);
   if (DIR > 0) w.y = -w.y;
   return w;
 }
@@ -62,7 +85,7 @@ __device__ __forceinline__ V tw_get(const V* __restrict__ tw, int m) {
 // One radix-4 Stockham pass over B transforms of length N stored at
 // buf[b * BS + i].  Ns is the product of the radices of the earlier passes.
 template <int N, int B, int BS, int NT, int DIR, typename V>
-__device__ __forceinline__ void fft_r4_pass(V* buf, const V* __restrict__ tw, int Ns) {
+__device__ __forceinline__ void fft_r4_pass(V* buf, const TwTab<N, V>& tw, int Ns) {
   constexpr int Q = N / 4;
   constexpr int NB = B * Q;
   constexpr int PER = NB / NT;
@@ -78,7 +101,7 @@ __device__ __forceinline__ void fft_r4_pass(V* buf, const V* __restrict__ tw, in
     for (int r = 0; r < 4; ++r) v[q][r] = base[j + r * Q];
   }
   __syncthreads();
-  const int stride = MG_TWN / (4 * Ns);
+  const int stride = N / (4 * Ns);
 #pragma unroll
   for (int q = 0; q < PER; ++q) {
     const int g = tid + q * NT;
@@ -104,7 +127,7 @@ __device__ __forceinline__ void fft_r4_pass(V* buf, const V* __restrict__ tw, in
 }
 
 template <int N, int B, int BS, int NT, int DIR, typename V>
-__device__ __forceinline__ void fft_r2_pass(V* buf, const V* __restrict__ tw, int Ns) {
+__device__ __forceinline__ void fft_r2_pass(V* buf, const TwTab<N, V>& tw, int Ns) {
   constexpr int Q = N / 2;
   constexpr int NB = B * Q;
   constexpr int PER = NB / NT;
@@ -120,7 +143,7 @@ __device__ __forceinline__ void fft_r2_pass(V* buf, const V* __restrict__ tw, in
     v[q][1] = base[j + Q];
   }
   __syncthreads();
-  const int stride = MG_TWN / (2 * Ns);
+  const int stride = N / (2 * Ns);
 #pragma unroll
   for (int q = 0; q < PER; ++q) {
     const int g = tid + q * NT;
@@ -137,10 +160,10 @@ __device__ __forceinline__ void fft_r2_pass(V* buf, const V* __restrict__ tw, in
 
 // B unnormalised transforms of length N (4 <= N <= MG_TWN), in place in LDS.
 // DIR = -1: X[k] = sum x[n] e^{-2 pi i nk/N};  DIR = +1: the inverse sign.
-// V is float2 or double2 (with a twiddle table of the same type).
-// The caller must __syncthreads() after filling buf.
+// V is float2 or double2 (with twiddle tables of the same type).
+// The caller must __syncthreads() after filling buf and tw.
 template <int N, int B, int BS, int NT, int DIR, typename V>
-__device__ __forceinline__ void fft_lds(V* buf, const V* __restrict__ tw) {
+__device__ __forceinline__ void fft_lds(V* buf, const TwTab<N, V>& tw) {
   constexpr int LOG = ilog2c(N);
   static_assert((1 << LOG) == N, "power of two");
   int Ns = 1;

@@ -1,0 +1,266 @@
+"""Serving loop for whole-song mixing-graph searches (continuous batching).
+
+Requests arrive over time.  Each one is a complete search on its own song:
+optimisation steps of the full console, then pruning rounds (batched trials,
+the decision rule, fine-tune steps under the new mask).  The server
+
+  * admits an arrived request as soon as a slot is free and its device
+    footprint (workspace, tensors, Adam moments) fits the memory budget;
+  * keeps every admitted search's state resident on the device until it
+    retires (dry tracks, target features, parameters, moments, masks);
+  * gives every active search its own HIP stream (default priority) and
+    enqueues its work in quanta, so the kernels of different searches
+    overlap on the GPU while the host prepares the next quanta;
+  * reads a search's losses back only at its pruning decisions, waiting on
+    events of that search's stream, never on the whole device.
+
+Every search is a coroutine that yields a HIP event after each enqueued
+quantum; the loop resumes it when the event has completed.  The arithmetic
+of every step runs in libmixgraph; this module schedules and moves buffers.
+Results of a search depend on its own inputs only (the kernels use no
+atomics and no state shared between graphs), so a search gives the same bits
+alone and in the mix.
+"""
+from __future__ import annotations
+
+import collections
+import dataclasses
+import time
+from typing import Callable, Dict, List, Optional
+
+import numpy as np
+
+from . import mixgraph as MG
+from . import workloads as W
+
+
+@dataclasses.dataclass(frozen=True)
+class SearchSpec:
+    steps: int = 300          # optimisation steps before pruning
+    rounds: int = 10          # pruning rounds
+    finetune: int = 50        # fine-tune steps after each round
+    tau: float = 1e-3         # relative loss tolerance of a round
+    candidates: int = 64      # trials per round
+    lr: float = 1e-2
+    quantum: int = 4          # steps enqueued before yielding to the loop
+
+
+class Search:
+    """One request: host inputs, device state, and its search coroutine."""
+
+    def __init__(self, rid: int, cfg, seed: int, spec: SearchSpec, song=None, params=None):
+        import synth
+        self.rid, self.cfg, self.seed, self.spec = rid, cfg, seed, spec
+        self.g, self.dry, self.noise = song if song is not None else synth.song(seed, cfg)
+        self.gt = synth.ground_truth_params(seed + 100, self.g, cfg)
+        self.init = params if params is not None else synth.init_params(seed, self.g, cfg)
+        self.bg = W.binding_graph(self.g, cfg, max_trials=spec.candidates)
+        P, nt = self.bg.n_proc, self.bg.n_theta
+        self.ws_bytes = MG.mg_workspace_size(self.bg.h, 1)
+        # workspace + dry + noise + target + mix + theta/wet with grads and moments
+        self.bytes = (self.ws_bytes + self.dry.nbytes + sum(n.nbytes for n in self.noise.values())
+                      + 3 * 2 * cfg.length * 4 + 5 * 4 * (nt + P))
+        self.trace: List[Dict] = []
+        self.result: Optional[Dict] = None
+
+    # ------------------------------------------------------------ device state
+    def _setup(self, torch, dev):
+        cfg, bg = self.cfg, self.bg
+        self.dry_d = torch.from_numpy(self.dry).to(dev)
+        self.noise_d = torch.from_numpy(W.noise_rows(bg, self.noise, cfg.reverb_length)).to(dev)
+        th_gt, we_gt = bg.flatten(*self.gt)
+        self.target_d = torch.zeros(2, cfg.length, device=dev)
+        # the target: the same console with ground-truth parameters, rendered by
+        # the library; the search's session is set up once the target holds it
+        render = MG.Session(bg, self.noise_d, self.target_d, mode=0)
+        render.forward(self.dry_d, torch.from_numpy(th_gt).to(dev), torch.from_numpy(we_gt).to(dev), None,
+                       self.target_d)
+        del render
+        self.sess = MG.Session(bg, self.noise_d, self.target_d, mode=1)
+        th, we = bg.flatten(*self.init)
+        self.theta = torch.from_numpy(th).to(dev)
+        self.wet = torch.from_numpy(we).to(dev)
+        self.gth = torch.empty_like(self.theta)
+        self.gwe = torch.empty_like(self.wet)
+        self.m_t, self.v_t = torch.zeros_like(self.theta), torch.zeros_like(self.theta)
+        self.m_w, self.v_w = torch.zeros_like(self.wet), torch.zeros_like(self.wet)
+        self.mask = torch.ones(bg.n_proc, device=dev)
+        self.alive = np.ones(bg.n_proc, np.uint8)
+        self.losses = torch.zeros(7, dtype=torch.float64, device=dev)
+        self.n_step = 0
+
+    def _step(self):
+        s = self.sess
+        st = s.stream()
+        self.n_step += 1
+        s.forward(self.dry_d, self.theta, self.wet, self.mask, None, self.losses)
+        s.backward(self.gth, self.gwe)
+        MG.mg_adam_step(self.theta, self.m_t, self.v_t, self.gth, self.bg.n_theta, self.spec.lr, 0.9, 0.999, 1e-8,
+                        self.n_step, st)
+        MG.mg_adam_step(self.wet, self.m_w, self.v_w, self.gwe, self.bg.n_proc, self.spec.lr, 0.9, 0.999, 1e-8,
+                        self.n_step, st)
+
+    def run(self, torch, dev):
+        """The search as a coroutine: yields an event after each quantum."""
+        spec = self.spec
+        self._setup(torch, dev)
+
+        def mark():
+            ev = torch.cuda.Event()
+            ev.record()
+            return ev
+
+        yield mark()
+        for i in range(spec.steps):
+            self._step()
+            if (i + 1) % spec.quantum == 0:
+                yield mark()
+        yield mark()
+        P = self.bg.n_proc
+        for r in range(spec.rounds):
+            # forward at the current mask, then single-bypass trials
+            self.sess.forward(self.dry_d, self.theta, self.wet, self.mask, None, self.losses)
+            yield mark()
+            L_min = float(self.losses[1].item())
+            cand = MG.mg_prune_candidates(self.wet.cpu().numpy(), self.mask.cpu().numpy(), self.alive,
+                                          spec.candidates)
+            out = torch.zeros(max(1, len(cand)), 7, dtype=torch.float64, device=dev)
+            if len(cand):
+                keep = np.ones((len(cand), P), np.uint8)
+                keep[np.arange(len(cand)), cand] = 0
+                self.sess.forward_trials(keep, out)
+                yield mark()
+            L_cand = out[:len(cand), 1].cpu().numpy()
+            order = MG.mg_prune_order(cand, L_cand, L_min, spec.tau) if len(cand) else np.zeros(0, np.int32)
+            k = 0
+            if len(order):
+                keep = np.ones((len(order), P), np.uint8)
+                for j in range(len(order)):
+                    keep[j, order[:j + 1]] = 0
+                outp = torch.zeros(len(order), 7, dtype=torch.float64, device=dev)
+                self.sess.forward_trials(keep, outp)
+                yield mark()
+                L_prefix = outp[:, 1].cpu().numpy()
+                k = MG.mg_prune_accept(L_prefix, L_min, spec.tau)
+            if k:
+                self.alive[order[:k]] = 0
+                self.mask = torch.from_numpy(self.alive.astype(np.float32)).to(dev)
+            self.trace.append({"round": r, "L_min": L_min, "candidates": len(cand), "within": len(order),
+                               "removed": int(k), "alive": int(self.alive.sum())})
+            for i in range(spec.finetune):
+                self._step()
+                if (i + 1) % spec.quantum == 0:
+                    yield mark()
+            yield mark()
+        # final loss at the final parameters and mask
+        self.sess.forward(self.dry_d, self.theta, self.wet, self.mask, None, self.losses)
+        yield mark()
+        self.result = {"losses": self.losses.cpu().numpy().copy(), "theta": self.theta.cpu().numpy().copy(),
+                       "wet": self.wet.cpu().numpy().copy(), "alive": self.alive.copy(), "trace": list(self.trace)}
+
+    def release(self):
+        for name in ("sess", "dry_d", "noise_d", "target_d", "theta", "wet", "gth", "gwe", "m_t", "v_t", "m_w",
+                     "v_w", "mask", "losses"):
+            if hasattr(self, name):
+                delattr(self, name)
+
+
+class Admission:
+    """Which arrived requests may start now: first come, first served, while
+    a slot is free and the footprint fits the budget (a request larger than
+    the whole budget runs alone)."""
+
+    def __init__(self, budget_bytes: int, max_active: int):
+        self.budget = budget_bytes
+        self.max_active = max_active
+        self.used = 0
+        self.active = 0
+
+    def can_admit(self, nbytes: int) -> bool:
+        if self.active >= self.max_active:
+            return False
+        return self.used + nbytes <= self.budget or self.active == 0
+
+    def admit(self, nbytes: int):
+        self.used += nbytes
+        self.active += 1
+
+    def retire(self, nbytes: int):
+        self.used -= nbytes
+        self.active -= 1
+
+
+class Server:
+    def __init__(self, budget_bytes: int, max_active: int = 8, device: str = "cuda"):
+        self.adm = Admission(budget_bytes, max_active)
+        self.device = device
+
+    def run(self, arrivals: List[tuple], make_search: Callable[[int, object, int], Search],
+            clock=time.perf_counter) -> Dict:
+        """arrivals: (arrival time s, cfg, seed) sorted by time.  Requests are
+        built on the host ahead of time (data preparation is not search
+        latency); each is admitted at or after its arrival time."""
+        import torch
+        searches = [make_search(i, cfg, seed) for i, (_, cfg, seed) in enumerate(arrivals)]
+        pending = collections.deque(range(len(arrivals)))
+        active: Dict[int, tuple] = {}
+        t0 = clock()
+        start, finish, admitted_at = {}, {}, {}
+        peak_active, peak_bytes = 0, 0
+        while pending or active:
+            now = clock() - t0
+            while pending and arrivals[pending[0]][0] <= now and self.adm.can_admit(searches[pending[0]].bytes):
+                i = pending.popleft()
+                self.adm.admit(searches[i].bytes)
+                stream = torch.cuda.Stream(device=self.device)
+                with torch.cuda.stream(stream):
+                    co = searches[i].run(torch, self.device)
+                    ev = next(co)
+                active[i] = (co, stream, ev)
+                admitted_at[i] = now
+                peak_active = max(peak_active, len(active))
+                peak_bytes = max(peak_bytes, self.adm.used)
+            progressed = False
+            for i in list(active):
+                co, stream, ev = active[i]
+                if not ev.query():
+                    continue
+                progressed = True
+                with torch.cuda.stream(stream):
+                    try:
+                        ev = next(co)
+                        active[i] = (co, stream, ev)
+                    except StopIteration:
+                        finish[i] = clock() - t0
+                        searches[i].release()
+                        self.adm.retire(searches[i].bytes)
+                        del active[i]
+            if not progressed:
+                if not active and pending:
+                    wait = arrivals[pending[0]][0] - (clock() - t0)
+                    if wait > 0:
+                        time.sleep(min(wait, 0.05))
+                else:
+                    time.sleep(50e-6)
+        lat = np.array([finish[i] - arrivals[i][0] for i in range(len(arrivals))])
+        audio = sum(cfg.seconds * (s.spec.steps + s.spec.rounds * s.spec.finetune)
+                    for (_, cfg, _), s in zip(arrivals, searches))
+        span = max(finish.values()) - min(a[0] for a in arrivals) if arrivals else 0.0
+        return {"results": [s.result for s in searches], "latency_s": lat.tolist(),
+                "p50_s": float(np.percentile(lat, 50)), "p99_s": float(np.percentile(lat, 99)),
+                "songs_per_s": len(arrivals) / span if span > 0 else 0.0,
+                "audio_s_per_s": audio / span if span > 0 else 0.0, "makespan_s": span,
+                "peak_active": peak_active, "peak_bytes": peak_bytes,
+                "queue_wait_s": [admitted_at[i] - arrivals[i][0] for i in range(len(arrivals))]}
+
+
+def run_alone(search: Search, device: str = "cuda") -> Dict:
+    """One search by itself on its own stream (the reference for the mix)."""
+    import torch
+    stream = torch.cuda.Stream(device=device)
+    with torch.cuda.stream(stream):
+        for ev in search.run(torch, device):
+            ev.synchronize()
+    res = search.result
+    search.release()
+    return res

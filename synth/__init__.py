@@ -463,3 +463,25 @@ def song(seed: int, cfg: ConsoleConfig):
     dry = dry_tracks(seed, cfg)
     noise = reverb_noise_all(seed, graph, cfg)
     return graph, dry, noise
+
+
+# ---------------------------------------------------------------------------
+# serving workload: whole-song searches arriving over time
+# ---------------------------------------------------------------------------
+def serving_requests(seed: int, n: int, rate: float, tracks=(4, 32), subgroups=(2, 8), seconds=(5.0, 30.0),
+                     fs: int = 44100, chain: str = "ecxsgdr", **kw) -> List[Tuple[float, ConsoleConfig, int]]:
+    """n requests: (arrival time in s, console sizes, song seed).  Arrivals
+    form a Poisson process of the given rate (exponential gaps); tracks and
+    subgroups are uniform integers in the closed ranges (subgroups capped at
+    the track count), lengths uniform in seconds."""
+    rng = _rng(seed, 4099)
+    t = 0.0
+    out = []
+    for i in range(n):
+        t += float(rng.exponential(1.0 / rate)) if rate > 0 else 0.0
+        k = int(rng.integers(tracks[0], tracks[1] + 1))
+        s = min(k, int(rng.integers(subgroups[0], subgroups[1] + 1)))
+        sec = round(float(rng.uniform(seconds[0], seconds[1])), 3)
+        cfg = ConsoleConfig(f"request{i}", k, s, sec, fs, True, chain=chain, **kw)
+        out.append((t, cfg, int(seed * 1000 + i)))
+    return out
