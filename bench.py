@@ -220,10 +220,11 @@ def cpu_baseline(cfg_name, budget_s=20.0):
 
 
 # ---------------------------------------------------------------- traffic
-def committed_traffic(kernel_class):
+def committed_traffic(kernel_class, workload):
     """HBM bytes per launch from the committed rocprofv3 PMC summary of this
-    kernel class, if it was taken on the current kernel sources; else None."""
-    path = os.path.join(ROOT, "profiles", f"{kernel_class}_traffic.json")
+    kernel class and workload, if it was taken on the current kernel sources;
+    else None."""
+    path = os.path.join(ROOT, "profiles", f"{kernel_class}_{workload}_console_traffic.json")
     if not os.path.exists(path):
         return None
     try:
@@ -238,6 +239,27 @@ def committed_traffic(kernel_class):
         return None
 
 
+def serving_leg(args):
+    """Whole-song searches arriving as a Poisson stream, served with
+    continuous batching (serve.Server): p50/p99 latency and throughput."""
+    import synth
+    from paper_2509_15948_amd import serve as SV
+    reqs = synth.serving_requests(3, args.serve_requests, rate=args.serve_rate, tracks=(4, 16), subgroups=(2, 4),
+                                  seconds=(2.0, 6.0), fs=44100)
+    spec = SV.SearchSpec(steps=args.serve_steps, rounds=2, finetune=5, tau=1e-3, candidates=16, quantum=4)
+    server = SV.Server(budget_bytes=int(args.serve_budget_gb * (1 << 30)), max_active=4)
+    out = server.run(reqs, lambda i, cfg, seed: SV.Search(i, cfg, seed, spec))
+    removed = [sum(r["removed"] for r in res["trace"]) for res in out["results"]]
+    return {"requests": len(reqs), "rate_per_s": args.serve_rate,
+            "workload": f"tracks U{{4..16}}, subgroups U{{2..4}}, 2-6 s at 44.1 kHz, chain ecxsgdr; search = "
+                        f"{spec.steps} steps + {spec.rounds} pruning rounds x ({spec.candidates} trials + "
+                        f"{spec.finetune} fine-tune steps)",
+            "p50_latency_s": round(out["p50_s"], 4), "p99_latency_s": round(out["p99_s"], 4),
+            "songs_per_s": round(out["songs_per_s"], 3), "audio_s_per_s": round(out["audio_s_per_s"], 1),
+            "makespan_s": round(out["makespan_s"], 3), "peak_active": out["peak_active"],
+            "peak_gb": round(out["peak_bytes"] / (1 << 30), 3), "processors_removed": removed}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -247,6 +269,13 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain-loop", action="store_true")
     ap.add_argument("--prune-masks", type=int, default=64)
+    ap.add_argument("--serve-requests", type=int, default=12,
+                    help="requests of the serving leg (0 skips it)")
+    ap.add_argument("--serve-rate", type=float, default=20.0, help="Poisson arrival rate, requests/s")
+    ap.add_argument("--serve-steps", type=int, default=20, help="optimisation steps per search")
+    ap.add_argument("--serve-budget-gb", type=float, default=64.0)
+    ap.add_argument("--pmc-run", action="store_true",
+                    help="for rocprofv3 counter runs: a calibration copy, then --steps steps, nothing else")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py runs on one GPU only: the console of one song lives on one device "
@@ -301,6 +330,18 @@ def main():
     torch.cuda.synchronize()
     log(f"warm-up done, loss {losses.cpu().numpy()[1]:.4f}")
 
+    if args.pmc_run:
+        from paper_2509_15948_amd.profiling import CALIB_BYTES
+        src = torch.ones(CALIB_BYTES // 4, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)          # calibration: CALIB_BYTES read and written once
+        torch.cuda.synchronize()
+        for _ in range(args.steps):
+            step()
+        torch.cuda.synchronize()
+        log(f"pmc run: calibration copy of {CALIB_BYTES} bytes, then {args.steps} steps")
+        return
+
     # one profiled step per kernel class to find the dominant one
     per_class = {}
     for cls in KERNEL_CLASSES:
@@ -332,7 +373,7 @@ def main():
     achieved = (k_bytes / k_n) / ((k_ms / k_n) / 1000.0) / 1e9 if k_n else 0.0
     roofline = {"bound": "hbm", "kernel": dominant, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": committed_traffic(dominant),
+                "traffic": committed_traffic(dominant, args.config),
                 "launches": k_n, "avg_launch_us": round(1000.0 * k_ms / max(k_n, 1), 2),
                 "alg_bytes_per_launch": round(k_bytes / max(k_n, 1))}
     mb = model_bytes_per_step(g, cfg)
@@ -386,6 +427,13 @@ def main():
         except Exception as e:  # the baseline must not break the headline
             plain = {"error": repr(e)[:200]}
 
+    serving = None
+    if args.serve_requests > 0:
+        try:
+            serving = serving_leg(args)
+        except Exception as e:  # the serving leg must not break the headline
+            serving = {"error": repr(e)[:300]}
+
     cpu = None
     if not args.no_cpu_baseline:
         try:
@@ -414,9 +462,14 @@ def main():
                    "fft_size": bg.info.fft_size, "parallelism": "single GPU"},
         "roofline": roofline,
         "hbm_model": hbm_model,
-        "kernel_ms_per_step": {k: round(v[0], 4) for k, v in per_class.items()},
+        "kernel_classes": {k: {"ms_per_step": round(v[0], 4), "launches": v[1],
+                               "alg_bytes_per_launch": round(v[2] / max(v[1], 1)),
+                               "alg_GBs": round(v[2] / (v[0] / 1000.0) / 1e9, 1) if v[0] > 0 else None,
+                               "traffic_bytes_per_launch": committed_traffic(k, args.config)}
+                           for k, v in per_class.items()},
         "prune_eval": prune,
         "plain_loop": plain,
+        "serving": serving,
         "cpu_baseline": cpu,
     }
     print(json.dumps(rec), flush=True)

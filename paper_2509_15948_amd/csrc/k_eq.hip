@@ -16,6 +16,7 @@
 namespace mg {
 
 constexpr int EQ_P = 8192;
+constexpr int EQ_NT = 1024;   // threads per block: 16 waves keep the CU busy at one or two blocks per CU
 
 struct EqArgs {
   const NodeDesc* desc;
@@ -37,6 +38,7 @@ struct EqArgs {
   int C, N, V, nblk;
   float alpha_g;
   const float2* tw;
+  const float2* twdl;
 };
 
 __device__ __forceinline__ const float* eq_input(const EqArgs& a, const NodeDesc& d, int64_t& cs) {
@@ -49,14 +51,14 @@ __device__ __forceinline__ const float* eq_input(const EqArgs& a, const NodeDesc
 }
 
 // H_P of every node of the stage: grid (nodes)
-__global__ __launch_bounds__(MG_BLOCK) void k_eq_spec(EqArgs a) {
+__global__ __launch_bounds__(EQ_NT) void k_eq_spec(EqArgs a) {
   __shared__ float2 buf[EQ_P];
   __shared__ TwTab<EQ_P, float2> tt;
-  tw_fill<EQ_P>(tt, a.tw);
+  tw_fill<EQ_P>(tt, a.tw, a.twdl);
   const NodeDesc d = a.desc[blockIdx.x];
   const float* h = a.h + (int64_t)d.aux * a.N;
   const int half = (a.N - 1) / 2;
-  for (int i = threadIdx.x; i < EQ_P; i += MG_BLOCK) {
+  for (int i = threadIdx.x; i < EQ_P; i += EQ_NT) {
     // circular position i holds tap m = i (i <= half) or m = i - P (i >= P - half)
     float v = 0.f;
     if (i <= half) v = h[half + i];
@@ -64,38 +66,38 @@ __global__ __launch_bounds__(MG_BLOCK) void k_eq_spec(EqArgs a) {
     buf[i] = make_float2(v, 0.f);
   }
   __syncthreads();
-  fft_lds<EQ_P, 1, EQ_P, MG_BLOCK, -1>(buf, tt);
+  fft_lds<EQ_P, 1, EQ_P, EQ_NT, -1>(buf, tt);
   float* o = a.HP + (int64_t)d.aux * EQ_P;
-  for (int i = threadIdx.x; i < EQ_P; i += MG_BLOCK) o[i] = buf[i].x;
+  for (int i = threadIdx.x; i < EQ_P; i += EQ_NT) o[i] = buf[i].x;
 }
 
 // forward: grid (nblk, nodes)
-__global__ __launch_bounds__(MG_BLOCK) void k_eq_fwd(EqArgs a) {
+__global__ __launch_bounds__(EQ_NT) void k_eq_fwd(EqArgs a) {
   __shared__ float2 buf[EQ_P];
-  __shared__ float red[MG_BLOCK];
+  __shared__ float red[EQ_NT];
   __shared__ TwTab<EQ_P, float2> tt;
-  tw_fill<EQ_P>(tt, a.tw);
+  tw_fill<EQ_P>(tt, a.tw, a.twdl);
   const int j = blockIdx.y, blk = blockIdx.x;
   const NodeDesc d = a.desc[j];
   int64_t cs;
   const float* u = eq_input(a, d, cs);
   const int half = (a.N - 1) / 2;
   const int64_t s0 = (int64_t)blk * a.V - half;   // window start
-  for (int i = threadIdx.x; i < EQ_P; i += MG_BLOCK) {
+  for (int i = threadIdx.x; i < EQ_P; i += EQ_NT) {
     const int64_t n = s0 + i;
     buf[i] = (n >= 0 && n < a.L) ? make_float2(u[n], u[cs + n]) : make_float2(0.f, 0.f);
   }
   __syncthreads();
-  fft_lds<EQ_P, 1, EQ_P, MG_BLOCK, -1>(buf, tt);
+  fft_lds<EQ_P, 1, EQ_P, EQ_NT, -1>(buf, tt);
   const float* H = a.HP + (int64_t)d.aux * EQ_P;
-  for (int i = threadIdx.x; i < EQ_P; i += MG_BLOCK) buf[i] = c_scale(buf[i], H[i] * (1.0f / EQ_P));
+  for (int i = threadIdx.x; i < EQ_P; i += EQ_NT) buf[i] = c_scale(buf[i], H[i] * (1.0f / EQ_P));
   __syncthreads();
-  fft_lds<EQ_P, 1, EQ_P, MG_BLOCK, +1>(buf, tt);
+  fft_lds<EQ_P, 1, EQ_P, EQ_NT, +1>(buf, tt);
   float w = node_w(a.wet, a.mask, d);
   float* y = a.Uo + (int64_t)d.out_slot * 2 * a.L;
   float* yb = a.ybar ? a.ybar + (int64_t)d.aux * 2 * a.L : nullptr;
   float ey = 0.f, eu = 0.f;
-  for (int i = half + threadIdx.x; i < half + a.V; i += MG_BLOCK) {
+  for (int i = half + threadIdx.x; i < half + a.V; i += EQ_NT) {
     const int64_t n = s0 + i;
     if (n >= a.L) break;
     const float2 v = buf[i];
@@ -110,8 +112,8 @@ __global__ __launch_bounds__(MG_BLOCK) void k_eq_fwd(EqArgs a) {
     ey += m * m;
     eu += um * um;
   }
-  const float sa = block_sum<MG_BLOCK>(ey, red);
-  const float sb = block_sum<MG_BLOCK>(eu, red);
+  const float sa = block_sum<EQ_NT>(ey, red);
+  const float sb = block_sum<EQ_NT>(eu, red);
   if (threadIdx.x == 0) {
     float* pr = a.part + ((int64_t)j * a.PB + blk) * PK;
     pr[0] = sa;
@@ -120,12 +122,12 @@ __global__ __launch_bounds__(MG_BLOCK) void k_eq_fwd(EqArgs a) {
 }
 
 // backward: grid (nblk, nodes); LDS holds two P-point windows (128 KB)
-__global__ __launch_bounds__(MG_BLOCK) void k_eq_bwd(EqArgs a) {
+__global__ __launch_bounds__(EQ_NT) void k_eq_bwd(EqArgs a) {
   __shared__ float2 A[EQ_P];
   __shared__ float2 B[EQ_P];
-  __shared__ float red[MG_BLOCK];
+  __shared__ float red[EQ_NT];
   __shared__ TwTab<EQ_P, float2> tt;
-  tw_fill<EQ_P>(tt, a.tw);
+  tw_fill<EQ_P>(tt, a.tw, a.twdl);
   const int j = blockIdx.y, blk = blockIdx.x;
   const NodeDesc d = a.desc[j];
   int64_t cs;
@@ -141,7 +143,7 @@ __global__ __launch_bounds__(MG_BLOCK) void k_eq_bwd(EqArgs a) {
   const float ky = (float)((double)a.alpha_g * sgn / Ey), ku = (float)((double)a.alpha_g * sgn / Eu);
   // dL/dybar over the whole window (A) and over the valid part only (B)
   float dw = 0.f;
-  for (int i = threadIdx.x; i < EQ_P; i += MG_BLOCK) {
+  for (int i = threadIdx.x; i < EQ_P; i += EQ_NT) {
     const int64_t n = s0 + i;
     float2 g = make_float2(0.f, 0.f);
     if (n >= 0 && n < a.L) {
@@ -158,11 +160,11 @@ __global__ __launch_bounds__(MG_BLOCK) void k_eq_bwd(EqArgs a) {
   const float* H = a.HP + (int64_t)d.aux * EQ_P;
   float* gin = d.gin >= 0 ? a.G + (int64_t)d.gin * 2 * a.L : nullptr;
   if (gin) {
-    fft_lds<EQ_P, 1, EQ_P, MG_BLOCK, -1>(A, tt);
-    for (int i = threadIdx.x; i < EQ_P; i += MG_BLOCK) A[i] = c_scale(A[i], H[i] * (1.0f / EQ_P));
+    fft_lds<EQ_P, 1, EQ_P, EQ_NT, -1>(A, tt);
+    for (int i = threadIdx.x; i < EQ_P; i += EQ_NT) A[i] = c_scale(A[i], H[i] * (1.0f / EQ_P));
     __syncthreads();
-    fft_lds<EQ_P, 1, EQ_P, MG_BLOCK, +1>(A, tt);
-    for (int i = half + threadIdx.x; i < half + a.V; i += MG_BLOCK) {
+    fft_lds<EQ_P, 1, EQ_P, EQ_NT, +1>(A, tt);
+    for (int i = half + threadIdx.x; i < half + a.V; i += EQ_NT) {
       const int64_t n = s0 + i;
       if (n >= a.L) break;
       const float um = u[n] + u[cs + n];
@@ -172,23 +174,23 @@ __global__ __launch_bounds__(MG_BLOCK) void k_eq_bwd(EqArgs a) {
     __syncthreads();
   }
   // FIR gradient: correlate the valid-part gradient (B) with the input window (A)
-  for (int i = threadIdx.x; i < EQ_P; i += MG_BLOCK) {
+  for (int i = threadIdx.x; i < EQ_P; i += EQ_NT) {
     const int64_t n = s0 + i;
     A[i] = (n >= 0 && n < a.L) ? make_float2(u[n], u[cs + n]) : make_float2(0.f, 0.f);
   }
   __syncthreads();
-  fft_lds<EQ_P, 1, EQ_P, MG_BLOCK, -1>(A, tt);
-  fft_lds<EQ_P, 1, EQ_P, MG_BLOCK, -1>(B, tt);
-  for (int i = threadIdx.x; i < EQ_P; i += MG_BLOCK) B[i] = c_scale(c_mulc(B[i], A[i]), 1.0f / EQ_P);
+  fft_lds<EQ_P, 1, EQ_P, EQ_NT, -1>(A, tt);
+  fft_lds<EQ_P, 1, EQ_P, EQ_NT, -1>(B, tt);
+  for (int i = threadIdx.x; i < EQ_P; i += EQ_NT) B[i] = c_scale(c_mulc(B[i], A[i]), 1.0f / EQ_P);
   __syncthreads();
-  fft_lds<EQ_P, 1, EQ_P, MG_BLOCK, +1>(B, tt);
+  fft_lds<EQ_P, 1, EQ_P, EQ_NT, +1>(B, tt);
   // lag m sits at circular index m mod P; dh index = m + half
   float* o = a.dhp + ((int64_t)d.aux * a.nblk + blk) * a.N;
-  for (int t = threadIdx.x; t < a.N; t += MG_BLOCK) {
+  for (int t = threadIdx.x; t < a.N; t += EQ_NT) {
     const int m = t - half;
     o[t] = B[m >= 0 ? m : m + EQ_P].x;
   }
-  const float s = block_sum<MG_BLOCK>(dw, red);
+  const float s = block_sum<EQ_NT>(dw, red);
   if (threadIdx.x == 0) a.part[((int64_t)j * a.PB + blk) * PK + 2] = s;
 }
 
@@ -228,6 +230,7 @@ static EqArgs eq_args(const Ctx& c, int desc_off, bool keep) {
   a.nblk = (int)((c.L + a.V - 1) / a.V);
   a.alpha_g = c.alpha_g;
   a.tw = wsp<float2>(c, g->ws.tw);
+  a.twdl = wsp<float2>(c, g->ws.twdl);
   return a;
 }
 
@@ -240,11 +243,11 @@ void eq_forward(const Ctx& c, int desc_off, int n, bool keep) {
   EqArgs a = eq_args(c, desc_off, keep);
   if (!c.trial) {
     ProfScope ps(c, "eq_spec", (double)n * (4.0 * a.N + 4.0 * EQ_P));
-    hipLaunchKernelGGL(k_eq_spec, dim3(n), dim3(MG_BLOCK), 0, c.st, a);
+    hipLaunchKernelGGL(k_eq_spec, dim3(n), dim3(EQ_NT), 0, c.st, a);
   }
   {
     ProfScope ps(c, "eq_conv", (double)n * ((8.0 * EQ_P) * a.nblk + (keep ? 16.0 : 8.0) * c.L + 8.0 * c.L));
-    hipLaunchKernelGGL(k_eq_fwd, dim3(a.nblk, n), dim3(MG_BLOCK), 0, c.st, a);
+    hipLaunchKernelGGL(k_eq_fwd, dim3(a.nblk, n), dim3(EQ_NT), 0, c.st, a);
   }
   launch_reduce_lg(c, desc_off, n, a.nblk);
 }
@@ -254,7 +257,7 @@ void eq_backward(const Ctx& c, int desc_off, int n) {
   {
     // reads dL/dy, ybar, u (window each) and u again; writes dL/du and the block FIR gradients
     ProfScope ps(c, "eq_conv", (double)n * ((24.0 * EQ_P) * a.nblk + 16.0 * c.L + 4.0 * a.N * a.nblk));
-    hipLaunchKernelGGL(k_eq_bwd, dim3(a.nblk, n), dim3(MG_BLOCK), 0, c.st, a);
+    hipLaunchKernelGGL(k_eq_bwd, dim3(a.nblk, n), dim3(EQ_NT), 0, c.st, a);
   }
   hipLaunchKernelGGL(k_eq_dh_reduce, dim3((a.N + MG_BLOCK - 1) / MG_BLOCK, n), dim3(MG_BLOCK), 0, c.st, a);
 }

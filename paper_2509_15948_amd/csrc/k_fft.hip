@@ -22,6 +22,13 @@
 
 namespace mg {
 
+// threads per block: the column kernels hold 64 KB of LDS (two blocks per
+// CU), so 512 threads give 16 waves per CU; row kernels use 512 threads from
+// N1 = 1024 up (fewer rows of butterflies below)
+constexpr int COL_NT = 512;
+template <int N1>
+constexpr int row_nt() { return N1 >= 1024 ? 512 : 256; }
+
 // W_N^e for e in [0, N), from two FP32 tables rounded from FP64 on the host:
 // twhi[j] = W_N^{1024 j}, twlo[j] = W_N^j.
 __device__ __forceinline__ float2 big_tw(const float2* __restrict__ twhi, const float2* __restrict__ twlo, int64_t e) {
@@ -33,6 +40,7 @@ __device__ __forceinline__ int64_t signed_lag(int64_t n, int64_t N) { return n <
 struct EngineArgs {
   int N, N1, N2;
   const float2* tw;
+  const float2* twdl;
   const float2* twhi;
   const float2* twlo;
 };
@@ -150,8 +158,8 @@ struct LdGrad {
     return make_float2(w * gl + rm, w * gr + rm);
   }
   __device__ void end(int j, int blk) {
-    __shared__ float red[MG_BLOCK];
-    const float s = block_sum<MG_BLOCK>(acc, red);
+    __shared__ float red[COL_NT];
+    const float s = block_sum<COL_NT>(acc, red);
     if (threadIdx.x == 0) part[((int64_t)j * PB + blk) * PK + 2] = s;
   }
 };
@@ -193,9 +201,9 @@ struct StFwd {
     eu += um * um;
   }
   __device__ void end(int j, int blk) {
-    __shared__ float red[MG_BLOCK];
-    const float a = block_sum<MG_BLOCK>(ey, red);
-    const float b = block_sum<MG_BLOCK>(eu, red);
+    __shared__ float red[COL_NT];
+    const float a = block_sum<COL_NT>(ey, red);
+    const float b = block_sum<COL_NT>(eu, red);
     if (threadIdx.x == 0) {
       part[((int64_t)j * PB + blk) * PK + 0] = a;
       part[((int64_t)j * PB + blk) * PK + 1] = b;
@@ -259,25 +267,25 @@ struct StGradH {
 
 // ---------------------------------------------------------------- KA: columns forward
 template <int N2, int TC, typename LD>
-__global__ __launch_bounds__(MG_BLOCK) void k_cols(LD ld, float2* __restrict__ T, EngineArgs ea) {
+__global__ __launch_bounds__(COL_NT) void k_cols(LD ld, float2* __restrict__ T, EngineArgs ea) {
   constexpr int BS = N2 + 1;
   __shared__ float2 buf[TC * BS];
   __shared__ TwTab<N2, float2> tt;
-  tw_fill<N2>(tt, ea.tw);
+  tw_fill<N2>(tt, ea.tw, ea.twdl);
   const int j = blockIdx.y;
   const int c0 = blockIdx.x * TC;
   const int N1 = ea.N1;
   ld.begin(j);
-  for (int idx = threadIdx.x; idx < TC * N2; idx += MG_BLOCK) {
+  for (int idx = threadIdx.x; idx < TC * N2; idx += COL_NT) {
     const int n2 = idx / TC, cc = idx % TC;
     buf[cc * BS + n2] = ld.load((int64_t)(c0 + cc) + (int64_t)N1 * n2);
   }
   ld.end(j, blockIdx.x);
   __syncthreads();
-  fft_lds<N2, TC, BS, MG_BLOCK, -1>(buf, tt);
+  fft_lds<N2, TC, BS, COL_NT, -1>(buf, tt);
   float2* Tn = T + (int64_t)j * ea.N;
   const int64_t mask = ea.N - 1;
-  for (int idx = threadIdx.x; idx < TC * N2; idx += MG_BLOCK) {
+  for (int idx = threadIdx.x; idx < TC * N2; idx += COL_NT) {
     const int k2 = idx / TC, cc = idx % TC;
     const int n1 = c0 + cc;
     const float2 w = big_tw(ea.twhi, ea.twlo, ((int64_t)n1 * k2) & mask);
@@ -287,24 +295,24 @@ __global__ __launch_bounds__(MG_BLOCK) void k_cols(LD ld, float2* __restrict__ T
 
 // ---------------------------------------------------------------- KC: columns inverse
 template <int N2, int TC, typename ST>
-__global__ __launch_bounds__(MG_BLOCK) void k_icols(ST st, const float2* __restrict__ T, EngineArgs ea) {
+__global__ __launch_bounds__(COL_NT) void k_icols(ST st, const float2* __restrict__ T, EngineArgs ea) {
   constexpr int BS = N2 + 1;
   __shared__ float2 buf[TC * BS];
   __shared__ TwTab<N2, float2> tt;
-  tw_fill<N2>(tt, ea.tw);
+  tw_fill<N2>(tt, ea.tw, ea.twdl);
   const int j = blockIdx.y;
   const int c0 = blockIdx.x * TC;
   const int N1 = ea.N1;
   const float2* Tn = T + (int64_t)j * ea.N;
-  for (int idx = threadIdx.x; idx < TC * N2; idx += MG_BLOCK) {
+  for (int idx = threadIdx.x; idx < TC * N2; idx += COL_NT) {
     const int k2 = idx / TC, cc = idx % TC;
     buf[cc * BS + k2] = Tn[(int64_t)k2 * N1 + c0 + cc];
   }
   __syncthreads();
-  fft_lds<N2, TC, BS, MG_BLOCK, +1>(buf, tt);
+  fft_lds<N2, TC, BS, COL_NT, +1>(buf, tt);
   const float sc = 1.0f / (float)ea.N;
   st.begin(j);
-  for (int idx = threadIdx.x; idx < TC * N2; idx += MG_BLOCK) {
+  for (int idx = threadIdx.x; idx < TC * N2; idx += COL_NT) {
     const int n2 = idx / TC, cc = idx % TC;
     st.store((int64_t)(c0 + cc) + (int64_t)N1 * n2, c_scale(buf[cc * BS + n2], sc));
   }
@@ -353,7 +361,7 @@ __device__ __forceinline__ float2 pack_lr(float2 l, float2 r) {  // l + i r
 
 template <int N1>
 __device__ __forceinline__ void load_rows(float2* buf, const float2* __restrict__ Tn, int ra, int rb) {
-  for (int i = threadIdx.x; i < N1; i += MG_BLOCK) {
+  for (int i = threadIdx.x; i < N1; i += blockDim.x) {
     buf[i] = Tn[(int64_t)ra * N1 + i];
     buf[N1 + i] = Tn[(int64_t)rb * N1 + i];
   }
@@ -363,7 +371,7 @@ template <int N1>
 __device__ __forceinline__ void store_rows(const float2* buf, float2* __restrict__ To, int ra, int rb,
                                            const EngineArgs& ea) {
   const int64_t mask = ea.N - 1;
-  for (int i = threadIdx.x; i < N1; i += MG_BLOCK) {
+  for (int i = threadIdx.x; i < N1; i += blockDim.x) {
     float2 wa = big_tw(ea.twhi, ea.twlo, ((int64_t)i * ra) & mask);
     float2 wb = big_tw(ea.twhi, ea.twlo, ((int64_t)i * rb) & mask);
     To[(int64_t)ra * N1 + i] = c_mul(buf[i], c_conj(wa));
@@ -373,19 +381,19 @@ __device__ __forceinline__ void store_rows(const float2* buf, float2* __restrict
 
 // spectrum only: S rows of the FIR -> ZH
 template <int N1>
-__global__ __launch_bounds__(MG_BLOCK) void k_rows_spec(const float2* __restrict__ T, float2* __restrict__ Z,
+__global__ __launch_bounds__(row_nt<N1>()) void k_rows_spec(const float2* __restrict__ T, float2* __restrict__ Z,
                                                          int z0, const NodeDesc* __restrict__ desc, EngineArgs ea) {
   __shared__ float2 buf[2 * N1];
   __shared__ TwTab<N1, float2> tt;
-  tw_fill<N1>(tt, ea.tw);
+  tw_fill<N1>(tt, ea.tw, ea.twdl);
   const int j = blockIdx.y;
   int ra, rb;
   row_pair(blockIdx.x, ea.N2, ra, rb);
   load_rows<N1>(buf, T + (int64_t)j * ea.N, ra, rb);
   __syncthreads();
-  fft_lds<N1, 2, N1, MG_BLOCK, -1>(buf, tt);
+  fft_lds<N1, 2, N1, row_nt<N1>(), -1>(buf, tt);
   float2* Zn = Z + (int64_t)(z0 + desc[j].aux) * ea.N;
-  for (int i = threadIdx.x; i < N1; i += MG_BLOCK) {
+  for (int i = threadIdx.x; i < N1; i += row_nt<N1>()) {
     Zn[(int64_t)ra * N1 + i] = buf[i];
     Zn[(int64_t)rb * N1 + i] = buf[N1 + i];
   }
@@ -393,30 +401,30 @@ __global__ __launch_bounds__(MG_BLOCK) void k_rows_spec(const float2* __restrict
 
 // forward convolution: Y = Xl Hl + i Xr Hr
 template <int N1>
-__global__ __launch_bounds__(MG_BLOCK) void k_rows_conv(const float2* __restrict__ Tin, float2* __restrict__ Tout,
+__global__ __launch_bounds__(row_nt<N1>()) void k_rows_conv(const float2* __restrict__ Tin, float2* __restrict__ Tout,
                                                          const float2* __restrict__ ZH, float2* __restrict__ ZU,
                                                          int z0, const NodeDesc* __restrict__ desc, EngineArgs ea) {
   __shared__ float2 buf[2 * N1];
   __shared__ TwTab<N1, float2> tt;
-  tw_fill<N1>(tt, ea.tw);
+  tw_fill<N1>(tt, ea.tw, ea.twdl);
   const int j = blockIdx.y;
   const int p = blockIdx.x;
   int ra, rb;
   row_pair(p, ea.N2, ra, rb);
   load_rows<N1>(buf, Tin + (int64_t)j * ea.N, ra, rb);
   __syncthreads();
-  fft_lds<N1, 2, N1, MG_BLOCK, -1>(buf, tt);
+  fft_lds<N1, 2, N1, row_nt<N1>(), -1>(buf, tt);
   const int64_t zr = (int64_t)(z0 + desc[j].aux) * ea.N;
   const float2* H = ZH + zr;
   if (ZU) {  // keep the input spectrum for the backward
     float2* Zs = ZU + zr;
-    for (int i = threadIdx.x; i < N1; i += MG_BLOCK) {
+    for (int i = threadIdx.x; i < N1; i += row_nt<N1>()) {
       Zs[(int64_t)ra * N1 + i] = buf[i];
       Zs[(int64_t)rb * N1 + i] = buf[N1 + i];
     }
     __syncthreads();  // every bin stored before the product below overwrites it
   }
-  for (int q = threadIdx.x; q < N1 + 1; q += MG_BLOCK) {
+  for (int q = threadIdx.x; q < N1 + 1; q += row_nt<N1>()) {
     int ia, ib;
     if (!mirror_pair<N1>(p, q, ia, ib)) continue;
     const int64_t ga = (ia < N1) ? (int64_t)ra * N1 + ia : (int64_t)rb * N1 + (ia - N1);
@@ -434,21 +442,21 @@ __global__ __launch_bounds__(MG_BLOCK) void k_rows_conv(const float2* __restrict
     buf[ib] = yb;
   }
   __syncthreads();
-  fft_lds<N1, 2, N1, MG_BLOCK, +1>(buf, tt);
+  fft_lds<N1, 2, N1, row_nt<N1>(), +1>(buf, tt);
   store_rows<N1>(buf, Tout + (int64_t)j * ea.N, ra, rb, ea);
 }
 
 // backward: P1 = Gl conj(Hl) + i Gr conj(Hr)   (input gradient)
 //           P2 = Gl conj(Xl) + i Gr conj(Xr)   (FIR gradient)
 template <int N1>
-__global__ __launch_bounds__(MG_BLOCK) void k_rows_bwd(const float2* __restrict__ Tin, float2* __restrict__ Tu,
+__global__ __launch_bounds__(row_nt<N1>()) void k_rows_bwd(const float2* __restrict__ Tin, float2* __restrict__ Tu,
                                                         float2* __restrict__ Th, const float2* __restrict__ ZH,
                                                         const float2* __restrict__ ZU, int z0,
                                                         const NodeDesc* __restrict__ desc, int want_u,
                                                         EngineArgs ea) {
   __shared__ float2 buf[4 * N1];
   __shared__ TwTab<N1, float2> tt;
-  tw_fill<N1>(tt, ea.tw);
+  tw_fill<N1>(tt, ea.tw, ea.twdl);
   float2* b1 = buf;
   float2* b2 = buf + 2 * N1;
   const int j = blockIdx.y;
@@ -457,11 +465,11 @@ __global__ __launch_bounds__(MG_BLOCK) void k_rows_bwd(const float2* __restrict_
   row_pair(p, ea.N2, ra, rb);
   load_rows<N1>(b1, Tin + (int64_t)j * ea.N, ra, rb);
   __syncthreads();
-  fft_lds<N1, 2, N1, MG_BLOCK, -1>(b1, tt);
+  fft_lds<N1, 2, N1, row_nt<N1>(), -1>(b1, tt);
   const int64_t zr = (int64_t)(z0 + desc[j].aux) * ea.N;
   const float2* H = ZH + zr;
   const float2* X = ZU + zr;
-  for (int q = threadIdx.x; q < N1 + 1; q += MG_BLOCK) {
+  for (int q = threadIdx.x; q < N1 + 1; q += row_nt<N1>()) {
     int ia, ib;
     if (!mirror_pair<N1>(p, q, ia, ib)) continue;
     const int64_t ga = (ia < N1) ? (int64_t)ra * N1 + ia : (int64_t)rb * N1 + (ia - N1);
@@ -489,10 +497,10 @@ __global__ __launch_bounds__(MG_BLOCK) void k_rows_bwd(const float2* __restrict_
   }
   __syncthreads();
   if (want_u) {
-    fft_lds<N1, 2, N1, MG_BLOCK, +1>(b1, tt);
+    fft_lds<N1, 2, N1, row_nt<N1>(), +1>(b1, tt);
     store_rows<N1>(b1, Tu + (int64_t)j * ea.N, ra, rb, ea);
   }
-  fft_lds<N1, 2, N1, MG_BLOCK, +1>(b2, tt);
+  fft_lds<N1, 2, N1, row_nt<N1>(), +1>(b2, tt);
   store_rows<N1>(b2, Th + (int64_t)j * ea.N, ra, rb, ea);
 }
 
@@ -501,7 +509,7 @@ template <typename LD>
 void run_cols(const Ctx& c, const LD& ld, float2* T, int n, const EngineArgs& ea, double in_bytes) {
   const int N2 = ea.N2;
   const int TC = 8192 / N2;
-  dim3 grid(ea.N1 / TC, n), blk(MG_BLOCK);
+  dim3 grid(ea.N1 / TC, n), blk(COL_NT);
   ProfScope ps(c, "conv_cols", (double)n * (in_bytes + 8.0 * ea.N));
   switch (N2) {
 #define MG_CASE(NN)                                                                   \
@@ -517,7 +525,7 @@ template <typename ST>
 void run_icols(const Ctx& c, const ST& st, const float2* T, int n, const EngineArgs& ea, double out_bytes) {
   const int N2 = ea.N2;
   const int TC = 8192 / N2;
-  dim3 grid(ea.N1 / TC, n), blk(MG_BLOCK);
+  dim3 grid(ea.N1 / TC, n), blk(COL_NT);
   ProfScope ps(c, "conv_icols", (double)n * (out_bytes + 8.0 * ea.N));
   switch (N2) {
 #define MG_CASE(NN)                                                                    \
@@ -536,6 +544,7 @@ static EngineArgs engine_args(const Ctx& c) {
   ea.N1 = g->fft.N1;
   ea.N2 = g->fft.N2;
   ea.tw = wsp<float2>(c, g->ws.tw);
+  ea.twdl = wsp<float2>(c, g->ws.twdl);
   ea.twhi = wsp<float2>(c, g->ws.twhi);
   ea.twlo = wsp<float2>(c, g->ws.twlo);
   return ea;
@@ -567,20 +576,20 @@ static NodeView node_view(const Ctx& c, int desc_off) {
 template <int N1>
 static void rows_spec_n(const Ctx& c, const float2* T, float2* Z, int z0, int desc_off, int n, const EngineArgs& ea) {
   ProfScope ps(c, "conv_rows", (double)n * 16.0 * ea.N);
-  hipLaunchKernelGGL(k_rows_spec<N1>, dim3(ea.N2 / 2, n), dim3(MG_BLOCK), 0, c.st, T, Z, z0, c.desc + desc_off, ea);
+  hipLaunchKernelGGL(k_rows_spec<N1>, dim3(ea.N2 / 2, n), dim3(row_nt<N1>()), 0, c.st, T, Z, z0, c.desc + desc_off, ea);
 }
 template <int N1>
 static void rows_conv_n(const Ctx& c, const float2* Tin, float2* Tout, const float2* ZH, float2* ZU, int z0,
                         int desc_off, int n, const EngineArgs& ea) {
   ProfScope ps(c, "conv_rows", (double)n * (ZU ? 32.0 : 24.0) * ea.N);
-  hipLaunchKernelGGL(k_rows_conv<N1>, dim3(ea.N2 / 2, n), dim3(MG_BLOCK), 0, c.st, Tin, Tout, ZH, ZU, z0,
+  hipLaunchKernelGGL(k_rows_conv<N1>, dim3(ea.N2 / 2, n), dim3(row_nt<N1>()), 0, c.st, Tin, Tout, ZH, ZU, z0,
                      c.desc + desc_off, ea);
 }
 template <int N1>
 static void rows_bwd_n(const Ctx& c, const float2* Tin, float2* Tu, float2* Th, const float2* ZH, const float2* ZU,
                        int z0, int desc_off, int n, int want_u, const EngineArgs& ea) {
   ProfScope ps(c, "conv_rows", (double)n * (want_u ? 40.0 : 32.0) * ea.N);
-  hipLaunchKernelGGL(k_rows_bwd<N1>, dim3(ea.N2 / 2, n), dim3(MG_BLOCK), 0, c.st, Tin, Tu, Th, ZH, ZU, z0,
+  hipLaunchKernelGGL(k_rows_bwd<N1>, dim3(ea.N2 / 2, n), dim3(row_nt<N1>()), 0, c.st, Tin, Tu, Th, ZH, ZU, z0,
                      c.desc + desc_off, want_u, ea);
 }
 
@@ -730,6 +739,13 @@ void fft_init_tables(const Ctx& c, float2* tw, float2* twhi, float2* twlo, int N
     a[m] = make_float2((float)cos(ang), (float)sin(ang));
   }
   hipMemcpyAsync(tw, a.data(), a.size() * sizeof(float2), hipMemcpyHostToDevice, st);
+  // W^m - 1 = (-2 sin^2(pi m / MG_TWN), -sin(2 pi m / MG_TWN)), without cancellation
+  std::vector<float2> dl(MG_TWN);
+  for (int m = 0; m < MG_TWN; ++m) {
+    const double h = pi * (double)m / MG_TWN;
+    dl[m] = make_float2((float)(-2.0 * sin(h) * sin(h)), (float)(-sin(2.0 * h)));
+  }
+  hipMemcpyAsync(wsp<float2>(c, c.g->ws.twdl), dl.data(), dl.size() * sizeof(float2), hipMemcpyHostToDevice, st);
   std::vector<double2> ad(MG_TWN);
   for (int m = 0; m < MG_TWN; ++m) {
     double ang = -2.0 * pi * (double)m / MG_TWN;

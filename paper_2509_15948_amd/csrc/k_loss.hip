@@ -19,6 +19,10 @@
 
 namespace mg {
 
+// threads per block of the frame kernels (up to 137 KB of LDS per block)
+constexpr int LOSS_NT = 512;
+
+
 constexpr double LOG_EPS = 1e-7;
 
 // Frames per workgroup: 2048 complex FP64 points per batch (32 KB of LDS),
@@ -52,7 +56,7 @@ struct LossArgs {
 template <int N>
 __device__ __forceinline__ void load_frames(double2* buf, const LossArgs& a, int f0) {
   constexpr int FPB = loss_fpb<N>();
-  for (int idx = threadIdx.x; idx < FPB * N; idx += MG_BLOCK) {
+  for (int idx = threadIdx.x; idx < FPB * N; idx += blockDim.x) {
     const int fl = idx / N, t = idx % N;
     const int f = f0 + fl;
     double2 z = make_double2(0.0, 0.0);
@@ -75,7 +79,7 @@ template <int N>
 __device__ __forceinline__ void frame_mags(const double2* buf, double* mag, const LossArgs& a) {
   constexpr int FPB = loss_fpb<N>();
   constexpr int NB = N / 2 + 1;
-  for (int idx = threadIdx.x; idx < FPB * NB; idx += MG_BLOCK) {
+  for (int idx = threadIdx.x; idx < FPB * NB; idx += blockDim.x) {
     const int fl = idx / NB, k = idx % NB;
     double2 xl, xr;
     split_pair(buf[fl * N + k], buf[fl * N + ((N - k) & (N - 1))], xl, xr);
@@ -101,23 +105,23 @@ __device__ __forceinline__ double mel_of(const double* mag, const LossArgs& a, i
 
 // MODE 0: target features (write tgt, partial sum Y^2); MODE 1: loss partials
 template <int N, int MODE>
-__global__ __launch_bounds__(MG_BLOCK) void k_loss_fwd(LossArgs a) {
+__global__ __launch_bounds__(LOSS_NT) void k_loss_fwd(LossArgs a) {
   constexpr int FPB = loss_fpb<N>();
   constexpr int NB = N / 2 + 1;
   __shared__ double2 buf[FPB * N];
   __shared__ TwTab<N, double2> tt;
-  tw_fill<N>(tt, a.tw);
+  tw_fill<N>(tt, a.tw, (const double2*)nullptr);
   __shared__ double mag[FPB * 4 * NB];
-  __shared__ double red[MG_BLOCK];
+  __shared__ double red[LOSS_NT];
   const int f0 = blockIdx.x * FPB;
   load_frames<N>(buf, a, f0);
   __syncthreads();
-  fft_lds<N, FPB, N, MG_BLOCK, -1>(buf, tt);
+  fft_lds<N, FPB, N, LOSS_NT, -1>(buf, tt);
   frame_mags<N>(buf, mag, a);
   __syncthreads();
   double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   const int items = FPB * 4 * a.nm;
-  for (int it = threadIdx.x; it < items; it += MG_BLOCK) {
+  for (int it = threadIdx.x; it < items; it += LOSS_NT) {
     const int fl = it / (4 * a.nm), x = (it / a.nm) % 4, b = it % a.nm;
     const int f = f0 + fl;
     if (f >= a.F) continue;
@@ -134,7 +138,7 @@ __global__ __launch_bounds__(MG_BLOCK) void k_loss_fwd(LossArgs a) {
     }
   }
   for (int k = 0; k < 8; ++k) {
-    const double s = block_sum<MG_BLOCK>(acc[k], red);
+    const double s = block_sum<LOSS_NT>(acc[k], red);
     if (threadIdx.x == 0) a.part[(int64_t)blockIdx.x * 8 + k] = s;
   }
 }
@@ -167,18 +171,18 @@ __global__ __launch_bounds__(MG_BLOCK) void k_loss_reduce(const double* __restri
 
 // per frame: dL/dy for the frame's samples (windowed), to scratch [F][N][2]
 template <int N>
-__global__ __launch_bounds__(MG_BLOCK) void k_loss_bwd(LossArgs a) {
+__global__ __launch_bounds__(LOSS_NT) void k_loss_bwd(LossArgs a) {
   constexpr int FPB = loss_fpb<N>();
   constexpr int NB = N / 2 + 1;
   __shared__ double2 buf[FPB * N];
   __shared__ TwTab<N, double2> tt;
-  tw_fill<N>(tt, a.tw);
+  tw_fill<N>(tt, a.tw, (const double2*)nullptr);
   __shared__ double mag[FPB * 4 * NB];
   __shared__ double dyh[FPB * 4 * 128];
   const int f0 = blockIdx.x * FPB;
   load_frames<N>(buf, a, f0);
   __syncthreads();
-  fft_lds<N, FPB, N, MG_BLOCK, -1>(buf, tt);
+  fft_lds<N, FPB, N, LOSS_NT, -1>(buf, tt);
   frame_mags<N>(buf, mag, a);
   __syncthreads();
   // dL/dYh per (frame, combo, band); every combo carries weight 1/4 in L_a
@@ -191,7 +195,7 @@ __global__ __launch_bounds__(MG_BLOCK) void k_loss_bwd(LossArgs a) {
     ksc[x] = D > 0.0 ? 0.25 / (D * (sqrt(Y2) + 1e-12)) : 0.0;
   }
   const int items = FPB * 4 * a.nm;
-  for (int it = threadIdx.x; it < items; it += MG_BLOCK) {
+  for (int it = threadIdx.x; it < items; it += LOSS_NT) {
     const int fl = it / (4 * a.nm), x = (it / a.nm) % 4, b = it % a.nm;
     const int f = f0 + fl;
     double g = 0.0;
@@ -206,7 +210,7 @@ __global__ __launch_bounds__(MG_BLOCK) void k_loss_bwd(LossArgs a) {
   }
   __syncthreads();
   // per bin pair (k, N-k): dL/dX for l and r, packed Hermitian spectrum
-  for (int idx = threadIdx.x; idx < FPB * NB; idx += MG_BLOCK) {
+  for (int idx = threadIdx.x; idx < FPB * NB; idx += LOSS_NT) {
     const int fl = idx / NB, k = idx % NB;
     const int km = (N - k) & (N - 1);
     double2 xl, xr;
@@ -235,8 +239,8 @@ __global__ __launch_bounds__(MG_BLOCK) void k_loss_bwd(LossArgs a) {
     }
   }
   __syncthreads();
-  fft_lds<N, FPB, N, MG_BLOCK, +1>(buf, tt);
-  for (int idx = threadIdx.x; idx < FPB * N; idx += MG_BLOCK) {
+  fft_lds<N, FPB, N, LOSS_NT, +1>(buf, tt);
+  for (int idx = threadIdx.x; idx < FPB * N; idx += LOSS_NT) {
     const int fl = idx / N, t = idx % N;
     const int f = f0 + fl;
     if (f >= a.F) continue;
@@ -407,11 +411,11 @@ static LossArgs loss_args(const Ctx& c, int i, const float* y) {
 
 template <int N, int MODE>
 static void fwd_n(const Ctx& c, const LossArgs& a, int blocks) {
-  hipLaunchKernelGGL((k_loss_fwd<N, MODE>), dim3(blocks), dim3(MG_BLOCK), 0, c.st, a);
+  hipLaunchKernelGGL((k_loss_fwd<N, MODE>), dim3(blocks), dim3(LOSS_NT), 0, c.st, a);
 }
 template <int N>
 static void bwd_n(const Ctx& c, const LossArgs& a, int blocks) {
-  hipLaunchKernelGGL(k_loss_bwd<N>, dim3(blocks), dim3(MG_BLOCK), 0, c.st, a);
+  hipLaunchKernelGGL(k_loss_bwd<N>, dim3(blocks), dim3(LOSS_NT), 0, c.st, a);
 }
 
 #define MG_LOSS_SWITCH(N_, CALL)   \

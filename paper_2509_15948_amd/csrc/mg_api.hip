@@ -66,6 +66,7 @@ static size_t plan_ws(mg_graph& g, int mode, bool commit) {
     take(w.twlo, 1024 * 8);
   }
   take(w.tw, MG_TWN * 8);
+  take(w.twdl, MG_TWN * 8);
   take(w.twd, MG_TWN * 16);
   if (n_eq) {
     take(w.eq_h, (size_t)n_eq * c.eq_taps * 4);

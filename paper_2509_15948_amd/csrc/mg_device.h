@@ -50,34 +50,57 @@ __device__ __forceinline__ V c_rot(V a) {
 
 constexpr int ilog2c(int n) { return n <= 1 ? 0 : 1 + ilog2c(n >> 1); }
 
-// Twiddles of an N-point transform, staged in LDS by the calling kernel:
-// hi[j] = W_N^{64 j} (N/64 entries, at least 1) and lo[j] = W_N^j (64
-// entries), W_N = exp(-2 pi i / N), so W_N^e = hi[e >> 6] lo[e & 63].  Both
-// are copied from the global table g[m] = exp(-2 pi i m / MG_TWN) (rounded
-// from FP64 on the host), so no butterfly reads global memory.
+// Twiddles of an N-point transform, staged in LDS by the calling kernel, so
+// no butterfly reads global memory.  W_N = exp(-2 pi i / N).
+//  * float2, N <= 1024: the full table lo[e] = W_N^e, each entry rounded once
+//    from FP64 (copied from g[m] = exp(-2 pi i m / MG_TWN));
+//  * float2, N > 1024: W_N^e = h (1 + d) with h = hi[e >> 6] = W_N^{64 (e >> 6)}
+//    and d = lo[e & 63] = W_N^{e & 63} - 1 taken from gd (also rounded from
+//    FP64), whose small magnitude keeps the product within about one rounding;
+//  * double2: W_N^e = hi[e >> 6] lo[e & 63] (FP64 rounding is far below the
+//    FP32 signals).
 template <int N, typename V>
 struct TwTab {
-  static constexpr int NH = N >= 64 ? N / 64 : 1;
+  static constexpr bool F32 = sizeof(V) == 8;
+  static constexpr bool FULL = F32 && N <= 1024;
+  static constexpr bool DELTA = F32 && N > 1024;
+  static constexpr int NH = FULL ? 1 : (N >= 64 ? N / 64 : 1);
+  static constexpr int NL = FULL ? N : 64;
   V hi[NH];
-  V lo[64];
+  V lo[NL];
 };
 
-// Fill t from g; the caller synchronises before the first transform.
+// Fill t from the global tables (gd: W^m - 1, used for float2 with N > 1024);
+// the caller synchronises before the first transform.
 template <int N, typename V>
-__device__ __forceinline__ void tw_fill(TwTab<N, V>& t, const V* __restrict__ g) {
+__device__ __forceinline__ void tw_fill(TwTab<N, V>& t, const V* __restrict__ g, const V* __restrict__ gd) {
   static_assert(N <= MG_TWN && MG_TWN % N == 0, "N must divide the table size");
   constexpr int S = MG_TWN / N;
-  constexpr int NH = TwTab<N, V>::NH;
-  for (int i = threadIdx.x; i < NH + 64; i += blockDim.x) {
-    if (i < NH) t.hi[i] = g[(64 * i * S) & (MG_TWN - 1)];
-    else t.lo[i - NH] = g[((i - NH) * S) & (MG_TWN - 1)];
+  using T = TwTab<N, V>;
+  for (int i = threadIdx.x; i < T::NH + T::NL; i += blockDim.x) {
+    if (i < T::NH) {
+      t.hi[i] = g[(64 * i * S) & (MG_TWN - 1)];
+    } else {
+      const int j = i - T::NH;
+      t.lo[j] = T::DELTA ? gd[(j * S) & (MG_TWN - 1)] : g[(j * S) & (MG_TWN - 1)];
+    }
   }
 }
 
 // W = exp(DIR * 2 pi i * e / N) for 0 <= e < N.
 template <int DIR, int N, typename V>
 __device__ __forceinline__ V tw_get(const TwTab<N, V>& t, int e) {
-  V w = c_mul(t.hi[e >> 6], t.lo[e & 63]);
+  using T = TwTab<N, V>;
+  V w;
+  if constexpr (T::FULL) {
+    w = t.lo[e];
+  } else if constexpr (T::DELTA) {
+    const V h = t.hi[e >> 6], d = t.lo[e & 63];
+    w.x = h.x + (h.x * d.x - h.y * d.y);
+    w.y = h.y + (h.x * d.y + h.y * d.x);
+  } else {
+    w = c_mul(t.hi[e >> 6], t.lo[e & 63]);
+  }
   if (DIR > 0) w.y = -w.y;
   return w;
 }

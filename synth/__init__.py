@@ -276,10 +276,18 @@ def dry_track(seed: int, k: int, L: int, fs: int, stereo: bool) -> np.ndarray:
 
 
 def dry_tracks(seed: int, cfg: ConsoleConfig) -> np.ndarray:
-    """All dry sources, shape [K][C][L], float32."""
+    """All dry sources, shape [K][C][L], float32 (tracks drawn in parallel
+    threads for long songs; each track has its own generator, so the values
+    do not depend on the threading)."""
     L = cfg.length
-    return np.stack([dry_track(seed, k, L, cfg.fs, cfg.stereo_tracks)
-                     for k in range(cfg.n_tracks)]).astype(np.float32)
+    if cfg.n_tracks * L > 20_000_000:
+        from concurrent.futures import ThreadPoolExecutor
+        import os
+        with ThreadPoolExecutor(max_workers=min(16, os.cpu_count() or 1)) as ex:
+            tracks = list(ex.map(lambda k: dry_track(seed, k, L, cfg.fs, cfg.stereo_tracks), range(cfg.n_tracks)))
+    else:
+        tracks = [dry_track(seed, k, L, cfg.fs, cfg.stereo_tracks) for k in range(cfg.n_tracks)]
+    return np.stack(tracks).astype(np.float32)
 
 
 def reverb_noise(seed: int, node: int, cfg: ConsoleConfig) -> np.ndarray:

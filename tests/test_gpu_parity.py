@@ -216,3 +216,43 @@ def test_forward_backward_is_bitwise_reproducible():
     for v in g1:
         assert np.array_equal(g1[v], g2[v]), v
     assert w1 == w2
+
+
+def test_large_console_properties():
+    """64 tracks, 8 subgroups, 60 s at 48 kHz, 2 s reverb, five loss
+    resolutions (2^22-point FFT engine, 13 GB of node outputs): every dry/wet
+    at 0 gives the plain sum of the tracks; a forward+backward is finite and
+    bitwise reproducible.  (The oracle is too slow at this size; its parity
+    is covered by the full-size console above.)"""
+    cfg = synth.CONFIGS["large"]
+    g, dry, noise = synth.song(4, cfg)
+    from paper_2509_15948_amd import workloads as W
+    bg = W.binding_graph(g, cfg)
+    print("large: nodes", g.n_nodes, "fft", bg.info.fft_size, flush=True)
+    dev = "cuda"
+    dry_d = torch.from_numpy(dry).to(dev)
+    noise_d = torch.from_numpy(W.noise_rows(bg, noise, cfg.reverb_length)).to(dev)
+    target_d = torch.from_numpy(dry.sum(0) * 0.5).to(dev)
+    sess = MG.Session(bg, noise_d, target_d, mode=1)
+    th, we = synth.init_params(4, g, cfg)
+    th_f, we_f = bg.flatten(th, we)
+    theta = torch.from_numpy(th_f).to(dev)
+    wet = torch.from_numpy(we_f).to(dev)
+    mix = torch.empty(2, cfg.length, device=dev)
+    zero = torch.zeros(bg.n_proc, device=dev)
+    losses = torch.zeros(7, dtype=torch.float64, device=dev)
+    sess.forward(dry_d, theta, wet, zero, mix, losses)
+    torch.cuda.synchronize()
+    assert torch.allclose(mix, dry_d.sum(0), rtol=1e-5, atol=1e-6)
+    outs = []
+    for _ in range(2):
+        sess.forward(dry_d, theta, wet, None, mix, losses)
+        gth = torch.empty_like(theta)
+        gwe = torch.empty_like(wet)
+        sess.backward(gth, gwe)
+        torch.cuda.synchronize()
+        outs.append((mix.cpu().numpy().copy(), losses.cpu().numpy().copy(), gth.cpu().numpy(), gwe.cpu().numpy()))
+    print("large losses", outs[0][1], flush=True)
+    assert np.all(np.isfinite(outs[0][1])) and np.all(np.isfinite(outs[0][2])) and np.all(np.isfinite(outs[0][3]))
+    for a, b in zip(outs[0], outs[1]):
+        assert np.array_equal(a, b)
