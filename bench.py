@@ -250,6 +250,7 @@ def serving_leg(args):
     server = SV.Server(budget_bytes=int(args.serve_budget_gb * (1 << 30)), max_active=4)
     out = server.run(reqs, lambda i, cfg, seed: SV.Search(i, cfg, seed, spec))
     removed = [sum(r["removed"] for r in res["trace"]) for res in out["results"]]
+    final = [res["processors"] for res in out["results"]]
     return {"requests": len(reqs), "rate_per_s": args.serve_rate,
             "workload": f"tracks U{{4..16}}, subgroups U{{2..4}}, 2-6 s at 44.1 kHz, chain ecxsgdr; search = "
                         f"{spec.steps} steps + {spec.rounds} pruning rounds x ({spec.candidates} trials + "
@@ -257,7 +258,8 @@ def serving_leg(args):
             "p50_latency_s": round(out["p50_s"], 4), "p99_latency_s": round(out["p99_s"], 4),
             "songs_per_s": round(out["songs_per_s"], 3), "audio_s_per_s": round(out["audio_s_per_s"], 1),
             "makespan_s": round(out["makespan_s"], 3), "peak_active": out["peak_active"],
-            "peak_gb": round(out["peak_bytes"] / (1 << 30), 3), "processors_removed": removed}
+            "peak_gb": round(out["peak_bytes"] / (1 << 30), 3), "processors_removed": removed,
+            "processors_left": final}
 
 
 def main():

@@ -216,6 +216,18 @@ int mg_adam_step(float* theta, float* m, float* v, const float* grad, int64_t n,
 int mg_graph_prune(const mg_graph* g, const uint8_t* keep, mg_graph** out,
                    int32_t* old_to_new);
 
+/* Parameters of a graph made by mg_graph_prune, taken from those of the
+ * original: each kept processor keeps its row of theta (its raw parameters,
+ * Sec. 3) and its dry/wet logit.  Any vector in theta's layout (Adam moments)
+ * maps the same way.
+ *   old_to_new  host int32[n_nodes of g], as filled by mg_graph_prune
+ *   src_theta   dev float[n_theta of g]      -> dst_theta dev float[n_theta of pruned]
+ *   src_wet     dev float[P of g]            -> dst_wet   dev float[P of pruned]
+ * Either pair may be NULL.  Device-to-device copies on the stream.          */
+int mg_remap_params(const mg_graph* g, const mg_graph* pruned, const int32_t* old_to_new,
+                    const float* src_theta, float* dst_theta, const float* src_wet, float* dst_wet,
+                    void* stream);
+
 /* Measurement of one kernel class (for roofline reporting, not part of the
  * method): after mg_profile_enable(g, cls), HIP events are recorded on the
  * caller's stream around every launch of that class ("conv_cols",

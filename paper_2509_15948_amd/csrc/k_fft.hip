@@ -97,28 +97,6 @@ struct LdFir {
   __device__ void end(int, int) {}
 };
 
-// multitap delay FIR from its tap table: per node [2][M] delays (as float
-// holding an exact integer) followed by [2][M][taps] coefficients
-struct LdDelay {
-  const NodeDesc* desc;
-  const float* tab;
-  int M, taps, half;
-  int64_t N, stride;
-  const float* t;
-  __device__ void begin(int j) { t = tab + (int64_t)desc[j].aux * stride; }
-  __device__ float2 load(int64_t n) const {
-    const int64_t lag = signed_lag(n, N);
-    float a[2] = {0.f, 0.f};
-    for (int c = 0; c < 2; ++c)
-      for (int m = 0; m < M; ++m) {
-        const int64_t k = lag - (int64_t)t[c * M + m] + half;
-        if (k >= 0 && k < taps) a[c] += t[2 * M + (c * M + m) * taps + k];
-      }
-    return make_float2(a[0], a[1]);
-  }
-  __device__ void end(int, int) {}
-};
-
 // backward: dL/dybar = w dL/dy + alpha_g s ybar_m / E_ybar, and the dry/wet
 // partial sum of dL/dy * (ybar - u)
 struct LdGrad {
@@ -630,15 +608,16 @@ void conv_fir_spectrum(const Ctx& c, int type, int desc_off, int n) {
     ld.shared = 0;
     run_cols(c, ld, T1, n, ea, 8.0 * cf.reverb_length);
   } else {
-    LdDelay ld;
+    // the compact delay FIR [2][dl_len] written by the synthesis
+    LdFir ld;
     ld.desc = c.desc + desc_off;
-    ld.tab = wsp<float>(c, g->ws.dl_tab);
-    ld.M = cf.delay_taps;
-    ld.taps = cf.delay_fir_taps;
-    ld.half = (cf.delay_fir_taps - 1) / 2;
+    ld.h = wsp<float>(c, g->ws.dl_h);
+    ld.Nh = g->dl_len;
+    ld.lag0 = -(cf.delay_fir_taps - 1) / 2;
     ld.N = ea.N;
-    ld.stride = 2 * (int64_t)cf.delay_taps * (1 + cf.delay_fir_taps);
-    run_cols(c, ld, T1, n, ea, 8.0 * cf.delay_taps * (1 + cf.delay_fir_taps));
+    ld.stride = 2 * g->dl_len;
+    ld.shared = 0;
+    run_cols(c, ld, T1, n, ea, 8.0 * g->dl_len);
   }
   MG_N1_SWITCH(rows_spec_n, c, T1, ZH, z0, desc_off, n, ea);
 }

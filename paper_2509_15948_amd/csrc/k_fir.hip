@@ -18,70 +18,97 @@
 namespace mg {
 
 // ---------------------------------------------------------------- equalizer
-// grid (ceil(N/256), nodes): one output tap per thread
+// Both directions are cosine sums of about a thousand terms per output.  Each
+// output is split over FIR_SPLIT threads (one wavefront per part); a thread
+// walks its part of the sum with an FP64 rotation e^{i theta} started from an
+// exactly reduced angle, so no table is read and the drift stays at the FP64
+// rounding level.  The parts are added in a fixed order.
+constexpr int FIR_SPLIT = 4;
+constexpr int FIR_PER_BLOCK = MG_BLOCK / FIR_SPLIT;   // outputs per block
+
+// exp(i 2 pi (a mod N) / N) in FP64
+__device__ __forceinline__ double2 unit_root(int64_t a, int N) {
+  const int64_t r = ((a % N) + N) % N;
+  double s, c;
+  sincospi(2.0 * (double)r / (double)N, &s, &c);
+  return make_double2(c, s);
+}
+
+// h[n] = v[n] (H0 + 2 sum_{k=1}^{K-1} H_k cos(2 pi k n / N)) / N, v = cos^2(pi n / N);
+// grid (ceil(N / FIR_PER_BLOCK), nodes)
 __global__ __launch_bounds__(MG_BLOCK) void k_eq_synth(const NodeDesc* __restrict__ desc,
-                                                        const float* __restrict__ theta,
-                                                        const float* __restrict__ cosN, int N,
+                                                        const float* __restrict__ theta, int N,
                                                         float* __restrict__ h_out) {
-  __shared__ float H[4096];
-  __shared__ float cs[8192];
+  __shared__ double H[4096];
+  __shared__ double part[FIR_SPLIT][FIR_PER_BLOCK];
   const NodeDesc d = desc[blockIdx.y];
   const int K = (N + 1) / 2;
   const float* p = theta + d.theta_off;
-  for (int k = threadIdx.x; k < K; k += MG_BLOCK) H[k] = expf(p[k]);
-  for (int m = threadIdx.x; m < N; m += MG_BLOCK) cs[m] = cosN[m];
+  for (int k = threadIdx.x; k < K; k += MG_BLOCK) H[k] = exp((double)p[k]);
   __syncthreads();
-  const int i = blockIdx.x * MG_BLOCK + threadIdx.x;
-  if (i >= N) return;
+  const int lane = threadIdx.x % FIR_PER_BLOCK, c = threadIdx.x / FIR_PER_BLOCK;
+  const int i = blockIdx.x * FIR_PER_BLOCK + lane;
   const int half = (N - 1) / 2;
   const int n = i - half;
-  const int nn = ((n % N) + N) % N;
+  const int Q = (K - 1 + FIR_SPLIT - 1) / FIR_SPLIT;
+  const int k0 = 1 + c * Q, k1 = min(K, k0 + Q);
   double acc = 0.0;
-  int idx = 0;
-  for (int k = 1; k < K; ++k) {
-    idx += nn;
-    if (idx >= N) idx -= N;
-    acc += (double)H[k] * (double)cs[idx];
+  if (i < N && k0 < k1) {
+    double2 w = unit_root((int64_t)k0 * n, N);
+    const double2 step = unit_root(n, N);
+    for (int k = k0; k < k1; ++k) {
+      acc = fma(H[k], w.x, acc);
+      w = c_mul(w, step);
+    }
   }
-  const double h0 = ((double)H[0] + 2.0 * acc) / (double)N;
-  const double v = 0.5 * (1.0 + (double)cs[nn]);  // cos^2(pi n / N)
+  part[c][lane] = acc;
+  __syncthreads();
+  if (c != 0 || i >= N) return;
+  double s = 0.0;
+  for (int q = 0; q < FIR_SPLIT; ++q) s += part[q][lane];
+  const double h0 = (H[0] + 2.0 * s) / (double)N;
+  const double2 r = unit_root(n, N);
+  const double v = 0.5 * (1.0 + r.x);  // cos^2(pi n / N)
   h_out[(int64_t)d.aux * N + i] = (float)(v * h0);
 }
 
-// dL/dp_k = H_k (c_k / N) sum_n v[n] dh[n] cos(2 pi k n / N); grid (ceil(K/256), nodes)
+// dL/dp_k = H_k (c_k / N) sum_n v[n] dh[n] cos(2 pi k n / N), c_0 = 1, c_k = 2;
+// grid (ceil(K / FIR_PER_BLOCK), nodes)
 __global__ __launch_bounds__(MG_BLOCK) void k_eq_adjoint(const NodeDesc* __restrict__ desc,
-                                                          const float* __restrict__ theta,
-                                                          const float* __restrict__ cosN, int N,
+                                                          const float* __restrict__ theta, int N,
                                                           const float* __restrict__ dh,
                                                           float* __restrict__ grad_theta) {
-  __shared__ float g[8192];
-  __shared__ float cs[8192];
+  __shared__ double gv[4096];
+  __shared__ double part[FIR_SPLIT][FIR_PER_BLOCK];
   const NodeDesc d = desc[blockIdx.y];
   const int K = (N + 1) / 2;
   const int half = (N - 1) / 2;
-  for (int m = threadIdx.x; m < N; m += MG_BLOCK) {
-    cs[m] = cosN[m];
-  }
-  __syncthreads();
   for (int i = threadIdx.x; i < N; i += MG_BLOCK) {
-    const int n = i - half;
-    const int nn = ((n % N) + N) % N;
-    g[i] = 0.5f * (1.0f + cs[nn]) * dh[(int64_t)d.aux * N + i];
+    const double2 r = unit_root(i - half, N);
+    gv[i] = 0.5 * (1.0 + r.x) * (double)dh[(int64_t)d.aux * N + i];
   }
   __syncthreads();
-  const int k = blockIdx.x * MG_BLOCK + threadIdx.x;
-  if (k >= K) return;
+  const int lane = threadIdx.x % FIR_PER_BLOCK, c = threadIdx.x / FIR_PER_BLOCK;
+  const int k = blockIdx.x * FIR_PER_BLOCK + lane;
+  const int Q = (N + FIR_SPLIT - 1) / FIR_SPLIT;
+  const int i0 = c * Q, i1 = min(N, i0 + Q);
   double acc = 0.0;
-  // n runs over -half..half; (k n) mod N advanced incrementally
-  int idx = ((-(int64_t)half * k) % N + N) % N;
-  for (int i = 0; i < N; ++i) {
-    acc += (double)g[i] * (double)cs[idx];
-    idx += k;
-    if (idx >= N) idx -= N;
+  if (k < K && i0 < i1) {
+    double2 w = unit_root((int64_t)k * (i0 - half), N);
+    const double2 step = unit_root(k, N);
+    for (int i = i0; i < i1; ++i) {
+      acc = fma(gv[i], w.x, acc);
+      w = c_mul(w, step);
+    }
   }
+  part[c][lane] = acc;
+  __syncthreads();
+  if (c != 0 || k >= K) return;
+  double s = 0.0;
+  for (int q = 0; q < FIR_SPLIT; ++q) s += part[q][lane];
   const double ck = (k == 0) ? 1.0 : 2.0;
   const float* p = theta + d.theta_off;
-  grad_theta[d.theta_off + k] = (float)(exp((double)p[k]) * ck / (double)N * acc);
+  grad_theta[d.theta_off + k] = (float)(exp((double)p[k]) * ck / (double)N * s);
 }
 
 // ---------------------------------------------------------------- multitap delay
@@ -124,6 +151,25 @@ __global__ __launch_bounds__(MG_BLOCK) void k_delay_synth(const NodeDesc* __rest
   }
 }
 
+// Dense compact delay FIR h[c][x] for lags x - half (x < dl_len): the sum over
+// taps m of c_m[x - d_m] where that index is inside the tap's FIR; the taps
+// are added in order m = 0..M-1.  grid (ceil(dl_len / 256), 2, nodes)
+__global__ __launch_bounds__(MG_BLOCK) void k_delay_compact(const NodeDesc* __restrict__ desc,
+                                                             const float* __restrict__ tab, int M, int taps,
+                                                             int64_t dl_len, float* __restrict__ h) {
+  const NodeDesc d = desc[blockIdx.z];
+  const int c = blockIdx.y;
+  const int64_t x = (int64_t)blockIdx.x * MG_BLOCK + threadIdx.x;
+  if (x >= dl_len) return;
+  const float* t = tab + (int64_t)d.aux * 2 * M * (1 + taps);
+  float a = 0.0f;
+  for (int m = 0; m < M; ++m) {
+    const int64_t k = x - (int64_t)t[c * M + m];
+    if (k >= 0 && k < taps) a += t[2 * M + (c * M + m) * taps + k];
+  }
+  h[((int64_t)d.aux * 2 + c) * dl_len + x] = a;
+}
+
 // P(a) = sum_{k=1}^{D-1} k a^{k-1}, closed form away from a = 1, Horner near it
 __device__ inline void poly_P(double ar, double ai, int D, double zDr, double zDi, double zD1r, double zD1i,
                               double wr, double wi, double& pr, double& pi) {
@@ -153,22 +199,28 @@ __device__ inline void poly_P(double ar, double ai, int D, double zDr, double zD
   }
 }
 
-// One workgroup per (node, channel, tap): dL/dc_m (-> log-magnitudes) and the
-// straight-through z gradient
+// One workgroup per (node, channel, tap, chunk of the delay range): the
+// straight-through z gradient as partial sums over its chunk of q,
 //   f'(z) = (1/D) sum_q Gc[q] w^q P(z w^q),  Gc[q] = sum_j c_m[j] dh[m D + q + j],
+// written to zpart; chunk 0 also forms dL/dc_m (-> log-magnitudes).
+// k_delay_zrule then adds the chunks in order and applies the update rule
 //   g = conj(f'(z)),  update = g/|g| + gamma (|z| - 1) z/|z|.
+constexpr int DL_CHUNKS = 8;
+
 __global__ __launch_bounds__(MG_BLOCK) void k_delay_adjoint(const NodeDesc* __restrict__ desc,
                                                              const float* __restrict__ theta,
                                                              const float* __restrict__ tab,
                                                              const float* __restrict__ cosT, int M, int D,
                                                              int taps, int64_t dl_len,
                                                              const float* __restrict__ dh,
-                                                             float* __restrict__ grad_theta, float gamma) {
+                                                             float* __restrict__ grad_theta,
+                                                             double2* __restrict__ zpart) {
   __shared__ double red_r[MG_BLOCK];
   __shared__ double red_i[MG_BLOCK];
   __shared__ float cm[256];
   __shared__ float dc[256];
-  const int j = blockIdx.y;
+  const int j = blockIdx.z;
+  const int chunk = blockIdx.y;
   const NodeDesc d = desc[j];
   const int cmi = blockIdx.x;  // c * M + m
   const int c = cmi / M, m = cmi % M;
@@ -185,26 +237,30 @@ __global__ __launch_bounds__(MG_BLOCK) void k_delay_adjoint(const NodeDesc* __re
   __syncthreads();
   const float* p = theta + d.theta_off + (int64_t)cmi * stride;
   float* gp = grad_theta + d.theta_off + (int64_t)cmi * stride;
-  // log-magnitudes of c_m
-  for (int k = threadIdx.x; k < Kc; k += MG_BLOCK) {
-    double acc = 0.0;
-    for (int i = 0; i < taps; ++i) {
-      const int n = i - half;
-      const int nn = ((n % taps) + taps) % taps;
-      const int idx = (int)(((int64_t)k * nn) % taps);
-      acc += 0.5 * (1.0 + (double)cosT[nn]) * (double)dc[i] * (double)cosT[idx];
+  if (chunk == 0) {
+    // log-magnitudes of c_m
+    for (int k = threadIdx.x; k < Kc; k += MG_BLOCK) {
+      double acc = 0.0;
+      for (int i = 0; i < taps; ++i) {
+        const int n = i - half;
+        const int nn = ((n % taps) + taps) % taps;
+        const int idx = (int)(((int64_t)k * nn) % taps);
+        acc += 0.5 * (1.0 + (double)cosT[nn]) * (double)dc[i] * (double)cosT[idx];
+      }
+      const double ck = (k == 0) ? 1.0 : 2.0;
+      gp[2 + k] = (float)(exp((double)p[2 + k]) * ck / (double)taps * acc);
     }
-    const double ck = (k == 0) ? 1.0 : 2.0;
-    gp[2 + k] = (float)(exp((double)p[2 + k]) * ck / (double)taps * acc);
   }
-  // z surrogate gradient
+  // z surrogate gradient over this chunk of q
   const double zr = p[0], zi = p[1];
   const double lz = 0.5 * log(zr * zr + zi * zi), az = atan2(zi, zr);
   const double mD = exp(D * lz), mD1 = exp((D - 1) * lz);
   const double zDr = mD * cos(D * az), zDi = mD * sin(D * az);
   const double zD1r = mD1 * cos((D - 1) * az), zD1i = mD1 * sin((D - 1) * az);
+  const int Qc = (D + DL_CHUNKS - 1) / DL_CHUNKS;
+  const int q0 = chunk * Qc, q1 = min(D, q0 + Qc);
   double sr = 0.0, si = 0.0;
-  for (int q = threadIdx.x; q < D; q += MG_BLOCK) {
+  for (int q = q0 + threadIdx.x; q < q1; q += MG_BLOCK) {
     double gc = 0.0;
     const int64_t base = (int64_t)m * D + q;
     for (int i = 0; i < taps; ++i) gc += (double)cm[i] * (double)dhc[base + i];
@@ -221,30 +277,49 @@ __global__ __launch_bounds__(MG_BLOCK) void k_delay_adjoint(const NodeDesc* __re
   red_r[threadIdx.x] = sr;
   red_i[threadIdx.x] = si;
   __syncthreads();
-  for (int s = MG_BLOCK / 2; s > 0; s >>= 1) {
-    if (threadIdx.x < s) {
-      red_r[threadIdx.x] += red_r[threadIdx.x + s];
-      red_i[threadIdx.x] += red_i[threadIdx.x + s];
+  for (int st = MG_BLOCK / 2; st > 0; st >>= 1) {
+    if (threadIdx.x < st) {
+      red_r[threadIdx.x] += red_r[threadIdx.x + st];
+      red_i[threadIdx.x] += red_i[threadIdx.x + st];
     }
     __syncthreads();
   }
-  if (threadIdx.x == 0) {
-    const double fr = red_r[0] / D, fi = red_i[0] / D;
-    double gr = fr, gi = -fi;  // conj(f')
-    const double ag = sqrt(gr * gr + gi * gi);
-    const double amz = sqrt(zr * zr + zi * zi);
-    double ur = 0.0, ui = 0.0;
-    if (ag > 0.0) {
-      ur = gr / ag;
-      ui = gi / ag;
-    }
-    if (amz > 0.0) {
-      ur += (double)gamma * (amz - 1.0) * zr / amz;
-      ui += (double)gamma * (amz - 1.0) * zi / amz;
-    }
-    gp[0] = (float)ur;
-    gp[1] = (float)ui;
+  if (threadIdx.x == 0) zpart[((int64_t)d.aux * 2 * M + cmi) * DL_CHUNKS + chunk] = make_double2(red_r[0], red_i[0]);
+}
+
+// grid (nodes), one thread per (channel, tap)
+__global__ void k_delay_zrule(const NodeDesc* __restrict__ desc, const float* __restrict__ theta, int M, int D,
+                              int taps, const double2* __restrict__ zpart, float* __restrict__ grad_theta,
+                              float gamma) {
+  const NodeDesc d = desc[blockIdx.x];
+  const int cmi = threadIdx.x;
+  if (cmi >= 2 * M) return;
+  const int stride = 2 + (taps + 1) / 2;
+  const float* p = theta + d.theta_off + (int64_t)cmi * stride;
+  float* gp = grad_theta + d.theta_off + (int64_t)cmi * stride;
+  double fr = 0.0, fi = 0.0;
+  for (int ch = 0; ch < DL_CHUNKS; ++ch) {
+    const double2 v = zpart[((int64_t)d.aux * 2 * M + cmi) * DL_CHUNKS + ch];
+    fr += v.x;
+    fi += v.y;
   }
+  fr /= D;
+  fi /= D;
+  const double zr = p[0], zi = p[1];
+  const double gr = fr, gi = -fi;  // conj(f')
+  const double ag = sqrt(gr * gr + gi * gi);
+  const double amz = sqrt(zr * zr + zi * zi);
+  double ur = 0.0, ui = 0.0;
+  if (ag > 0.0) {
+    ur = gr / ag;
+    ui = gi / ag;
+  }
+  if (amz > 0.0) {
+    ur += (double)gamma * (amz - 1.0) * zr / amz;
+    ui += (double)gamma * (amz - 1.0) * zi / amz;
+  }
+  gp[0] = (float)ur;
+  gp[1] = (float)ui;
 }
 
 // ---------------------------------------------------------------- reverb
@@ -580,11 +655,14 @@ void fir_synth(const Ctx& c, int type, int desc_off, int n) {
   ProfScope ps(c, "fir", 0.0);
   const NodeDesc* d = c.desc + desc_off;
   if (type == MG_EQ) {
-    hipLaunchKernelGGL(k_eq_synth, dim3((cf.eq_taps + MG_BLOCK - 1) / MG_BLOCK, n), dim3(MG_BLOCK), 0, c.st, d,
-                       c.theta, wsp<float>(c, g->ws.eq_cos), cf.eq_taps, wsp<float>(c, g->ws.eq_h));
+    hipLaunchKernelGGL(k_eq_synth, dim3((cf.eq_taps + FIR_PER_BLOCK - 1) / FIR_PER_BLOCK, n), dim3(MG_BLOCK), 0,
+                       c.st, d, c.theta, cf.eq_taps, wsp<float>(c, g->ws.eq_h));
   } else if (type == MG_DELAY) {
     hipLaunchKernelGGL(k_delay_synth, dim3(n), dim3(MG_BLOCK), 0, c.st, d, c.theta, wsp<float>(c, g->ws.dl_cos),
                        cf.delay_taps, cf.delay_range, cf.delay_fir_taps, wsp<float>(c, g->ws.dl_tab));
+    hipLaunchKernelGGL(k_delay_compact, dim3((unsigned)((g->dl_len + MG_BLOCK - 1) / MG_BLOCK), 2, n), dim3(MG_BLOCK),
+                       0, c.st, d, wsp<float>(c, g->ws.dl_tab), cf.delay_taps, cf.delay_fir_taps, g->dl_len,
+                       wsp<float>(c, g->ws.dl_h));
   } else if (type == MG_REVERB) {
     const float gb = (float)reverb_gain_bias(cf.sample_rate);
     const float db = (float)reverb_decay_offset(cf.sample_rate, cf.reverb_hop);
@@ -606,12 +684,15 @@ void fir_adjoint(const Ctx& c, int type, int desc_off, int n, float* grad_theta)
   const NodeDesc* d = c.desc + desc_off;
   if (type == MG_EQ) {
     const int K = (cf.eq_taps + 1) / 2;
-    hipLaunchKernelGGL(k_eq_adjoint, dim3((K + MG_BLOCK - 1) / MG_BLOCK, n), dim3(MG_BLOCK), 0, c.st, d, c.theta,
-                       wsp<float>(c, g->ws.eq_cos), cf.eq_taps, wsp<float>(c, g->ws.eq_dh), grad_theta);
+    hipLaunchKernelGGL(k_eq_adjoint, dim3((K + FIR_PER_BLOCK - 1) / FIR_PER_BLOCK, n), dim3(MG_BLOCK), 0, c.st, d,
+                       c.theta, cf.eq_taps, wsp<float>(c, g->ws.eq_dh), grad_theta);
   } else if (type == MG_DELAY) {
-    hipLaunchKernelGGL(k_delay_adjoint, dim3(2 * cf.delay_taps, n), dim3(MG_BLOCK), 0, c.st, d, c.theta,
+    double2* zp = wsp<double2>(c, g->ws.dl_zp);
+    hipLaunchKernelGGL(k_delay_adjoint, dim3(2 * cf.delay_taps, DL_CHUNKS, n), dim3(MG_BLOCK), 0, c.st, d, c.theta,
                        wsp<float>(c, g->ws.dl_tab), wsp<float>(c, g->ws.dl_cos), cf.delay_taps, cf.delay_range,
-                       cf.delay_fir_taps, g->dl_len, wsp<float>(c, g->ws.dl_dh), grad_theta, 0.01f);
+                       cf.delay_fir_taps, g->dl_len, wsp<float>(c, g->ws.dl_dh), grad_theta, zp);
+    hipLaunchKernelGGL(k_delay_zrule, dim3(n), dim3(128), 0, c.st, d, c.theta, cf.delay_taps, cf.delay_range,
+                       cf.delay_fir_taps, (const double2*)zp, grad_theta, 0.01f);
   } else if (type == MG_REVERB) {
     const float gb = (float)reverb_gain_bias(cf.sample_rate);
     const float db = (float)reverb_decay_offset(cf.sample_rate, cf.reverb_hop);

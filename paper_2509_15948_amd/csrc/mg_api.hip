@@ -79,7 +79,11 @@ static size_t plan_ws(mg_graph& g, int mode, bool commit) {
   }
   if (n_dl) {
     take(w.dl_tab, (size_t)n_dl * 2 * c.delay_taps * (1 + c.delay_fir_taps) * 4);
-    if (mode) take(w.dl_dh, (size_t)n_dl * 2 * g.dl_len * 4);
+    take(w.dl_h, (size_t)n_dl * 2 * g.dl_len * 4);
+    if (mode) {
+      take(w.dl_dh, (size_t)n_dl * 2 * g.dl_len * 4);
+      take(w.dl_zp, (size_t)n_dl * 2 * c.delay_taps * 8 * 16);  // z partial sums, 8 chunks
+    }
     take(w.dl_cos, (size_t)c.delay_fir_taps * 4);
   }
   if (n_rv) {

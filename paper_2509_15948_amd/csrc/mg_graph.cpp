@@ -511,3 +511,29 @@ extern "C" int mg_graph_prune(const mg_graph* g, const uint8_t* keep, mg_graph**
     for (int v = 0; v < g->n_nodes; ++v) old_to_new[v] = map[v];
   return rc;
 }
+
+extern "C" int mg_remap_params(const mg_graph* g, const mg_graph* pruned, const int32_t* old_to_new,
+                               const float* src_theta, float* dst_theta, const float* src_wet, float* dst_wet,
+                               void* stream) {
+  if (!g || !pruned || !old_to_new) return fail(MG_ERR_INVALID_ARG, "NULL argument");
+  if ((src_theta == nullptr) != (dst_theta == nullptr) || (src_wet == nullptr) != (dst_wet == nullptr))
+    return fail(MG_ERR_INVALID_ARG, "source and destination must both be given or both be NULL");
+  hipStream_t st = (hipStream_t)stream;
+  for (int v = 0; v < g->n_nodes; ++v) {
+    const int u = old_to_new[v];
+    if (u < 0 || g->proc_idx[v] < 0) continue;
+    if (u >= pruned->n_nodes || pruned->type[u] != g->type[v] || pruned->proc_idx[u] < 0)
+      return fail(MG_ERR_GRAPH, "old_to_new does not match the pruned graph");
+    hipError_t e = hipSuccess;
+    if (src_theta) {
+      const int64_t len = g->type_np[g->type[v]];
+      if (len > 0)
+        e = hipMemcpyAsync(dst_theta + pruned->param_off[u], src_theta + g->param_off[v], (size_t)len * 4,
+                           hipMemcpyDeviceToDevice, st);
+    }
+    if (e == hipSuccess && src_wet)
+      e = hipMemcpyAsync(dst_wet + pruned->proc_idx[u], src_wet + g->proc_idx[v], 4, hipMemcpyDeviceToDevice, st);
+    if (e != hipSuccess) return fail(MG_ERR_HIP, std::string("remap copy: ") + hipGetErrorString(e));
+  }
+  return MG_OK;
+}

@@ -46,7 +46,7 @@ _lib = None
 EXPORTS = ("mg_graph_create", "mg_graph_destroy", "mg_graph_info", "mg_graph_layout", "mg_workspace_size",
            "mg_setup", "mg_forward", "mg_backward", "mg_forward_masked", "mg_adam_step", "mg_graph_prune",
            "mg_last_error", "mg_profile_enable", "mg_profile_read", "mg_forward_trials", "mg_prune_candidates",
-           "mg_prune_order", "mg_prune_accept")
+           "mg_prune_order", "mg_prune_accept", "mg_remap_params")
 
 
 def lib() -> ctypes.CDLL:
@@ -77,6 +77,7 @@ def lib() -> ctypes.CDLL:
         "mg_prune_candidates": [i32, vp, vp, vp, i32, vp, vp],
         "mg_prune_order": [i32, vp, vp, ctypes.c_double, ctypes.c_double, vp, vp],
         "mg_prune_accept": [i32, vp, ctypes.c_double, ctypes.c_double, vp],
+        "mg_remap_params": [vp, vp, vp, vp, vp, vp, vp, vp],
         "mg_profile_enable": [vp, ctypes.c_char_p],
         "mg_profile_read": [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64),
                             ctypes.POINTER(ctypes.c_double)],
@@ -216,6 +217,13 @@ def mg_prune_accept(L_prefix: np.ndarray, L_min: float, tau: float) -> int:
     k = ctypes.c_int32()
     _check(lib().mg_prune_accept(len(lp), lp.ctypes.data if len(lp) else None, L_min, tau, ctypes.byref(k)))
     return k.value
+
+
+def mg_remap_params(g: int, pruned: int, old_to_new: np.ndarray, src_theta, dst_theta, src_wet, dst_wet,
+                    stream: int) -> None:
+    o2n = np.ascontiguousarray(old_to_new, dtype=np.int32)
+    _check(lib().mg_remap_params(g, pruned, o2n.ctypes.data, _ptr(src_theta), _ptr(dst_theta), _ptr(src_wet),
+                                 _ptr(dst_wet), stream))
 
 
 def mg_adam_step(theta, m, v, grad, n: int, lr: float, b1: float, b2: float, eps: float, step: int,
@@ -394,6 +402,31 @@ def prune_round(session: Session, dry, theta, wet, mask=None, tau: float = 1e-3,
     return {"alive": new_alive, "L_min": min(L_min, float(L_prefix[k - 1])) if k else L_min, "L_start": L_min,
             "La": La, "candidates": cand.tolist(), "L_cand": L_cand.tolist(), "order": order.tolist(),
             "L_prefix": L_prefix.tolist(), "k": k, "evaluated": evaluated}
+
+
+def compact(graph: Graph, alive: np.ndarray, noise: Dict[int, np.ndarray], reverb_length: int, target,
+            theta_like=(), wet_like=(), device: str = "cuda"):
+    """Graph surgery after pruning (Sec. 1.2: bypass equals removal): the
+    graph without the processors whose alive entry is 0, a new session on it
+    (mode 1, same target), and remapped copies of the given device vectors in
+    theta's layout (parameters, Adam moments) and in the dry/wet layout.
+    noise maps the original graph's reverb node ids to their fixed noise."""
+    import torch
+    new, o2n = graph.prune(np.asarray(alive, np.uint8))
+    inv = {int(u): v for v, u in enumerate(o2n) if u >= 0}
+    rows = new.reverb_rows()
+    nz = (np.stack([noise[inv[u]] for u in rows]).astype(np.float32) if rows
+          else np.zeros((1, 2, max(reverb_length, 1)), np.float32))
+    noise_d = torch.from_numpy(nz).to(device)
+    sess = Session(new, noise_d, target, mode=1, device=device)
+    st = sess.stream()
+    th_out = [torch.empty(new.n_theta, dtype=torch.float32, device=device) for _ in theta_like]
+    we_out = [torch.empty(new.n_proc, dtype=torch.float32, device=device) for _ in wet_like]
+    for a, b in zip(theta_like, th_out):
+        mg_remap_params(graph.h, new.h, o2n, a, b, None, None, st)
+    for a, b in zip(wet_like, we_out):
+        mg_remap_params(graph.h, new.h, o2n, None, None, a, b, st)
+    return new, o2n, sess, noise_d, th_out, we_out
 
 
 def console_loss(session: Session, dry, theta, wet, mask=None):

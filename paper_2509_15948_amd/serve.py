@@ -2,7 +2,8 @@
 
 Requests arrive over time.  Each one is a complete search on its own song:
 optimisation steps of the full console, then pruning rounds (batched trials,
-the decision rule, fine-tune steps under the new mask).  The server
+the decision rule, graph surgery, fine-tune steps on the smaller graph).  The
+server
 
   * admits an arrived request as soon as a slot is free and its device
     footprint (workspace, tensors, Adam moments) fits the memory budget;
@@ -86,8 +87,24 @@ class Search:
         self.m_w, self.v_w = torch.zeros_like(self.wet), torch.zeros_like(self.wet)
         self.mask = torch.ones(bg.n_proc, device=dev)
         self.alive = np.ones(bg.n_proc, np.uint8)
+        self.noise_by_node = dict(self.noise)
         self.losses = torch.zeros(7, dtype=torch.float64, device=dev)
         self.n_step = 0
+
+    def _compact(self, torch, dev):
+        """Remove the pruned processors from the graph (graph surgery) and
+        carry parameters and Adam moments over to the smaller graph."""
+        new, o2n, sess, noise_d, th, we = MG.compact(self.bg, self.alive, self.noise_by_node, self.cfg.reverb_length,
+                                                     self.target_d, (self.theta, self.m_t, self.v_t),
+                                                     (self.wet, self.m_w, self.v_w), dev)
+        self.noise_by_node = {int(o2n[v]): nz for v, nz in self.noise_by_node.items() if o2n[v] >= 0}
+        self.bg, self.sess, self.noise_d = new, sess, noise_d
+        self.theta, self.m_t, self.v_t = th
+        self.wet, self.m_w, self.v_w = we
+        self.gth = torch.empty_like(self.theta)
+        self.gwe = torch.empty_like(self.wet)
+        self.mask = torch.ones(new.n_proc, device=dev)
+        self.alive = np.ones(new.n_proc, np.uint8)
 
     def _step(self):
         s = self.sess
@@ -144,9 +161,10 @@ class Search:
                 k = MG.mg_prune_accept(L_prefix, L_min, spec.tau)
             if k:
                 self.alive[order[:k]] = 0
-                self.mask = torch.from_numpy(self.alive.astype(np.float32)).to(dev)
+                self._compact(torch, dev)
             self.trace.append({"round": r, "L_min": L_min, "candidates": len(cand), "within": len(order),
-                               "removed": int(k), "alive": int(self.alive.sum())})
+                               "removed": int(k), "processors": int(self.bg.n_proc)})
+            P = self.bg.n_proc
             for i in range(spec.finetune):
                 self._step()
                 if (i + 1) % spec.quantum == 0:
@@ -156,11 +174,12 @@ class Search:
         self.sess.forward(self.dry_d, self.theta, self.wet, self.mask, None, self.losses)
         yield mark()
         self.result = {"losses": self.losses.cpu().numpy().copy(), "theta": self.theta.cpu().numpy().copy(),
-                       "wet": self.wet.cpu().numpy().copy(), "alive": self.alive.copy(), "trace": list(self.trace)}
+                       "wet": self.wet.cpu().numpy().copy(), "processors": int(self.bg.n_proc),
+                       "types": list(self.bg.types), "trace": list(self.trace)}
 
     def release(self):
         for name in ("sess", "dry_d", "noise_d", "target_d", "theta", "wet", "gth", "gwe", "m_t", "v_t", "m_w",
-                     "v_w", "mask", "losses"):
+                     "v_w", "mask", "losses", "noise_by_node"):
             if hasattr(self, name):
                 delattr(self, name)
 

@@ -191,3 +191,30 @@ def test_pruning_round_matches_the_oracle_rule():
     near = near or any(abs(L - L0 * (1 + 1e-2)) < margin for L in oinfo["L_prefix"])
     if not near:
         assert onew == new
+
+
+def test_compacted_graph_gives_the_masked_audio_loss():
+    """Sec. 1.2: removing the bypassed processors (graph surgery, parameters
+    remapped) leaves the mix, and so L_a, bit for bit as under the mask."""
+    case = _trial_case(4, mode=1, seed=6)
+    P = case.bg.n_proc
+    alive = np.ones(P, np.uint8)
+    alive[[1, 4, 9, 17, 30]] = 0
+    mask_d = torch.from_numpy(alive.astype(np.float32)).cuda()
+    mix_m = torch.empty(2, case.cfg.length, device="cuda")
+    lm = torch.zeros(7, dtype=torch.float64, device="cuda")
+    case.sess.forward(case.dry_d, case.theta_d, case.wet_d, mask_d, mix_m, lm)
+    new, o2n, sess, noise_d, (th,), (we,) = MG.compact(case.bg, alive, case.noise, case.cfg.reverb_length,
+                                                       case.target_d, (case.theta_d,), (case.wet_d,))
+    assert new.n_proc == P - 5
+    mix_c = torch.empty(2, case.cfg.length, device="cuda")
+    lc = torch.zeros(7, dtype=torch.float64, device="cuda")
+    sess.forward(case.dry_d, th, we, None, mix_c, lc)
+    torch.cuda.synchronize()
+    assert torch.equal(mix_m, mix_c)
+    assert lm[1].item() == lc[1].item()
+    gth = torch.empty(new.n_theta, device="cuda")
+    gwe = torch.empty(new.n_proc, device="cuda")
+    sess.backward(gth, gwe)
+    torch.cuda.synchronize()
+    assert torch.isfinite(gth).all() and torch.isfinite(gwe).all()
