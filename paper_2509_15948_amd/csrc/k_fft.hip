@@ -29,10 +29,12 @@ constexpr int COL_NT = 512;
 template <int N1>
 constexpr int row_nt() { return N1 >= 1024 ? 512 : 256; }
 
-// W_N^e for e in [0, N), from two FP32 tables rounded from FP64 on the host:
-// twhi[j] = W_N^{1024 j}, twlo[j] = W_N^j.
+// W_N^e for e in [0, N) as h (1 + d), from two FP32 tables rounded from FP64
+// on the host: twhi[j] = W_N^{1024 j} and twlo[j] = W_N^j - 1 (small, so the
+// product adds little to the rounding of h).
 __device__ __forceinline__ float2 big_tw(const float2* __restrict__ twhi, const float2* __restrict__ twlo, int64_t e) {
-  return c_mul(twhi[e >> 10], twlo[e & 1023]);
+  const float2 h = twhi[e >> 10], d = twlo[e & 1023];
+  return make_float2(h.x + (h.x * d.x - h.y * d.y), h.y + (h.x * d.y + h.y * d.x));
 }
 
 __device__ __forceinline__ int64_t signed_lag(int64_t n, int64_t N) { return n < N / 2 ? n : n - N; }
@@ -737,9 +739,9 @@ void fft_init_tables(const Ctx& c, float2* tw, float2* twhi, float2* twlo, int N
       double ang = -2.0 * pi * (double)(1024 * (int64_t)j) / N;
       hi[j] = make_float2((float)cos(ang), (float)sin(ang));
     }
-    for (int j = 0; j < 1024; ++j) {
-      double ang = -2.0 * pi * (double)j / N;
-      lo[j] = make_float2((float)cos(ang), (float)sin(ang));
+    for (int j = 0; j < 1024; ++j) {  // W_N^j - 1 without cancellation
+      const double h = pi * (double)j / N;
+      lo[j] = make_float2((float)(-2.0 * sin(h) * sin(h)), (float)(-sin(2.0 * h)));
     }
     hipMemcpyAsync(twhi, hi.data(), hi.size() * sizeof(float2), hipMemcpyHostToDevice, st);
     hipMemcpyAsync(twlo, lo.data(), lo.size() * sizeof(float2), hipMemcpyHostToDevice, st);

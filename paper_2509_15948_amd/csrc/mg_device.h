@@ -105,83 +105,97 @@ __device__ __forceinline__ V tw_get(const TwTab<N, V>& t, int e) {
   return w;
 }
 
-// One radix-4 Stockham pass over B transforms of length N stored at
-// buf[b * BS + i].  Ns is the product of the radices of the earlier passes.
-template <int N, int B, int BS, int NT, int DIR, typename V>
-__device__ __forceinline__ void fft_r4_pass(V* buf, const TwTab<N, V>& tw, int Ns) {
-  constexpr int Q = N / 4;
+// Stockham passes over B transforms of length N stored at buf[b * BS + i]:
+// each butterfly reads its R inputs (stride N/R, contiguous across threads)
+// into registers, the block synchronises, then every butterfly applies its
+// twiddles, an R-point DFT and writes its R outputs.  Ns is the product of
+// the radices of the earlier passes.  When B N / R is not a multiple of NT the
+// threads past the last butterfly only take part in the barriers.
+
+// 4-point DFT in place (natural order)
+template <int DIR, typename V>
+__device__ __forceinline__ void dft4(V& x0, V& x1, V& x2, V& x3) {
+  const V t0 = c_add(x0, x2), t1 = c_sub(x0, x2);
+  const V t2 = c_add(x1, x3), t3 = c_rot<DIR>(c_sub(x1, x3));
+  x0 = c_add(t0, t2);
+  x1 = c_add(t1, t3);
+  x2 = c_sub(t0, t2);
+  x3 = c_sub(t1, t3);
+}
+
+template <int N, int R, int B, int BS, int NT, int DIR, typename V>
+__device__ __forceinline__ void fft_pass(V* buf, const TwTab<N, V>& tw, int Ns) {
+  constexpr int Q = N / R;
   constexpr int NB = B * Q;
-  constexpr int PER = NB / NT;
-  static_assert(NB % NT == 0, "butterflies must divide evenly");
-  V v[PER][4];
+  constexpr int PER = (NB + NT - 1) / NT;
+  V v[PER][R];
   const int tid = threadIdx.x;
 #pragma unroll
   for (int q = 0; q < PER; ++q) {
     const int g = tid + q * NT;
-    const int b = g / Q, j = g % Q;
-    const V* base = buf + b * BS;
+    if (NB % NT == 0 || g < NB) {
+      const int b = g / Q, j = g % Q;
+      const V* base = buf + b * BS;
 #pragma unroll
-    for (int r = 0; r < 4; ++r) v[q][r] = base[j + r * Q];
+      for (int r = 0; r < R; ++r) v[q][r] = base[j + r * Q];
+    }
   }
   __syncthreads();
-  const int stride = N / (4 * Ns);
+  const int stride = N / (R * Ns);
 #pragma unroll
   for (int q = 0; q < PER; ++q) {
     const int g = tid + q * NT;
+    if (NB % NT != 0 && g >= NB) continue;
     const int b = g / Q, j = g % Q;
     const int k = j & (Ns - 1);
     if (Ns > 1) {
-      v[q][1] = c_mul(v[q][1], tw_get<DIR>(tw, k * stride));
-      v[q][2] = c_mul(v[q][2], tw_get<DIR>(tw, 2 * k * stride));
-      v[q][3] = c_mul(v[q][3], tw_get<DIR>(tw, 3 * k * stride));
+#pragma unroll
+      for (int r = 1; r < R; ++r) v[q][r] = c_mul(v[q][r], tw_get<DIR>(tw, r * k * stride));
     }
-    V t0 = c_add(v[q][0], v[q][2]);
-    V t1 = c_sub(v[q][0], v[q][2]);
-    V t2 = c_add(v[q][1], v[q][3]);
-    V t3 = c_rot<DIR>(c_sub(v[q][1], v[q][3]));
     V* base = buf + b * BS;
-    const int idx = (j - k) * 4 + k;
-    base[idx] = c_add(t0, t2);
-    base[idx + Ns] = c_add(t1, t3);
-    base[idx + 2 * Ns] = c_sub(t0, t2);
-    base[idx + 3 * Ns] = c_sub(t1, t3);
+    const int idx = (j - k) * R + k;
+    if (R == 2) {
+      base[idx] = c_add(v[q][0], v[q][1]);
+      base[idx + Ns] = c_sub(v[q][0], v[q][1]);
+    } else if (R == 4) {
+      dft4<DIR>(v[q][0], v[q][1], v[q][2], v[q][3]);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) base[idx + r * Ns] = v[q][r];
+    } else {  // R == 8: radix-2 step, then two 4-point DFTs (even and odd outputs)
+      using S = decltype(v[q][0].x);
+      const S h = (S)0.70710678118654752440;
+      V a[4], c[4];
+#pragma unroll
+      for (int n = 0; n < 4; ++n) {
+        a[n] = c_add(v[q][n], v[q][n + 4]);
+        c[n] = c_sub(v[q][n], v[q][n + 4]);
+      }
+      // c[n] *= W8^n, W8 = exp(DIR i pi / 4)
+      {
+        V t = c[1];
+        // (1 + DIR i) / sqrt 2 times t
+        c[1].x = h * (t.x - (S)DIR * t.y);
+        c[1].y = h * (t.y + (S)DIR * t.x);
+        c[2] = c_rot<DIR>(c[2]);
+        t = c[3];
+        // (-1 + DIR i) / sqrt 2 times t
+        c[3].x = h * (-t.x - (S)DIR * t.y);
+        c[3].y = h * (-t.y + (S)DIR * t.x);
+      }
+      dft4<DIR>(a[0], a[1], a[2], a[3]);
+      dft4<DIR>(c[0], c[1], c[2], c[3]);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        base[idx + (2 * r) * Ns] = a[r];
+        base[idx + (2 * r + 1) * Ns] = c[r];
+      }
+    }
   }
   __syncthreads();
 }
 
-template <int N, int B, int BS, int NT, int DIR, typename V>
-__device__ __forceinline__ void fft_r2_pass(V* buf, const TwTab<N, V>& tw, int Ns) {
-  constexpr int Q = N / 2;
-  constexpr int NB = B * Q;
-  constexpr int PER = NB / NT;
-  static_assert(NB % NT == 0, "butterflies must divide evenly");
-  V v[PER][2];
-  const int tid = threadIdx.x;
-#pragma unroll
-  for (int q = 0; q < PER; ++q) {
-    const int g = tid + q * NT;
-    const int b = g / Q, j = g % Q;
-    const V* base = buf + b * BS;
-    v[q][0] = base[j];
-    v[q][1] = base[j + Q];
-  }
-  __syncthreads();
-  const int stride = N / (2 * Ns);
-#pragma unroll
-  for (int q = 0; q < PER; ++q) {
-    const int g = tid + q * NT;
-    const int b = g / Q, j = g % Q;
-    const int k = j & (Ns - 1);
-    if (Ns > 1) v[q][1] = c_mul(v[q][1], tw_get<DIR>(tw, k * stride));
-    V* base = buf + b * BS;
-    const int idx = (j - k) * 2 + k;
-    base[idx] = c_add(v[q][0], v[q][1]);
-    base[idx + Ns] = c_sub(v[q][0], v[q][1]);
-  }
-  __syncthreads();
-}
-
-// B unnormalised transforms of length N (4 <= N <= MG_TWN), in place in LDS.
+// B unnormalised transforms of length N (4 <= N <= MG_TWN), in place in LDS:
+// radix-8 passes, then one radix-4 or radix-2 pass for the remaining factor.
 // DIR = -1: X[k] = sum x[n] e^{-2 pi i nk/N};  DIR = +1: the inverse sign.
 // V is float2 or double2 (with twiddle tables of the same type).
 // The caller must __syncthreads() after filling buf and tw.
@@ -191,11 +205,12 @@ __device__ __forceinline__ void fft_lds(V* buf, const TwTab<N, V>& tw) {
   static_assert((1 << LOG) == N, "power of two");
   int Ns = 1;
 #pragma unroll
-  for (int p = 0; p < LOG / 2; ++p) {
-    fft_r4_pass<N, B, BS, NT, DIR>(buf, tw, Ns);
-    Ns *= 4;
+  for (int p = 0; p < LOG / 3; ++p) {
+    fft_pass<N, 8, B, BS, NT, DIR>(buf, tw, Ns);
+    Ns *= 8;
   }
-  if (LOG & 1) fft_r2_pass<N, B, BS, NT, DIR>(buf, tw, Ns);
+  if (LOG % 3 == 2) fft_pass<N, 4, B, BS, NT, DIR>(buf, tw, Ns);
+  if (LOG % 3 == 1) fft_pass<N, 2, B, BS, NT, DIR>(buf, tw, Ns);
 }
 
 // Fixed-order sum over the workgroup; every thread gets the result.
