@@ -27,7 +27,7 @@ namespace mg {
 // N1 = 1024 up (fewer rows of butterflies below)
 constexpr int COL_NT = 512;
 template <int N1>
-constexpr int row_nt() { return N1 >= 1024 ? 512 : 256; }
+constexpr int row_nt() { return N1 >= 4096 ? 1024 : (N1 >= 1024 ? 512 : 256); }
 
 // W_N^e for e in [0, N) as h (1 + d), from two FP32 tables rounded from FP64
 // on the host: twhi[j] = W_N^{1024 j} and twlo[j] = W_N^j - 1 (small, so the

@@ -256,3 +256,53 @@ def test_large_console_properties():
     assert np.all(np.isfinite(outs[0][1])) and np.all(np.isfinite(outs[0][2])) and np.all(np.isfinite(outs[0][3]))
     for a, b in zip(outs[0], outs[1]):
         assert np.array_equal(a, b)
+
+
+def test_tiny_console_adam_trajectory():
+    """20 Adam steps (lr 1e-2) of the tiny console from the initial
+    parameters, on the GPU (FP32, mg_adam_step) and in the oracle (FP64): the
+    per-step loss stays within the FP32 tolerance for the first steps and
+    within 1e-3 relative over all 20; the step where it first leaves the tight
+    bound is reported."""
+    cfg = synth.CONFIGS["tiny"]
+    case = Case(cfg, seed=0, params="init")
+    n, P = case.bg.n_theta, case.bg.n_proc
+    st = torch.cuda.current_stream().cuda_stream
+    th_d, we_d = case.theta_d.clone(), case.wet_d.clone()
+    m_t, v_t = torch.zeros_like(th_d), torch.zeros_like(th_d)
+    m_w, v_w = torch.zeros_like(we_d), torch.zeros_like(we_d)
+    gth = torch.empty_like(th_d)
+    gwe = torch.empty_like(we_d)
+    losses = torch.zeros(7, dtype=torch.float64, device="cuda")
+    th = {v: p.copy() for v, p in case.th.items()}
+    we = {v: np.array([w]) for v, w in case.we.items()}
+    mo = {v: np.zeros_like(p) for v, p in th.items()}
+    vo = {v: np.zeros_like(p) for v, p in th.items()}
+    mwo = {v: np.zeros(1) for v in we}
+    vwo = {v: np.zeros(1) for v in we}
+    tgt = case.target.astype(np.float64)
+    tol0 = None
+    first_out = None
+    for step in range(1, 21):
+        case.sess.forward(case.dry_d, th_d, we_d, None, None, losses)
+        case.sess.backward(gth, gwe)
+        MG.mg_adam_step(th_d, m_t, v_t, gth, n, cfg.lr, 0.9, 0.999, 1e-8, step, st)
+        MG.mg_adam_step(we_d, m_w, v_w, gwe, P, cfg.lr, 0.9, 0.999, 1e-8, step, st)
+        torch.cuda.synchronize()
+        Lg = float(losses[0].item())
+        vals, gt, gw, omix = TR.loss_and_grad(case.g, cfg, case.dry, case.noise, tgt, th,
+                                              {v: float(w[0]) for v, w in we.items()}, None, case.alpha_g,
+                                              case.alpha_p)
+        if tol0 is None:
+            tol0 = loss_tolerances(case, omix)["L"]
+        for v in th:
+            TR.adam_step(th[v], mo[v], vo[v], gt[v], step, lr=cfg.lr)
+            TR.adam_step(we[v], mwo[v], vwo[v], np.array([gw[v]]), step, lr=cfg.lr)
+        err = abs(Lg - vals["L"])
+        print("step", step, "L gpu", Lg, "oracle", vals["L"], "rel", err / abs(vals["L"]), flush=True)
+        if first_out is None and err > tol0:
+            first_out = step
+        if step <= 3:
+            assert err <= tol0, (step, err, tol0)
+        assert err <= 1e-3 * abs(vals["L"]), (step, err)
+    print("first step beyond the FP32 tolerance:", first_out, flush=True)
