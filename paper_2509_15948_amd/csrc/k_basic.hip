@@ -38,8 +38,23 @@ __global__ __launch_bounds__(MG_BLOCK) void k_sum(const NodeDesc* __restrict__ d
                                                    const float* __restrict__ dry, const float* __restrict__ U,
                                                    const float* __restrict__ G, float* __restrict__ out_base,
                                                    int64_t L, int C, int dest_kind) {
+  constexpr int MAXS = 64;  // sources resolved once per block (more are read directly)
+  __shared__ const float* sp[MAXS];
+  __shared__ int64_t sc[MAXS];
   const NodeDesc d = desc[blockIdx.y];
   if (d.src_count == 0) return;
+  const int ns = d.src_count;
+  for (int s = threadIdx.x; s < ns && s < MAXS; s += MG_BLOCK) {
+    const SrcRef r = srcs[d.src_begin + s];
+    if (r.kind == 0) {
+      sp[s] = dry + (int64_t)r.slot * C * L;
+      sc[s] = (C == 1) ? 0 : L;
+    } else {
+      sp[s] = (r.kind == 1 ? U : G) + (int64_t)r.slot * 2 * L;
+      sc[s] = L;
+    }
+  }
+  __syncthreads();
   const int64_t slot = dest_kind == 0 ? d.out_slot : (dest_kind == 1 ? d.gout : d.in_slot);
   float* out = out_base + slot * 2 * L;
   const int64_t n2 = 2 * L;
@@ -47,12 +62,16 @@ __global__ __launch_bounds__(MG_BLOCK) void k_sum(const NodeDesc* __restrict__ d
     const int ch = (int)(i / L);
     const int64_t t = i - (int64_t)ch * L;
     float acc = 0.0f;
-    for (int s = 0; s < d.src_count; ++s) {
-      const SrcRef r = srcs[d.src_begin + s];
+    for (int s = 0; s < ns; ++s) {
       float v;
-      if (r.kind == 0) v = dry[(int64_t)r.slot * C * L + (C == 1 ? 0 : ch * L) + t];
-      else if (r.kind == 1) v = U[(int64_t)r.slot * 2 * L + i];
-      else v = G[(int64_t)r.slot * 2 * L + i];
+      if (s < MAXS) {
+        v = sp[s][ch * sc[s] + t];
+      } else {
+        const SrcRef r = srcs[d.src_begin + s];
+        if (r.kind == 0) v = dry[(int64_t)r.slot * C * L + (C == 1 ? 0 : ch * L) + t];
+        else if (r.kind == 1) v = U[(int64_t)r.slot * 2 * L + i];
+        else v = G[(int64_t)r.slot * 2 * L + i];
+      }
       acc += v;
     }
     out[i] = acc;
@@ -272,6 +291,45 @@ void launch_finish_grads(const Ctx& c, int desc_off, int n, int nblocks, int npa
   hipLaunchKernelGGL(k_finish_grads, dim3(n), dim3(MG_BLOCK), 0, c.st, c.desc + desc_off,
                      c.part + (int64_t)desc_off * c.PB * PK, c.PB, nblocks, nparams, c.wet, c.mask, c.alpha_p,
                      grad_theta, grad_wet);
+}
+
+// The same for every processor of the graph in one launch: fin[j] holds the
+// partial-sum blocks and the direct parameter count of descriptor j (0, 0
+// for mix/output nodes).  Every block reads only its own node's partials.
+__global__ __launch_bounds__(MG_BLOCK) void k_finish_all(const NodeDesc* __restrict__ desc,
+                                                          const float* __restrict__ part, int PB,
+                                                          const int2* __restrict__ fin,
+                                                          const float* __restrict__ wet,
+                                                          const float* __restrict__ mask, float alpha_p,
+                                                          float* __restrict__ grad_theta,
+                                                          float* __restrict__ grad_wet) {
+  __shared__ double red[MG_BLOCK];
+  const int j = blockIdx.x;
+  const NodeDesc d = desc[j];
+  if (d.proc < 0) return;
+  const int2 f = fin[j];
+  const float* pr = part + (int64_t)j * PB * PK;
+  for (int q = 0; q < 1 + f.y; ++q) {
+    const int kk = (q == 0) ? 2 : 2 + q;
+    double s = 0.0;
+    for (int b = threadIdx.x; b < f.x; b += MG_BLOCK) s += (double)pr[b * PK + kk];
+    s = block_sum<MG_BLOCK>(s, red);
+    if (threadIdx.x == 0) {
+      if (q == 0) {
+        const double sg = 1.0 / (1.0 + exp(-(double)wet[d.proc]));
+        const double m = mask ? (double)mask[d.mrow] : 1.0;
+        grad_wet[d.proc] = (float)((s + (double)alpha_p) * sg * (1.0 - sg) * m);
+      } else {
+        grad_theta[d.theta_off + (q - 1)] = (float)s;
+      }
+    }
+  }
+}
+
+void launch_finish_all(const Ctx& c, int n_desc, const int2* fin, float* grad_theta, float* grad_wet) {
+  if (n_desc <= 0) return;
+  hipLaunchKernelGGL(k_finish_all, dim3(n_desc), dim3(MG_BLOCK), 0, c.st, c.desc, c.part, c.PB, fin, c.wet, c.mask,
+                     c.alpha_p, grad_theta, grad_wet);
 }
 
 // L_g energies: lg[desc] = (sum over blocks of partial 0, of partial 1)

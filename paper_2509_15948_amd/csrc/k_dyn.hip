@@ -164,20 +164,31 @@ __global__ __launch_bounds__(MG_BLOCK) void k_dyn_sum(DynView v, float* __restri
   if (t == 0) sums[(int64_t)blockIdx.y * nchunks + blockIdx.x] = red[0];
 }
 
-// pass 2: carries (state entering each chunk), FP64 chain; one thread per node
-__global__ void k_dyn_carry(DynView v, const float* __restrict__ sums, double* __restrict__ carry, int nchunks,
-                            int n) {
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= n) return;
+// pass 2: carries (state entering each chunk), FP64 chain.  One block of 64
+// threads per node: the chunk sums are staged in LDS, one lane runs the chain
+// in order, and the carries are written back by all lanes.
+constexpr int DYN_MAXCH = 4096;  // chunks per node staged in LDS
+
+__global__ __launch_bounds__(64) void k_dyn_carry(DynView v, const float* __restrict__ sums,
+                                                  double* __restrict__ carry, int nchunks, int n) {
+  __shared__ float s_in[DYN_MAXCH];
+  __shared__ double s_out[DYN_MAXCH];
+  const int j = blockIdx.x;
   const NodeDesc d = v.desc[j];
   const float* p = v.theta + d.theta_off;
   const double loga = -log1p(exp(-(double)p[0]));
   const double aC = exp(loga * DYN_CH);
-  double c = 0.0;
-  for (int k = 0; k < nchunks; ++k) {
-    carry[(int64_t)j * nchunks + k] = c;
-    c = aC * c + (double)sums[(int64_t)j * nchunks + k];
+  for (int k = threadIdx.x; k < nchunks; k += blockDim.x) s_in[k] = sums[(int64_t)j * nchunks + k];
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double c = 0.0;
+    for (int k = 0; k < nchunks; ++k) {
+      s_out[k] = c;
+      c = aC * c + (double)s_in[k];
+    }
   }
+  __syncthreads();
+  for (int k = threadIdx.x; k < nchunks; k += blockDim.x) carry[(int64_t)j * nchunks + k] = s_out[k];
 }
 
 // exclusive scan across threads of per-thread segment states (uniform decay
@@ -299,19 +310,26 @@ __global__ __launch_bounds__(MG_BLOCK) void k_dyn_bsum(DynView v, float* __restr
 }
 
 // pass 2 (reverse): lambda entering each chunk from the right
-__global__ void k_dyn_bcarry(DynView v, const float* __restrict__ sums, double* __restrict__ carry, int nchunks,
-                             int n) {
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= n) return;
+__global__ __launch_bounds__(64) void k_dyn_bcarry(DynView v, const float* __restrict__ sums,
+                                                   double* __restrict__ carry, int nchunks, int n) {
+  __shared__ float s_in[DYN_MAXCH];
+  __shared__ double s_out[DYN_MAXCH];
+  const int j = blockIdx.x;
   const NodeDesc d = v.desc[j];
   const float* p = v.theta + d.theta_off;
   const double loga = -log1p(exp(-(double)p[0]));
   const double aC = exp(loga * DYN_CH);
-  double c = 0.0;
-  for (int k = nchunks - 1; k >= 0; --k) {
-    carry[(int64_t)j * nchunks + k] = c;  // lambda at the first sample of chunk k+1
-    c = (double)sums[(int64_t)j * nchunks + k] + aC * c;
+  for (int k = threadIdx.x; k < nchunks; k += blockDim.x) s_in[k] = sums[(int64_t)j * nchunks + k];
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double c = 0.0;
+    for (int k = nchunks - 1; k >= 0; --k) {
+      s_out[k] = c;  // lambda at the first sample of chunk k+1
+      c = (double)s_in[k] + aC * c;
+    }
   }
+  __syncthreads();
+  for (int k = threadIdx.x; k < nchunks; k += blockDim.x) carry[(int64_t)j * nchunks + k] = s_out[k];
 }
 
 template <int GATE>
@@ -550,7 +568,7 @@ void dyn_forward(const Ctx& c, int type, int desc_off, int n) {
   float* sums = wsp<float>(c, g->ws.cmp_sum);
   double* carry = wsp<double>(c, g->ws.cmp_carry);
   hipLaunchKernelGGL(k_dyn_sum, dim3(nch, n), dim3(MG_BLOCK), 0, c.st, v, sums, nch);
-  hipLaunchKernelGGL(k_dyn_carry, dim3((n + 63) / 64), dim3(64), 0, c.st, v, sums, carry, nch, n);
+  hipLaunchKernelGGL(k_dyn_carry, dim3(n), dim3(64), 0, c.st, v, sums, carry, nch, n);
   if (type == MG_GATE) hipLaunchKernelGGL(k_dyn_apply<1>, dim3(nch, n), dim3(MG_BLOCK), 0, c.st, v, carry, nch);
   else hipLaunchKernelGGL(k_dyn_apply<0>, dim3(nch, n), dim3(MG_BLOCK), 0, c.st, v, carry, nch);
 }
@@ -569,11 +587,11 @@ void dyn_backward(const Ctx& c, int type, int desc_off, int n) {
   double* carry = wsp<double>(c, g->ws.cmp_carry);
   if (type == MG_GATE) {
     hipLaunchKernelGGL(k_dyn_bsum<1>, dim3(nch, n), dim3(MG_BLOCK), 0, c.st, v, sums, nch);
-    hipLaunchKernelGGL(k_dyn_bcarry, dim3((n + 63) / 64), dim3(64), 0, c.st, v, sums, carry, nch, n);
+    hipLaunchKernelGGL(k_dyn_bcarry, dim3(n), dim3(64), 0, c.st, v, sums, carry, nch, n);
     hipLaunchKernelGGL(k_dyn_bapply<1>, dim3(nch, n), dim3(MG_BLOCK), 0, c.st, v, carry, nch);
   } else {
     hipLaunchKernelGGL(k_dyn_bsum<0>, dim3(nch, n), dim3(MG_BLOCK), 0, c.st, v, sums, nch);
-    hipLaunchKernelGGL(k_dyn_bcarry, dim3((n + 63) / 64), dim3(64), 0, c.st, v, sums, carry, nch, n);
+    hipLaunchKernelGGL(k_dyn_bcarry, dim3(n), dim3(64), 0, c.st, v, sums, carry, nch, n);
     hipLaunchKernelGGL(k_dyn_bapply<0>, dim3(nch, n), dim3(MG_BLOCK), 0, c.st, v, carry, nch);
   }
 }

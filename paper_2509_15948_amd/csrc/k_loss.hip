@@ -145,12 +145,26 @@ __global__ __launch_bounds__(LOSS_NT) void k_loss_fwd(LossArgs a) {
 
 // stats[x][0] = sum Y^2 (MODE 0), [1] = sum (Y - Yh)^2, [2] = sum|dlog| / cells
 // (fixed order: strided per thread, then a tree)
-// tgt: the target's statistics of this resolution (setup), copied into a
-// separate record (pruning trials) so that it is complete on its own.
-__global__ __launch_bounds__(MG_BLOCK) void k_loss_reduce(const double* __restrict__ part, int nblocks, int cells,
-                                                           int mode, double* __restrict__ stats,
-                                                           const double* __restrict__ tgt) {
+// One block per resolution.  stats[x][0] = sum Y^2 (MODE 0), [1] = sum
+// (Y - Yh)^2, [2] = sum |dlog| / cells.  tgt: the target's statistics of the
+// resolution (setup), copied into a separate record (pruning trials) so that
+// it is complete on its own.
+struct ReduceArgs {
+  const double* part[8];
+  int nblocks[8];
+  int cells[8];
+  double* stats[8];
+  const double* tgt[8];
+  int mode;
+};
+
+__global__ __launch_bounds__(MG_BLOCK) void k_loss_reduce(ReduceArgs ra) {
   __shared__ double red[MG_BLOCK];
+  const int i = blockIdx.x;
+  const double* part = ra.part[i];
+  double* stats = ra.stats[i];
+  const double* tgt = ra.tgt[i];
+  const int nblocks = ra.nblocks[i], mode = ra.mode;
   if (mode == 1 && tgt != stats && threadIdx.x < 4) stats[threadIdx.x * 4 + 0] = tgt[threadIdx.x * 4 + 0];
   for (int q = 0; q < 8; ++q) {
     double s = 0.0;
@@ -161,7 +175,7 @@ __global__ __launch_bounds__(MG_BLOCK) void k_loss_reduce(const double* __restri
       if (mode == 0) {
         if (q < 4) stats[x * 4 + 0] = s;
       } else if (q < 4) {
-        stats[x * 4 + 2] = s / (double)cells;
+        stats[x * 4 + 2] = s / (double)ra.cells[i];
       } else {
         stats[x * 4 + 1] = s;
       }
@@ -430,6 +444,8 @@ static void bwd_n(const Ctx& c, const LossArgs& a, int blocks) {
 static void run_loss_fwd(const Ctx& c, const float* y, int mode, double* stats_out) {
   const mg_graph* g = c.g;
   double* stats = stats_out ? stats_out : wsp<double>(c, g->ws.ls_stats);
+  ReduceArgs ra;
+  ra.mode = mode;
   for (size_t i = 0; i < g->lres.size(); ++i) {
     const LossRes& r = g->lres[i];
     LossArgs a = loss_args(c, (int)i, y);
@@ -444,9 +460,13 @@ static void run_loss_fwd(const Ctx& c, const float* y, int mode, double* stats_o
     }
 #undef MG_F0
 #undef MG_F1
-    hipLaunchKernelGGL(k_loss_reduce, dim3(1), dim3(MG_BLOCK), 0, c.st, a.part, blocks, r.frames * g->cfg.n_mels, mode,
-                       stats + i * 16, wsp<double>(c, g->ws.ls_stats) + i * 16);
+    ra.part[i] = a.part;
+    ra.nblocks[i] = blocks;
+    ra.cells[i] = r.frames * g->cfg.n_mels;
+    ra.stats[i] = stats + i * 16;
+    ra.tgt[i] = wsp<double>(c, g->ws.ls_stats) + i * 16;
   }
+  hipLaunchKernelGGL(k_loss_reduce, dim3((unsigned)g->lres.size()), dim3(MG_BLOCK), 0, c.st, ra);
 }
 
 void loss_setup(const Ctx& c, const float* target) {

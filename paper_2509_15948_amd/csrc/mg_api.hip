@@ -43,6 +43,7 @@ static size_t plan_ws(mg_graph& g, int mode, bool commit) {
   take(w.desc, std::max<size_t>(1, n_win) * sizeof(NodeDesc));
   take(w.srcs, std::max<size_t>(1, g.n_src_base + g.trial_src_cap) * sizeof(SrcRef));
   take(w.losses_tmp, std::max(1, n_desc) * sizeof(int));
+  take(w.fin, std::max(1, n_desc) * 8);
   take(w.U, (size_t)(g.n_uslots + g.trial_slots) * 2 * L * 4);
   if (Bt > 0) {
     take(w.tr_desc, (size_t)std::max(1, g.trial_desc_cap) * sizeof(NodeDesc));
@@ -283,6 +284,20 @@ extern "C" int mg_setup(mg_graph* g, void* workspace, size_t workspace_bytes, in
   if ((rc = hip_check(hipMemcpyAsync(g->base + g->ws.losses_tmp, flag.data(), flag.size() * sizeof(int),
                                      hipMemcpyHostToDevice, st), "flag upload")))
     return rc;
+  // partial-sum blocks and direct parameter counts of every processor, for
+  // the one gradient-finishing launch at the end of the backward
+  std::vector<int2> fin(std::max<size_t>(1, g->desc.size()), make_int2(0, 0));
+  for (size_t j = 0; j < g->desc.size(); ++j) {
+    const int t = g->type[g->desc[j].node];
+    if (t == MG_GAINPAN || t == MG_IMAGER || t == MG_DIST) fin[j] = make_int2(128, g->type_np[t]);
+    else if (t == MG_COMP || t == MG_GATE)
+      fin[j] = make_int2((t == MG_COMP && g->cfg.comp_mode == 1) ? 1 : g->dyn_chunks, g->type_np[t]);
+    else if (t == MG_EQ) fin[j] = make_int2(eq_blocks(g), 0);
+    else if (is_conv(t)) fin[j] = make_int2(g->fft.N1 / (8192 / g->fft.N2), 0);
+  }
+  if ((rc = hip_check(hipMemcpyAsync(g->base + g->ws.fin, fin.data(), fin.size() * sizeof(int2), hipMemcpyHostToDevice,
+                                     st), "finish table upload")))
+    return rc;
   Ctx c = make_ctx(g, st);
   fft_init_tables(c, (float2*)(g->base + g->ws.tw), g->fft.N ? (float2*)(g->base + g->ws.twhi) : nullptr,
                   g->fft.N ? (float2*)(g->base + g->ws.twlo) : nullptr, g->fft.N, st);
@@ -353,7 +368,6 @@ extern "C" int mg_backward(mg_graph* g, float* grad_theta, float* grad_wet, void
   const float* yhat = c.U + (int64_t)g->uslot[o] * 2 * c.L;
   float* dy = c.G + (int64_t)g->gslot[o] * 2 * c.L;
   loss_backward(c, yhat, dy);
-  const mg_config& cf = g->cfg;
   for (size_t s = g->stages.size() - 1; s >= 1; --s) {
     const Stage& S = g->stages[s];
     const int n = (int)S.nodes.size();
@@ -362,23 +376,21 @@ extern "C" int mg_backward(mg_graph* g, float* grad_theta, float* grad_wet, void
     if (t == MG_MIX || t == MG_OUT) continue;
     if (t == MG_GAINPAN || t == MG_IMAGER || t == MG_DIST) {
       launch_pointwise_bwd(c, t, off, n);
-      launch_finish_grads(c, off, n, 128, g->type_np[t], grad_theta, grad_wet);
     } else if (t == MG_COMP || t == MG_GATE) {
       dyn_backward(c, t, off, n);
-      const bool ar = (t == MG_COMP && cf.comp_mode == 1);
-      launch_finish_grads(c, off, n, ar ? 1 : g->dyn_chunks, g->type_np[t], grad_theta, grad_wet);
     } else if (t == MG_EQ) {
       eq_backward(c, off, n);
       fir_adjoint(c, t, off, n, grad_theta);
-      launch_finish_grads(c, off, n, eq_blocks(g), 0, grad_theta, grad_wet);
     } else if (is_conv(t)) {
       conv_backward(c, t, off, n);
       fir_adjoint(c, t, off, n, grad_theta);
-      launch_finish_grads(c, off, n, g->fft.N1 / (8192 / g->fft.N2), 0, grad_theta, grad_wet);
     }
     // processors with several predecessors: every predecessor's dL/dy is
     // this node's dL/du (aliased slots), nothing to scatter
   }
+  // dry/wet and direct parameter gradients of every processor from its
+  // partial sums (kept per descriptor), in one launch
+  launch_finish_all(c, (int)g->desc.size(), (const int2*)(g->base + g->ws.fin), grad_theta, grad_wet);
   g->have_forward = false;
   return hip_check(hipGetLastError(), "backward launch");
 }

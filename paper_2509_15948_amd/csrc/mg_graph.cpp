@@ -312,6 +312,8 @@ int validate_config(const mg_config& c, const std::vector<int>& type) {
   bool has[NTYPES] = {false};
   for (int t : type) has[t] = true;
   if (c.length < 64) return fail(MG_ERR_INVALID_ARG, "length must be >= 64");
+  if ((has[MG_COMP] || has[MG_GATE]) && c.length > (int64_t)4096 * 4096)
+    return fail(MG_ERR_INVALID_ARG, "compressor/noisegate signals are limited to 4096 chunks of 4096 samples");
   if (c.sample_rate <= 0) return fail(MG_ERR_INVALID_ARG, "sample_rate must be > 0");
   if (has[MG_EQ] && (c.eq_taps < 3 || (c.eq_taps & 1) == 0 || c.eq_taps > 4095))
     return fail(MG_ERR_INVALID_ARG, "eq_taps must be odd in [3, 4095]");

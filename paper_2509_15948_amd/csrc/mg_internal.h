@@ -73,6 +73,7 @@ struct WsPlan {
   size_t ls_stats = 0;       // double: per (res, combo): |Y|^2, |Y-Yh|^2, sum|dlog|
   size_t lg = 0;             // double per node: E_ybar, E_u
   size_t losses_tmp = 0;
+  size_t fin = 0;            // int2 per descriptor: partial blocks, direct parameters
   // pruning trials (mg_forward_trials)
   size_t tr_desc = 0;        // staged copy descriptors of every batch
   size_t tr_keep = 0;        // float [max_trials][P] keep flags

@@ -71,6 +71,7 @@ void launch_pointwise_fwd(const Ctx& c, int type, int desc_off, int n);
 void launch_pointwise_bwd(const Ctx& c, int type, int desc_off, int n);
 void launch_finish_grads(const Ctx& c, int desc_off, int n, int nblocks, int nparams, float* grad_theta,
                          float* grad_wet);
+void launch_finish_all(const Ctx& c, int n_desc, const int2* fin, float* grad_theta, float* grad_wet);
 void launch_reduce_lg(const Ctx& c, int desc_off, int n, int nblocks);
 void launch_finalize_losses(const Ctx& c, double* losses, const double* lstats, int n_res, int n_desc);
 // one block per trial b: losses + 7 b, lstats + 128 b, mask + P b, sub + n_desc b
