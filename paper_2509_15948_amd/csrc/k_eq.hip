@@ -194,15 +194,30 @@ __global__ __launch_bounds__(EQ_NT) void k_eq_bwd(EqArgs a) {
   if (threadIdx.x == 0) a.part[((int64_t)j * a.PB + blk) * PK + 2] = s;
 }
 
-// dh[row][t] = sum over blocks (fixed order, FP64); grid (ceil(N/256), nodes)
+// dh[row][t] = sum over blocks (fixed order, FP64): each tap's blocks are
+// split into DH_SPLIT runs added by separate lanes, then the runs in order.
+// grid (ceil(N / DH_TAPS), nodes), DH_TAPS x DH_SPLIT threads
+constexpr int DH_SPLIT = 8;
+constexpr int DH_TAPS = MG_BLOCK / DH_SPLIT;
+
 __global__ __launch_bounds__(MG_BLOCK) void k_eq_dh_reduce(EqArgs a) {
+  __shared__ double part[DH_SPLIT][DH_TAPS];
   const NodeDesc d = a.desc[blockIdx.y];
-  const int t = blockIdx.x * MG_BLOCK + threadIdx.x;
-  if (t >= a.N) return;
-  const float* src = a.dhp + (int64_t)d.aux * a.nblk * a.N + t;
+  const int lane = threadIdx.x % DH_TAPS, r = threadIdx.x / DH_TAPS;
+  const int t = blockIdx.x * DH_TAPS + lane;
+  const int Q = (a.nblk + DH_SPLIT - 1) / DH_SPLIT;
+  const int b0 = r * Q, b1 = min(a.nblk, b0 + Q);
   double s = 0.0;
-  for (int b = 0; b < a.nblk; ++b) s += (double)src[(int64_t)b * a.N];
-  a.dh[(int64_t)d.aux * a.N + t] = (float)s;
+  if (t < a.N) {
+    const float* src = a.dhp + (int64_t)d.aux * a.nblk * a.N + t;
+    for (int b = b0; b < b1; ++b) s += (double)src[(int64_t)b * a.N];
+  }
+  part[r][lane] = s;
+  __syncthreads();
+  if (r != 0 || t >= a.N) return;
+  double tot = 0.0;
+  for (int q = 0; q < DH_SPLIT; ++q) tot += part[q][lane];
+  a.dh[(int64_t)d.aux * a.N + t] = (float)tot;
 }
 
 static EqArgs eq_args(const Ctx& c, int desc_off, bool keep) {
@@ -239,12 +254,14 @@ int eq_blocks(const mg_graph* g) {
   return (int)((g->cfg.length + V - 1) / V);
 }
 
+void eq_spectrum(const Ctx& c, int desc_off, int n) {
+  EqArgs a = eq_args(c, desc_off, false);
+  ProfScope ps(c, "eq_spec", (double)n * (4.0 * a.N + 4.0 * EQ_P));
+  hipLaunchKernelGGL(k_eq_spec, dim3(n), dim3(EQ_NT), 0, c.st, a);
+}
+
 void eq_forward(const Ctx& c, int desc_off, int n, bool keep) {
   EqArgs a = eq_args(c, desc_off, keep);
-  if (!c.trial) {
-    ProfScope ps(c, "eq_spec", (double)n * (4.0 * a.N + 4.0 * EQ_P));
-    hipLaunchKernelGGL(k_eq_spec, dim3(n), dim3(EQ_NT), 0, c.st, a);
-  }
   {
     ProfScope ps(c, "eq_conv", (double)n * ((8.0 * EQ_P) * a.nblk + (keep ? 16.0 : 8.0) * c.L + 8.0 * c.L));
     hipLaunchKernelGGL(k_eq_fwd, dim3(a.nblk, n), dim3(EQ_NT), 0, c.st, a);
@@ -259,7 +276,11 @@ void eq_backward(const Ctx& c, int desc_off, int n) {
     ProfScope ps(c, "eq_conv", (double)n * ((24.0 * EQ_P) * a.nblk + 16.0 * c.L + 4.0 * a.N * a.nblk));
     hipLaunchKernelGGL(k_eq_bwd, dim3(a.nblk, n), dim3(EQ_NT), 0, c.st, a);
   }
-  hipLaunchKernelGGL(k_eq_dh_reduce, dim3((a.N + MG_BLOCK - 1) / MG_BLOCK, n), dim3(MG_BLOCK), 0, c.st, a);
+}
+
+void eq_backward_fir(const Ctx& c, int desc_off, int n) {
+  EqArgs a = eq_args(c, desc_off, true);
+  hipLaunchKernelGGL(k_eq_dh_reduce, dim3((a.N + DH_TAPS - 1) / DH_TAPS, n), dim3(MG_BLOCK), 0, c.st, a);
 }
 
 }  // namespace mg

@@ -582,11 +582,10 @@ static void rows_bwd_n(const Ctx& c, const float2* Tin, float2* Tu, float2* Th, 
   }
 
 // FIR spectra of the stage's nodes -> ZH (from the compact FIRs)
-void conv_fir_spectrum(const Ctx& c, int type, int desc_off, int n) {
+void conv_fir_spectrum(const Ctx& c, int type, int desc_off, int n, float2* T1) {
   const mg_graph* g = c.g;
   const mg_config& cf = g->cfg;
   EngineArgs ea = engine_args(c);
-  float2* T1 = wsp<float2>(c, g->ws.T1);
   float2* ZH = wsp<float2>(c, g->ws.ZH);
   const int z0 = conv_base(g, type);
   if (type == MG_EQ) {
@@ -652,13 +651,14 @@ void conv_forward(const Ctx& c, int type, int desc_off, int n, bool keep_input_s
   launch_reduce_lg(c, desc_off, n, ea.N1 / (8192 / ea.N2));
 }
 
-void conv_backward(const Ctx& c, int type, int desc_off, int n) {
+// Backward of one stage, input-gradient part: column FFTs of dL/dybar, the
+// row pass (both products), inverse columns of the input gradient.  The FIR
+// gradient spectrum is left in T3 for conv_backward_fir.
+void conv_backward(const Ctx& c, int type, int desc_off, int n, float2* T3) {
   const mg_graph* g = c.g;
-  const mg_config& cf = g->cfg;
   EngineArgs ea = engine_args(c);
   float2* T1 = wsp<float2>(c, g->ws.T1);
   float2* T2 = wsp<float2>(c, g->ws.T2);
-  float2* T3 = wsp<float2>(c, g->ws.T3);
   const float2* ZH = wsp<float2>(c, g->ws.ZH);
   const float2* ZU = wsp<float2>(c, g->ws.ZU);
   const int z0 = conv_base(g, type);
@@ -686,16 +686,18 @@ void conv_backward(const Ctx& c, int type, int desc_off, int n) {
     su.alpha_g = c.alpha_g;
     run_icols(c, su, T2, n, ea, 24.0 * c.L);
   }
+}
+
+// Backward of one stage, FIR-gradient part: inverse columns of T3 at the
+// FIR's lags only.
+void conv_backward_fir(const Ctx& c, int type, int desc_off, int n, const float2* T3) {
+  const mg_graph* g = c.g;
+  const mg_config& cf = g->cfg;
+  EngineArgs ea = engine_args(c);
   StGradH sh;
   sh.desc = c.desc + desc_off;
   sh.N = ea.N;
-  if (type == MG_EQ) {
-    sh.dh = wsp<float>(c, g->ws.eq_dh);
-    sh.Nh = cf.eq_taps;
-    sh.lag0 = -(cf.eq_taps - 1) / 2;
-    sh.stride = cf.eq_taps;
-    sh.shared = 1;
-  } else if (type == MG_REVERB) {
+  if (type == MG_REVERB) {
     sh.dh = wsp<float>(c, g->ws.rv_dh);
     sh.Nh = cf.reverb_length;
     sh.lag0 = 0;
@@ -708,7 +710,7 @@ void conv_backward(const Ctx& c, int type, int desc_off, int n) {
     sh.stride = 2 * g->dl_len;
     sh.shared = 0;
   }
-  run_icols(c, sh, T3, n, ea, (sh.shared ? 4.0 : 8.0) * sh.Nh);
+  run_icols(c, sh, T3, n, ea, 8.0 * sh.Nh);
 }
 
 // tables for the LDS FFT (size MG_TWN) and for the big twiddles of N

@@ -19,11 +19,11 @@ namespace mg {
 
 // ---------------------------------------------------------------- equalizer
 // Both directions are cosine sums of about a thousand terms per output.  Each
-// output is split over FIR_SPLIT threads (one wavefront per part); a thread
+// output is split over FIR_SPLIT threads of one block; a thread
 // walks its part of the sum with an FP64 rotation e^{i theta} started from an
 // exactly reduced angle, so no table is read and the drift stays at the FP64
 // rounding level.  The parts are added in a fixed order.
-constexpr int FIR_SPLIT = 4;
+constexpr int FIR_SPLIT = 16;
 constexpr int FIR_PER_BLOCK = MG_BLOCK / FIR_SPLIT;   // outputs per block
 
 // exp(i 2 pi (a mod N) / N) in FP64

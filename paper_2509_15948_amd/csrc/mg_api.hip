@@ -61,8 +61,12 @@ static size_t plan_ws(mg_graph& g, int mode, bool commit) {
     take(w.ZH, (size_t)(n_dl + n_rv) * N * 8);
     if (mode) take(w.ZU, (size_t)(n_dl + n_rv) * N * 8);
     take(w.T1, (size_t)g.max_conv_stage * N * 8);
+    take(w.T1s, (size_t)g.max_conv_stage * N * 8);  // FIR spectra on the side stream
     take(w.T2, (size_t)g.max_conv_stage * N * 8);
-    if (mode) take(w.T3, (size_t)g.max_conv_stage * N * 8);
+    if (mode) {
+      take(w.T3, (size_t)g.max_conv_stage * N * 8);
+      take(w.T3b, (size_t)g.max_conv_stage * N * 8);  // alternate stages: the side stream may still read T3
+    }
     take(w.twhi, (size_t)std::max<int64_t>(1, N / 1024) * 8);
     take(w.twlo, 1024 * 8);
   }
@@ -214,23 +218,49 @@ void forward_stage(const Ctx& c, int t, int off, int n, bool keep, const NodeDes
     const int cap = std::max(1, g->max_stage);
     for (int j = 0; j < n; j += cap) dyn_forward(c, t, off + j, std::min(cap, n - j));
   } else if (t == MG_EQ) {
-    if (!c.trial) fir_synth(c, t, off, n);
     eq_forward(c, off, n, keep);
   } else if (is_conv(t)) {
-    if (!c.trial) {
-      fir_synth(c, t, off, n);
-      conv_fir_spectrum(c, t, off, n);
-    }
     const int cap = std::max(1, g->max_conv_stage);
     for (int j = 0; j < n; j += cap) conv_forward(c, t, off + j, std::min(cap, n - j), keep);
   }
 }
 
+// FIR synthesis and FIR spectra of one stage (they depend on theta only)
+static void fir_stage(const Ctx& c, int t, int off, int n, float2* T) {
+  fir_synth(c, t, off, n);
+  if (t == MG_EQ) eq_spectrum(c, off, n);
+  else conv_fir_spectrum(c, t, off, n, T);
+}
+
 static void run_forward(mg_graph* g, hipStream_t st, bool keep, double* losses, float* mix) {
   Ctx c = make_ctx(g, st);
   const int n_desc = (int)g->desc.size();
+  // The FIRs of every EQ/delay/reverb stage depend on theta only: they are
+  // synthesised on the side stream, ahead of the chain, and each stage waits
+  // for its own FIRs.
+  std::vector<int> ready(g->stages.size(), -1);
+  const bool side = g->side != nullptr;
+  if (side) {
+    Ctx cs = c;
+    cs.st = g->side;
+    hipEventRecord(g->sev[0], st);
+    hipStreamWaitEvent(g->side, g->sev[0], 0);
+    int ev = 1;
+    for (size_t s = 1; s < g->stages.size(); ++s) {
+      const Stage& S = g->stages[s];
+      if (!is_conv(S.type)) continue;
+      fir_stage(cs, S.type, S.desc_off, (int)S.nodes.size(), (float2*)(g->base + g->ws.T1s));
+      ready[s] = ev;
+      hipEventRecord(g->sev[ev], g->side);
+      ev = ev + 1 < (int)g->sev.size() ? ev + 1 : 1;
+    }
+  }
   for (size_t s = 1; s < g->stages.size(); ++s) {
     const Stage& S = g->stages[s];
+    if (is_conv(S.type)) {
+      if (ready[s] >= 0) hipStreamWaitEvent(st, g->sev[ready[s]], 0);
+      else fir_stage(c, S.type, S.desc_off, (int)S.nodes.size(), (float2*)(g->base + g->ws.T1));
+    }
     forward_stage(c, S.type, S.desc_off, (int)S.nodes.size(), keep, g->desc.data() + S.desc_off);
   }
   const float* yhat = c.U + (int64_t)g->uslot[g->output_node] * 2 * c.L;
@@ -298,6 +328,12 @@ extern "C" int mg_setup(mg_graph* g, void* workspace, size_t workspace_bytes, in
   if ((rc = hip_check(hipMemcpyAsync(g->base + g->ws.fin, fin.data(), fin.size() * sizeof(int2), hipMemcpyHostToDevice,
                                      st), "finish table upload")))
     return rc;
+  if (!g->side) {
+    if ((rc = hip_check(hipStreamCreateWithFlags(&g->side, hipStreamNonBlocking), "side stream"))) return rc;
+    g->sev.resize(64);
+    for (auto& e : g->sev)
+      if ((rc = hip_check(hipEventCreateWithFlags(&e, hipEventDisableTiming), "event create"))) return rc;
+  }
   Ctx c = make_ctx(g, st);
   fft_init_tables(c, (float2*)(g->base + g->ws.tw), g->fft.N ? (float2*)(g->base + g->ws.twhi) : nullptr,
                   g->fft.N ? (float2*)(g->base + g->ws.twlo) : nullptr, g->fft.N, st);
@@ -368,6 +404,22 @@ extern "C" int mg_backward(mg_graph* g, float* grad_theta, float* grad_wet, void
   const float* yhat = c.U + (int64_t)g->uslot[o] * 2 * c.L;
   float* dy = c.G + (int64_t)g->gslot[o] * 2 * c.L;
   loss_backward(c, yhat, dy);
+  // The input-gradient chain stays on the caller's stream; each FIR stage's
+  // parameter-gradient work (FIR-gradient inverse columns, block sums, the
+  // adjoints back to the raw parameters) is handed to the side stream after
+  // an event, so it overlaps the next stages.  Long-FIR stages alternate
+  // between two FIR-gradient spectra (T3, T3b); a stage waits until the side
+  // stream has read the buffer it is about to overwrite.
+  Ctx cs = c;
+  cs.st = g->side;
+  int ev = 0;
+  auto fork = [&]() {
+    hipEventRecord(g->sev[ev], st);
+    hipStreamWaitEvent(g->side, g->sev[ev], 0);
+    ev = (ev + 1) % (int)g->sev.size();
+  };
+  hipEvent_t t3_done[2] = {nullptr, nullptr};
+  int n_conv = 0;
   for (size_t s = g->stages.size() - 1; s >= 1; --s) {
     const Stage& S = g->stages[s];
     const int n = (int)S.nodes.size();
@@ -380,14 +432,27 @@ extern "C" int mg_backward(mg_graph* g, float* grad_theta, float* grad_wet, void
       dyn_backward(c, t, off, n);
     } else if (t == MG_EQ) {
       eq_backward(c, off, n);
-      fir_adjoint(c, t, off, n, grad_theta);
+      fork();
+      eq_backward_fir(cs, off, n);
+      fir_adjoint(cs, t, off, n, grad_theta);
     } else if (is_conv(t)) {
-      conv_backward(c, t, off, n);
-      fir_adjoint(c, t, off, n, grad_theta);
+      const int b = n_conv++ & 1;
+      float2* T3 = (float2*)(g->base + (b ? g->ws.T3b : g->ws.T3));
+      if (t3_done[b]) hipStreamWaitEvent(st, t3_done[b], 0);
+      conv_backward(c, t, off, n, T3);
+      fork();
+      conv_backward_fir(cs, t, off, n, T3);
+      t3_done[b] = g->sev[ev];
+      hipEventRecord(t3_done[b], g->side);
+      ev = (ev + 1) % (int)g->sev.size();
+      fir_adjoint(cs, t, off, n, grad_theta);
     }
     // processors with several predecessors: every predecessor's dL/dy is
     // this node's dL/du (aliased slots), nothing to scatter
   }
+  // join: the side stream's gradients before anything later on the stream
+  hipEventRecord(g->sev[ev], g->side);
+  hipStreamWaitEvent(st, g->sev[ev], 0);
   // dry/wet and direct parameter gradients of every processor from its
   // partial sums (kept per descriptor), in one launch
   launch_finish_all(c, (int)g->desc.size(), (const int2*)(g->base + g->ws.fin), grad_theta, grad_wet);

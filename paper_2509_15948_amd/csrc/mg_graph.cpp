@@ -434,6 +434,8 @@ extern "C" int mg_graph_destroy(mg_graph* g) {
   if (g) {
     for (auto& e : g->prof.ev) (void)hipEventDestroy(e);
     if (g->trial_ev) (void)hipEventDestroy(g->trial_ev);
+    for (auto& e : g->sev) (void)hipEventDestroy(e);
+    if (g->side) (void)hipStreamDestroy(g->side);
   }
   delete g;
   return MG_OK;

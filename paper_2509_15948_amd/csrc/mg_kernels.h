@@ -85,15 +85,21 @@ void launch_trial_mask(float* mask, const float* base, const float* keep, int P,
 
 // k_fft.hip: the FIR convolution engine
 void fft_init_tables(const Ctx& c, float2* tw, float2* twhi, float2* twlo, int N, hipStream_t st);
-// forward conv of stage nodes; fir spectra ZH must be ready
-void conv_fir_spectrum(const Ctx& c, int type, int desc_off, int n);
+// FIR spectra of the stage's nodes -> ZH (T: column-pass temporary); the
+// forward conv of stage nodes needs them ready
+void conv_fir_spectrum(const Ctx& c, int type, int desc_off, int n, float2* T);
 void conv_forward(const Ctx& c, int type, int desc_off, int n, bool keep_input_spectrum);
-void conv_backward(const Ctx& c, int type, int desc_off, int n);
+// backward in two parts: the input gradient (leaves the FIR-gradient
+// spectrum in T3) and the FIR gradient at the FIR's lags (reads T3)
+void conv_backward(const Ctx& c, int type, int desc_off, int n, float2* T3);
+void conv_backward_fir(const Ctx& c, int type, int desc_off, int n, const float2* T3);
 
 // k_eq.hip: equalizer by overlap-save in LDS
 int eq_blocks(const mg_graph* g);
-void eq_forward(const Ctx& c, int desc_off, int n, bool keep);  // c.trial: reuse the block spectra
-void eq_backward(const Ctx& c, int desc_off, int n);
+void eq_spectrum(const Ctx& c, int desc_off, int n);            // H_P of the stage's nodes
+void eq_forward(const Ctx& c, int desc_off, int n, bool keep);  // needs H_P ready
+void eq_backward(const Ctx& c, int desc_off, int n);      // input gradient and per-block FIR gradients
+void eq_backward_fir(const Ctx& c, int desc_off, int n);  // FIR gradient: fixed-order sum over blocks
 
 // k_fir.hip: FIR synthesis and adjoints
 void fir_setup(const Ctx& c, const float* reverb_noise);
