@@ -77,6 +77,19 @@ def stats_markdown(dirpath, command):
     return "\n".join(out) + "\n"
 
 
+def class_markdown(dirpath):
+    """Average duration per kernel class over every dispatch of the trace
+    (the classes of mg_profile_enable; bench.py times the same classes)."""
+    rows = list(csv.DictReader(open(_find(dirpath, "kernel_trace.csv"))))
+    out = ["| class | dispatches | avg us |", "|---|---:|---:|"]
+    for cls, pat in CLASSES.items():
+        rx = re.compile(pat)
+        d = [(int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3 for r in rows if rx.search(r["Kernel_Name"])]
+        if d:
+            out.append(f"| {cls} | {len(d)} | {sum(d) / len(d):.1f} |")
+    return "\n".join(out) + "\n"
+
+
 def _counter_rows(dirpath):
     path = _find(dirpath, "counter_collection.csv")
     return list(csv.DictReader(open(path)))
@@ -131,9 +144,27 @@ def traffic_records(fetch_dir, write_dir, command):
     return out
 
 
+def traffic_markdown(recs, workload):
+    any_rec = next(iter(recs.values()))
+    cal = any_rec["calibration"]
+    out = [f"# HBM traffic per launch by kernel class: {workload} console", "",
+           "Two runs, one counter each (FETCH_SIZE, then WRITE_SIZE):", "",
+           "`" + any_rec["command"] + "`", "",
+           f"Calibration: a device copy of {cal['bytes']} bytes (`{cal['kernel']}`) reads as {cal['fetch_factor']} x "
+           f"its size in FETCH_SIZE and {cal['write_factor']} x in WRITE_SIZE; the counters are divided by these "
+           "factors.  The run covers target rendering, loss setup, one warm-up step and two steps.", "",
+           "| class | launches | fetch MB/launch | write MB/launch | total MB/launch |", "|---|---:|---:|---:|---:|"]
+    for cls in sorted(recs):
+        r = recs[cls]
+        out.append(f"| {cls} | {r['launches']} | {r['fetch_bytes_per_launch'] / 1e6:.1f} | "
+                   f"{r['write_bytes_per_launch'] / 1e6:.1f} | {r['bytes_per_launch'] / 1e6:.1f} |")
+    return "\n".join(out) + "\n"
+
+
 def main(argv):
     if argv[0] == "stats":
         sys.stdout.write(stats_markdown(argv[1], " ".join(argv[2:])))
+        sys.stdout.write("\nBy kernel class:\n\n" + class_markdown(argv[1]))
     elif argv[0] == "traffic":
         # argv: traffic FETCH_DIR WRITE_DIR OUT_DIR WORKLOAD CMD...
         recs = traffic_records(argv[1], argv[2], " ".join(argv[5:]))
@@ -142,6 +173,8 @@ def main(argv):
             rec["workload"] = argv[4]
             json.dump(rec, open(os.path.join(argv[3], f"{cls}_{argv[4]}_console_traffic.json"), "w"), indent=1)
             print(cls, rec["bytes_per_launch"], "bytes per launch over", rec["launches"], "launches")
+        with open(os.path.join(argv[3], f"console_{argv[4]}_traffic.md"), "w") as f:
+            f.write(traffic_markdown(recs, argv[4]))
     else:
         raise SystemExit(__doc__)
 
