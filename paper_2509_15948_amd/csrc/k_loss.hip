@@ -441,18 +441,42 @@ static void bwd_n(const Ctx& c, const LossArgs& a, int blocks) {
     case 4096: CALL(4096); break;  \
   }
 
+// The resolutions are independent: odd ones run on the side stream (forked
+// from and joined back to the caller's stream), which fills the tail of each
+// frame kernel with the next one's blocks.
+constexpr int EV_LOSS_FORK = 62, EV_LOSS_JOIN = 63;
+
+static bool loss_fork(const Ctx& c, Ctx& cs) {
+  const mg_graph* g = c.g;
+  if (!g->side || g->sev.size() < 64 || g->lres.size() < 2) return false;
+  cs = c;
+  cs.st = g->side;
+  hipEventRecord(g->sev[EV_LOSS_FORK], c.st);
+  hipStreamWaitEvent(g->side, g->sev[EV_LOSS_FORK], 0);
+  return true;
+}
+
+static void loss_join(const Ctx& c) {
+  const mg_graph* g = c.g;
+  hipEventRecord(g->sev[EV_LOSS_JOIN], g->side);
+  hipStreamWaitEvent(c.st, g->sev[EV_LOSS_JOIN], 0);
+}
+
 static void run_loss_fwd(const Ctx& c, const float* y, int mode, double* stats_out) {
   const mg_graph* g = c.g;
   double* stats = stats_out ? stats_out : wsp<double>(c, g->ws.ls_stats);
   ReduceArgs ra;
   ra.mode = mode;
+  Ctx cs;
+  const bool forked = loss_fork(c, cs);
   for (size_t i = 0; i < g->lres.size(); ++i) {
     const LossRes& r = g->lres[i];
+    const Ctx& cc = (forked && (i & 1)) ? cs : c;
     LossArgs a = loss_args(c, (int)i, y);
     const int FPB = r.nfft >= 2048 ? 1 : 2048 / r.nfft;
     const int blocks = (r.frames + FPB - 1) / FPB;
-#define MG_F0(NN) fwd_n<NN, 0>(c, a, blocks)
-#define MG_F1(NN) fwd_n<NN, 1>(c, a, blocks)
+#define MG_F0(NN) fwd_n<NN, 0>(cc, a, blocks)
+#define MG_F1(NN) fwd_n<NN, 1>(cc, a, blocks)
     if (mode == 0) {
       MG_LOSS_SWITCH(r.nfft, MG_F0)
     } else {
@@ -466,6 +490,7 @@ static void run_loss_fwd(const Ctx& c, const float* y, int mode, double* stats_o
     ra.stats[i] = stats + i * 16;
     ra.tgt[i] = wsp<double>(c, g->ws.ls_stats) + i * 16;
   }
+  if (forked) loss_join(c);
   hipLaunchKernelGGL(k_loss_reduce, dim3((unsigned)g->lres.size()), dim3(MG_BLOCK), 0, c.st, ra);
 }
 
@@ -495,13 +520,16 @@ void loss_backward(const Ctx& c, const float* yhat, float* dyhat) {
   ga.L = c.L;
   ga.out = dyhat;
   size_t off = g->ws.ls_part;
+  Ctx cs;
+  const bool forked = loss_fork(c, cs);
   for (size_t i = 0; i < g->lres.size(); ++i) {
     const LossRes& r = g->lres[i];
+    const Ctx& cc = (forked && (i & 1)) ? cs : c;
     LossArgs a = loss_args(c, (int)i, yhat);
     a.scratch = (float*)(c.base + off);
     const int FPB = r.nfft >= 2048 ? 1 : 2048 / r.nfft;
     const int blocks = (r.frames + FPB - 1) / FPB;
-#define MG_B(NN) bwd_n<NN>(c, a, blocks)
+#define MG_B(NN) bwd_n<NN>(cc, a, blocks)
     MG_LOSS_SWITCH(r.nfft, MG_B)
 #undef MG_B
     ga.r[i].scratch = a.scratch;
@@ -510,6 +538,7 @@ void loss_backward(const Ctx& c, const float* yhat, float* dyhat) {
     ga.r[i].F = r.frames;
     off += (((size_t)r.frames * r.nfft * 2 * 4) + 255) / 256 * 256;
   }
+  if (forked) loss_join(c);
   int64_t blocks = (c.L + MG_BLOCK - 1) / MG_BLOCK;
   if (blocks > 2048) blocks = 2048;
   hipLaunchKernelGGL(k_loss_gather, dim3((unsigned)blocks), dim3(MG_BLOCK), 0, c.st, ga);
