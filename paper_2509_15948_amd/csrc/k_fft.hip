@@ -23,7 +23,8 @@
 namespace mg {
 
 // threads per block: the column kernels hold 64 KB of LDS (two blocks per
-// CU), so 512 threads give 16 waves per CU; row kernels use 512 threads from
+// CU), so 512 threads give 16 waves per CU (16384-element tiles with 1024
+// threads, one block per CU, measured slower); row kernels use 512 threads from
 // N1 = 1024 up (fewer rows of butterflies below)
 constexpr int COL_NT = 512;
 template <int N1>
@@ -488,13 +489,13 @@ __global__ __launch_bounds__(row_nt<N1>()) void k_rows_bwd(const float2* __restr
 template <typename LD>
 void run_cols(const Ctx& c, const LD& ld, float2* T, int n, const EngineArgs& ea, double in_bytes) {
   const int N2 = ea.N2;
-  const int TC = 8192 / N2;
+  const int TC = COL_TILE / N2;
   dim3 grid(ea.N1 / TC, n), blk(COL_NT);
   ProfScope ps(c, "conv_cols", (double)n * (in_bytes + 8.0 * ea.N));
   switch (N2) {
 #define MG_CASE(NN)                                                                   \
   case NN:                                                                            \
-    hipLaunchKernelGGL((k_cols<NN, 8192 / NN, LD>), grid, blk, 0, c.st, ld, T, ea); \
+    hipLaunchKernelGGL((k_cols<NN, COL_TILE / NN, LD>), grid, blk, 0, c.st, ld, T, ea); \
     break;
     MG_CASE(16) MG_CASE(32) MG_CASE(64) MG_CASE(128) MG_CASE(256) MG_CASE(512) MG_CASE(1024)
 #undef MG_CASE
@@ -504,13 +505,13 @@ void run_cols(const Ctx& c, const LD& ld, float2* T, int n, const EngineArgs& ea
 template <typename ST>
 void run_icols(const Ctx& c, const ST& st, const float2* T, int n, const EngineArgs& ea, double out_bytes) {
   const int N2 = ea.N2;
-  const int TC = 8192 / N2;
+  const int TC = COL_TILE / N2;
   dim3 grid(ea.N1 / TC, n), blk(COL_NT);
   ProfScope ps(c, "conv_icols", (double)n * (out_bytes + 8.0 * ea.N));
   switch (N2) {
 #define MG_CASE(NN)                                                                    \
   case NN:                                                                             \
-    hipLaunchKernelGGL((k_icols<NN, 8192 / NN, ST>), grid, blk, 0, c.st, st, T, ea); \
+    hipLaunchKernelGGL((k_icols<NN, COL_TILE / NN, ST>), grid, blk, 0, c.st, st, T, ea); \
     break;
     MG_CASE(16) MG_CASE(32) MG_CASE(64) MG_CASE(128) MG_CASE(256) MG_CASE(512) MG_CASE(1024)
 #undef MG_CASE
@@ -648,7 +649,7 @@ void conv_forward(const Ctx& c, int type, int desc_off, int n, bool keep_input_s
     st.ybar_base = nullptr;
   }
   run_icols(c, st, T2, n, ea, (keep_input_spectrum ? 24.0 : 16.0) * c.L);
-  launch_reduce_lg(c, desc_off, n, ea.N1 / (8192 / ea.N2));
+  launch_reduce_lg(c, desc_off, n, ea.N1 / (COL_TILE / ea.N2));
 }
 
 // Backward of one stage, input-gradient part: column FFTs of dL/dybar, the

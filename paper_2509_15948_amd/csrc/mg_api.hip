@@ -167,7 +167,7 @@ static void finish_compile(mg_graph& g) {
   }
   g.dyn_chunks = (int)((g.cfg.length + 4095) / 4096);
   int pb = 128;
-  if (g.fft.N > 0) pb = std::max(pb, g.fft.N / 8192);
+  if (g.fft.N > 0) pb = std::max(pb, g.fft.N / COL_TILE);
   pb = std::max(pb, g.dyn_chunks);
   if (g.type_count[MG_EQ] > 0) pb = std::max(pb, eq_blocks(&g));
   g.part_blocks = pb;
@@ -323,7 +323,7 @@ extern "C" int mg_setup(mg_graph* g, void* workspace, size_t workspace_bytes, in
     else if (t == MG_COMP || t == MG_GATE)
       fin[j] = make_int2((t == MG_COMP && g->cfg.comp_mode == 1) ? 1 : g->dyn_chunks, g->type_np[t]);
     else if (t == MG_EQ) fin[j] = make_int2(eq_blocks(g), 0);
-    else if (is_conv(t)) fin[j] = make_int2(g->fft.N1 / (8192 / g->fft.N2), 0);
+    else if (is_conv(t)) fin[j] = make_int2(g->fft.N1 / (COL_TILE / g->fft.N2), 0);
   }
   if ((rc = hip_check(hipMemcpyAsync(g->base + g->ws.fin, fin.data(), fin.size() * sizeof(int2), hipMemcpyHostToDevice,
                                      st), "finish table upload")))

@@ -5,6 +5,8 @@
 namespace mg {
 
 constexpr int PK = 8;  // floats of partial sums per (node, block)
+// elements of one column block of the FFT engine (TC = COL_TILE / N2 columns)
+constexpr int COL_TILE = 8192;
 
 struct Ctx {
   const mg_graph* g;
