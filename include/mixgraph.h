@@ -79,6 +79,9 @@ typedef struct mg_config {
                               0 picks max_trials x the largest suffix of one
                               processor, so single-processor trials run as
                               one batch                                      */
+  int32_t unfused;         /* 1: one launch per pointwise stage instead of one
+                              per chain of consecutive pointwise stages (same
+                              results; for checks)                           */
   double alpha_g;          /* gain-staging regulariser weight                 */
   double alpha_p;          /* dry/wet l1 regulariser weight                   */
 } mg_config;
@@ -229,14 +232,16 @@ int mg_remap_params(const mg_graph* g, const mg_graph* pruned, const int32_t* ol
                     void* stream);
 
 /* Measurement of one kernel class (for roofline reporting, not part of the
- * method): after mg_profile_enable(g, cls), HIP events are recorded on the
- * caller's stream around every launch of that class ("conv_cols",
- * "conv_rows", "conv_icols", "eq_conv", "eq_spec", "dyn", "pointwise", "sum",
- * "loss", "fir", "reverb_fir"; NULL
- * disables; at most 4096 launches between reads).  mg_profile_read
- * synchronises on the recorded events and returns the summed device time in
- * ms, the number of timed launches and the algorithmic bytes they move (the
- * reads and writes each kernel is designed to make), then resets. */
+ * method): after mg_profile_enable(g, cls), every kernel launched for that
+ * class ("conv_cols", "conv_rows", "conv_icols", "eq_conv", "eq_spec", "dyn",
+ * "pointwise", "sum", "loss", "fir", "reverb_fir"; NULL disables) carries a
+ * start/stop HIP event pair stamped by its own dispatch, so timing inserts
+ * nothing between kernels.  One launch of a class may be several kernels
+ * (the dynamics passes, the loss resolutions); their durations add.  At most
+ * 4096 timed kernels between reads, else mg_profile_read fails and resets.
+ * mg_profile_read synchronises on the events and returns the summed kernel
+ * time in ms, the number of class launches and the algorithmic bytes they
+ * move (the reads and writes each kernel is designed to make), then resets. */
 int mg_profile_enable(mg_graph* g, const char* kernel_class);
 int mg_profile_read(mg_graph* g, double* ms, int64_t* launches, double* bytes);
 

@@ -82,74 +82,101 @@ void launch_sum(const Ctx& c, int desc_off, int n, const SrcRef* srcs, float* ou
   if (n <= 0) return;
   dim3 grid(256, n);
   ProfScope ps(c, "sum", (double)n * 8.0 * c.L * 2);
-  hipLaunchKernelGGL(k_sum, grid, dim3(MG_BLOCK), 0, c.st, c.desc + desc_off, srcs, c.dry, c.U, c.G, out_base, c.L,
+  MG_LAUNCH(c, k_sum, grid, dim3(MG_BLOCK), 0, c.st, c.desc + desc_off, srcs, c.dry, c.U, c.G, out_base, c.L,
                      c.C, dest_kind);
 }
 
 // ---------------------------------------------------------------- pointwise processors
+// Each processor keeps two numbers (a, b) derived from its raw parameters.
+// Contraction is off from here to the end of the fused chains and every
+// product that feeds an addition is an explicit fmaf: the per-stage kernels
+// and the fused chains below then round identically (the compiler would
+// otherwise fuse a product into a later subtraction only where the product
+// has no other use, which differs between the two).
+#pragma clang fp contract(off)
 template <int T>
 struct PW;
 
-// Sec. 3.1 gain/panning: ybar_c = exp(p_c) u_c
+// Sec. 3.1 gain/panning: ybar_c = exp(p_c) u_c;  a, b = exp(p_l), exp(p_r)
 template <>
 struct PW<MG_GAINPAN> {
-  float a0, a1;
+  float a, b;
   __device__ void init(const float* p) {
-    a0 = expf(p[0]);
-    a1 = expf(p[1]);
+    a = expf(p[0]);
+    b = expf(p[1]);
   }
   __device__ void fwd(float l, float r, float& yl, float& yr) const {
-    yl = a0 * l;
-    yr = a1 * r;
+    yl = a * l;
+    yr = b * r;
   }
   // dl, dr: dL/dybar.  returns dL/du and accumulates parameter partials
   __device__ void bwd(float l, float r, float dl, float dr, float& gl, float& gr, float* pp) const {
-    gl = a0 * dl;
-    gr = a1 * dr;
-    pp[0] += dl * a0 * l;
-    pp[1] += dr * a1 * r;
+    gl = a * dl;
+    gr = b * dr;
+    pp[0] = fmaf(dl * a, l, pp[0]);
+    pp[1] = fmaf(dr * b, r, pp[1]);
   }
 };
 
-// Sec. 3.2 stereo imager: ym = l + r, ys = exp(p)(l - r), ybar = ((ym + ys)/2, (ym - ys)/2)
+// Sec. 3.2 stereo imager: ym = l + r, ys = exp(p)(l - r), ybar = ((ym + ys)/2,
+// (ym - ys)/2);  a = exp(p)
 template <>
 struct PW<MG_IMAGER> {
-  float s;
-  __device__ void init(const float* p) { s = expf(p[0]); }
+  float a, b;
+  __device__ void init(const float* p) {
+    a = expf(p[0]);
+    b = 0.0f;
+  }
   __device__ void fwd(float l, float r, float& yl, float& yr) const {
-    const float ym = l + r, ys = s * (l - r);
-    yl = 0.5f * (ym + ys);
-    yr = 0.5f * (ym - ys);
+    const float ym = l + r, d = l - r;
+    yl = 0.5f * fmaf(a, d, ym);
+    yr = 0.5f * fmaf(-a, d, ym);
   }
   __device__ void bwd(float l, float r, float dl, float dr, float& gl, float& gr, float* pp) const {
     const float dm = 0.5f * (dl + dr), ds = 0.5f * (dl - dr);
-    gl = dm + s * ds;
-    gr = dm - s * ds;
-    pp[0] += ds * s * (l - r);
+    gl = fmaf(a, ds, dm);
+    gr = fmaf(-a, ds, dm);
+    pp[0] = fmaf(ds * a, l - r, pp[0]);
   }
 };
 
-// tanh waveshaper: ybar = exp(p_o) tanh(exp(p_i) u)
+// tanh waveshaper: ybar = exp(p_o) tanh(exp(p_i) u);  a, b = exp(p_i), exp(p_o)
 template <>
 struct PW<MG_DIST> {
-  float gi, go;
+  float a, b;
   __device__ void init(const float* p) {
-    gi = expf(p[0]);
-    go = expf(p[1]);
+    a = expf(p[0]);
+    b = expf(p[1]);
   }
   __device__ void fwd(float l, float r, float& yl, float& yr) const {
-    yl = go * tanhf(gi * l);
-    yr = go * tanhf(gi * r);
+    yl = b * tanhf(a * l);
+    yr = b * tanhf(a * r);
   }
   __device__ void bwd(float l, float r, float dl, float dr, float& gl, float& gr, float* pp) const {
-    const float tl = tanhf(gi * l), tr = tanhf(gi * r);
-    const float sl = go * gi * (1.0f - tl * tl), sr = go * gi * (1.0f - tr * tr);
+    const float tl = tanhf(a * l), tr = tanhf(a * r);
+    const float sl = b * a * fmaf(-tl, tl, 1.0f), sr = b * a * fmaf(-tr, tr, 1.0f);
     gl = dl * sl;
     gr = dr * sr;
-    pp[0] += dl * sl * l + dr * sr * r;   // d/dp_i = ybar'(u) * u
-    pp[1] += dl * go * tl + dr * go * tr; // d/dp_o = ybar
+    pp[0] = fmaf(dl * sl, l, fmaf(dr * sr, r, pp[0]));   // d/dp_i = ybar'(u) u
+    pp[1] = fmaf(dl * b, tl, fmaf(dr * b, tr, pp[1]));   // d/dp_o = ybar
   }
 };
+
+// dry/wet mix y = w ybar + (1 - w) u
+__device__ __forceinline__ float dw_mix(float w, float yb, float u) { return fmaf(w, yb, (1.0f - w) * u); }
+
+// Adjoint of one processor with its dry/wet mix at one stereo sample: input
+// (l, r), wet output (yl, yr), dL/dy (dl, dr) -> dL/du (gl, gr); dry/wet and
+// parameter partials accumulated.
+template <int T>
+__device__ __forceinline__ void pw_level_bwd(const PW<T>& f, float w, float l, float r, float yl, float yr, float dl,
+                                             float dr, float& gl, float& gr, float& dw, float* pp) {
+  dw = fmaf(dl, yl - l, fmaf(dr, yr - r, dw));
+  float bl, br;
+  f.bwd(l, r, w * dl, w * dr, bl, br, pp);
+  gl = fmaf(1.0f - w, dl, bl);
+  gr = fmaf(1.0f - w, dr, br);
+}
 
 template <int T>
 __global__ __launch_bounds__(MG_BLOCK) void k_pointwise_fwd(const NodeDesc* __restrict__ desc,
@@ -168,8 +195,20 @@ __global__ __launch_bounds__(MG_BLOCK) void k_pointwise_fwd(const NodeDesc* __re
     const float l = u[t], r = u[cs + t];
     float yl, yr;
     f.fwd(l, r, yl, yr);
-    y[t] = w * yl + (1.0f - w) * l;
-    y[L + t] = w * yr + (1.0f - w) * r;
+    y[t] = dw_mix(w, yl, l);
+    y[L + t] = dw_mix(w, yr, r);
+  }
+}
+
+// partial sums of one processor: [2] dry/wet, [3], [4] parameters
+__device__ __forceinline__ void pw_partials(float* pr, float dw, float p0, float p1, float* red) {
+  const float s_dw = block_sum<MG_BLOCK>(dw, red);
+  const float s0 = block_sum<MG_BLOCK>(p0, red);
+  const float s1 = block_sum<MG_BLOCK>(p1, red);
+  if (threadIdx.x == 0) {
+    pr[2] = s_dw;
+    pr[3] = s0;
+    pr[4] = s1;
   }
 }
 
@@ -181,7 +220,7 @@ __global__ __launch_bounds__(MG_BLOCK) void k_pointwise_bwd(const NodeDesc* __re
                                                              const float* __restrict__ wet,
                                                              const float* __restrict__ mask, int64_t L, int C,
                                                              float* __restrict__ part, int PB) {
-  __shared__ float red[MG_BLOCK];
+  __shared__ float red[MG_BLOCK / 64];
   const NodeDesc d = desc[blockIdx.y];
   PW<T> f;
   f.init(theta + d.theta_off);
@@ -194,27 +233,151 @@ __global__ __launch_bounds__(MG_BLOCK) void k_pointwise_bwd(const NodeDesc* __re
   float dw = 0.0f;
   for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < L; t += (int64_t)gridDim.x * blockDim.x) {
     const float l = u[t], r = u[cs + t];
-    const float dl = dy[t], dr = dy[L + t];
-    float yl, yr;
+    float yl, yr, gl, gr;
     f.fwd(l, r, yl, yr);
-    dw += dl * (yl - l) + dr * (yr - r);
-    float gl, gr;
-    f.bwd(l, r, w * dl, w * dr, gl, gr, pp);
+    pw_level_bwd(f, w, l, r, yl, yr, dy[t], dy[L + t], gl, gr, dw, pp);
     if (gin) {
-      gin[t] = gl + (1.0f - w) * dl;
-      gin[L + t] = gr + (1.0f - w) * dr;
+      gin[t] = gl;
+      gin[L + t] = gr;
     }
   }
-  float* pr = part + ((int64_t)(blockIdx.y) * PB + blockIdx.x) * PK;
-  const float s_dw = block_sum<MG_BLOCK>(dw, red);
-  const float s0 = block_sum<MG_BLOCK>(pp[0], red);
-  const float s1 = block_sum<MG_BLOCK>(pp[1], red);
-  if (threadIdx.x == 0) {
-    pr[2] = s_dw;
-    pr[3] = s0;
-    pr[4] = s1;
+  pw_partials(part + ((int64_t)(blockIdx.y) * PB + blockIdx.x) * PK, dw, pp[0], pp[1], red);
+}
+
+// ---------------------------------------------------------------- fused pointwise chains
+// K consecutive pointwise stages whose node j feeds only node j of the next
+// stage (x -> s -> g of every console chain) in one launch.  Forward: one
+// read of the chain input, every level's output written (the backward, the
+// pruning trials and the next stage read them).  Backward: the level inputs
+// are recomputed from the chain input, dL/dy of the last level is carried
+// back through the levels in registers and only the chain's input gradient
+// is written; the per-level partials are those of the per-stage kernels.
+struct PwChain {
+  const NodeDesc* desc[PW_MAXK];  // descriptors of each level's stage
+  float* part[PW_MAXK];           // partial rows of each level's stage
+  int type[PW_MAXK];
+  int K;
+};
+
+__device__ __forceinline__ void pw_init_rt(int type, const float* p, float& a, float& b) {
+  if (type == MG_GAINPAN) {
+    PW<MG_GAINPAN> f;
+    f.init(p);
+    a = f.a;
+    b = f.b;
+  } else if (type == MG_IMAGER) {
+    PW<MG_IMAGER> f;
+    f.init(p);
+    a = f.a;
+    b = f.b;
+  } else {
+    PW<MG_DIST> f;
+    f.init(p);
+    a = f.a;
+    b = f.b;
   }
 }
+
+__device__ __forceinline__ void pw_fwd_rt(int type, float a, float b, float l, float r, float& yl, float& yr) {
+  if (type == MG_GAINPAN) PW<MG_GAINPAN>{a, b}.fwd(l, r, yl, yr);
+  else if (type == MG_IMAGER) PW<MG_IMAGER>{a, b}.fwd(l, r, yl, yr);
+  else PW<MG_DIST>{a, b}.fwd(l, r, yl, yr);
+}
+
+__device__ __forceinline__ void pw_bwd_rt(int type, float a, float b, float w, float l, float r, float yl, float yr,
+                                          float dl, float dr, float& gl, float& gr, float& dw, float* pp) {
+  if (type == MG_GAINPAN) pw_level_bwd(PW<MG_GAINPAN>{a, b}, w, l, r, yl, yr, dl, dr, gl, gr, dw, pp);
+  else if (type == MG_IMAGER) pw_level_bwd(PW<MG_IMAGER>{a, b}, w, l, r, yl, yr, dl, dr, gl, gr, dw, pp);
+  else pw_level_bwd(PW<MG_DIST>{a, b}, w, l, r, yl, yr, dl, dr, gl, gr, dw, pp);
+}
+
+__global__ __launch_bounds__(MG_BLOCK) void k_pw_chain_fwd(PwChain ch, const float* __restrict__ dry,
+                                                            float* __restrict__ U, const float* __restrict__ theta,
+                                                            const float* __restrict__ wet,
+                                                            const float* __restrict__ mask, int64_t L, int C) {
+  float pa[PW_MAXK], pb[PW_MAXK], pw[PW_MAXK];
+  float* y[PW_MAXK];
+#pragma unroll
+  for (int i = 0; i < PW_MAXK; ++i) {
+    if (i >= ch.K) break;
+    const NodeDesc d = ch.desc[i][blockIdx.y];
+    pw_init_rt(ch.type[i], theta + d.theta_off, pa[i], pb[i]);
+    pw[i] = node_w(wet, mask, d);
+    y[i] = U + (int64_t)d.out_slot * 2 * L;
+  }
+  int64_t cs;
+  const float* u = resolve_in(ch.desc[0][blockIdx.y], dry, U, L, C, cs);
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < L; t += (int64_t)gridDim.x * blockDim.x) {
+    float l = u[t], r = u[cs + t];
+#pragma unroll
+    for (int i = 0; i < PW_MAXK; ++i) {
+      if (i >= ch.K) break;
+      float yl, yr;
+      pw_fwd_rt(ch.type[i], pa[i], pb[i], l, r, yl, yr);
+      l = dw_mix(pw[i], yl, l);
+      r = dw_mix(pw[i], yr, r);
+      y[i][t] = l;
+      y[i][L + t] = r;
+    }
+  }
+}
+
+__global__ __launch_bounds__(MG_BLOCK) void k_pw_chain_bwd(PwChain ch, const float* __restrict__ dry,
+                                                            const float* __restrict__ U, float* __restrict__ G,
+                                                            const float* __restrict__ theta,
+                                                            const float* __restrict__ wet,
+                                                            const float* __restrict__ mask, int64_t L, int C,
+                                                            int PB) {
+  __shared__ float red[MG_BLOCK / 64];
+  float pa[PW_MAXK], pb[PW_MAXK], pw[PW_MAXK];
+  float dw[PW_MAXK], pp[PW_MAXK][2];
+#pragma unroll
+  for (int i = 0; i < PW_MAXK; ++i) {
+    dw[i] = pp[i][0] = pp[i][1] = 0.0f;
+    if (i >= ch.K) continue;
+    const NodeDesc d = ch.desc[i][blockIdx.y];
+    pw_init_rt(ch.type[i], theta + d.theta_off, pa[i], pb[i]);
+    pw[i] = node_w(wet, mask, d);
+  }
+  const NodeDesc d0 = ch.desc[0][blockIdx.y];
+  int64_t cs;
+  const float* u = resolve_in(d0, dry, U, L, C, cs);
+  const float* dy = G + (int64_t)ch.desc[ch.K - 1][blockIdx.y].gout * 2 * L;
+  float* gin = d0.gin >= 0 ? G + (int64_t)d0.gin * 2 * L : nullptr;
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < L; t += (int64_t)gridDim.x * blockDim.x) {
+    float li[PW_MAXK], ri[PW_MAXK], yl[PW_MAXK], yr[PW_MAXK];
+    float l = u[t], r = u[cs + t];
+#pragma unroll
+    for (int i = 0; i < PW_MAXK; ++i) {
+      if (i >= ch.K) break;
+      li[i] = l;
+      ri[i] = r;
+      pw_fwd_rt(ch.type[i], pa[i], pb[i], l, r, yl[i], yr[i]);
+      l = dw_mix(pw[i], yl[i], l);
+      r = dw_mix(pw[i], yr[i], r);
+    }
+    float gl = dy[t], gr = dy[L + t];
+#pragma unroll
+    for (int i = PW_MAXK - 1; i >= 0; --i) {
+      if (i >= ch.K) continue;
+      float ol, orr;
+      pw_bwd_rt(ch.type[i], pa[i], pb[i], pw[i], li[i], ri[i], yl[i], yr[i], gl, gr, ol, orr, dw[i], pp[i]);
+      gl = ol;
+      gr = orr;
+    }
+    if (gin) {
+      gin[t] = gl;
+      gin[L + t] = gr;
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < PW_MAXK; ++i) {
+    if (i >= ch.K) break;
+    pw_partials(ch.part[i] + ((int64_t)(blockIdx.y) * PB + blockIdx.x) * PK, dw[i], pp[i][0], pp[i][1], red);
+  }
+}
+
+#pragma clang fp contract(fast)
 
 void launch_pointwise_fwd(const Ctx& c, int type, int desc_off, int n) {
   dim3 grid(128, n), blk(MG_BLOCK);
@@ -222,13 +385,13 @@ void launch_pointwise_fwd(const Ctx& c, int type, int desc_off, int n) {
   const NodeDesc* d = c.desc + desc_off;
   switch (type) {
     case MG_GAINPAN:
-      hipLaunchKernelGGL(k_pointwise_fwd<MG_GAINPAN>, grid, blk, 0, c.st, d, c.dry, c.U, c.theta, c.wet, c.mask, c.L, c.C);
+      MG_LAUNCH(c, k_pointwise_fwd<MG_GAINPAN>, grid, blk, 0, c.st, d, c.dry, c.U, c.theta, c.wet, c.mask, c.L, c.C);
       break;
     case MG_IMAGER:
-      hipLaunchKernelGGL(k_pointwise_fwd<MG_IMAGER>, grid, blk, 0, c.st, d, c.dry, c.U, c.theta, c.wet, c.mask, c.L, c.C);
+      MG_LAUNCH(c, k_pointwise_fwd<MG_IMAGER>, grid, blk, 0, c.st, d, c.dry, c.U, c.theta, c.wet, c.mask, c.L, c.C);
       break;
     case MG_DIST:
-      hipLaunchKernelGGL(k_pointwise_fwd<MG_DIST>, grid, blk, 0, c.st, d, c.dry, c.U, c.theta, c.wet, c.mask, c.L, c.C);
+      MG_LAUNCH(c, k_pointwise_fwd<MG_DIST>, grid, blk, 0, c.st, d, c.dry, c.U, c.theta, c.wet, c.mask, c.L, c.C);
       break;
   }
 }
@@ -240,18 +403,44 @@ void launch_pointwise_bwd(const Ctx& c, int type, int desc_off, int n) {
   float* part = c.part + (int64_t)desc_off * c.PB * PK;
   switch (type) {
     case MG_GAINPAN:
-      hipLaunchKernelGGL(k_pointwise_bwd<MG_GAINPAN>, grid, blk, 0, c.st, d, c.dry, c.U, c.G, c.theta, c.wet, c.mask,
-                         c.L, c.C, part, c.PB);
+      MG_LAUNCH(c, k_pointwise_bwd<MG_GAINPAN>, grid, blk, 0, c.st, d, c.dry, c.U, c.G, c.theta, c.wet, c.mask,
+                c.L, c.C, part, c.PB);
       break;
     case MG_IMAGER:
-      hipLaunchKernelGGL(k_pointwise_bwd<MG_IMAGER>, grid, blk, 0, c.st, d, c.dry, c.U, c.G, c.theta, c.wet, c.mask,
-                         c.L, c.C, part, c.PB);
+      MG_LAUNCH(c, k_pointwise_bwd<MG_IMAGER>, grid, blk, 0, c.st, d, c.dry, c.U, c.G, c.theta, c.wet, c.mask,
+                c.L, c.C, part, c.PB);
       break;
     case MG_DIST:
-      hipLaunchKernelGGL(k_pointwise_bwd<MG_DIST>, grid, blk, 0, c.st, d, c.dry, c.U, c.G, c.theta, c.wet, c.mask,
-                         c.L, c.C, part, c.PB);
+      MG_LAUNCH(c, k_pointwise_bwd<MG_DIST>, grid, blk, 0, c.st, d, c.dry, c.U, c.G, c.theta, c.wet, c.mask,
+                c.L, c.C, part, c.PB);
       break;
   }
+}
+
+static PwChain pw_chain(const Ctx& c, const int* types, const int* offs, int K) {
+  PwChain ch;
+  ch.K = K;
+  for (int i = 0; i < PW_MAXK; ++i) {
+    const int k = i < K ? i : 0;
+    ch.desc[i] = c.desc + offs[k];
+    ch.part[i] = c.part + (int64_t)offs[k] * c.PB * PK;
+    ch.type[i] = types[k];
+  }
+  return ch;
+}
+
+void launch_pw_chain_fwd(const Ctx& c, const int* types, const int* offs, int K, int n) {
+  dim3 grid(128, n), blk(MG_BLOCK);
+  ProfScope ps(c, "pointwise", (double)n * (8.0 + 8.0 * K) * c.L);
+  MG_LAUNCH(c, k_pw_chain_fwd, grid, blk, 0, c.st, pw_chain(c, types, offs, K), c.dry, c.U, c.theta, c.wet, c.mask,
+            c.L, c.C);
+}
+
+void launch_pw_chain_bwd(const Ctx& c, const int* types, const int* offs, int K, int n) {
+  dim3 grid(128, n), blk(MG_BLOCK);
+  ProfScope ps(c, "pointwise", (double)n * 24.0 * c.L);
+  MG_LAUNCH(c, k_pw_chain_bwd, grid, blk, 0, c.st, pw_chain(c, types, offs, K), c.dry, c.U, c.G, c.theta, c.wet,
+            c.mask, c.L, c.C, c.PB);
 }
 
 // ---------------------------------------------------------------- reductions
@@ -288,7 +477,7 @@ __global__ __launch_bounds__(MG_BLOCK) void k_finish_grads(const NodeDesc* __res
 void launch_finish_grads(const Ctx& c, int desc_off, int n, int nblocks, int nparams, float* grad_theta,
                          float* grad_wet) {
   if (n <= 0) return;
-  hipLaunchKernelGGL(k_finish_grads, dim3(n), dim3(MG_BLOCK), 0, c.st, c.desc + desc_off,
+  MG_LAUNCH(c, k_finish_grads, dim3(n), dim3(MG_BLOCK), 0, c.st, c.desc + desc_off,
                      c.part + (int64_t)desc_off * c.PB * PK, c.PB, nblocks, nparams, c.wet, c.mask, c.alpha_p,
                      grad_theta, grad_wet);
 }
@@ -328,7 +517,7 @@ __global__ __launch_bounds__(MG_BLOCK) void k_finish_all(const NodeDesc* __restr
 
 void launch_finish_all(const Ctx& c, int n_desc, const int2* fin, float* grad_theta, float* grad_wet) {
   if (n_desc <= 0) return;
-  hipLaunchKernelGGL(k_finish_all, dim3(n_desc), dim3(MG_BLOCK), 0, c.st, c.desc, c.part, c.PB, fin, c.wet, c.mask,
+  MG_LAUNCH(c, k_finish_all, dim3(n_desc), dim3(MG_BLOCK), 0, c.st, c.desc, c.part, c.PB, fin, c.wet, c.mask,
                      c.alpha_p, grad_theta, grad_wet);
 }
 
@@ -347,7 +536,7 @@ __global__ __launch_bounds__(MG_BLOCK) void k_reduce_lg(const float* __restrict_
 
 void launch_reduce_lg(const Ctx& c, int desc_off, int n, int nblocks) {
   if (n <= 0) return;
-  hipLaunchKernelGGL(k_reduce_lg, dim3(n), dim3(MG_BLOCK), 0, c.st, c.part + (int64_t)desc_off * c.PB * PK, c.PB,
+  MG_LAUNCH(c, k_reduce_lg, dim3(n), dim3(MG_BLOCK), 0, c.st, c.part + (int64_t)desc_off * c.PB * PK, c.PB,
                      nblocks, c.lg + 2 * desc_off);
 }
 
@@ -405,7 +594,7 @@ __global__ __launch_bounds__(MG_BLOCK) void k_finalize_losses(double* __restrict
 
 void launch_finalize_losses(const Ctx& c, double* losses, const double* lstats, int n_res, int n_desc) {
   const int* flag = reinterpret_cast<const int*>(c.base + c.g->ws.losses_tmp);
-  hipLaunchKernelGGL(k_finalize_losses, dim3(1), dim3(MG_BLOCK), 0, c.st, losses, lstats, n_res, c.desc, n_desc,
+  MG_LAUNCH(c, k_finalize_losses, dim3(1), dim3(MG_BLOCK), 0, c.st, losses, lstats, n_res, c.desc, n_desc,
                      c.lg, c.wet, c.mask, 0, (const int*)nullptr, c.alpha_g, c.alpha_p, flag);
 }
 
@@ -413,7 +602,7 @@ void launch_finalize_trials(const Ctx& c, double* losses, const double* lstats, 
                             const float* mask, int P, const int* sub, int n_trials) {
   if (n_trials <= 0) return;
   const int* flag = reinterpret_cast<const int*>(c.base + c.g->ws.losses_tmp);
-  hipLaunchKernelGGL(k_finalize_losses, dim3(n_trials), dim3(MG_BLOCK), 0, c.st, losses, lstats, n_res, c.desc,
+  MG_LAUNCH(c, k_finalize_losses, dim3(n_trials), dim3(MG_BLOCK), 0, c.st, losses, lstats, n_res, c.desc,
                      n_desc, c.lg, c.wet, mask, P, sub, c.alpha_g, c.alpha_p, flag);
 }
 

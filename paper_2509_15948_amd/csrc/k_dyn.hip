@@ -561,16 +561,16 @@ void dyn_forward(const Ctx& c, int type, int desc_off, int n) {
   ProfScope ps(c, "dyn", (double)n * 20.0 * c.L);
   const bool ar = (type == MG_COMP && g->cfg.comp_mode == 1);
   if (ar) {
-    if (type == MG_COMP) hipLaunchKernelGGL(k_dyn_ar_fwd<0>, dim3(n), dim3(64), 0, c.st, v);
+    if (type == MG_COMP) MG_LAUNCH(c, k_dyn_ar_fwd<0>, dim3(n), dim3(64), 0, c.st, v);
     return;
   }
   const int nch = g->dyn_chunks;
   float* sums = wsp<float>(c, g->ws.cmp_sum);
   double* carry = wsp<double>(c, g->ws.cmp_carry);
-  hipLaunchKernelGGL(k_dyn_sum, dim3(nch, n), dim3(MG_BLOCK), 0, c.st, v, sums, nch);
-  hipLaunchKernelGGL(k_dyn_carry, dim3(n), dim3(64), 0, c.st, v, sums, carry, nch, n);
-  if (type == MG_GATE) hipLaunchKernelGGL(k_dyn_apply<1>, dim3(nch, n), dim3(MG_BLOCK), 0, c.st, v, carry, nch);
-  else hipLaunchKernelGGL(k_dyn_apply<0>, dim3(nch, n), dim3(MG_BLOCK), 0, c.st, v, carry, nch);
+  MG_LAUNCH(c, k_dyn_sum, dim3(nch, n), dim3(MG_BLOCK), 0, c.st, v, sums, nch);
+  MG_LAUNCH(c, k_dyn_carry, dim3(n), dim3(64), 0, c.st, v, sums, carry, nch, n);
+  if (type == MG_GATE) MG_LAUNCH(c, k_dyn_apply<1>, dim3(nch, n), dim3(MG_BLOCK), 0, c.st, v, carry, nch);
+  else MG_LAUNCH(c, k_dyn_apply<0>, dim3(nch, n), dim3(MG_BLOCK), 0, c.st, v, carry, nch);
 }
 
 void dyn_backward(const Ctx& c, int type, int desc_off, int n) {
@@ -579,20 +579,20 @@ void dyn_backward(const Ctx& c, int type, int desc_off, int n) {
   ProfScope ps(c, "dyn", (double)n * 28.0 * c.L);
   const bool ar = (type == MG_COMP && g->cfg.comp_mode == 1);
   if (ar) {
-    hipLaunchKernelGGL(k_dyn_ar_bwd<0>, dim3(n), dim3(64), 0, c.st, v);
+    MG_LAUNCH(c, k_dyn_ar_bwd<0>, dim3(n), dim3(64), 0, c.st, v);
     return;
   }
   const int nch = g->dyn_chunks;
   float* sums = wsp<float>(c, g->ws.cmp_sum);
   double* carry = wsp<double>(c, g->ws.cmp_carry);
   if (type == MG_GATE) {
-    hipLaunchKernelGGL(k_dyn_bsum<1>, dim3(nch, n), dim3(MG_BLOCK), 0, c.st, v, sums, nch);
-    hipLaunchKernelGGL(k_dyn_bcarry, dim3(n), dim3(64), 0, c.st, v, sums, carry, nch, n);
-    hipLaunchKernelGGL(k_dyn_bapply<1>, dim3(nch, n), dim3(MG_BLOCK), 0, c.st, v, carry, nch);
+    MG_LAUNCH(c, k_dyn_bsum<1>, dim3(nch, n), dim3(MG_BLOCK), 0, c.st, v, sums, nch);
+    MG_LAUNCH(c, k_dyn_bcarry, dim3(n), dim3(64), 0, c.st, v, sums, carry, nch, n);
+    MG_LAUNCH(c, k_dyn_bapply<1>, dim3(nch, n), dim3(MG_BLOCK), 0, c.st, v, carry, nch);
   } else {
-    hipLaunchKernelGGL(k_dyn_bsum<0>, dim3(nch, n), dim3(MG_BLOCK), 0, c.st, v, sums, nch);
-    hipLaunchKernelGGL(k_dyn_bcarry, dim3(n), dim3(64), 0, c.st, v, sums, carry, nch, n);
-    hipLaunchKernelGGL(k_dyn_bapply<0>, dim3(nch, n), dim3(MG_BLOCK), 0, c.st, v, carry, nch);
+    MG_LAUNCH(c, k_dyn_bsum<0>, dim3(nch, n), dim3(MG_BLOCK), 0, c.st, v, sums, nch);
+    MG_LAUNCH(c, k_dyn_bcarry, dim3(n), dim3(64), 0, c.st, v, sums, carry, nch, n);
+    MG_LAUNCH(c, k_dyn_bapply<0>, dim3(nch, n), dim3(MG_BLOCK), 0, c.st, v, carry, nch);
   }
 }
 

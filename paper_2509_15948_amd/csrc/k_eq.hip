@@ -257,14 +257,14 @@ int eq_blocks(const mg_graph* g) {
 void eq_spectrum(const Ctx& c, int desc_off, int n) {
   EqArgs a = eq_args(c, desc_off, false);
   ProfScope ps(c, "eq_spec", (double)n * (4.0 * a.N + 4.0 * EQ_P));
-  hipLaunchKernelGGL(k_eq_spec, dim3(n), dim3(EQ_NT), 0, c.st, a);
+  MG_LAUNCH(c, k_eq_spec, dim3(n), dim3(EQ_NT), 0, c.st, a);
 }
 
 void eq_forward(const Ctx& c, int desc_off, int n, bool keep) {
   EqArgs a = eq_args(c, desc_off, keep);
   {
     ProfScope ps(c, "eq_conv", (double)n * ((8.0 * EQ_P) * a.nblk + (keep ? 16.0 : 8.0) * c.L + 8.0 * c.L));
-    hipLaunchKernelGGL(k_eq_fwd, dim3(a.nblk, n), dim3(EQ_NT), 0, c.st, a);
+    MG_LAUNCH(c, k_eq_fwd, dim3(a.nblk, n), dim3(EQ_NT), 0, c.st, a);
   }
   launch_reduce_lg(c, desc_off, n, a.nblk);
 }
@@ -274,13 +274,13 @@ void eq_backward(const Ctx& c, int desc_off, int n) {
   {
     // reads dL/dy, ybar, u (window each) and u again; writes dL/du and the block FIR gradients
     ProfScope ps(c, "eq_conv", (double)n * ((24.0 * EQ_P) * a.nblk + 16.0 * c.L + 4.0 * a.N * a.nblk));
-    hipLaunchKernelGGL(k_eq_bwd, dim3(a.nblk, n), dim3(EQ_NT), 0, c.st, a);
+    MG_LAUNCH(c, k_eq_bwd, dim3(a.nblk, n), dim3(EQ_NT), 0, c.st, a);
   }
 }
 
 void eq_backward_fir(const Ctx& c, int desc_off, int n) {
   EqArgs a = eq_args(c, desc_off, true);
-  hipLaunchKernelGGL(k_eq_dh_reduce, dim3((a.N + DH_TAPS - 1) / DH_TAPS, n), dim3(MG_BLOCK), 0, c.st, a);
+  MG_LAUNCH(c, k_eq_dh_reduce, dim3((a.N + DH_TAPS - 1) / DH_TAPS, n), dim3(MG_BLOCK), 0, c.st, a);
 }
 
 }  // namespace mg

@@ -495,7 +495,7 @@ void run_cols(const Ctx& c, const LD& ld, float2* T, int n, const EngineArgs& ea
   switch (N2) {
 #define MG_CASE(NN)                                                                   \
   case NN:                                                                            \
-    hipLaunchKernelGGL((k_cols<NN, COL_TILE / NN, LD>), grid, blk, 0, c.st, ld, T, ea); \
+    MG_LAUNCH(c, (k_cols<NN, COL_TILE / NN, LD>), grid, blk, 0, c.st, ld, T, ea); \
     break;
     MG_CASE(16) MG_CASE(32) MG_CASE(64) MG_CASE(128) MG_CASE(256) MG_CASE(512) MG_CASE(1024)
 #undef MG_CASE
@@ -511,7 +511,7 @@ void run_icols(const Ctx& c, const ST& st, const float2* T, int n, const EngineA
   switch (N2) {
 #define MG_CASE(NN)                                                                    \
   case NN:                                                                             \
-    hipLaunchKernelGGL((k_icols<NN, COL_TILE / NN, ST>), grid, blk, 0, c.st, st, T, ea); \
+    MG_LAUNCH(c, (k_icols<NN, COL_TILE / NN, ST>), grid, blk, 0, c.st, st, T, ea); \
     break;
     MG_CASE(16) MG_CASE(32) MG_CASE(64) MG_CASE(128) MG_CASE(256) MG_CASE(512) MG_CASE(1024)
 #undef MG_CASE
@@ -557,20 +557,20 @@ static NodeView node_view(const Ctx& c, int desc_off) {
 template <int N1>
 static void rows_spec_n(const Ctx& c, const float2* T, float2* Z, int z0, int desc_off, int n, const EngineArgs& ea) {
   ProfScope ps(c, "conv_rows", (double)n * 16.0 * ea.N);
-  hipLaunchKernelGGL(k_rows_spec<N1>, dim3(ea.N2 / 2, n), dim3(row_nt<N1>()), 0, c.st, T, Z, z0, c.desc + desc_off, ea);
+  MG_LAUNCH(c, k_rows_spec<N1>, dim3(ea.N2 / 2, n), dim3(row_nt<N1>()), 0, c.st, T, Z, z0, c.desc + desc_off, ea);
 }
 template <int N1>
 static void rows_conv_n(const Ctx& c, const float2* Tin, float2* Tout, const float2* ZH, float2* ZU, int z0,
                         int desc_off, int n, const EngineArgs& ea) {
   ProfScope ps(c, "conv_rows", (double)n * (ZU ? 32.0 : 24.0) * ea.N);
-  hipLaunchKernelGGL(k_rows_conv<N1>, dim3(ea.N2 / 2, n), dim3(row_nt<N1>()), 0, c.st, Tin, Tout, ZH, ZU, z0,
+  MG_LAUNCH(c, k_rows_conv<N1>, dim3(ea.N2 / 2, n), dim3(row_nt<N1>()), 0, c.st, Tin, Tout, ZH, ZU, z0,
                      c.desc + desc_off, ea);
 }
 template <int N1>
 static void rows_bwd_n(const Ctx& c, const float2* Tin, float2* Tu, float2* Th, const float2* ZH, const float2* ZU,
                        int z0, int desc_off, int n, int want_u, const EngineArgs& ea) {
   ProfScope ps(c, "conv_rows", (double)n * (want_u ? 40.0 : 32.0) * ea.N);
-  hipLaunchKernelGGL(k_rows_bwd<N1>, dim3(ea.N2 / 2, n), dim3(row_nt<N1>()), 0, c.st, Tin, Tu, Th, ZH, ZU, z0,
+  MG_LAUNCH(c, k_rows_bwd<N1>, dim3(ea.N2 / 2, n), dim3(row_nt<N1>()), 0, c.st, Tin, Tu, Th, ZH, ZU, z0,
                      c.desc + desc_off, want_u, ea);
 }
 

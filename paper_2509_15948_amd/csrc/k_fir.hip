@@ -641,7 +641,7 @@ void fir_setup(const Ctx& c, const float* reverb_noise) {
     hipMemcpyAsync(wsp<float>(c, g->ws.rv_win), win.data(), win.size() * 4, hipMemcpyHostToDevice, c.st);
     hipMemcpyAsync(wsp<float>(c, g->ws.rv_wsum), ws.data(), ws.size() * 4, hipMemcpyHostToDevice, c.st);
     const int nrv = g->type_count[MG_REVERB];
-    hipLaunchKernelGGL(k_rv_noise_stft, dim3((g->nf_rev + RV_FPB - 1) / RV_FPB, 2, nrv), dim3(MG_BLOCK), 0, c.st,
+    MG_LAUNCH(c, k_rv_noise_stft, dim3((g->nf_rev + RV_FPB - 1) / RV_FPB, 2, nrv), dim3(MG_BLOCK), 0, c.st,
                        reverb_noise,
                        cf.reverb_length, g->nf_rev, wsp<float2>(c, g->ws.rv_cs), wsp<float>(c, g->ws.rv_win),
                        wsp<float2>(c, g->ws.rv_U));
@@ -655,23 +655,23 @@ void fir_synth(const Ctx& c, int type, int desc_off, int n) {
   ProfScope ps(c, "fir", 0.0);
   const NodeDesc* d = c.desc + desc_off;
   if (type == MG_EQ) {
-    hipLaunchKernelGGL(k_eq_synth, dim3((cf.eq_taps + FIR_PER_BLOCK - 1) / FIR_PER_BLOCK, n), dim3(MG_BLOCK), 0,
-                       c.st, d, c.theta, cf.eq_taps, wsp<float>(c, g->ws.eq_h));
+    MG_LAUNCH(c, k_eq_synth, dim3((cf.eq_taps + FIR_PER_BLOCK - 1) / FIR_PER_BLOCK, n), dim3(MG_BLOCK), 0,
+              c.st, d, c.theta, cf.eq_taps, wsp<float>(c, g->ws.eq_h));
   } else if (type == MG_DELAY) {
-    hipLaunchKernelGGL(k_delay_synth, dim3(n), dim3(MG_BLOCK), 0, c.st, d, c.theta, wsp<float>(c, g->ws.dl_cos),
+    MG_LAUNCH(c, k_delay_synth, dim3(n), dim3(MG_BLOCK), 0, c.st, d, c.theta, wsp<float>(c, g->ws.dl_cos),
                        cf.delay_taps, cf.delay_range, cf.delay_fir_taps, wsp<float>(c, g->ws.dl_tab));
-    hipLaunchKernelGGL(k_delay_compact, dim3((unsigned)((g->dl_len + MG_BLOCK - 1) / MG_BLOCK), 2, n), dim3(MG_BLOCK),
+    MG_LAUNCH(c, k_delay_compact, dim3((unsigned)((g->dl_len + MG_BLOCK - 1) / MG_BLOCK), 2, n), dim3(MG_BLOCK),
                        0, c.st, d, wsp<float>(c, g->ws.dl_tab), cf.delay_taps, cf.delay_fir_taps, g->dl_len,
                        wsp<float>(c, g->ws.dl_h));
   } else if (type == MG_REVERB) {
     const float gb = (float)reverb_gain_bias(cf.sample_rate);
     const float db = (float)reverb_decay_offset(cf.sample_rate, cf.reverb_hop);
     ProfScope pr(c, "reverb_fir", (double)n * 2 * g->nf_rev * (192 * 8 + 384 * 4));
-    hipLaunchKernelGGL(k_rv_frames, dim3((g->nf_rev + RV_FPB - 1) / RV_FPB, 2, n), dim3(MG_BLOCK), 0, c.st, d,
+    MG_LAUNCH(c, k_rv_frames, dim3((g->nf_rev + RV_FPB - 1) / RV_FPB, 2, n), dim3(MG_BLOCK), 0, c.st, d,
                        c.theta,
                        wsp<float2>(c, g->ws.rv_U), g->nf_rev, wsp<float2>(c, g->ws.rv_cs),
                        wsp<float>(c, g->ws.rv_win), gb, db, wsp<float>(c, g->ws.rv_fr));
-    hipLaunchKernelGGL(k_rv_ola, dim3((cf.reverb_length + MG_BLOCK - 1) / MG_BLOCK, n), dim3(MG_BLOCK), 0, c.st, d,
+    MG_LAUNCH(c, k_rv_ola, dim3((cf.reverb_length + MG_BLOCK - 1) / MG_BLOCK, n), dim3(MG_BLOCK), 0, c.st, d,
                        wsp<float>(c, g->ws.rv_fr), g->nf_rev, cf.reverb_length, wsp<float>(c, g->ws.rv_wsum),
                        wsp<float>(c, g->ws.rv_h));
   }
@@ -684,25 +684,25 @@ void fir_adjoint(const Ctx& c, int type, int desc_off, int n, float* grad_theta)
   const NodeDesc* d = c.desc + desc_off;
   if (type == MG_EQ) {
     const int K = (cf.eq_taps + 1) / 2;
-    hipLaunchKernelGGL(k_eq_adjoint, dim3((K + FIR_PER_BLOCK - 1) / FIR_PER_BLOCK, n), dim3(MG_BLOCK), 0, c.st, d,
+    MG_LAUNCH(c, k_eq_adjoint, dim3((K + FIR_PER_BLOCK - 1) / FIR_PER_BLOCK, n), dim3(MG_BLOCK), 0, c.st, d,
                        c.theta, cf.eq_taps, wsp<float>(c, g->ws.eq_dh), grad_theta);
   } else if (type == MG_DELAY) {
     double2* zp = wsp<double2>(c, g->ws.dl_zp);
-    hipLaunchKernelGGL(k_delay_adjoint, dim3(2 * cf.delay_taps, DL_CHUNKS, n), dim3(MG_BLOCK), 0, c.st, d, c.theta,
+    MG_LAUNCH(c, k_delay_adjoint, dim3(2 * cf.delay_taps, DL_CHUNKS, n), dim3(MG_BLOCK), 0, c.st, d, c.theta,
                        wsp<float>(c, g->ws.dl_tab), wsp<float>(c, g->ws.dl_cos), cf.delay_taps, cf.delay_range,
                        cf.delay_fir_taps, g->dl_len, wsp<float>(c, g->ws.dl_dh), grad_theta, zp);
-    hipLaunchKernelGGL(k_delay_zrule, dim3(n), dim3(128), 0, c.st, d, c.theta, cf.delay_taps, cf.delay_range,
+    MG_LAUNCH(c, k_delay_zrule, dim3(n), dim3(128), 0, c.st, d, c.theta, cf.delay_taps, cf.delay_range,
                        cf.delay_fir_taps, (const double2*)zp, grad_theta, 0.01f);
   } else if (type == MG_REVERB) {
     const float gb = (float)reverb_gain_bias(cf.sample_rate);
     const float db = (float)reverb_decay_offset(cf.sample_rate, cf.reverb_hop);
     ProfScope pr(c, "reverb_fir", (double)n * 2 * g->nf_rev * (192 * 8 + 384 * 4 + 192 * 4));
-    hipLaunchKernelGGL(k_rv_adj_frames, dim3((g->nf_rev + RV_FPB - 1) / RV_FPB, 2, n), dim3(MG_BLOCK), 0, c.st, d,
+    MG_LAUNCH(c, k_rv_adj_frames, dim3((g->nf_rev + RV_FPB - 1) / RV_FPB, 2, n), dim3(MG_BLOCK), 0, c.st, d,
                        c.theta,
                        wsp<float2>(c, g->ws.rv_U), g->nf_rev, cf.reverb_length, wsp<float2>(c, g->ws.rv_cs),
                        wsp<float>(c, g->ws.rv_win), wsp<float>(c, g->ws.rv_wsum), gb, db,
                        wsp<float>(c, g->ws.rv_dh), wsp<float>(c, g->ws.rv_dM));
-    hipLaunchKernelGGL(k_rv_adj_reduce, dim3(192 / 16, 2, n), dim3(MG_BLOCK), 0, c.st, d, g->nf_rev,
+    MG_LAUNCH(c, k_rv_adj_reduce, dim3(192 / 16, 2, n), dim3(MG_BLOCK), 0, c.st, d, g->nf_rev,
                        wsp<float>(c, g->ws.rv_dM), c.theta, db, grad_theta);
   }
 }

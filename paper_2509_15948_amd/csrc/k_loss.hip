@@ -425,11 +425,11 @@ static LossArgs loss_args(const Ctx& c, int i, const float* y) {
 
 template <int N, int MODE>
 static void fwd_n(const Ctx& c, const LossArgs& a, int blocks) {
-  hipLaunchKernelGGL((k_loss_fwd<N, MODE>), dim3(blocks), dim3(LOSS_NT), 0, c.st, a);
+  MG_LAUNCH(c, (k_loss_fwd<N, MODE>), dim3(blocks), dim3(LOSS_NT), 0, c.st, a);
 }
 template <int N>
 static void bwd_n(const Ctx& c, const LossArgs& a, int blocks) {
-  hipLaunchKernelGGL(k_loss_bwd<N>, dim3(blocks), dim3(LOSS_NT), 0, c.st, a);
+  MG_LAUNCH(c, k_loss_bwd<N>, dim3(blocks), dim3(LOSS_NT), 0, c.st, a);
 }
 
 #define MG_LOSS_SWITCH(N_, CALL)   \
@@ -491,7 +491,7 @@ static void run_loss_fwd(const Ctx& c, const float* y, int mode, double* stats_o
     ra.tgt[i] = wsp<double>(c, g->ws.ls_stats) + i * 16;
   }
   if (forked) loss_join(c);
-  hipLaunchKernelGGL(k_loss_reduce, dim3((unsigned)g->lres.size()), dim3(MG_BLOCK), 0, c.st, ra);
+  MG_LAUNCH(c, k_loss_reduce, dim3((unsigned)g->lres.size()), dim3(MG_BLOCK), 0, c.st, ra);
 }
 
 void loss_setup(const Ctx& c, const float* target) {
@@ -541,7 +541,7 @@ void loss_backward(const Ctx& c, const float* yhat, float* dyhat) {
   if (forked) loss_join(c);
   int64_t blocks = (c.L + MG_BLOCK - 1) / MG_BLOCK;
   if (blocks > 2048) blocks = 2048;
-  hipLaunchKernelGGL(k_loss_gather, dim3((unsigned)blocks), dim3(MG_BLOCK), 0, c.st, ga);
+  MG_LAUNCH(c, k_loss_gather, dim3((unsigned)blocks), dim3(MG_BLOCK), 0, c.st, ga);
 }
 
 }  // namespace mg

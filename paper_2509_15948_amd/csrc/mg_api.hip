@@ -150,7 +150,47 @@ static int suffix_slots(const mg_graph& g, int v) {
   return n;
 }
 
+static bool is_pointwise(int t) { return t == MG_GAINPAN || t == MG_IMAGER || t == MG_DIST; }
+
+// stage B continues a pointwise chain of stage A: node j of A feeds node j of
+// B and nothing else, B has no other input, and B's dL/du is A's dL/dy
+static bool pw_link(const mg_graph& g, const Stage& A, const Stage& B) {
+  if (A.nodes.size() != B.nodes.size() || A.nodes.empty()) return false;
+  for (size_t j = 0; j < A.nodes.size(); ++j) {
+    const int va = A.nodes[j], vb = B.nodes[j];
+    const NodeDesc& da = g.desc[A.desc_off + j];
+    const NodeDesc& db = g.desc[B.desc_off + j];
+    if (g.succs[va].size() != 1 || g.succs[va][0] != vb || g.preds[vb].size() != 1) return false;
+    if (db.in_kind != 1 || db.in_slot != da.out_slot || db.src_count != 0 || db.gin != da.gout) return false;
+  }
+  return true;
+}
+
+// maximal runs of up to PW_MAXK linked pointwise stages
+static void plan_pointwise_chains(mg_graph& g) {
+  const size_t S = g.stages.size();
+  g.pw_run.assign(S, 0);
+  if (g.cfg.unfused) return;
+  for (size_t s = 1; s < S;) {
+    const Stage& A = g.stages[s];
+    bool ok = is_pointwise(A.type);
+    for (size_t j = 0; ok && j < A.nodes.size(); ++j)
+      if (g.desc[A.desc_off + j].src_count != 0) ok = false;
+    size_t k = ok ? 1 : 0;
+    while (ok && s + k < S && k < (size_t)PW_MAXK && is_pointwise(g.stages[s + k].type) &&
+           pw_link(g, g.stages[s + k - 1], g.stages[s + k]))
+      ++k;
+    if (k >= 2) {
+      g.pw_run[s] = (int)k;
+      s += k;
+    } else {
+      s += 1;
+    }
+  }
+}
+
 static void finish_compile(mg_graph& g) {
+  plan_pointwise_chains(g);
   g.n_src_base = (int)(g.srcs.size() + g.gsrcs.size());
   const int Bt = std::max(0, g.cfg.max_trials);
   if (Bt > 0) {
@@ -257,6 +297,17 @@ static void run_forward(mg_graph* g, hipStream_t st, bool keep, double* losses, 
   }
   for (size_t s = 1; s < g->stages.size(); ++s) {
     const Stage& S = g->stages[s];
+    if (g->pw_run[s] >= 2) {
+      const int K = g->pw_run[s];
+      int types[PW_MAXK], offs[PW_MAXK];
+      for (int i = 0; i < K; ++i) {
+        types[i] = g->stages[s + i].type;
+        offs[i] = g->stages[s + i].desc_off;
+      }
+      launch_pw_chain_fwd(c, types, offs, K, (int)S.nodes.size());
+      s += K - 1;
+      continue;
+    }
     if (is_conv(S.type)) {
       if (ready[s] >= 0) hipStreamWaitEvent(st, g->sev[ready[s]], 0);
       else fir_stage(c, S.type, S.desc_off, (int)S.nodes.size(), (float2*)(g->base + g->ws.T1));
@@ -420,12 +471,27 @@ extern "C" int mg_backward(mg_graph* g, float* grad_theta, float* grad_wet, void
   };
   hipEvent_t t3_done[2] = {nullptr, nullptr};
   int n_conv = 0;
+  // stage s ends the fused chain that starts at chain_start[s]
+  std::vector<int> chain_start(g->stages.size(), -1);
+  for (size_t s = 1; s < g->stages.size(); ++s)
+    if (g->pw_run[s] >= 2) chain_start[s + g->pw_run[s] - 1] = (int)s;
   for (size_t s = g->stages.size() - 1; s >= 1; --s) {
     const Stage& S = g->stages[s];
     const int n = (int)S.nodes.size();
     const int off = S.desc_off;
     const int t = S.type;
     if (t == MG_MIX || t == MG_OUT) continue;
+    if (chain_start[s] >= 0) {
+      const int s0 = chain_start[s], K = g->pw_run[s0];
+      int types[PW_MAXK], offs[PW_MAXK];
+      for (int i = 0; i < K; ++i) {
+        types[i] = g->stages[s0 + i].type;
+        offs[i] = g->stages[s0 + i].desc_off;
+      }
+      launch_pw_chain_bwd(c, types, offs, K, n);
+      s = (size_t)s0;
+      continue;
+    }
     if (t == MG_GAINPAN || t == MG_IMAGER || t == MG_DIST) {
       launch_pointwise_bwd(c, t, off, n);
     } else if (t == MG_COMP || t == MG_GATE) {
@@ -467,6 +533,7 @@ extern "C" int mg_profile_enable(mg_graph* g, const char* kernel_class) {
   p.used = 0;
   p.bytes = 0.0;
   p.launches = 0;
+  p.overflow = false;
   if (!p.cls.empty() && p.ev.empty()) {
     p.ev.resize(8192);
     for (auto& e : p.ev) {
@@ -480,6 +547,13 @@ extern "C" int mg_profile_enable(mg_graph* g, const char* kernel_class) {
 extern "C" int mg_profile_read(mg_graph* g, double* ms, int64_t* launches, double* bytes) {
   if (!g || !ms || !launches || !bytes) return fail(MG_ERR_INVALID_ARG, "NULL argument");
   Profiler& p = g->prof;
+  if (p.overflow) {
+    p.used = 0;
+    p.bytes = 0.0;
+    p.launches = 0;
+    p.overflow = false;
+    return fail(MG_ERR_INVALID_ARG, "more timed kernels than events between reads");
+  }
   double total = 0.0;
   for (int i = 0; i + 1 < p.used; i += 2) {
     int rc = hip_check(hipEventSynchronize(p.ev[i + 1]), "event sync");

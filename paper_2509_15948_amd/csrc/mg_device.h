@@ -213,18 +213,28 @@ __device__ __forceinline__ void fft_lds(V* buf, const TwTab<N, V>& tw) {
   if (LOG % 3 == 1) fft_pass<N, 2, B, BS, NT, DIR>(buf, tw, Ns);
 }
 
-// Fixed-order sum over the workgroup; every thread gets the result.
+// Fixed-order sum over the workgroup; every thread gets the result.  Each
+// wave folds its 64 lanes with an xor butterfly (a + b and b + a agree, so all
+// lanes hold the same bits), then every thread adds the NT/64 wave sums in
+// wave order.  red must hold NT/64 entries.
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
 template <int NT, typename T>
 __device__ __forceinline__ T block_sum(T v, T* red) {
-  const int tid = threadIdx.x;
-  red[tid] = v;
+  static_assert(NT % 64 == 0, "whole waves");
+  constexpr int NW = NT / 64;
+  v = wave_sum(v);
+  if (NW == 1) return v;
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
   __syncthreads();
-#pragma unroll
-  for (int s = NT / 2; s > 0; s >>= 1) {
-    if (tid < s) red[tid] += red[tid + s];
-    __syncthreads();
-  }
   T r = red[0];
+#pragma unroll
+  for (int i = 1; i < NW; ++i) r += red[i];
   __syncthreads();
   return r;
 }

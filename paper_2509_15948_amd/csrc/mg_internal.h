@@ -103,6 +103,8 @@ struct Profiler {
   std::string cls;                       // empty: disabled
   std::vector<hipEvent_t> ev;            // pool of start/stop pairs
   int used = 0;                          // events used since the last read
+  const char* cur = nullptr;             // class of the innermost open scope
+  bool overflow = false;                 // launches went untimed (pool full)
   double bytes = 0.0;                    // algorithmic bytes of the timed launches
   int64_t launches = 0;
 };
@@ -135,6 +137,8 @@ struct mg_graph {
   int output_node = -1;
   // slots
   std::vector<int> uslot;                 // node -> U slot (-1 for inputs)
+  std::vector<int> pw_run;                // stage s starts a fused chain of pw_run[s] >= 2
+                                          // pointwise stages (0: not fused)
   int n_uslots = 0;
   std::vector<int> gslot, ginslot;        // node -> gradient slot of dL/dy, dL/du
   int n_gslots = 0;

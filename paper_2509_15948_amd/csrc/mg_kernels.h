@@ -1,9 +1,12 @@
 // Launch context and kernel launchers of the mixgraph library.
 #pragma once
+#include <hip/hip_ext.h>
+
 #include "mg_internal.h"
 
 namespace mg {
 
+constexpr int PW_MAXK = 4;  // pointwise stages fused into one launch at most
 constexpr int PK = 8;  // floats of partial sums per (node, block)
 // elements of one column block of the FFT engine (TC = COL_TILE / N2 columns)
 constexpr int COL_TILE = 8192;
@@ -43,25 +46,45 @@ inline T* wsp(const Ctx& c, size_t off) {
   return reinterpret_cast<T*>(c.base + off);
 }
 
-// Measurement scope around a launch of kernel class cls moving `bytes`
-// algorithmic bytes; a no-op unless the graph's profiler targets cls.
+// Measurement scope of kernel class cls moving `bytes` algorithmic bytes: a
+// no-op unless the graph's profiler targets cls.  Scopes nest; the innermost
+// one names the class of the launches made inside it.  Timed launches carry
+// their own start/stop events (hipExtLaunchKernelGGL stamps the dispatch
+// itself), so timing adds no packets between kernels.
 struct ProfScope {
-  Profiler* p = nullptr;
-  hipStream_t st;
-  ProfScope(const Ctx& c, const char* cls, double bytes) : st(c.st) {
-    Profiler* q = const_cast<Profiler*>(&c.g->prof);
-    if (q->cls.empty() || q->cls != cls || q->used + 2 > (int)q->ev.size()) return;
-    p = q;
-    hipEventRecord(p->ev[p->used], st);
-    p->bytes += bytes;
-    p->launches += 1;
+  Profiler* q;
+  const char* prev;
+  ProfScope(const Ctx& c, const char* cls, double bytes) : q(const_cast<Profiler*>(&c.g->prof)), prev(q->cur) {
+    q->cur = cls;
+    if (q->cls.empty() || q->cls != cls) return;
+    q->bytes += bytes;
+    q->launches += 1;
   }
-  ~ProfScope() {
-    if (!p) return;
-    hipEventRecord(p->ev[p->used + 1], st);
-    p->used += 2;
-  }
+  ~ProfScope() { q->cur = prev; }
 };
+
+// the event pair of the next launch when it is timed; false otherwise
+inline bool prof_pair(const Ctx& c, hipEvent_t& a, hipEvent_t& b) {
+  Profiler* p = const_cast<Profiler*>(&c.g->prof);
+  if (p->cls.empty() || !p->cur || p->cls != p->cur) return false;
+  if (p->used + 2 > (int)p->ev.size()) {
+    p->overflow = true;
+    return false;
+  }
+  a = p->ev[p->used];
+  b = p->ev[p->used + 1];
+  p->used += 2;
+  return true;
+}
+
+#define MG_LAUNCH(C, K, GRID, BLOCK, SHMEM, STREAM, ...)                                \
+  do {                                                                                  \
+    hipEvent_t ev_a_, ev_b_;                                                            \
+    if (prof_pair(C, ev_a_, ev_b_))                                                     \
+      hipExtLaunchKernelGGL(K, GRID, BLOCK, SHMEM, STREAM, ev_a_, ev_b_, 0, __VA_ARGS__); \
+    else                                                                                \
+      hipLaunchKernelGGL(K, GRID, BLOCK, SHMEM, STREAM, __VA_ARGS__);                   \
+  } while (0)
 
 // mg_api.hip
 Ctx make_ctx(const mg_graph* g, hipStream_t st);
@@ -71,6 +94,9 @@ void forward_stage(const Ctx& c, int t, int off, int n, bool keep, const NodeDes
 void launch_sum(const Ctx& c, int desc_off, int n, const SrcRef* srcs, float* out_base, int dest_kind);
 void launch_pointwise_fwd(const Ctx& c, int type, int desc_off, int n);
 void launch_pointwise_bwd(const Ctx& c, int type, int desc_off, int n);
+// K (<= PW_MAXK) consecutive pointwise stages of n nodes each (types[i], descriptor offsets offs[i])
+void launch_pw_chain_fwd(const Ctx& c, const int* types, const int* offs, int K, int n);
+void launch_pw_chain_bwd(const Ctx& c, const int* types, const int* offs, int K, int n);
 void launch_finish_grads(const Ctx& c, int desc_off, int n, int nblocks, int nparams, float* grad_theta,
                          float* grad_wet);
 void launch_finish_all(const Ctx& c, int n_desc, const int2* fin, float* grad_theta, float* grad_wet);

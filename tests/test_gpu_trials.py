@@ -88,7 +88,7 @@ def test_trials_against_the_oracle():
     for b in range(len(keep)):
         mask = {v: float(keep[b, int(case.bg.proc_index[v])]) for v in procs}
         omix, ol, _, _ = case.oracle(mask, grads=False)
-        tol = loss_tolerances(case, omix)
+        tol = loss_tolerances(case, omix, mask)
         for i, k in enumerate(MG.LOSS_KEYS):
             bound = max(1e-5 * abs(ol[k]), tol.get(k, 0.0))
             print("trial", b, k, got[b][i], ol[k], flush=True)
