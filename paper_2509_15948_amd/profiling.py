@@ -33,7 +33,7 @@ CLASSES = {
     "eq_conv": r"mg::k_eq_(fwd|bwd)\b",
     "eq_spec": r"mg::k_eq_spec\b",
     "dyn": r"mg::k_dyn_",
-    "pointwise": r"mg::k_pointwise_",
+    "pointwise": r"mg::k_(pointwise_|pw_chain_)",
     "sum": r"mg::k_sum\b",
     "loss": r"mg::k_loss_",
     "reverb_fir": r"mg::k_rv_",
