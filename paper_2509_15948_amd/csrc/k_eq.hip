@@ -16,7 +16,8 @@
 namespace mg {
 
 constexpr int EQ_P = 8192;
-constexpr int EQ_NT = 1024;   // threads per block: 16 waves keep the CU busy at one or two blocks per CU
+constexpr int EQ_NT = 512;    // forward and spectrum: 8 waves per block, two blocks per CU (LDS and registers)
+constexpr int EQ_BNT = 1024;  // backward: two windows in LDS, one block per CU, 16 waves
 
 struct EqArgs {
   const NodeDesc* desc;
@@ -122,10 +123,10 @@ __global__ __launch_bounds__(EQ_NT) void k_eq_fwd(EqArgs a) {
 }
 
 // backward: grid (nblk, nodes); LDS holds two P-point windows (128 KB)
-__global__ __launch_bounds__(EQ_NT) void k_eq_bwd(EqArgs a) {
+__global__ __launch_bounds__(EQ_BNT) void k_eq_bwd(EqArgs a) {
   __shared__ float2 A[EQ_P];
   __shared__ float2 B[EQ_P];
-  __shared__ float red[EQ_NT];
+  __shared__ float red[EQ_BNT];
   __shared__ TwTab<EQ_P, float2> tt;
   tw_fill<EQ_P>(tt, a.tw, a.twdl);
   const int j = blockIdx.y, blk = blockIdx.x;
@@ -143,7 +144,7 @@ __global__ __launch_bounds__(EQ_NT) void k_eq_bwd(EqArgs a) {
   const float ky = (float)((double)a.alpha_g * sgn / Ey), ku = (float)((double)a.alpha_g * sgn / Eu);
   // dL/dybar over the whole window (A) and over the valid part only (B)
   float dw = 0.f;
-  for (int i = threadIdx.x; i < EQ_P; i += EQ_NT) {
+  for (int i = threadIdx.x; i < EQ_P; i += EQ_BNT) {
     const int64_t n = s0 + i;
     float2 g = make_float2(0.f, 0.f);
     if (n >= 0 && n < a.L) {
@@ -160,11 +161,11 @@ __global__ __launch_bounds__(EQ_NT) void k_eq_bwd(EqArgs a) {
   const float* H = a.HP + (int64_t)d.aux * EQ_P;
   float* gin = d.gin >= 0 ? a.G + (int64_t)d.gin * 2 * a.L : nullptr;
   if (gin) {
-    fft_lds<EQ_P, 1, EQ_P, EQ_NT, -1>(A, tt);
-    for (int i = threadIdx.x; i < EQ_P; i += EQ_NT) A[i] = c_scale(A[i], H[i] * (1.0f / EQ_P));
+    fft_lds<EQ_P, 1, EQ_P, EQ_BNT, -1>(A, tt);
+    for (int i = threadIdx.x; i < EQ_P; i += EQ_BNT) A[i] = c_scale(A[i], H[i] * (1.0f / EQ_P));
     __syncthreads();
-    fft_lds<EQ_P, 1, EQ_P, EQ_NT, +1>(A, tt);
-    for (int i = half + threadIdx.x; i < half + a.V; i += EQ_NT) {
+    fft_lds<EQ_P, 1, EQ_P, EQ_BNT, +1>(A, tt);
+    for (int i = half + threadIdx.x; i < half + a.V; i += EQ_BNT) {
       const int64_t n = s0 + i;
       if (n >= a.L) break;
       const float um = u[n] + u[cs + n];
@@ -174,23 +175,23 @@ __global__ __launch_bounds__(EQ_NT) void k_eq_bwd(EqArgs a) {
     __syncthreads();
   }
   // FIR gradient: correlate the valid-part gradient (B) with the input window (A)
-  for (int i = threadIdx.x; i < EQ_P; i += EQ_NT) {
+  for (int i = threadIdx.x; i < EQ_P; i += EQ_BNT) {
     const int64_t n = s0 + i;
     A[i] = (n >= 0 && n < a.L) ? make_float2(u[n], u[cs + n]) : make_float2(0.f, 0.f);
   }
   __syncthreads();
-  fft_lds<EQ_P, 1, EQ_P, EQ_NT, -1>(A, tt);
-  fft_lds<EQ_P, 1, EQ_P, EQ_NT, -1>(B, tt);
-  for (int i = threadIdx.x; i < EQ_P; i += EQ_NT) B[i] = c_scale(c_mulc(B[i], A[i]), 1.0f / EQ_P);
+  fft_lds<EQ_P, 1, EQ_P, EQ_BNT, -1>(A, tt);
+  fft_lds<EQ_P, 1, EQ_P, EQ_BNT, -1>(B, tt);
+  for (int i = threadIdx.x; i < EQ_P; i += EQ_BNT) B[i] = c_scale(c_mulc(B[i], A[i]), 1.0f / EQ_P);
   __syncthreads();
-  fft_lds<EQ_P, 1, EQ_P, EQ_NT, +1>(B, tt);
+  fft_lds<EQ_P, 1, EQ_P, EQ_BNT, +1>(B, tt);
   // lag m sits at circular index m mod P; dh index = m + half
   float* o = a.dhp + ((int64_t)d.aux * a.nblk + blk) * a.N;
-  for (int t = threadIdx.x; t < a.N; t += EQ_NT) {
+  for (int t = threadIdx.x; t < a.N; t += EQ_BNT) {
     const int m = t - half;
     o[t] = B[m >= 0 ? m : m + EQ_P].x;
   }
-  const float s = block_sum<EQ_NT>(dw, red);
+  const float s = block_sum<EQ_BNT>(dw, red);
   if (threadIdx.x == 0) a.part[((int64_t)j * a.PB + blk) * PK + 2] = s;
 }
 
@@ -274,7 +275,7 @@ void eq_backward(const Ctx& c, int desc_off, int n) {
   {
     // reads dL/dy, ybar, u (window each) and u again; writes dL/du and the block FIR gradients
     ProfScope ps(c, "eq_conv", (double)n * ((24.0 * EQ_P) * a.nblk + 16.0 * c.L + 4.0 * a.N * a.nblk));
-    MG_LAUNCH(c, k_eq_bwd, dim3(a.nblk, n), dim3(EQ_NT), 0, c.st, a);
+    MG_LAUNCH(c, k_eq_bwd, dim3(a.nblk, n), dim3(EQ_BNT), 0, c.st, a);
   }
 }
 
