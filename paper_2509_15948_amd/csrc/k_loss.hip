@@ -25,10 +25,10 @@ constexpr int LOSS_NT = 512;
 
 constexpr double LOG_EPS = 1e-7;
 
-// Frames per workgroup: 2048 complex FP64 points per batch (32 KB of LDS),
-// one frame for the 4096-point resolution.
+// Frames per workgroup: 1024 complex FP64 points per batch (16 KB of LDS),
+// so two or three workgroups share a CU; one frame from 1024 points up.
 template <int N>
-constexpr int loss_fpb() { return N >= 2048 ? 1 : 2048 / N; }
+constexpr int loss_fpb() { return N >= 1024 ? 1 : 1024 / N; }
 
 struct LossTabs {
   const double* win;    // [N]
@@ -473,7 +473,7 @@ static void run_loss_fwd(const Ctx& c, const float* y, int mode, double* stats_o
     const LossRes& r = g->lres[i];
     const Ctx& cc = (forked && (i & 1)) ? cs : c;
     LossArgs a = loss_args(c, (int)i, y);
-    const int FPB = r.nfft >= 2048 ? 1 : 2048 / r.nfft;
+    const int FPB = loss_frames_per_block(r.nfft);
     const int blocks = (r.frames + FPB - 1) / FPB;
 #define MG_F0(NN) fwd_n<NN, 0>(cc, a, blocks)
 #define MG_F1(NN) fwd_n<NN, 1>(cc, a, blocks)
@@ -529,7 +529,7 @@ void loss_backward(const Ctx& c, const float* yhat, float* dyhat) {
     const Ctx& cc = (forked && i >= 1) ? cs : c;
     LossArgs a = loss_args(c, (int)i, yhat);
     a.scratch = (float*)(c.base + off);
-    const int FPB = r.nfft >= 2048 ? 1 : 2048 / r.nfft;
+    const int FPB = loss_frames_per_block(r.nfft);
     const int blocks = (r.frames + FPB - 1) / FPB;
 #define MG_B(NN) bwd_n<NN>(cc, a, blocks)
     MG_LOSS_SWITCH(r.nfft, MG_B)
