@@ -23,10 +23,11 @@
 namespace mg {
 
 // threads per block: the column kernels hold 64 KB of LDS (two blocks per
-// CU), so 512 threads give 16 waves per CU (16384-element tiles with 1024
-// threads, one block per CU, measured slower); row kernels use 512 threads from
-// N1 = 1024 up (fewer rows of butterflies below)
-constexpr int COL_NT = 512;
+// CU) and need few registers, so 1024 threads give 32 waves per CU (512
+// threads, 16 waves, measured 4 % slower per step; 4096-element tiles, 64-byte
+// row segments, slower still); row kernels use 512 threads from N1 = 1024 up
+// (fewer rows of butterflies below)
+constexpr int COL_NT = 1024;
 template <int N1>
 constexpr int row_nt() { return N1 >= 4096 ? 1024 : (N1 >= 1024 ? 512 : 256); }
 
