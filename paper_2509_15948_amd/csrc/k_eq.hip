@@ -16,7 +16,7 @@
 namespace mg {
 
 constexpr int EQ_P = 8192;
-constexpr int EQ_NT = 512;    // forward and spectrum: 8 waves per block, two blocks per CU (LDS and registers)
+constexpr int EQ_NT = 1024;   // forward and spectrum: 16 waves per block, two blocks per CU (LDS; registers capped at 64)
 constexpr int EQ_BNT = 1024;  // backward: two windows in LDS, one block per CU, 16 waves
 
 struct EqArgs {
@@ -73,9 +73,9 @@ __global__ __launch_bounds__(EQ_NT) void k_eq_spec(EqArgs a) {
 }
 
 // forward: grid (nblk, nodes)
-__global__ __launch_bounds__(EQ_NT) void k_eq_fwd(EqArgs a) {
+__global__ __launch_bounds__(EQ_NT, 8) void k_eq_fwd(EqArgs a) {
   __shared__ float2 buf[EQ_P];
-  __shared__ float red[EQ_NT];
+  __shared__ float red[EQ_NT / 64];
   __shared__ TwTab<EQ_P, float2> tt;
   tw_fill<EQ_P>(tt, a.tw, a.twdl);
   const int j = blockIdx.y, blk = blockIdx.x;
