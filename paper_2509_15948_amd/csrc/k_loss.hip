@@ -524,9 +524,7 @@ void loss_backward(const Ctx& c, const float* yhat, float* dyhat) {
   const bool forked = loss_fork(c, cs);
   for (size_t i = 0; i < g->lres.size(); ++i) {
     const LossRes& r = g->lres[i];
-    // the shortest transform's adjoint is the longest kernel: alone on the
-    // caller's stream, the others on the side stream
-    const Ctx& cc = (forked && i >= 1) ? cs : c;
+    const Ctx& cc = (forked && (i & 1)) ? cs : c;
     LossArgs a = loss_args(c, (int)i, yhat);
     a.scratch = (float*)(c.base + off);
     const int FPB = loss_frames_per_block(r.nfft);

@@ -471,6 +471,11 @@ extern "C" int mg_backward(mg_graph* g, float* grad_theta, float* grad_wet, void
   };
   hipEvent_t t3_done[2] = {nullptr, nullptr};
   int n_conv = 0;
+  // the first FIR stage of the schedule is the last one here: nothing on the
+  // caller's stream is left to overlap its FIR-gradient work, so it stays there
+  size_t last_fir = 0;
+  for (size_t s = 1; s < g->stages.size() && !last_fir; ++s)
+    if (is_conv(g->stages[s].type)) last_fir = s;
   // stage s ends the fused chain that starts at chain_start[s]
   std::vector<int> chain_start(g->stages.size(), -1);
   for (size_t s = 1; s < g->stages.size(); ++s)
@@ -498,9 +503,10 @@ extern "C" int mg_backward(mg_graph* g, float* grad_theta, float* grad_wet, void
       dyn_backward(c, t, off, n);
     } else if (t == MG_EQ) {
       eq_backward(c, off, n);
-      fork();
-      eq_backward_fir(cs, off, n);
-      fir_adjoint(cs, t, off, n, grad_theta);
+      const Ctx& cf = (s == last_fir) ? c : cs;
+      if (s != last_fir) fork();
+      eq_backward_fir(cf, off, n);
+      fir_adjoint(cf, t, off, n, grad_theta);
     } else if (is_conv(t)) {
       const int b = n_conv++ & 1;
       float2* T3 = (float2*)(g->base + (b ? g->ws.T3b : g->ws.T3));
