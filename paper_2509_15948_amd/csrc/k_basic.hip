@@ -178,12 +178,29 @@ __device__ __forceinline__ void pw_level_bwd(const PW<T>& f, float w, float l, f
   gr = fmaf(1.0f - w, dr, br);
 }
 
+// Sample visiting shared by every pointwise kernel: with vec set (L a
+// multiple of 4 and 16-byte aligned rows, decided once per call on the host)
+// each thread takes runs of 4 consecutive samples, one float4 per channel
+// row, else single samples; the order is the same in the per-stage and the
+// fused kernels, so their per-thread partial sums agree bit for bit.
+__device__ __forceinline__ void ld4(const float* p, float (&v)[4]) {
+  const float4 t = *reinterpret_cast<const float4*>(p);
+  v[0] = t.x;
+  v[1] = t.y;
+  v[2] = t.z;
+  v[3] = t.w;
+}
+__device__ __forceinline__ void st4(float* p, const float (&v)[4]) {
+  *reinterpret_cast<float4*>(p) = make_float4(v[0], v[1], v[2], v[3]);
+}
+
 template <int T>
 __global__ __launch_bounds__(MG_BLOCK) void k_pointwise_fwd(const NodeDesc* __restrict__ desc,
                                                              const float* __restrict__ dry, float* __restrict__ U,
                                                              const float* __restrict__ theta,
                                                              const float* __restrict__ wet,
-                                                             const float* __restrict__ mask, int64_t L, int C) {
+                                                             const float* __restrict__ mask, int64_t L, int C,
+                                                             int vec) {
   const NodeDesc d = desc[blockIdx.y];
   PW<T> f;
   f.init(theta + d.theta_off);
@@ -191,7 +208,25 @@ __global__ __launch_bounds__(MG_BLOCK) void k_pointwise_fwd(const NodeDesc* __re
   int64_t cs;
   const float* u = resolve_in(d, dry, U, L, C, cs);
   float* y = U + (int64_t)d.out_slot * 2 * L;
-  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < L; t += (int64_t)gridDim.x * blockDim.x) {
+  const int64_t start = (int64_t)blockIdx.x * blockDim.x + threadIdx.x, stride = (int64_t)gridDim.x * blockDim.x;
+  if (vec) {
+    for (int64_t q = start; q < L / 4; q += stride) {
+      float l[4], r[4], ol[4], orr[4];
+      ld4(u + 4 * q, l);
+      ld4(u + cs + 4 * q, r);
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        float yl, yr;
+        f.fwd(l[k], r[k], yl, yr);
+        ol[k] = dw_mix(w, yl, l[k]);
+        orr[k] = dw_mix(w, yr, r[k]);
+      }
+      st4(y + 4 * q, ol);
+      st4(y + L + 4 * q, orr);
+    }
+    return;
+  }
+  for (int64_t t = start; t < L; t += stride) {
     const float l = u[t], r = u[cs + t];
     float yl, yr;
     f.fwd(l, r, yl, yr);
@@ -219,7 +254,7 @@ __global__ __launch_bounds__(MG_BLOCK) void k_pointwise_bwd(const NodeDesc* __re
                                                              const float* __restrict__ theta,
                                                              const float* __restrict__ wet,
                                                              const float* __restrict__ mask, int64_t L, int C,
-                                                             float* __restrict__ part, int PB) {
+                                                             float* __restrict__ part, int PB, int vec) {
   __shared__ float red[MG_BLOCK / 64];
   const NodeDesc d = desc[blockIdx.y];
   PW<T> f;
@@ -231,14 +266,35 @@ __global__ __launch_bounds__(MG_BLOCK) void k_pointwise_bwd(const NodeDesc* __re
   float* gin = d.gin >= 0 ? G + (int64_t)d.gin * 2 * L : nullptr;
   float pp[2] = {0.0f, 0.0f};
   float dw = 0.0f;
-  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < L; t += (int64_t)gridDim.x * blockDim.x) {
-    const float l = u[t], r = u[cs + t];
-    float yl, yr, gl, gr;
-    f.fwd(l, r, yl, yr);
-    pw_level_bwd(f, w, l, r, yl, yr, dy[t], dy[L + t], gl, gr, dw, pp);
-    if (gin) {
-      gin[t] = gl;
-      gin[L + t] = gr;
+  const int64_t start = (int64_t)blockIdx.x * blockDim.x + threadIdx.x, stride = (int64_t)gridDim.x * blockDim.x;
+  if (vec) {
+    for (int64_t q = start; q < L / 4; q += stride) {
+      float l[4], r[4], dl[4], dr[4], gl[4], gr[4];
+      ld4(u + 4 * q, l);
+      ld4(u + cs + 4 * q, r);
+      ld4(dy + 4 * q, dl);
+      ld4(dy + L + 4 * q, dr);
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        float yl, yr;
+        f.fwd(l[k], r[k], yl, yr);
+        pw_level_bwd(f, w, l[k], r[k], yl, yr, dl[k], dr[k], gl[k], gr[k], dw, pp);
+      }
+      if (gin) {
+        st4(gin + 4 * q, gl);
+        st4(gin + L + 4 * q, gr);
+      }
+    }
+  } else {
+    for (int64_t t = start; t < L; t += stride) {
+      const float l = u[t], r = u[cs + t];
+      float yl, yr, gl, gr;
+      f.fwd(l, r, yl, yr);
+      pw_level_bwd(f, w, l, r, yl, yr, dy[t], dy[L + t], gl, gr, dw, pp);
+      if (gin) {
+        gin[t] = gl;
+        gin[L + t] = gr;
+      }
     }
   }
   pw_partials(part + ((int64_t)(blockIdx.y) * PB + blockIdx.x) * PK, dw, pp[0], pp[1], red);
@@ -294,7 +350,8 @@ __device__ __forceinline__ void pw_bwd_rt(int type, float a, float b, float w, f
 __global__ __launch_bounds__(MG_BLOCK) void k_pw_chain_fwd(PwChain ch, const float* __restrict__ dry,
                                                             float* __restrict__ U, const float* __restrict__ theta,
                                                             const float* __restrict__ wet,
-                                                            const float* __restrict__ mask, int64_t L, int C) {
+                                                            const float* __restrict__ mask, int64_t L, int C,
+                                                            int vec) {
   float pa[PW_MAXK], pb[PW_MAXK], pw[PW_MAXK];
   float* y[PW_MAXK];
 #pragma unroll
@@ -307,7 +364,29 @@ __global__ __launch_bounds__(MG_BLOCK) void k_pw_chain_fwd(PwChain ch, const flo
   }
   int64_t cs;
   const float* u = resolve_in(ch.desc[0][blockIdx.y], dry, U, L, C, cs);
-  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < L; t += (int64_t)gridDim.x * blockDim.x) {
+  const int64_t start = (int64_t)blockIdx.x * blockDim.x + threadIdx.x, stride = (int64_t)gridDim.x * blockDim.x;
+  if (vec) {
+    for (int64_t q = start; q < L / 4; q += stride) {
+      float l[4], r[4];
+      ld4(u + 4 * q, l);
+      ld4(u + cs + 4 * q, r);
+#pragma unroll
+      for (int i = 0; i < PW_MAXK; ++i) {
+        if (i >= ch.K) break;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          float yl, yr;
+          pw_fwd_rt(ch.type[i], pa[i], pb[i], l[k], r[k], yl, yr);
+          l[k] = dw_mix(pw[i], yl, l[k]);
+          r[k] = dw_mix(pw[i], yr, r[k]);
+        }
+        st4(y[i] + 4 * q, l);
+        st4(y[i] + L + 4 * q, r);
+      }
+    }
+    return;
+  }
+  for (int64_t t = start; t < L; t += stride) {
     float l = u[t], r = u[cs + t];
 #pragma unroll
     for (int i = 0; i < PW_MAXK; ++i) {
@@ -327,7 +406,7 @@ __global__ __launch_bounds__(MG_BLOCK) void k_pw_chain_bwd(PwChain ch, const flo
                                                             const float* __restrict__ theta,
                                                             const float* __restrict__ wet,
                                                             const float* __restrict__ mask, int64_t L, int C,
-                                                            int PB) {
+                                                            int PB, int vec) {
   __shared__ float red[MG_BLOCK / 64];
   float pa[PW_MAXK], pb[PW_MAXK], pw[PW_MAXK];
   float dw[PW_MAXK], pp[PW_MAXK][2];
@@ -344,7 +423,46 @@ __global__ __launch_bounds__(MG_BLOCK) void k_pw_chain_bwd(PwChain ch, const flo
   const float* u = resolve_in(d0, dry, U, L, C, cs);
   const float* dy = G + (int64_t)ch.desc[ch.K - 1][blockIdx.y].gout * 2 * L;
   float* gin = d0.gin >= 0 ? G + (int64_t)d0.gin * 2 * L : nullptr;
-  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < L; t += (int64_t)gridDim.x * blockDim.x) {
+  // one sample through the chain and back; returns dL/du
+  auto sample = [&](float l, float r, float gl, float gr, float& ol, float& orr) {
+    float li[PW_MAXK], ri[PW_MAXK], yl[PW_MAXK], yr[PW_MAXK];
+#pragma unroll
+    for (int i = 0; i < PW_MAXK; ++i) {
+      if (i >= ch.K) break;
+      li[i] = l;
+      ri[i] = r;
+      pw_fwd_rt(ch.type[i], pa[i], pb[i], l, r, yl[i], yr[i]);
+      l = dw_mix(pw[i], yl[i], l);
+      r = dw_mix(pw[i], yr[i], r);
+    }
+#pragma unroll
+    for (int i = PW_MAXK - 1; i >= 0; --i) {
+      if (i >= ch.K) continue;
+      float bl, br;
+      pw_bwd_rt(ch.type[i], pa[i], pb[i], pw[i], li[i], ri[i], yl[i], yr[i], gl, gr, bl, br, dw[i], pp[i]);
+      gl = bl;
+      gr = br;
+    }
+    ol = gl;
+    orr = gr;
+  };
+  const int64_t start = (int64_t)blockIdx.x * blockDim.x + threadIdx.x, stride = (int64_t)gridDim.x * blockDim.x;
+  if (vec) {
+    for (int64_t q = start; q < L / 4; q += stride) {
+      float l[4], r[4], dl[4], dr[4], gl[4], gr[4];
+      ld4(u + 4 * q, l);
+      ld4(u + cs + 4 * q, r);
+      ld4(dy + 4 * q, dl);
+      ld4(dy + L + 4 * q, dr);
+#pragma unroll
+      for (int k = 0; k < 4; ++k) sample(l[k], r[k], dl[k], dr[k], gl[k], gr[k]);
+      if (gin) {
+        st4(gin + 4 * q, gl);
+        st4(gin + L + 4 * q, gr);
+      }
+    }
+  }
+  for (int64_t t = start; t < L && !vec; t += stride) {
     float li[PW_MAXK], ri[PW_MAXK], yl[PW_MAXK], yr[PW_MAXK];
     float l = u[t], r = u[cs + t];
 #pragma unroll
@@ -385,13 +503,13 @@ void launch_pointwise_fwd(const Ctx& c, int type, int desc_off, int n) {
   const NodeDesc* d = c.desc + desc_off;
   switch (type) {
     case MG_GAINPAN:
-      MG_LAUNCH(c, k_pointwise_fwd<MG_GAINPAN>, grid, blk, 0, c.st, d, c.dry, c.U, c.theta, c.wet, c.mask, c.L, c.C);
+      MG_LAUNCH(c, k_pointwise_fwd<MG_GAINPAN>, grid, blk, 0, c.st, d, c.dry, c.U, c.theta, c.wet, c.mask, c.L, c.C, c.vec4);
       break;
     case MG_IMAGER:
-      MG_LAUNCH(c, k_pointwise_fwd<MG_IMAGER>, grid, blk, 0, c.st, d, c.dry, c.U, c.theta, c.wet, c.mask, c.L, c.C);
+      MG_LAUNCH(c, k_pointwise_fwd<MG_IMAGER>, grid, blk, 0, c.st, d, c.dry, c.U, c.theta, c.wet, c.mask, c.L, c.C, c.vec4);
       break;
     case MG_DIST:
-      MG_LAUNCH(c, k_pointwise_fwd<MG_DIST>, grid, blk, 0, c.st, d, c.dry, c.U, c.theta, c.wet, c.mask, c.L, c.C);
+      MG_LAUNCH(c, k_pointwise_fwd<MG_DIST>, grid, blk, 0, c.st, d, c.dry, c.U, c.theta, c.wet, c.mask, c.L, c.C, c.vec4);
       break;
   }
 }
@@ -404,15 +522,15 @@ void launch_pointwise_bwd(const Ctx& c, int type, int desc_off, int n) {
   switch (type) {
     case MG_GAINPAN:
       MG_LAUNCH(c, k_pointwise_bwd<MG_GAINPAN>, grid, blk, 0, c.st, d, c.dry, c.U, c.G, c.theta, c.wet, c.mask,
-                c.L, c.C, part, c.PB);
+                c.L, c.C, part, c.PB, c.vec4);
       break;
     case MG_IMAGER:
       MG_LAUNCH(c, k_pointwise_bwd<MG_IMAGER>, grid, blk, 0, c.st, d, c.dry, c.U, c.G, c.theta, c.wet, c.mask,
-                c.L, c.C, part, c.PB);
+                c.L, c.C, part, c.PB, c.vec4);
       break;
     case MG_DIST:
       MG_LAUNCH(c, k_pointwise_bwd<MG_DIST>, grid, blk, 0, c.st, d, c.dry, c.U, c.G, c.theta, c.wet, c.mask,
-                c.L, c.C, part, c.PB);
+                c.L, c.C, part, c.PB, c.vec4);
       break;
   }
 }
@@ -433,14 +551,14 @@ void launch_pw_chain_fwd(const Ctx& c, const int* types, const int* offs, int K,
   dim3 grid(128, n), blk(MG_BLOCK);
   ProfScope ps(c, "pointwise", (double)n * (8.0 + 8.0 * K) * c.L);
   MG_LAUNCH(c, k_pw_chain_fwd, grid, blk, 0, c.st, pw_chain(c, types, offs, K), c.dry, c.U, c.theta, c.wet, c.mask,
-            c.L, c.C);
+            c.L, c.C, c.vec4);
 }
 
 void launch_pw_chain_bwd(const Ctx& c, const int* types, const int* offs, int K, int n) {
   dim3 grid(128, n), blk(MG_BLOCK);
   ProfScope ps(c, "pointwise", (double)n * 24.0 * c.L);
   MG_LAUNCH(c, k_pw_chain_bwd, grid, blk, 0, c.st, pw_chain(c, types, offs, K), c.dry, c.U, c.G, c.theta, c.wet,
-            c.mask, c.L, c.C, c.PB);
+            c.mask, c.L, c.C, c.PB, c.vec4);
 }
 
 // ---------------------------------------------------------------- reductions

@@ -233,6 +233,7 @@ Ctx make_ctx(const mg_graph* g, hipStream_t st) {
   c.lg = (double*)(g->base + g->ws.lg);
   c.alpha_g = (float)g->cfg.alpha_g;
   c.alpha_p = (float)g->cfg.alpha_p;
+  c.vec4 = (c.L % 4 == 0) && ((uintptr_t)c.dry % 16 == 0);
   return c;
 }
 

@@ -33,6 +33,8 @@ struct Ctx {
   char* base;            // workspace base
   bool trial = false;    // pruning-trial copies: keep no backward state, reuse
                          // the FIR tables and spectra of the last forward
+  int vec4 = 0;          // L a multiple of 4 and the dry rows 16-byte aligned:
+                         // the pointwise kernels move float4 runs
 };
 
 // effective dry/wet weight w = sigmoid(logit) * mask (Sec. 5.1 and the masked

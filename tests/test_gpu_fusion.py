@@ -35,6 +35,15 @@ def test_fused_chains_match_per_stage_launches(chain):
     _same(fused, plain)
 
 
+def test_fused_chains_odd_length():
+    """A length that is not a multiple of 4 takes the single-sample path of
+    the pointwise kernels (and every kernel's ragged tails)."""
+    cfg = synth.small_config(seconds=8001 / 16000, fs=16000, n_tracks=3, n_subgroups=2, chain="ecxsgdr")
+    assert cfg.length == 8001
+    fused, plain = _pair(cfg, seed=7)
+    _same(fused, plain)
+
+
 def test_fused_chains_with_a_mask():
     cfg = synth.small_config(seconds=0.5, fs=16000, n_tracks=3, n_subgroups=2, chain="ecxsgdr")
     fused, plain = _pair(cfg, seed=6)
