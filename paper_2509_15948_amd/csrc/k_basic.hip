@@ -639,23 +639,44 @@ void launch_finish_all(const Ctx& c, int n_desc, const int2* fin, float* grad_th
                      c.alpha_p, grad_theta, grad_wet);
 }
 
-// L_g energies: lg[desc] = (sum over blocks of partial 0, of partial 1)
-__global__ __launch_bounds__(MG_BLOCK) void k_reduce_lg(const float* __restrict__ part, int PB, int nblocks,
-                                                         double* __restrict__ lg) {
-  __shared__ double red[MG_BLOCK];
-  const float* pr = part + (int64_t)blockIdx.x * PB * PK;
+// L_g energies of one node: out[k] = sum over blocks of partial k, k = 0, 1
+// (E_ybar, E_u), strided per thread then the block sum
+__device__ __forceinline__ void reduce_lg_row(const float* pr, int nblocks, double* out, double* red) {
   for (int k = 0; k < 2; ++k) {
     double s = 0.0;
     for (int b = threadIdx.x; b < nblocks; b += MG_BLOCK) s += (double)pr[b * PK + k];
     s = block_sum<MG_BLOCK>(s, red);
-    if (threadIdx.x == 0) lg[2 * blockIdx.x + k] = s;
+    if (threadIdx.x == 0) out[k] = s;
   }
 }
 
+__global__ __launch_bounds__(MG_BLOCK) void k_reduce_lg(const float* __restrict__ part, int PB, int nblocks,
+                                                         double* __restrict__ lg) {
+  __shared__ double red[MG_BLOCK / 64];
+  reduce_lg_row(part + (int64_t)blockIdx.x * PB * PK, nblocks, lg + 2 * blockIdx.x, red);
+}
+
+// every FIR node of the graph in one launch (fin[j].x partial blocks, flag[j]
+// set for FIR nodes); the same sums as one k_reduce_lg per stage
+__global__ __launch_bounds__(MG_BLOCK) void k_reduce_lg_all(const float* __restrict__ part, int PB,
+                                                             const int2* __restrict__ fin,
+                                                             const int* __restrict__ flag,
+                                                             double* __restrict__ lg) {
+  __shared__ double red[MG_BLOCK / 64];
+  const int j = blockIdx.x;
+  if (!flag[j]) return;
+  reduce_lg_row(part + (int64_t)j * PB * PK, fin[j].x, lg + 2 * j, red);
+}
+
 void launch_reduce_lg(const Ctx& c, int desc_off, int n, int nblocks) {
-  if (n <= 0) return;
+  if (n <= 0 || c.defer_lg) return;
   MG_LAUNCH(c, k_reduce_lg, dim3(n), dim3(MG_BLOCK), 0, c.st, c.part + (int64_t)desc_off * c.PB * PK, c.PB,
                      nblocks, c.lg + 2 * desc_off);
+}
+
+void launch_reduce_lg_all(const Ctx& c, int n_desc, const int2* fin, const int* flag) {
+  if (n_desc <= 0) return;
+  MG_LAUNCH(c, k_reduce_lg_all, dim3(n_desc), dim3(MG_BLOCK), 0, c.st, c.part, c.PB, fin, flag, c.lg);
 }
 
 // losses[7] = L, La, Llr, Lm, Ls, Lg, Lp.

@@ -275,6 +275,7 @@ static void fir_stage(const Ctx& c, int t, int off, int n, float2* T) {
 
 static void run_forward(mg_graph* g, hipStream_t st, bool keep, double* losses, float* mix) {
   Ctx c = make_ctx(g, st);
+  c.defer_lg = true;  // one L_g reduction for every FIR stage, after the chain
   const int n_desc = (int)g->desc.size();
   // The FIRs of every EQ/delay/reverb stage depend on theta only: they are
   // synthesised on the side stream, ahead of the chain, and each stage waits
@@ -316,6 +317,7 @@ static void run_forward(mg_graph* g, hipStream_t st, bool keep, double* losses, 
     forward_stage(c, S.type, S.desc_off, (int)S.nodes.size(), keep, g->desc.data() + S.desc_off);
   }
   const float* yhat = c.U + (int64_t)g->uslot[g->output_node] * 2 * c.L;
+  launch_reduce_lg_all(c, n_desc, (const int2*)(g->base + g->ws.fin), (const int*)(g->base + g->ws.losses_tmp));
   loss_forward(c, yhat);
   launch_finalize_losses(c, losses, (const double*)(g->base + g->ws.ls_stats), (int)g->lres.size(), n_desc);
   if (mix) hipMemcpyAsync(mix, yhat, (size_t)2 * c.L * 4, hipMemcpyDeviceToDevice, st);

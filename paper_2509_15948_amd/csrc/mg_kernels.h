@@ -35,6 +35,7 @@ struct Ctx {
                          // the FIR tables and spectra of the last forward
   int vec4 = 0;          // L a multiple of 4 and the dry rows 16-byte aligned:
                          // the pointwise kernels move float4 runs
+  bool defer_lg = false; // L_g energies reduced once after all stages
 };
 
 // effective dry/wet weight w = sigmoid(logit) * mask (Sec. 5.1 and the masked
@@ -105,6 +106,8 @@ void launch_finish_grads(const Ctx& c, int desc_off, int n, int nblocks, int npa
                          float* grad_wet);
 void launch_finish_all(const Ctx& c, int n_desc, const int2* fin, float* grad_theta, float* grad_wet);
 void launch_reduce_lg(const Ctx& c, int desc_off, int n, int nblocks);
+// all FIR nodes at once (fin: partial blocks per descriptor, flag: FIR node)
+void launch_reduce_lg_all(const Ctx& c, int n_desc, const int2* fin, const int* flag);
 void launch_finalize_losses(const Ctx& c, double* losses, const double* lstats, int n_res, int n_desc);
 // one block per trial b: losses + 7 b, lstats + 128 b, mask + P b, sub + n_desc b
 void launch_finalize_trials(const Ctx& c, double* losses, const double* lstats, int n_res, int n_desc,
