@@ -17,7 +17,7 @@ namespace mg {
 
 constexpr int EQ_P = 8192;
 constexpr int EQ_NT = 1024;   // forward and spectrum: 16 waves per block, two blocks per CU (LDS; registers capped at 64)
-constexpr int EQ_BNT = 1024;  // backward: two windows in LDS, one block per CU, 16 waves
+constexpr int EQ_BNT = 1024;  // backward: one window in LDS, two blocks per CU (registers capped at 64)
 
 struct EqArgs {
   const NodeDesc* desc;
@@ -29,6 +29,7 @@ struct EqArgs {
   const float* h;       // compact FIRs [row][N]
   float* HP;            // [row][P] real spectra
   float* dhp;           // [row][nblk][N] per-block FIR gradients
+  float2* XU;           // [row][nblk][P] input-window spectra kept by the forward (or null)
   float* dh;            // [row][N]
   const float* wet;
   const float* mask;
@@ -91,7 +92,12 @@ __global__ __launch_bounds__(EQ_NT, 8) void k_eq_fwd(EqArgs a) {
   __syncthreads();
   fft_lds<EQ_P, 1, EQ_P, EQ_NT, -1>(buf, tt);
   const float* H = a.HP + (int64_t)d.aux * EQ_P;
-  for (int i = threadIdx.x; i < EQ_P; i += EQ_NT) buf[i] = c_scale(buf[i], H[i] * (1.0f / EQ_P));
+  float2* xu = a.XU ? a.XU + ((int64_t)d.aux * a.nblk + blk) * EQ_P : nullptr;
+  for (int i = threadIdx.x; i < EQ_P; i += EQ_NT) {
+    const float2 x = buf[i];
+    if (xu) xu[i] = x;   // kept for the FIR gradient of the backward
+    buf[i] = c_scale(x, H[i] * (1.0f / EQ_P));
+  }
   __syncthreads();
   fft_lds<EQ_P, 1, EQ_P, EQ_NT, +1>(buf, tt);
   float w = node_w(a.wet, a.mask, d);
@@ -122,11 +128,13 @@ __global__ __launch_bounds__(EQ_NT, 8) void k_eq_fwd(EqArgs a) {
   }
 }
 
-// backward: grid (nblk, nodes); LDS holds two P-point windows (128 KB)
-__global__ __launch_bounds__(EQ_BNT) void k_eq_bwd(EqArgs a) {
+// backward: grid (nblk, nodes); one P-point window in LDS.
+//   input gradient: gbar over the whole window (packed l + i r) times H_P;
+//   FIR gradient: gbar over the valid part only, times the conjugate of the
+//   input-window spectrum the forward kept, inverse -> lags -half..half.
+__global__ __launch_bounds__(EQ_BNT, 8) void k_eq_bwd(EqArgs a) {
   __shared__ float2 A[EQ_P];
-  __shared__ float2 B[EQ_P];
-  __shared__ float red[EQ_BNT];
+  __shared__ float red[EQ_BNT / 64];
   __shared__ TwTab<EQ_P, float2> tt;
   tw_fill<EQ_P>(tt, a.tw, a.twdl);
   const int j = blockIdx.y, blk = blockIdx.x;
@@ -142,26 +150,20 @@ __global__ __launch_bounds__(EQ_BNT) void k_eq_bwd(EqArgs a) {
   const double diff = 0.5 * log(Ey) - 0.5 * log(Eu);
   const double sgn = diff > 0 ? 1.0 : (diff < 0 ? -1.0 : 0.0);
   const float ky = (float)((double)a.alpha_g * sgn / Ey), ku = (float)((double)a.alpha_g * sgn / Eu);
-  // dL/dybar over the whole window (A) and over the valid part only (B)
-  float dw = 0.f;
-  for (int i = threadIdx.x; i < EQ_P; i += EQ_BNT) {
-    const int64_t n = s0 + i;
-    float2 g = make_float2(0.f, 0.f);
-    if (n >= 0 && n < a.L) {
-      const float bl = yb[n], br = yb[a.L + n];
-      const float rm = ky * (bl + br);
-      const float gl = dy[n], gr = dy[a.L + n];
-      g = make_float2(w * gl + rm, w * gr + rm);
-      if (i >= half && i < half + a.V) dw += gl * (bl - u[n]) + gr * (br - u[cs + n]);
-    }
-    A[i] = g;
-    B[i] = (i >= half && i < half + a.V) ? g : make_float2(0.f, 0.f);
-  }
-  __syncthreads();
-  const float* H = a.HP + (int64_t)d.aux * EQ_P;
   float* gin = d.gin >= 0 ? a.G + (int64_t)d.gin * 2 * a.L : nullptr;
   if (gin) {
+    for (int i = threadIdx.x; i < EQ_P; i += EQ_BNT) {
+      const int64_t n = s0 + i;
+      float2 g = make_float2(0.f, 0.f);
+      if (n >= 0 && n < a.L) {
+        const float rm = ky * (yb[n] + yb[a.L + n]);
+        g = make_float2(w * dy[n] + rm, w * dy[a.L + n] + rm);
+      }
+      A[i] = g;
+    }
+    __syncthreads();
     fft_lds<EQ_P, 1, EQ_P, EQ_BNT, -1>(A, tt);
+    const float* H = a.HP + (int64_t)d.aux * EQ_P;
     for (int i = threadIdx.x; i < EQ_P; i += EQ_BNT) A[i] = c_scale(A[i], H[i] * (1.0f / EQ_P));
     __syncthreads();
     fft_lds<EQ_P, 1, EQ_P, EQ_BNT, +1>(A, tt);
@@ -174,22 +176,31 @@ __global__ __launch_bounds__(EQ_BNT) void k_eq_bwd(EqArgs a) {
     }
     __syncthreads();
   }
-  // FIR gradient: correlate the valid-part gradient (B) with the input window (A)
+  // FIR gradient: the valid-part gradient correlated with the input window
+  float dw = 0.f;
   for (int i = threadIdx.x; i < EQ_P; i += EQ_BNT) {
     const int64_t n = s0 + i;
-    A[i] = (n >= 0 && n < a.L) ? make_float2(u[n], u[cs + n]) : make_float2(0.f, 0.f);
+    float2 g = make_float2(0.f, 0.f);
+    if (i >= half && i < half + a.V && n < a.L) {
+      const float bl = yb[n], br = yb[a.L + n];
+      const float rm = ky * (bl + br);
+      const float gl = dy[n], gr = dy[a.L + n];
+      g = make_float2(w * gl + rm, w * gr + rm);
+      dw += gl * (bl - u[n]) + gr * (br - u[cs + n]);
+    }
+    A[i] = g;
   }
   __syncthreads();
   fft_lds<EQ_P, 1, EQ_P, EQ_BNT, -1>(A, tt);
-  fft_lds<EQ_P, 1, EQ_P, EQ_BNT, -1>(B, tt);
-  for (int i = threadIdx.x; i < EQ_P; i += EQ_BNT) B[i] = c_scale(c_mulc(B[i], A[i]), 1.0f / EQ_P);
+  const float2* xu = a.XU + ((int64_t)d.aux * a.nblk + blk) * EQ_P;
+  for (int i = threadIdx.x; i < EQ_P; i += EQ_BNT) A[i] = c_scale(c_mulc(A[i], xu[i]), 1.0f / EQ_P);
   __syncthreads();
-  fft_lds<EQ_P, 1, EQ_P, EQ_BNT, +1>(B, tt);
+  fft_lds<EQ_P, 1, EQ_P, EQ_BNT, +1>(A, tt);
   // lag m sits at circular index m mod P; dh index = m + half
   float* o = a.dhp + ((int64_t)d.aux * a.nblk + blk) * a.N;
   for (int t = threadIdx.x; t < a.N; t += EQ_BNT) {
     const int m = t - half;
-    o[t] = B[m >= 0 ? m : m + EQ_P].x;
+    o[t] = A[m >= 0 ? m : m + EQ_P].x;
   }
   const float s = block_sum<EQ_BNT>(dw, red);
   if (threadIdx.x == 0) a.part[((int64_t)j * a.PB + blk) * PK + 2] = s;
@@ -233,6 +244,7 @@ static EqArgs eq_args(const Ctx& c, int desc_off, bool keep) {
   a.h = wsp<float>(c, g->ws.eq_h);
   a.HP = wsp<float>(c, g->ws.eq_HP);
   a.dhp = g->mode ? wsp<float>(c, g->ws.eq_dhp) : nullptr;
+  a.XU = (g->mode && keep) ? wsp<float2>(c, g->ws.eq_XU) : nullptr;
   a.dh = g->mode ? wsp<float>(c, g->ws.eq_dh) : nullptr;
   a.wet = c.wet;
   a.mask = c.mask;

@@ -79,6 +79,7 @@ static size_t plan_ws(mg_graph& g, int mode, bool commit) {
     if (mode) {
       take(w.eq_dh, (size_t)n_eq * c.eq_taps * 4);
       take(w.eq_dhp, (size_t)n_eq * eq_blocks(&g) * c.eq_taps * 4);
+      take(w.eq_XU, (size_t)n_eq * eq_blocks(&g) * 8192 * 8);  // input-window spectra for the backward
     }
     take(w.eq_cos, (size_t)c.eq_taps * 4);
   }
@@ -404,7 +405,7 @@ extern "C" int mg_setup(mg_graph* g, void* workspace, size_t workspace_bytes, in
         {"desc", w.desc}, {"srcs", w.srcs}, {"U", w.U}, {"YB", w.YB}, {"ENV", w.ENV}, {"G", w.G},
         {"ZH", w.ZH}, {"ZU", w.ZU}, {"T1", w.T1}, {"T2", w.T2}, {"T3", w.T3}, {"twhi", w.twhi},
         {"twlo", w.twlo}, {"tw", w.tw}, {"twd", w.twd}, {"eq_h", w.eq_h}, {"eq_HP", w.eq_HP},
-        {"eq_dh", w.eq_dh}, {"eq_dhp", w.eq_dhp}, {"eq_cos", w.eq_cos}, {"dl_tab", w.dl_tab},
+        {"eq_dh", w.eq_dh}, {"eq_dhp", w.eq_dhp}, {"eq_XU", w.eq_XU}, {"eq_cos", w.eq_cos}, {"dl_tab", w.dl_tab},
         {"dl_dh", w.dl_dh}, {"dl_cos", w.dl_cos}, {"rv_U", w.rv_U}, {"rv_fr", w.rv_fr}, {"rv_h", w.rv_h},
         {"rv_dh", w.rv_dh}, {"rv_dM", w.rv_dM}, {"rv_cs", w.rv_cs}, {"rv_win", w.rv_win},
         {"rv_wsum", w.rv_wsum}, {"cmp_sum", w.cmp_sum}, {"cmp_carry", w.cmp_carry}, {"part", w.part},
