@@ -93,6 +93,43 @@ __device__ __forceinline__ void frame_mags(const double2* buf, double* mag, cons
   }
 }
 
+// The same magnitudes written over the spectrum itself (the forward needs
+// the spectrum no further): every thread first takes its bins' values into
+// registers, the block synchronises, then the magnitudes go to mag, which
+// aliases buf (FPB (N + 2) complex values hold FPB * 4 * (N/2 + 1) doubles).
+template <int N>
+__device__ __forceinline__ void frame_mags_inplace(double2* buf, const LossArgs& a) {
+  constexpr int FPB = loss_fpb<N>();
+  constexpr int NB = N / 2 + 1;
+  constexpr int Q = (FPB * NB + LOSS_NT - 1) / LOSS_NT;
+  double m4[Q][4];
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    const int idx = threadIdx.x + q * LOSS_NT;
+    if (idx >= FPB * NB) break;
+    const int fl = idx / NB, k = idx % NB;
+    double2 xl, xr;
+    split_pair(buf[fl * N + k], buf[fl * N + ((N - k) & (N - 1))], xl, xr);
+    const double aw = a.tb.aw[k];
+    m4[q][0] = aw * sqrt(xl.x * xl.x + xl.y * xl.y);
+    m4[q][1] = aw * sqrt(xr.x * xr.x + xr.y * xr.y);
+    const double mr = xl.x + xr.x, mi = xl.y + xr.y, sr = xl.x - xr.x, si = xl.y - xr.y;
+    m4[q][2] = aw * sqrt(mr * mr + mi * mi);
+    m4[q][3] = aw * sqrt(sr * sr + si * si);
+  }
+  __syncthreads();
+  double* mag = reinterpret_cast<double*>(buf);
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    const int idx = threadIdx.x + q * LOSS_NT;
+    if (idx >= FPB * NB) break;
+    const int fl = idx / NB, k = idx % NB;
+    double* m = mag + (fl * 4) * NB + k;
+#pragma unroll
+    for (int x = 0; x < 4; ++x) m[x * NB] = m4[q][x];
+  }
+}
+
 template <int N>
 __device__ __forceinline__ double mel_of(const double* mag, const LossArgs& a, int fl, int x, int b) {
   constexpr int NB = N / 2 + 1;
@@ -107,17 +144,16 @@ __device__ __forceinline__ double mel_of(const double* mag, const LossArgs& a, i
 template <int N, int MODE>
 __global__ __launch_bounds__(LOSS_NT) void k_loss_fwd(LossArgs a) {
   constexpr int FPB = loss_fpb<N>();
-  constexpr int NB = N / 2 + 1;
-  __shared__ double2 buf[FPB * N];
+  __shared__ double2 buf[FPB * (N + 2)];   // spectra, then the magnitudes over them
   __shared__ TwTab<N, double2> tt;
   tw_fill<N>(tt, a.tw, (const double2*)nullptr);
-  __shared__ double mag[FPB * 4 * NB];
-  __shared__ double red[LOSS_NT];
+  __shared__ double red[LOSS_NT / 64];
+  const double* mag = reinterpret_cast<const double*>(buf);
   const int f0 = blockIdx.x * FPB;
   load_frames<N>(buf, a, f0);
   __syncthreads();
   fft_lds<N, FPB, N, LOSS_NT, -1>(buf, tt);
-  frame_mags<N>(buf, mag, a);
+  frame_mags_inplace<N>(buf, a);
   __syncthreads();
   double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   const int items = FPB * 4 * a.nm;
