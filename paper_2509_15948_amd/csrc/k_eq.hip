@@ -276,7 +276,10 @@ void eq_spectrum(const Ctx& c, int desc_off, int n) {
 void eq_forward(const Ctx& c, int desc_off, int n, bool keep) {
   EqArgs a = eq_args(c, desc_off, keep);
   {
-    ProfScope ps(c, "eq_conv", (double)n * ((8.0 * EQ_P) * a.nblk + (keep ? 16.0 : 8.0) * c.L + 8.0 * c.L));
+    // reads the input windows (and u for the mix), writes y (and ybar and the
+    // kept window spectra when keeping)
+    ProfScope ps(c, "eq_conv",
+                 (double)n * ((keep ? 16.0 : 8.0) * EQ_P * a.nblk + (keep ? 16.0 : 8.0) * c.L + 8.0 * c.L));
     MG_LAUNCH(c, k_eq_fwd, dim3(a.nblk, n), dim3(EQ_NT), 0, c.st, a);
   }
   launch_reduce_lg(c, desc_off, n, a.nblk);
@@ -285,8 +288,9 @@ void eq_forward(const Ctx& c, int desc_off, int n, bool keep) {
 void eq_backward(const Ctx& c, int desc_off, int n) {
   EqArgs a = eq_args(c, desc_off, true);
   {
-    // reads dL/dy, ybar, u (window each) and u again; writes dL/du and the block FIR gradients
-    ProfScope ps(c, "eq_conv", (double)n * ((24.0 * EQ_P) * a.nblk + 16.0 * c.L + 4.0 * a.N * a.nblk));
+    // reads dL/dy, ybar, u (window each), u again and the kept window spectra;
+    // writes dL/du and the block FIR gradients
+    ProfScope ps(c, "eq_conv", (double)n * ((32.0 * EQ_P) * a.nblk + 16.0 * c.L + 4.0 * a.N * a.nblk));
     MG_LAUNCH(c, k_eq_bwd, dim3(a.nblk, n), dim3(EQ_BNT), 0, c.st, a);
   }
 }
