@@ -31,6 +31,16 @@ constexpr int COL_NT = 1024;
 template <int N1>
 constexpr int row_nt() { return N1 >= 4096 ? 1024 : (N1 >= 1024 ? 512 : 256); }
 
+// the row and column transforms keep one spare LDS slot per 16 points: the
+// first two radix-8 passes then put at most two lanes on a bank where they
+// put eight to sixteen (measured 1.9 % faster per step; the same padding in
+// the equalizer and loss windows measured slower, through register spills
+// and extra index arithmetic)
+constexpr int FFT_PAD = 4;
+template <int N>
+constexpr int pad_len() { return lds_len<N, FFT_PAD>(); }
+__device__ __forceinline__ int px(int i) { return lds_ix<FFT_PAD>(i); }
+
 // W_N^e for e in [0, N) as h (1 + d), from two FP32 tables rounded from FP64
 // on the host: twhi[j] = W_N^{1024 j} and twlo[j] = W_N^j - 1 (small, so the
 // product adds little to the rounding of h).
@@ -250,7 +260,7 @@ struct StGradH {
 // ---------------------------------------------------------------- KA: columns forward
 template <int N2, int TC, typename LD>
 __global__ __launch_bounds__(COL_NT) void k_cols(LD ld, float2* __restrict__ T, EngineArgs ea) {
-  constexpr int BS = N2 + 1;
+  constexpr int BS = pad_len<N2>() + 1;
   __shared__ float2 buf[TC * BS];
   __shared__ TwTab<N2, float2> tt;
   tw_fill<N2>(tt, ea.tw, ea.twdl);
@@ -260,25 +270,25 @@ __global__ __launch_bounds__(COL_NT) void k_cols(LD ld, float2* __restrict__ T, 
   ld.begin(j);
   for (int idx = threadIdx.x; idx < TC * N2; idx += COL_NT) {
     const int n2 = idx / TC, cc = idx % TC;
-    buf[cc * BS + n2] = ld.load((int64_t)(c0 + cc) + (int64_t)N1 * n2);
+    buf[cc * BS + px(n2)] = ld.load((int64_t)(c0 + cc) + (int64_t)N1 * n2);
   }
   ld.end(j, blockIdx.x);
   __syncthreads();
-  fft_lds<N2, TC, BS, COL_NT, -1>(buf, tt);
+  fft_lds<N2, TC, BS, COL_NT, -1, FFT_PAD>(buf, tt);
   float2* Tn = T + (int64_t)j * ea.N;
   const int64_t mask = ea.N - 1;
   for (int idx = threadIdx.x; idx < TC * N2; idx += COL_NT) {
     const int k2 = idx / TC, cc = idx % TC;
     const int n1 = c0 + cc;
     const float2 w = big_tw(ea.twhi, ea.twlo, ((int64_t)n1 * k2) & mask);
-    Tn[(int64_t)k2 * N1 + n1] = c_mul(buf[cc * BS + k2], w);
+    Tn[(int64_t)k2 * N1 + n1] = c_mul(buf[cc * BS + px(k2)], w);
   }
 }
 
 // ---------------------------------------------------------------- KC: columns inverse
 template <int N2, int TC, typename ST>
 __global__ __launch_bounds__(COL_NT) void k_icols(ST st, const float2* __restrict__ T, EngineArgs ea) {
-  constexpr int BS = N2 + 1;
+  constexpr int BS = pad_len<N2>() + 1;
   __shared__ float2 buf[TC * BS];
   __shared__ TwTab<N2, float2> tt;
   tw_fill<N2>(tt, ea.tw, ea.twdl);
@@ -288,15 +298,15 @@ __global__ __launch_bounds__(COL_NT) void k_icols(ST st, const float2* __restric
   const float2* Tn = T + (int64_t)j * ea.N;
   for (int idx = threadIdx.x; idx < TC * N2; idx += COL_NT) {
     const int k2 = idx / TC, cc = idx % TC;
-    buf[cc * BS + k2] = Tn[(int64_t)k2 * N1 + c0 + cc];
+    buf[cc * BS + px(k2)] = Tn[(int64_t)k2 * N1 + c0 + cc];
   }
   __syncthreads();
-  fft_lds<N2, TC, BS, COL_NT, +1>(buf, tt);
+  fft_lds<N2, TC, BS, COL_NT, +1, FFT_PAD>(buf, tt);
   const float sc = 1.0f / (float)ea.N;
   st.begin(j);
   for (int idx = threadIdx.x; idx < TC * N2; idx += COL_NT) {
     const int n2 = idx / TC, cc = idx % TC;
-    st.store((int64_t)(c0 + cc) + (int64_t)N1 * n2, c_scale(buf[cc * BS + n2], sc));
+    st.store((int64_t)(c0 + cc) + (int64_t)N1 * n2, c_scale(buf[cc * BS + px(n2)], sc));
   }
   st.end(j, blockIdx.x);
 }
@@ -341,11 +351,17 @@ __device__ __forceinline__ float2 pack_lr(float2 l, float2 r) {  // l + i r
   return make_float2(l.x - r.y, l.y + r.x);
 }
 
+// LDS slot of element i in [0, 2 N1) of a row pair (row a, then row b)
+template <int N1>
+__device__ __forceinline__ int rslot(int i) {
+  return i < N1 ? px(i) : pad_len<N1>() + px(i - N1);
+}
+
 template <int N1>
 __device__ __forceinline__ void load_rows(float2* buf, const float2* __restrict__ Tn, int ra, int rb) {
   for (int i = threadIdx.x; i < N1; i += blockDim.x) {
-    buf[i] = Tn[(int64_t)ra * N1 + i];
-    buf[N1 + i] = Tn[(int64_t)rb * N1 + i];
+    buf[px(i)] = Tn[(int64_t)ra * N1 + i];
+    buf[pad_len<N1>() + px(i)] = Tn[(int64_t)rb * N1 + i];
   }
 }
 
@@ -356,8 +372,8 @@ __device__ __forceinline__ void store_rows(const float2* buf, float2* __restrict
   for (int i = threadIdx.x; i < N1; i += blockDim.x) {
     float2 wa = big_tw(ea.twhi, ea.twlo, ((int64_t)i * ra) & mask);
     float2 wb = big_tw(ea.twhi, ea.twlo, ((int64_t)i * rb) & mask);
-    To[(int64_t)ra * N1 + i] = c_mul(buf[i], c_conj(wa));
-    To[(int64_t)rb * N1 + i] = c_mul(buf[N1 + i], c_conj(wb));
+    To[(int64_t)ra * N1 + i] = c_mul(buf[px(i)], c_conj(wa));
+    To[(int64_t)rb * N1 + i] = c_mul(buf[pad_len<N1>() + px(i)], c_conj(wb));
   }
 }
 
@@ -365,7 +381,7 @@ __device__ __forceinline__ void store_rows(const float2* buf, float2* __restrict
 template <int N1>
 __global__ __launch_bounds__(row_nt<N1>()) void k_rows_spec(const float2* __restrict__ T, float2* __restrict__ Z,
                                                          int z0, const NodeDesc* __restrict__ desc, EngineArgs ea) {
-  __shared__ float2 buf[2 * N1];
+  __shared__ float2 buf[2 * pad_len<N1>()];
   __shared__ TwTab<N1, float2> tt;
   tw_fill<N1>(tt, ea.tw, ea.twdl);
   const int j = blockIdx.y;
@@ -373,11 +389,11 @@ __global__ __launch_bounds__(row_nt<N1>()) void k_rows_spec(const float2* __rest
   row_pair(blockIdx.x, ea.N2, ra, rb);
   load_rows<N1>(buf, T + (int64_t)j * ea.N, ra, rb);
   __syncthreads();
-  fft_lds<N1, 2, N1, row_nt<N1>(), -1>(buf, tt);
+  fft_lds<N1, 2, pad_len<N1>(), row_nt<N1>(), -1, FFT_PAD>(buf, tt);
   float2* Zn = Z + (int64_t)(z0 + desc[j].aux) * ea.N;
   for (int i = threadIdx.x; i < N1; i += row_nt<N1>()) {
-    Zn[(int64_t)ra * N1 + i] = buf[i];
-    Zn[(int64_t)rb * N1 + i] = buf[N1 + i];
+    Zn[(int64_t)ra * N1 + i] = buf[px(i)];
+    Zn[(int64_t)rb * N1 + i] = buf[pad_len<N1>() + px(i)];
   }
 }
 
@@ -386,7 +402,7 @@ template <int N1>
 __global__ __launch_bounds__(row_nt<N1>()) void k_rows_conv(const float2* __restrict__ Tin, float2* __restrict__ Tout,
                                                          const float2* __restrict__ ZH, float2* __restrict__ ZU,
                                                          int z0, const NodeDesc* __restrict__ desc, EngineArgs ea) {
-  __shared__ float2 buf[2 * N1];
+  __shared__ float2 buf[2 * pad_len<N1>()];
   __shared__ TwTab<N1, float2> tt;
   tw_fill<N1>(tt, ea.tw, ea.twdl);
   const int j = blockIdx.y;
@@ -395,14 +411,14 @@ __global__ __launch_bounds__(row_nt<N1>()) void k_rows_conv(const float2* __rest
   row_pair(p, ea.N2, ra, rb);
   load_rows<N1>(buf, Tin + (int64_t)j * ea.N, ra, rb);
   __syncthreads();
-  fft_lds<N1, 2, N1, row_nt<N1>(), -1>(buf, tt);
+  fft_lds<N1, 2, pad_len<N1>(), row_nt<N1>(), -1, FFT_PAD>(buf, tt);
   const int64_t zr = (int64_t)(z0 + desc[j].aux) * ea.N;
   const float2* H = ZH + zr;
   if (ZU) {  // keep the input spectrum for the backward
     float2* Zs = ZU + zr;
     for (int i = threadIdx.x; i < N1; i += row_nt<N1>()) {
-      Zs[(int64_t)ra * N1 + i] = buf[i];
-      Zs[(int64_t)rb * N1 + i] = buf[N1 + i];
+      Zs[(int64_t)ra * N1 + i] = buf[px(i)];
+      Zs[(int64_t)rb * N1 + i] = buf[pad_len<N1>() + px(i)];
     }
     __syncthreads();  // every bin stored before the product below overwrites it
   }
@@ -411,7 +427,8 @@ __global__ __launch_bounds__(row_nt<N1>()) void k_rows_conv(const float2* __rest
     if (!mirror_pair<N1>(p, q, ia, ib)) continue;
     const int64_t ga = (ia < N1) ? (int64_t)ra * N1 + ia : (int64_t)rb * N1 + (ia - N1);
     const int64_t gb = (ib < N1) ? (int64_t)ra * N1 + ib : (int64_t)rb * N1 + (ib - N1);
-    const float2 za = buf[ia], zb = buf[ib];
+    const int sa = rslot<N1>(ia), sb = rslot<N1>(ib);
+    const float2 za = buf[sa], zb = buf[sb];
     const float2 ha = H[ga], hb = H[gb];
     float2 xl, xr, hl, hr;
     split_lr(za, zb, xl, xr);
@@ -420,11 +437,11 @@ __global__ __launch_bounds__(row_nt<N1>()) void k_rows_conv(const float2* __rest
     split_lr(zb, za, xl, xr);
     split_lr(hb, ha, hl, hr);
     const float2 yb = pack_lr(c_mul(xl, hl), c_mul(xr, hr));
-    buf[ia] = ya;
-    buf[ib] = yb;
+    buf[sa] = ya;
+    buf[sb] = yb;
   }
   __syncthreads();
-  fft_lds<N1, 2, N1, row_nt<N1>(), +1>(buf, tt);
+  fft_lds<N1, 2, pad_len<N1>(), row_nt<N1>(), +1, FFT_PAD>(buf, tt);
   store_rows<N1>(buf, Tout + (int64_t)j * ea.N, ra, rb, ea);
 }
 
@@ -436,18 +453,18 @@ __global__ __launch_bounds__(row_nt<N1>()) void k_rows_bwd(const float2* __restr
                                                         const float2* __restrict__ ZU, int z0,
                                                         const NodeDesc* __restrict__ desc, int want_u,
                                                         EngineArgs ea) {
-  __shared__ float2 buf[4 * N1];
+  __shared__ float2 buf[4 * pad_len<N1>()];
   __shared__ TwTab<N1, float2> tt;
   tw_fill<N1>(tt, ea.tw, ea.twdl);
   float2* b1 = buf;
-  float2* b2 = buf + 2 * N1;
+  float2* b2 = buf + 2 * pad_len<N1>();
   const int j = blockIdx.y;
   const int p = blockIdx.x;
   int ra, rb;
   row_pair(p, ea.N2, ra, rb);
   load_rows<N1>(b1, Tin + (int64_t)j * ea.N, ra, rb);
   __syncthreads();
-  fft_lds<N1, 2, N1, row_nt<N1>(), -1>(b1, tt);
+  fft_lds<N1, 2, pad_len<N1>(), row_nt<N1>(), -1, FFT_PAD>(b1, tt);
   const int64_t zr = (int64_t)(z0 + desc[j].aux) * ea.N;
   const float2* H = ZH + zr;
   const float2* X = ZU + zr;
@@ -456,7 +473,8 @@ __global__ __launch_bounds__(row_nt<N1>()) void k_rows_bwd(const float2* __restr
     if (!mirror_pair<N1>(p, q, ia, ib)) continue;
     const int64_t ga = (ia < N1) ? (int64_t)ra * N1 + ia : (int64_t)rb * N1 + (ia - N1);
     const int64_t gb = (ib < N1) ? (int64_t)ra * N1 + ib : (int64_t)rb * N1 + (ib - N1);
-    const float2 za = b1[ia], zb = b1[ib];
+    const int sa = rslot<N1>(ia), sb = rslot<N1>(ib);
+    const float2 za = b1[sa], zb = b1[sb];
     const float2 ha = H[ga], hb = H[gb];
     const float2 xa = X[ga], xb = X[gb];
     float2 gl, gr, hl, hr, xl, xr;
@@ -472,17 +490,17 @@ __global__ __launch_bounds__(row_nt<N1>()) void k_rows_bwd(const float2* __restr
     split_lr(xb, xa, xl, xr);
     const float2 u_b = pack_lr(c_mulc(gl, hl), c_mulc(gr, hr));
     const float2 h_b = pack_lr(c_mulc(gl, xl), c_mulc(gr, xr));
-    b1[ia] = u_a;
-    b1[ib] = u_b;
-    b2[ia] = h_a;
-    b2[ib] = h_b;
+    b1[sa] = u_a;
+    b1[sb] = u_b;
+    b2[sa] = h_a;
+    b2[sb] = h_b;
   }
   __syncthreads();
   if (want_u) {
-    fft_lds<N1, 2, N1, row_nt<N1>(), +1>(b1, tt);
+    fft_lds<N1, 2, pad_len<N1>(), row_nt<N1>(), +1, FFT_PAD>(b1, tt);
     store_rows<N1>(b1, Tu + (int64_t)j * ea.N, ra, rb, ea);
   }
-  fft_lds<N1, 2, N1, row_nt<N1>(), +1>(b2, tt);
+  fft_lds<N1, 2, pad_len<N1>(), row_nt<N1>(), +1, FFT_PAD>(b2, tt);
   store_rows<N1>(b2, Th + (int64_t)j * ea.N, ra, rb, ea);
 }
 

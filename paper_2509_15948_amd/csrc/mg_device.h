@@ -123,7 +123,20 @@ __device__ __forceinline__ void dft4(V& x0, V& x1, V& x2, V& x3) {
   x3 = c_sub(t1, t3);
 }
 
-template <int N, int R, int B, int BS, int NT, int DIR, typename V>
+// LDS slot of element i of a transform stored with one spare slot after every
+// 2^PAD elements (PAD = 0: no padding).  The early Stockham passes write with
+// strides of 8 and 64 elements, which would put many lanes of a wave on the
+// same LDS banks; the spare slots spread them.
+template <int PAD>
+__device__ __forceinline__ int lds_ix(int i) {
+  return PAD ? i + (i >> PAD) : i;
+}
+template <int N, int PAD>
+constexpr int lds_len() {
+  return PAD ? N + (N >> PAD) : N;
+}
+
+template <int N, int R, int B, int BS, int NT, int DIR, int PAD, typename V>
 __device__ __forceinline__ void fft_pass(V* buf, const TwTab<N, V>& tw, int Ns) {
   constexpr int Q = N / R;
   constexpr int NB = B * Q;
@@ -137,7 +150,7 @@ __device__ __forceinline__ void fft_pass(V* buf, const TwTab<N, V>& tw, int Ns) 
       const int b = g / Q, j = g % Q;
       const V* base = buf + b * BS;
 #pragma unroll
-      for (int r = 0; r < R; ++r) v[q][r] = base[j + r * Q];
+      for (int r = 0; r < R; ++r) v[q][r] = base[lds_ix<PAD>(j + r * Q)];
     }
   }
   __syncthreads();
@@ -155,12 +168,12 @@ __device__ __forceinline__ void fft_pass(V* buf, const TwTab<N, V>& tw, int Ns) 
     V* base = buf + b * BS;
     const int idx = (j - k) * R + k;
     if (R == 2) {
-      base[idx] = c_add(v[q][0], v[q][1]);
-      base[idx + Ns] = c_sub(v[q][0], v[q][1]);
+      base[lds_ix<PAD>(idx)] = c_add(v[q][0], v[q][1]);
+      base[lds_ix<PAD>(idx + Ns)] = c_sub(v[q][0], v[q][1]);
     } else if (R == 4) {
       dft4<DIR>(v[q][0], v[q][1], v[q][2], v[q][3]);
 #pragma unroll
-      for (int r = 0; r < 4; ++r) base[idx + r * Ns] = v[q][r];
+      for (int r = 0; r < 4; ++r) base[lds_ix<PAD>(idx + r * Ns)] = v[q][r];
     } else {  // R == 8: radix-2 step, then two 4-point DFTs (even and odd outputs)
       using S = decltype(v[q][0].x);
       const S h = (S)0.70710678118654752440;
@@ -186,8 +199,8 @@ __device__ __forceinline__ void fft_pass(V* buf, const TwTab<N, V>& tw, int Ns) 
       dft4<DIR>(c[0], c[1], c[2], c[3]);
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        base[idx + (2 * r) * Ns] = a[r];
-        base[idx + (2 * r + 1) * Ns] = c[r];
+        base[lds_ix<PAD>(idx + (2 * r) * Ns)] = a[r];
+        base[lds_ix<PAD>(idx + (2 * r + 1) * Ns)] = c[r];
       }
     }
   }
@@ -197,20 +210,22 @@ __device__ __forceinline__ void fft_pass(V* buf, const TwTab<N, V>& tw, int Ns) 
 // B unnormalised transforms of length N (4 <= N <= MG_TWN), in place in LDS:
 // radix-8 passes, then one radix-4 or radix-2 pass for the remaining factor.
 // DIR = -1: X[k] = sum x[n] e^{-2 pi i nk/N};  DIR = +1: the inverse sign.
-// V is float2 or double2 (with twiddle tables of the same type).
+// V is float2 or double2 (with twiddle tables of the same type).  Element i
+// of transform b sits at buf[b * BS + lds_ix<PAD>(i)] (BS >= lds_len<N, PAD>).
 // The caller must __syncthreads() after filling buf and tw.
-template <int N, int B, int BS, int NT, int DIR, typename V>
+template <int N, int B, int BS, int NT, int DIR, int PAD = 0, typename V>
 __device__ __forceinline__ void fft_lds(V* buf, const TwTab<N, V>& tw) {
   constexpr int LOG = ilog2c(N);
   static_assert((1 << LOG) == N, "power of two");
+  static_assert(B == 1 || BS >= lds_len<N, PAD>(), "transforms overlap");
   int Ns = 1;
 #pragma unroll
   for (int p = 0; p < LOG / 3; ++p) {
-    fft_pass<N, 8, B, BS, NT, DIR>(buf, tw, Ns);
+    fft_pass<N, 8, B, BS, NT, DIR, PAD>(buf, tw, Ns);
     Ns *= 8;
   }
-  if (LOG % 3 == 2) fft_pass<N, 4, B, BS, NT, DIR>(buf, tw, Ns);
-  if (LOG % 3 == 1) fft_pass<N, 2, B, BS, NT, DIR>(buf, tw, Ns);
+  if (LOG % 3 == 2) fft_pass<N, 4, B, BS, NT, DIR, PAD>(buf, tw, Ns);
+  if (LOG % 3 == 1) fft_pass<N, 2, B, BS, NT, DIR, PAD>(buf, tw, Ns);
 }
 
 // Fixed-order sum over the workgroup; every thread gets the result.  Each
