@@ -11,6 +11,7 @@
 // The adjoint recomputes each frame, forms dL/dX per bin, packs the two
 // channel gradients into one Hermitian-split spectrum, inverse transforms it
 // and windows it; a gather kernel overlap-adds the four frames per sample.
+#include <algorithm>
 #include <cstring>
 #include <vector>
 
@@ -140,16 +141,39 @@ __device__ __forceinline__ double mel_of(const double* mag, const LossArgs& a, i
   return yh;
 }
 
-// MODE 0: target features (write tgt, partial sum Y^2); MODE 1: loss partials
+// LDS of one frame workgroup, in bytes: forward = spectra (the magnitudes
+// are written over them), twiddles, block-sum slots; backward = spectra,
+// twiddles, magnitudes, dL/dYh per (frame, combo, band)
+template <int N>
+constexpr int loss_fwd_lds() {
+  return loss_fpb<N>() * (N + 2) * 16 + (int)sizeof(TwTab<N, double2>) + LOSS_NT / 64 * 8;
+}
+template <int N>
+constexpr int loss_bwd_lds() {
+  return loss_fpb<N>() * N * 16 + (int)sizeof(TwTab<N, double2>) + loss_fpb<N>() * 4 * (N / 2 + 1) * 8 +
+         loss_fpb<N>() * 4 * 128 * 8;
+}
+constexpr int cmax(int x, int y) { return x > y ? x : y; }
+// the largest over the sizes 256 .. NMAX
+template <int NMAX, bool FWD>
+constexpr int loss_lds_max() {
+  const int here = FWD ? loss_fwd_lds<NMAX>() : loss_bwd_lds<NMAX>();
+  if constexpr (NMAX <= 256) return here;
+  else return cmax(here, loss_lds_max<NMAX / 2, FWD>());
+}
+
+// MODE 0: target features (write tgt, partial sum Y^2); MODE 1: loss partials.
+// blk: the workgroup's index within its resolution; smem: loss_fwd_lds<N>()
+// bytes of LDS (16-byte aligned)
 template <int N, int MODE>
-__global__ __launch_bounds__(LOSS_NT) void k_loss_fwd(LossArgs a) {
+__device__ __forceinline__ void loss_fwd_body(const LossArgs& a, int blk, double2* smem) {
   constexpr int FPB = loss_fpb<N>();
-  __shared__ double2 buf[FPB * (N + 2)];   // spectra, then the magnitudes over them
-  __shared__ TwTab<N, double2> tt;
+  double2* buf = smem;   // spectra, then the magnitudes over them
+  TwTab<N, double2>& tt = *reinterpret_cast<TwTab<N, double2>*>(smem + FPB * (N + 2));
+  double* red = reinterpret_cast<double*>(reinterpret_cast<char*>(&tt) + sizeof(TwTab<N, double2>));
   tw_fill<N>(tt, a.tw, (const double2*)nullptr);
-  __shared__ double red[LOSS_NT / 64];
   const double* mag = reinterpret_cast<const double*>(buf);
-  const int f0 = blockIdx.x * FPB;
+  const int f0 = blk * FPB;
   load_frames<N>(buf, a, f0);
   __syncthreads();
   fft_lds<N, FPB, N, LOSS_NT, -1>(buf, tt);
@@ -175,7 +199,7 @@ __global__ __launch_bounds__(LOSS_NT) void k_loss_fwd(LossArgs a) {
   }
   for (int k = 0; k < 8; ++k) {
     const double s = block_sum<LOSS_NT>(acc[k], red);
-    if (threadIdx.x == 0) a.part[(int64_t)blockIdx.x * 8 + k] = s;
+    if (threadIdx.x == 0) a.part[(int64_t)blk * 8 + k] = s;
   }
 }
 
@@ -219,17 +243,18 @@ __global__ __launch_bounds__(MG_BLOCK) void k_loss_reduce(ReduceArgs ra) {
   }
 }
 
-// per frame: dL/dy for the frame's samples (windowed), to scratch [F][N][2]
+// per frame: dL/dy for the frame's samples (windowed), to scratch [F][N][2];
+// blk and smem (loss_bwd_lds<N>() bytes) as in the forward
 template <int N>
-__global__ __launch_bounds__(LOSS_NT) void k_loss_bwd(LossArgs a) {
+__device__ __forceinline__ void loss_bwd_body(const LossArgs& a, int blk, double2* smem) {
   constexpr int FPB = loss_fpb<N>();
   constexpr int NB = N / 2 + 1;
-  __shared__ double2 buf[FPB * N];
-  __shared__ TwTab<N, double2> tt;
+  double2* buf = smem;
+  TwTab<N, double2>& tt = *reinterpret_cast<TwTab<N, double2>*>(smem + FPB * N);
+  double* mag = reinterpret_cast<double*>(reinterpret_cast<char*>(&tt) + sizeof(TwTab<N, double2>));
+  double* dyh = mag + FPB * 4 * NB;
   tw_fill<N>(tt, a.tw, (const double2*)nullptr);
-  __shared__ double mag[FPB * 4 * NB];
-  __shared__ double dyh[FPB * 4 * 128];
-  const int f0 = blockIdx.x * FPB;
+  const int f0 = blk * FPB;
   load_frames<N>(buf, a, f0);
   __syncthreads();
   fft_lds<N, FPB, N, LOSS_NT, -1>(buf, tt);
@@ -335,6 +360,54 @@ __global__ __launch_bounds__(MG_BLOCK) void k_loss_gather(GatherArgs a) {
     }
     a.out[n] = sl;
     a.out[a.L + n] = sr;
+  }
+}
+
+// Several resolutions in one launch: workgroup b belongs to resolution i
+// when first[i] <= b < first[i + 1] and runs the frame body of that size.
+// One grid for all of them needs no second stream (no fork and join on the
+// caller's queue) and lets the short transforms fill the long ones' tail.
+struct LossMulti {
+  LossArgs a[8];
+  int first[9];
+  int nfft[8];
+  int nres;
+};
+
+__device__ __forceinline__ int multi_res(const LossMulti& m, int& blk) {
+  int i = 0;
+  while (i + 1 < m.nres && (int)blockIdx.x >= m.first[i + 1]) ++i;
+  blk = (int)blockIdx.x - m.first[i];
+  return i;
+}
+
+template <int NMAX, int MODE>
+__global__ __launch_bounds__(LOSS_NT) void k_loss_fwd_multi(LossMulti m) {
+  __shared__ double2 smem[loss_lds_max<NMAX, true>() / 16 + 1];
+  int blk;
+  const int i = multi_res(m, blk);
+  switch (m.nfft[i]) {
+#define MG_FB(NN)                                                \
+  case NN:                                                       \
+    if constexpr (NN <= NMAX) loss_fwd_body<NN, MODE>(m.a[i], blk, smem); \
+    break;
+    MG_FB(256) MG_FB(512) MG_FB(1024) MG_FB(2048) MG_FB(4096)
+#undef MG_FB
+  }
+}
+
+template <int NMAX>
+__global__ __launch_bounds__(LOSS_NT) void k_loss_bwd_multi(LossMulti m) {
+  __shared__ double2 smem[loss_lds_max<NMAX, false>() / 16 + 1];
+  int blk;
+  const int i = multi_res(m, blk);
+  switch (m.nfft[i]) {
+#define MG_BB(NN)                                                \
+  case NN:                                                       \
+    if constexpr (NN <= NMAX) loss_bwd_body<NN>(m.a[i], blk, smem); \
+    break;
+    MG_BB(256) MG_BB(512) MG_BB(1024) MG_BB(2048) MG_BB(4096)
+#undef MG_BB
   }
 }
 
@@ -459,13 +532,18 @@ static LossArgs loss_args(const Ctx& c, int i, const float* y) {
   return a;
 }
 
-template <int N, int MODE>
-static void fwd_n(const Ctx& c, const LossArgs& a, int blocks) {
-  MG_LAUNCH(c, (k_loss_fwd<N, MODE>), dim3(blocks), dim3(LOSS_NT), 0, c.st, a);
+// The resolutions up to 2048 points share one launch (the 4096-point body
+// needs more registers and LDS, which would halve the short ones' occupancy);
+// larger ones get a launch of their own, on the same stream.
+constexpr int LOSS_SPLIT_N = 2048;
+
+template <int NMAX, int MODE>
+static void fwd_multi(const Ctx& c, const LossMulti& m) {
+  MG_LAUNCH(c, (k_loss_fwd_multi<NMAX, MODE>), dim3(m.first[m.nres]), dim3(LOSS_NT), 0, c.st, m);
 }
-template <int N>
-static void bwd_n(const Ctx& c, const LossArgs& a, int blocks) {
-  MG_LAUNCH(c, k_loss_bwd<N>, dim3(blocks), dim3(LOSS_NT), 0, c.st, a);
+template <int NMAX>
+static void bwd_multi(const Ctx& c, const LossMulti& m) {
+  MG_LAUNCH(c, k_loss_bwd_multi<NMAX>, dim3(m.first[m.nres]), dim3(LOSS_NT), 0, c.st, m);
 }
 
 #define MG_LOSS_SWITCH(N_, CALL)   \
@@ -477,25 +555,24 @@ static void bwd_n(const Ctx& c, const LossArgs& a, int blocks) {
     case 4096: CALL(4096); break;  \
   }
 
-// The resolutions are independent: odd ones run on the side stream (forked
-// from and joined back to the caller's stream), which fills the tail of each
-// frame kernel with the next one's blocks.
-constexpr int EV_LOSS_FORK = 62, EV_LOSS_JOIN = 63;
-
-static bool loss_fork(const Ctx& c, Ctx& cs) {
-  const mg_graph* g = c.g;
-  if (!g->side || g->sev.size() < 64 || g->lres.size() < 2) return false;
-  cs = c;
-  cs.st = g->side;
-  hipEventRecord(g->sev[EV_LOSS_FORK], c.st);
-  hipStreamWaitEvent(g->side, g->sev[EV_LOSS_FORK], 0);
-  return true;
-}
-
-static void loss_join(const Ctx& c) {
-  const mg_graph* g = c.g;
-  hipEventRecord(g->sev[EV_LOSS_JOIN], g->side);
-  hipStreamWaitEvent(c.st, g->sev[EV_LOSS_JOIN], 0);
+// launch groups: every resolution in [lo, hi] points, with its args from
+// args_of(i); fills the group's grid layout and returns its largest size
+template <typename F>
+static int loss_group(const mg_graph* g, int lo, int hi, LossMulti& m, F args_of) {
+  m.nres = 0;
+  m.first[0] = 0;
+  int nmax = 0;
+  for (size_t i = 0; i < g->lres.size(); ++i) {
+    const LossRes& r = g->lres[i];
+    if (r.nfft < lo || r.nfft > hi) continue;
+    const int FPB = loss_frames_per_block(r.nfft);
+    const int k = m.nres++;
+    m.a[k] = args_of((int)i);
+    m.nfft[k] = r.nfft;
+    m.first[k + 1] = m.first[k] + (r.frames + FPB - 1) / FPB;
+    nmax = std::max(nmax, r.nfft);
+  }
+  return nmax;
 }
 
 static void run_loss_fwd(const Ctx& c, const float* y, int mode, double* stats_out) {
@@ -503,30 +580,30 @@ static void run_loss_fwd(const Ctx& c, const float* y, int mode, double* stats_o
   double* stats = stats_out ? stats_out : wsp<double>(c, g->ws.ls_stats);
   ReduceArgs ra;
   ra.mode = mode;
-  Ctx cs;
-  const bool forked = loss_fork(c, cs);
   for (size_t i = 0; i < g->lres.size(); ++i) {
     const LossRes& r = g->lres[i];
-    const Ctx& cc = (forked && (i & 1)) ? cs : c;
-    LossArgs a = loss_args(c, (int)i, y);
     const int FPB = loss_frames_per_block(r.nfft);
-    const int blocks = (r.frames + FPB - 1) / FPB;
-#define MG_F0(NN) fwd_n<NN, 0>(cc, a, blocks)
-#define MG_F1(NN) fwd_n<NN, 1>(cc, a, blocks)
-    if (mode == 0) {
-      MG_LOSS_SWITCH(r.nfft, MG_F0)
-    } else {
-      MG_LOSS_SWITCH(r.nfft, MG_F1)
-    }
-#undef MG_F0
-#undef MG_F1
-    ra.part[i] = a.part;
-    ra.nblocks[i] = blocks;
+    ra.part[i] = (double*)(c.base + r.part_off);
+    ra.nblocks[i] = (r.frames + FPB - 1) / FPB;
     ra.cells[i] = r.frames * g->cfg.n_mels;
     ra.stats[i] = stats + i * 16;
     ra.tgt[i] = wsp<double>(c, g->ws.ls_stats) + i * 16;
   }
-  if (forked) loss_join(c);
+  const int groups[2][2] = {{0, LOSS_SPLIT_N}, {LOSS_SPLIT_N + 1, 1 << 30}};
+  for (const auto& gr : groups) {
+    LossMulti m;
+    const int nmax = loss_group(g, gr[0], gr[1], m, [&](int i) { return loss_args(c, i, y); });
+    if (m.nres == 0) continue;
+#define MG_F0(NN) fwd_multi<NN, 0>(c, m)
+#define MG_F1(NN) fwd_multi<NN, 1>(c, m)
+    if (mode == 0) {
+      MG_LOSS_SWITCH(nmax, MG_F0)
+    } else {
+      MG_LOSS_SWITCH(nmax, MG_F1)
+    }
+#undef MG_F0
+#undef MG_F1
+  }
   MG_LAUNCH(c, k_loss_reduce, dim3((unsigned)g->lres.size()), dim3(MG_BLOCK), 0, c.st, ra);
 }
 
@@ -555,26 +632,31 @@ void loss_backward(const Ctx& c, const float* yhat, float* dyhat) {
   ga.skip = g->cfg.loss_skip;
   ga.L = c.L;
   ga.out = dyhat;
+  // per-resolution dL/dy frames, one after another in the scratch area
+  std::vector<float*> scratch(g->lres.size());
   size_t off = g->ws.ls_part;
-  Ctx cs;
-  const bool forked = loss_fork(c, cs);
   for (size_t i = 0; i < g->lres.size(); ++i) {
     const LossRes& r = g->lres[i];
-    const Ctx& cc = (forked && (i & 1)) ? cs : c;
-    LossArgs a = loss_args(c, (int)i, yhat);
-    a.scratch = (float*)(c.base + off);
-    const int FPB = loss_frames_per_block(r.nfft);
-    const int blocks = (r.frames + FPB - 1) / FPB;
-#define MG_B(NN) bwd_n<NN>(cc, a, blocks)
-    MG_LOSS_SWITCH(r.nfft, MG_B)
-#undef MG_B
-    ga.r[i].scratch = a.scratch;
+    scratch[i] = (float*)(c.base + off);
+    ga.r[i].scratch = scratch[i];
     ga.r[i].N = r.nfft;
     ga.r[i].hop = r.hop;
     ga.r[i].F = r.frames;
     off += (((size_t)r.frames * r.nfft * 2 * 4) + 255) / 256 * 256;
   }
-  if (forked) loss_join(c);
+  const int groups[2][2] = {{0, LOSS_SPLIT_N}, {LOSS_SPLIT_N + 1, 1 << 30}};
+  for (const auto& gr : groups) {
+    LossMulti m;
+    const int nmax = loss_group(g, gr[0], gr[1], m, [&](int i) {
+      LossArgs a = loss_args(c, i, yhat);
+      a.scratch = scratch[i];
+      return a;
+    });
+    if (m.nres == 0) continue;
+#define MG_B(NN) bwd_multi<NN>(c, m)
+    MG_LOSS_SWITCH(nmax, MG_B)
+#undef MG_B
+  }
   int64_t blocks = (c.L + MG_BLOCK - 1) / MG_BLOCK;
   if (blocks > 2048) blocks = 2048;
   MG_LAUNCH(c, k_loss_gather, dim3((unsigned)blocks), dim3(MG_BLOCK), 0, c.st, ga);

@@ -64,8 +64,12 @@ static size_t plan_ws(mg_graph& g, int mode, bool commit) {
     take(w.T1s, (size_t)g.max_conv_stage * N * 8);  // FIR spectra on the side stream
     take(w.T2, (size_t)g.max_conv_stage * N * 8);
     if (mode) {
-      take(w.T3, (size_t)g.max_conv_stage * N * 8);
-      take(w.T3b, (size_t)g.max_conv_stage * N * 8);  // alternate stages: the side stream may still read T3
+      // FIR-gradient spectra, one row per node of every long-FIR stage: the
+      // side stream reads a stage's rows while later stages write their own
+      size_t conv_nodes = 0;
+      for (const Stage& S : g.stages)
+        if (S.type == MG_DELAY || S.type == MG_REVERB) conv_nodes += S.nodes.size();
+      take(w.T3, std::max<size_t>(1, conv_nodes) * N * 8);
     }
     take(w.twhi, (size_t)std::max<int64_t>(1, N / 1024) * 8);
     take(w.twlo, 1024 * 8);
@@ -462,9 +466,9 @@ extern "C" int mg_backward(mg_graph* g, float* grad_theta, float* grad_wet, void
   // The input-gradient chain stays on the caller's stream; each FIR stage's
   // parameter-gradient work (FIR-gradient inverse columns, block sums, the
   // adjoints back to the raw parameters) is handed to the side stream after
-  // an event, so it overlaps the next stages.  Long-FIR stages alternate
-  // between two FIR-gradient spectra (T3, T3b); a stage waits until the side
-  // stream has read the buffer it is about to overwrite.
+  // an event, so it overlaps the next stages.  Every long-FIR stage has FIR-
+  // gradient spectrum rows of its own, so the caller's stream never waits on
+  // the side stream before the join.
   Ctx cs = c;
   cs.st = g->side;
   int ev = 0;
@@ -473,8 +477,7 @@ extern "C" int mg_backward(mg_graph* g, float* grad_theta, float* grad_wet, void
     hipStreamWaitEvent(g->side, g->sev[ev], 0);
     ev = (ev + 1) % (int)g->sev.size();
   };
-  hipEvent_t t3_done[2] = {nullptr, nullptr};
-  int n_conv = 0;
+  size_t t3_row = 0;   // first FIR-gradient spectrum row of the next long-FIR stage
   // the first FIR stage of the schedule is the last one here: nothing on the
   // caller's stream is left to overlap its FIR-gradient work, so it stays there
   size_t last_fir = 0;
@@ -512,15 +515,11 @@ extern "C" int mg_backward(mg_graph* g, float* grad_theta, float* grad_wet, void
       eq_backward_fir(cf, off, n);
       fir_adjoint(cf, t, off, n, grad_theta);
     } else if (is_conv(t)) {
-      const int b = n_conv++ & 1;
-      float2* T3 = (float2*)(g->base + (b ? g->ws.T3b : g->ws.T3));
-      if (t3_done[b]) hipStreamWaitEvent(st, t3_done[b], 0);
+      float2* T3 = (float2*)(g->base + g->ws.T3) + t3_row * (size_t)g->fft.N;
+      t3_row += (size_t)n;
       conv_backward(c, t, off, n, T3);
       fork();
       conv_backward_fir(cs, t, off, n, T3);
-      t3_done[b] = g->sev[ev];
-      hipEventRecord(t3_done[b], g->side);
-      ev = (ev + 1) % (int)g->sev.size();
       fir_adjoint(cs, t, off, n, grad_theta);
     }
     // processors with several predecessors: every predecessor's dL/dy is

@@ -61,7 +61,7 @@ struct WsPlan {
   size_t total = 0;
   size_t desc = 0, srcs = 0;
   size_t U = 0, YB = 0, ENV = 0, G = 0;
-  size_t ZU = 0, ZH = 0, T1 = 0, T1s = 0, T2 = 0, T3 = 0, T3b = 0;
+  size_t ZU = 0, ZH = 0, T1 = 0, T1s = 0, T2 = 0, T3 = 0;
   size_t tw = 0, twd = 0, twdl = 0, twhi = 0, twlo = 0;
   size_t eq_h = 0, eq_dh = 0, eq_cos = 0, eq_HP = 0, eq_dhp = 0, eq_XU = 0;
   size_t dl_tab = 0, dl_h = 0, dl_dh = 0, dl_cos = 0, dl_zp = 0;
