@@ -31,15 +31,19 @@ constexpr int COL_NT = 1024;
 template <int N1>
 constexpr int row_nt() { return N1 >= 4096 ? 1024 : (N1 >= 1024 ? 512 : 256); }
 
-// the row and column transforms keep one spare LDS slot per 16 points: the
-// first two radix-8 passes then put at most two lanes on a bank where they
-// put eight to sixteen (measured 1.9 % faster per step; the same padding in
-// the equalizer and loss windows measured slower, through register spills
-// and extra index arithmetic)
-constexpr int FFT_PAD = 4;
-template <int N>
-constexpr int pad_len() { return lds_len<N, FFT_PAD>(); }
-__device__ __forceinline__ int px(int i) { return lds_ix<FFT_PAD>(i); }
+// Row transforms up to 2048 points and column transforms up to 256 keep one
+// spare LDS slot per 16 points: the first two radix-8 passes then put at most
+// two lanes on a bank where they put eight to sixteen (1.9 % faster per step
+// at 2^19 points).  The longer transforms of a 2^22-point engine stay
+// unpadded: there the larger blocks left less LDS to the other stream's
+// kernels and the step measured 4 % slower.  The equalizer and loss windows
+// stay unpadded too (register spills, extra index arithmetic: slower).
+template <int N, bool ROW>
+constexpr int eng_pad() { return (ROW ? N <= 2048 : N <= 256) ? 4 : 0; }
+template <int N, bool ROW>
+constexpr int pad_len() { return lds_len<N, eng_pad<N, ROW>()>(); }
+template <int N, bool ROW>
+__device__ __forceinline__ int px(int i) { return lds_ix<eng_pad<N, ROW>()>(i); }
 
 // W_N^e for e in [0, N) as h (1 + d), from two FP32 tables rounded from FP64
 // on the host: twhi[j] = W_N^{1024 j} and twlo[j] = W_N^j - 1 (small, so the
@@ -260,7 +264,7 @@ struct StGradH {
 // ---------------------------------------------------------------- KA: columns forward
 template <int N2, int TC, typename LD>
 __global__ __launch_bounds__(COL_NT) void k_cols(LD ld, float2* __restrict__ T, EngineArgs ea) {
-  constexpr int BS = pad_len<N2>() + 1;
+  constexpr int BS = pad_len<N2, false>() + 1;
   __shared__ float2 buf[TC * BS];
   __shared__ TwTab<N2, float2> tt;
   tw_fill<N2>(tt, ea.tw, ea.twdl);
@@ -270,25 +274,25 @@ __global__ __launch_bounds__(COL_NT) void k_cols(LD ld, float2* __restrict__ T, 
   ld.begin(j);
   for (int idx = threadIdx.x; idx < TC * N2; idx += COL_NT) {
     const int n2 = idx / TC, cc = idx % TC;
-    buf[cc * BS + px(n2)] = ld.load((int64_t)(c0 + cc) + (int64_t)N1 * n2);
+    buf[cc * BS + px<N2, false>(n2)] = ld.load((int64_t)(c0 + cc) + (int64_t)N1 * n2);
   }
   ld.end(j, blockIdx.x);
   __syncthreads();
-  fft_lds<N2, TC, BS, COL_NT, -1, FFT_PAD>(buf, tt);
+  fft_lds<N2, TC, BS, COL_NT, -1, eng_pad<N2, false>()>(buf, tt);
   float2* Tn = T + (int64_t)j * ea.N;
   const int64_t mask = ea.N - 1;
   for (int idx = threadIdx.x; idx < TC * N2; idx += COL_NT) {
     const int k2 = idx / TC, cc = idx % TC;
     const int n1 = c0 + cc;
     const float2 w = big_tw(ea.twhi, ea.twlo, ((int64_t)n1 * k2) & mask);
-    Tn[(int64_t)k2 * N1 + n1] = c_mul(buf[cc * BS + px(k2)], w);
+    Tn[(int64_t)k2 * N1 + n1] = c_mul(buf[cc * BS + px<N2, false>(k2)], w);
   }
 }
 
 // ---------------------------------------------------------------- KC: columns inverse
 template <int N2, int TC, typename ST>
 __global__ __launch_bounds__(COL_NT) void k_icols(ST st, const float2* __restrict__ T, EngineArgs ea) {
-  constexpr int BS = pad_len<N2>() + 1;
+  constexpr int BS = pad_len<N2, false>() + 1;
   __shared__ float2 buf[TC * BS];
   __shared__ TwTab<N2, float2> tt;
   tw_fill<N2>(tt, ea.tw, ea.twdl);
@@ -298,15 +302,15 @@ __global__ __launch_bounds__(COL_NT) void k_icols(ST st, const float2* __restric
   const float2* Tn = T + (int64_t)j * ea.N;
   for (int idx = threadIdx.x; idx < TC * N2; idx += COL_NT) {
     const int k2 = idx / TC, cc = idx % TC;
-    buf[cc * BS + px(k2)] = Tn[(int64_t)k2 * N1 + c0 + cc];
+    buf[cc * BS + px<N2, false>(k2)] = Tn[(int64_t)k2 * N1 + c0 + cc];
   }
   __syncthreads();
-  fft_lds<N2, TC, BS, COL_NT, +1, FFT_PAD>(buf, tt);
+  fft_lds<N2, TC, BS, COL_NT, +1, eng_pad<N2, false>()>(buf, tt);
   const float sc = 1.0f / (float)ea.N;
   st.begin(j);
   for (int idx = threadIdx.x; idx < TC * N2; idx += COL_NT) {
     const int n2 = idx / TC, cc = idx % TC;
-    st.store((int64_t)(c0 + cc) + (int64_t)N1 * n2, c_scale(buf[cc * BS + px(n2)], sc));
+    st.store((int64_t)(c0 + cc) + (int64_t)N1 * n2, c_scale(buf[cc * BS + px<N2, false>(n2)], sc));
   }
   st.end(j, blockIdx.x);
 }
@@ -354,14 +358,14 @@ __device__ __forceinline__ float2 pack_lr(float2 l, float2 r) {  // l + i r
 // LDS slot of element i in [0, 2 N1) of a row pair (row a, then row b)
 template <int N1>
 __device__ __forceinline__ int rslot(int i) {
-  return i < N1 ? px(i) : pad_len<N1>() + px(i - N1);
+  return i < N1 ? px<N1, true>(i) : pad_len<N1, true>() + px<N1, true>(i - N1);
 }
 
 template <int N1>
 __device__ __forceinline__ void load_rows(float2* buf, const float2* __restrict__ Tn, int ra, int rb) {
   for (int i = threadIdx.x; i < N1; i += blockDim.x) {
-    buf[px(i)] = Tn[(int64_t)ra * N1 + i];
-    buf[pad_len<N1>() + px(i)] = Tn[(int64_t)rb * N1 + i];
+    buf[px<N1, true>(i)] = Tn[(int64_t)ra * N1 + i];
+    buf[pad_len<N1, true>() + px<N1, true>(i)] = Tn[(int64_t)rb * N1 + i];
   }
 }
 
@@ -372,8 +376,8 @@ __device__ __forceinline__ void store_rows(const float2* buf, float2* __restrict
   for (int i = threadIdx.x; i < N1; i += blockDim.x) {
     float2 wa = big_tw(ea.twhi, ea.twlo, ((int64_t)i * ra) & mask);
     float2 wb = big_tw(ea.twhi, ea.twlo, ((int64_t)i * rb) & mask);
-    To[(int64_t)ra * N1 + i] = c_mul(buf[px(i)], c_conj(wa));
-    To[(int64_t)rb * N1 + i] = c_mul(buf[pad_len<N1>() + px(i)], c_conj(wb));
+    To[(int64_t)ra * N1 + i] = c_mul(buf[px<N1, true>(i)], c_conj(wa));
+    To[(int64_t)rb * N1 + i] = c_mul(buf[pad_len<N1, true>() + px<N1, true>(i)], c_conj(wb));
   }
 }
 
@@ -381,7 +385,7 @@ __device__ __forceinline__ void store_rows(const float2* buf, float2* __restrict
 template <int N1>
 __global__ __launch_bounds__(row_nt<N1>()) void k_rows_spec(const float2* __restrict__ T, float2* __restrict__ Z,
                                                          int z0, const NodeDesc* __restrict__ desc, EngineArgs ea) {
-  __shared__ float2 buf[2 * pad_len<N1>()];
+  __shared__ float2 buf[2 * pad_len<N1, true>()];
   __shared__ TwTab<N1, float2> tt;
   tw_fill<N1>(tt, ea.tw, ea.twdl);
   const int j = blockIdx.y;
@@ -389,11 +393,11 @@ __global__ __launch_bounds__(row_nt<N1>()) void k_rows_spec(const float2* __rest
   row_pair(blockIdx.x, ea.N2, ra, rb);
   load_rows<N1>(buf, T + (int64_t)j * ea.N, ra, rb);
   __syncthreads();
-  fft_lds<N1, 2, pad_len<N1>(), row_nt<N1>(), -1, FFT_PAD>(buf, tt);
+  fft_lds<N1, 2, pad_len<N1, true>(), row_nt<N1>(), -1, eng_pad<N1, true>()>(buf, tt);
   float2* Zn = Z + (int64_t)(z0 + desc[j].aux) * ea.N;
   for (int i = threadIdx.x; i < N1; i += row_nt<N1>()) {
-    Zn[(int64_t)ra * N1 + i] = buf[px(i)];
-    Zn[(int64_t)rb * N1 + i] = buf[pad_len<N1>() + px(i)];
+    Zn[(int64_t)ra * N1 + i] = buf[px<N1, true>(i)];
+    Zn[(int64_t)rb * N1 + i] = buf[pad_len<N1, true>() + px<N1, true>(i)];
   }
 }
 
@@ -402,7 +406,7 @@ template <int N1>
 __global__ __launch_bounds__(row_nt<N1>()) void k_rows_conv(const float2* __restrict__ Tin, float2* __restrict__ Tout,
                                                          const float2* __restrict__ ZH, float2* __restrict__ ZU,
                                                          int z0, const NodeDesc* __restrict__ desc, EngineArgs ea) {
-  __shared__ float2 buf[2 * pad_len<N1>()];
+  __shared__ float2 buf[2 * pad_len<N1, true>()];
   __shared__ TwTab<N1, float2> tt;
   tw_fill<N1>(tt, ea.tw, ea.twdl);
   const int j = blockIdx.y;
@@ -411,14 +415,14 @@ __global__ __launch_bounds__(row_nt<N1>()) void k_rows_conv(const float2* __rest
   row_pair(p, ea.N2, ra, rb);
   load_rows<N1>(buf, Tin + (int64_t)j * ea.N, ra, rb);
   __syncthreads();
-  fft_lds<N1, 2, pad_len<N1>(), row_nt<N1>(), -1, FFT_PAD>(buf, tt);
+  fft_lds<N1, 2, pad_len<N1, true>(), row_nt<N1>(), -1, eng_pad<N1, true>()>(buf, tt);
   const int64_t zr = (int64_t)(z0 + desc[j].aux) * ea.N;
   const float2* H = ZH + zr;
   if (ZU) {  // keep the input spectrum for the backward
     float2* Zs = ZU + zr;
     for (int i = threadIdx.x; i < N1; i += row_nt<N1>()) {
-      Zs[(int64_t)ra * N1 + i] = buf[px(i)];
-      Zs[(int64_t)rb * N1 + i] = buf[pad_len<N1>() + px(i)];
+      Zs[(int64_t)ra * N1 + i] = buf[px<N1, true>(i)];
+      Zs[(int64_t)rb * N1 + i] = buf[pad_len<N1, true>() + px<N1, true>(i)];
     }
     __syncthreads();  // every bin stored before the product below overwrites it
   }
@@ -441,7 +445,7 @@ __global__ __launch_bounds__(row_nt<N1>()) void k_rows_conv(const float2* __rest
     buf[sb] = yb;
   }
   __syncthreads();
-  fft_lds<N1, 2, pad_len<N1>(), row_nt<N1>(), +1, FFT_PAD>(buf, tt);
+  fft_lds<N1, 2, pad_len<N1, true>(), row_nt<N1>(), +1, eng_pad<N1, true>()>(buf, tt);
   store_rows<N1>(buf, Tout + (int64_t)j * ea.N, ra, rb, ea);
 }
 
@@ -453,18 +457,18 @@ __global__ __launch_bounds__(row_nt<N1>()) void k_rows_bwd(const float2* __restr
                                                         const float2* __restrict__ ZU, int z0,
                                                         const NodeDesc* __restrict__ desc, int want_u,
                                                         EngineArgs ea) {
-  __shared__ float2 buf[4 * pad_len<N1>()];
+  __shared__ float2 buf[4 * pad_len<N1, true>()];
   __shared__ TwTab<N1, float2> tt;
   tw_fill<N1>(tt, ea.tw, ea.twdl);
   float2* b1 = buf;
-  float2* b2 = buf + 2 * pad_len<N1>();
+  float2* b2 = buf + 2 * pad_len<N1, true>();
   const int j = blockIdx.y;
   const int p = blockIdx.x;
   int ra, rb;
   row_pair(p, ea.N2, ra, rb);
   load_rows<N1>(b1, Tin + (int64_t)j * ea.N, ra, rb);
   __syncthreads();
-  fft_lds<N1, 2, pad_len<N1>(), row_nt<N1>(), -1, FFT_PAD>(b1, tt);
+  fft_lds<N1, 2, pad_len<N1, true>(), row_nt<N1>(), -1, eng_pad<N1, true>()>(b1, tt);
   const int64_t zr = (int64_t)(z0 + desc[j].aux) * ea.N;
   const float2* H = ZH + zr;
   const float2* X = ZU + zr;
@@ -497,10 +501,10 @@ __global__ __launch_bounds__(row_nt<N1>()) void k_rows_bwd(const float2* __restr
   }
   __syncthreads();
   if (want_u) {
-    fft_lds<N1, 2, pad_len<N1>(), row_nt<N1>(), +1, FFT_PAD>(b1, tt);
+    fft_lds<N1, 2, pad_len<N1, true>(), row_nt<N1>(), +1, eng_pad<N1, true>()>(b1, tt);
     store_rows<N1>(b1, Tu + (int64_t)j * ea.N, ra, rb, ea);
   }
-  fft_lds<N1, 2, pad_len<N1>(), row_nt<N1>(), +1, FFT_PAD>(b2, tt);
+  fft_lds<N1, 2, pad_len<N1, true>(), row_nt<N1>(), +1, eng_pad<N1, true>()>(b2, tt);
   store_rows<N1>(b2, Th + (int64_t)j * ea.N, ra, rb, ea);
 }
 

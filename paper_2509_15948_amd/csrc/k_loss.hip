@@ -534,8 +534,30 @@ static LossArgs loss_args(const Ctx& c, int i, const float* y) {
 
 // The resolutions up to 2048 points share one launch (the 4096-point body
 // needs more registers and LDS, which would halve the short ones' occupancy);
-// larger ones get a launch of their own, on the same stream.
+// larger ones get a launch of their own on the side stream, forked from and
+// joined back to the caller's stream, so that the two groups overlap.
 constexpr int LOSS_SPLIT_N = 2048;
+constexpr int EV_LOSS_FORK = 62, EV_LOSS_JOIN = 63;
+
+// when the resolutions form two groups: the context of the second one (the
+// side stream after a fork) in cs; false when everything stays on c's stream
+static bool loss_fork(const Ctx& c, Ctx& cs) {
+  const mg_graph* g = c.g;
+  bool lo = false, hi = false;
+  for (const LossRes& r : g->lres) (r.nfft <= LOSS_SPLIT_N ? lo : hi) = true;
+  cs = c;
+  if (!lo || !hi || !g->side || g->sev.size() < 64) return false;
+  cs.st = g->side;
+  hipEventRecord(g->sev[EV_LOSS_FORK], c.st);
+  hipStreamWaitEvent(g->side, g->sev[EV_LOSS_FORK], 0);
+  return true;
+}
+
+static void loss_join(const Ctx& c) {
+  const mg_graph* g = c.g;
+  hipEventRecord(g->sev[EV_LOSS_JOIN], g->side);
+  hipStreamWaitEvent(c.st, g->sev[EV_LOSS_JOIN], 0);
+}
 
 template <int NMAX, int MODE>
 static void fwd_multi(const Ctx& c, const LossMulti& m) {
@@ -590,12 +612,15 @@ static void run_loss_fwd(const Ctx& c, const float* y, int mode, double* stats_o
     ra.tgt[i] = wsp<double>(c, g->ws.ls_stats) + i * 16;
   }
   const int groups[2][2] = {{0, LOSS_SPLIT_N}, {LOSS_SPLIT_N + 1, 1 << 30}};
-  for (const auto& gr : groups) {
+  Ctx cs;
+  const bool forked = loss_fork(c, cs);
+  for (int k = 0; k < 2; ++k) {
+    const Ctx& cc = (k == 1) ? cs : c;
     LossMulti m;
-    const int nmax = loss_group(g, gr[0], gr[1], m, [&](int i) { return loss_args(c, i, y); });
+    const int nmax = loss_group(g, groups[k][0], groups[k][1], m, [&](int i) { return loss_args(c, i, y); });
     if (m.nres == 0) continue;
-#define MG_F0(NN) fwd_multi<NN, 0>(c, m)
-#define MG_F1(NN) fwd_multi<NN, 1>(c, m)
+#define MG_F0(NN) fwd_multi<NN, 0>(cc, m)
+#define MG_F1(NN) fwd_multi<NN, 1>(cc, m)
     if (mode == 0) {
       MG_LOSS_SWITCH(nmax, MG_F0)
     } else {
@@ -604,6 +629,7 @@ static void run_loss_fwd(const Ctx& c, const float* y, int mode, double* stats_o
 #undef MG_F0
 #undef MG_F1
   }
+  if (forked) loss_join(c);
   MG_LAUNCH(c, k_loss_reduce, dim3((unsigned)g->lres.size()), dim3(MG_BLOCK), 0, c.st, ra);
 }
 
@@ -645,18 +671,22 @@ void loss_backward(const Ctx& c, const float* yhat, float* dyhat) {
     off += (((size_t)r.frames * r.nfft * 2 * 4) + 255) / 256 * 256;
   }
   const int groups[2][2] = {{0, LOSS_SPLIT_N}, {LOSS_SPLIT_N + 1, 1 << 30}};
-  for (const auto& gr : groups) {
+  Ctx cs;
+  const bool forked = loss_fork(c, cs);
+  for (int k = 0; k < 2; ++k) {
+    const Ctx& cc = (k == 1) ? cs : c;
     LossMulti m;
-    const int nmax = loss_group(g, gr[0], gr[1], m, [&](int i) {
+    const int nmax = loss_group(g, groups[k][0], groups[k][1], m, [&](int i) {
       LossArgs a = loss_args(c, i, yhat);
       a.scratch = scratch[i];
       return a;
     });
     if (m.nres == 0) continue;
-#define MG_B(NN) bwd_multi<NN>(c, m)
+#define MG_B(NN) bwd_multi<NN>(cc, m)
     MG_LOSS_SWITCH(nmax, MG_B)
 #undef MG_B
   }
+  if (forked) loss_join(c);
   int64_t blocks = (c.L + MG_BLOCK - 1) / MG_BLOCK;
   if (blocks > 2048) blocks = 2048;
   MG_LAUNCH(c, k_loss_gather, dim3((unsigned)blocks), dim3(MG_BLOCK), 0, c.st, ga);
