@@ -30,6 +30,9 @@ namespace mg {
 constexpr int COL_NT = 1024;
 template <int N1>
 constexpr int row_nt() { return N1 >= 4096 ? 1024 : (N1 >= 1024 ? 512 : 256); }
+// the backward rows batch four transforms: 1024 threads from 2048 points
+template <int N1>
+constexpr int rowb_nt() { return N1 >= 2048 ? 1024 : row_nt<N1>(); }
 
 // Row transforms up to 2048 points and column transforms up to 256 keep one
 // spare LDS slot per 16 points: the first two radix-8 passes then put at most
@@ -381,6 +384,22 @@ __device__ __forceinline__ void store_rows(const float2* buf, float2* __restrict
   }
 }
 
+// store_rows of two row pairs that share their twiddles (x -> To, z -> Tz)
+template <int N1>
+__device__ __forceinline__ void store_rows2(const float2* x, const float2* z, float2* __restrict__ To,
+                                            float2* __restrict__ Tz, int ra, int rb, const EngineArgs& ea) {
+  const int64_t mask = ea.N - 1;
+  for (int i = threadIdx.x; i < N1; i += blockDim.x) {
+    const float2 wa = c_conj(big_tw(ea.twhi, ea.twlo, ((int64_t)i * ra) & mask));
+    const float2 wb = c_conj(big_tw(ea.twhi, ea.twlo, ((int64_t)i * rb) & mask));
+    const int ia = px<N1, true>(i), ib = pad_len<N1, true>() + px<N1, true>(i);
+    To[(int64_t)ra * N1 + i] = c_mul(x[ia], wa);
+    To[(int64_t)rb * N1 + i] = c_mul(x[ib], wb);
+    Tz[(int64_t)ra * N1 + i] = c_mul(z[ia], wa);
+    Tz[(int64_t)rb * N1 + i] = c_mul(z[ib], wb);
+  }
+}
+
 // spectrum only: S rows of the FIR -> ZH
 template <int N1>
 __global__ __launch_bounds__(row_nt<N1>()) void k_rows_spec(const float2* __restrict__ T, float2* __restrict__ Z,
@@ -452,7 +471,7 @@ __global__ __launch_bounds__(row_nt<N1>()) void k_rows_conv(const float2* __rest
 // backward: P1 = Gl conj(Hl) + i Gr conj(Hr)   (input gradient)
 //           P2 = Gl conj(Xl) + i Gr conj(Xr)   (FIR gradient)
 template <int N1>
-__global__ __launch_bounds__(row_nt<N1>()) void k_rows_bwd(const float2* __restrict__ Tin, float2* __restrict__ Tu,
+__global__ __launch_bounds__(rowb_nt<N1>(), 4) void k_rows_bwd(const float2* __restrict__ Tin, float2* __restrict__ Tu,
                                                         float2* __restrict__ Th, const float2* __restrict__ ZH,
                                                         const float2* __restrict__ ZU, int z0,
                                                         const NodeDesc* __restrict__ desc, int want_u,
@@ -468,11 +487,11 @@ __global__ __launch_bounds__(row_nt<N1>()) void k_rows_bwd(const float2* __restr
   row_pair(p, ea.N2, ra, rb);
   load_rows<N1>(b1, Tin + (int64_t)j * ea.N, ra, rb);
   __syncthreads();
-  fft_lds<N1, 2, pad_len<N1, true>(), row_nt<N1>(), -1, eng_pad<N1, true>()>(b1, tt);
+  fft_lds<N1, 2, pad_len<N1, true>(), rowb_nt<N1>(), -1, eng_pad<N1, true>()>(b1, tt);
   const int64_t zr = (int64_t)(z0 + desc[j].aux) * ea.N;
   const float2* H = ZH + zr;
   const float2* X = ZU + zr;
-  for (int q = threadIdx.x; q < N1 + 1; q += row_nt<N1>()) {
+  for (int q = threadIdx.x; q < N1 + 1; q += rowb_nt<N1>()) {
     int ia, ib;
     if (!mirror_pair<N1>(p, q, ia, ib)) continue;
     const int64_t ga = (ia < N1) ? (int64_t)ra * N1 + ia : (int64_t)rb * N1 + (ia - N1);
@@ -501,11 +520,14 @@ __global__ __launch_bounds__(row_nt<N1>()) void k_rows_bwd(const float2* __restr
   }
   __syncthreads();
   if (want_u) {
-    fft_lds<N1, 2, pad_len<N1, true>(), row_nt<N1>(), +1, eng_pad<N1, true>()>(b1, tt);
-    store_rows<N1>(b1, Tu + (int64_t)j * ea.N, ra, rb, ea);
+    // both products (b1, b2: four consecutive rows) in one batch of
+    // transforms: half the barriers, twice the butterflies between them
+    fft_lds<N1, 4, pad_len<N1, true>(), rowb_nt<N1>(), +1, eng_pad<N1, true>()>(buf, tt);
+    store_rows2<N1>(b1, b2, Tu + (int64_t)j * ea.N, Th + (int64_t)j * ea.N, ra, rb, ea);
+  } else {
+    fft_lds<N1, 2, pad_len<N1, true>(), rowb_nt<N1>(), +1, eng_pad<N1, true>()>(b2, tt);
+    store_rows<N1>(b2, Th + (int64_t)j * ea.N, ra, rb, ea);
   }
-  fft_lds<N1, 2, pad_len<N1, true>(), row_nt<N1>(), +1, eng_pad<N1, true>()>(b2, tt);
-  store_rows<N1>(b2, Th + (int64_t)j * ea.N, ra, rb, ea);
 }
 
 // ---------------------------------------------------------------- dispatch
@@ -593,7 +615,7 @@ template <int N1>
 static void rows_bwd_n(const Ctx& c, const float2* Tin, float2* Tu, float2* Th, const float2* ZH, const float2* ZU,
                        int z0, int desc_off, int n, int want_u, const EngineArgs& ea) {
   ProfScope ps(c, "conv_rows", (double)n * (want_u ? 40.0 : 32.0) * ea.N);
-  MG_LAUNCH(c, k_rows_bwd<N1>, dim3(ea.N2 / 2, n), dim3(row_nt<N1>()), 0, c.st, Tin, Tu, Th, ZH, ZU, z0,
+  MG_LAUNCH(c, k_rows_bwd<N1>, dim3(ea.N2 / 2, n), dim3(rowb_nt<N1>()), 0, c.st, Tin, Tu, Th, ZH, ZU, z0,
                      c.desc + desc_off, want_u, ea);
 }
 
