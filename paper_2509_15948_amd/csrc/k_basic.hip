@@ -30,14 +30,33 @@ __device__ __forceinline__ float wet_of(const NodeDesc& d, const float* wet, con
   return w;
 }
 
+// Sample visiting shared by every pointwise kernel: with vec set (L a
+// multiple of 4 and 16-byte aligned rows, decided once per call on the host)
+// each thread takes runs of 4 consecutive samples, one float4 per channel
+// row, else single samples; the order is the same in the per-stage and the
+// fused kernels, so their per-thread partial sums agree bit for bit.
+__device__ __forceinline__ void ld4(const float* p, float (&v)[4]) {
+  const float4 t = *reinterpret_cast<const float4*>(p);
+  v[0] = t.x;
+  v[1] = t.y;
+  v[2] = t.z;
+  v[3] = t.w;
+}
+__device__ __forceinline__ void st4(float* p, const float (&v)[4]) {
+  *reinterpret_cast<float4*>(p) = make_float4(v[0], v[1], v[2], v[3]);
+}
+
 // ---------------------------------------------------------------- sums
 // out[slot] = sum of sources, fixed order.  Sources: dry tracks, U slots or
 // gradient slots.  dest_kind 0: the node's output slot; 1: its gradient
-// slot; 2: its input-sum slot (processors with several predecessors).
+// slot; 2: its input-sum slot (processors with several predecessors).  With
+// vec (L a multiple of 4, 16-byte aligned rows) each thread adds runs of four
+// samples as float4; every sample's sources are added in the same order
+// either way.
 __global__ __launch_bounds__(MG_BLOCK) void k_sum(const NodeDesc* __restrict__ desc, const SrcRef* __restrict__ srcs,
-                                                   const float* __restrict__ dry, const float* __restrict__ U,
-                                                   const float* __restrict__ G, float* __restrict__ out_base,
-                                                   int64_t L, int C, int dest_kind) {
+                                                  const float* __restrict__ dry, const float* __restrict__ U,
+                                                  const float* __restrict__ G, float* __restrict__ out_base,
+                                                  int64_t L, int C, int dest_kind, int vec) {
   constexpr int MAXS = 64;  // sources resolved once per block (more are read directly)
   __shared__ const float* sp[MAXS];
   __shared__ int64_t sc[MAXS];
@@ -57,10 +76,27 @@ __global__ __launch_bounds__(MG_BLOCK) void k_sum(const NodeDesc* __restrict__ d
   __syncthreads();
   const int64_t slot = dest_kind == 0 ? d.out_slot : (dest_kind == 1 ? d.gout : d.in_slot);
   float* out = out_base + slot * 2 * L;
-  const int64_t n2 = 2 * L;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n2; i += (int64_t)gridDim.x * blockDim.x) {
-    const int ch = (int)(i / L);
-    const int64_t t = i - (int64_t)ch * L;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const int64_t k0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (vec && ns <= MAXS) {
+    const int64_t q4 = L / 4;
+    for (int64_t k = k0; k < 2 * q4; k += stride) {
+      const int ch = k >= q4 ? 1 : 0;
+      const int64_t t = (k - ch * q4) * 4;
+      float acc[4] = {0.f, 0.f, 0.f, 0.f};
+      for (int s = 0; s < ns; ++s) {
+        float v[4];
+        ld4(sp[s] + ch * sc[s] + t, v);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) acc[e] += v[e];
+      }
+      st4(out + ch * L + t, acc);
+    }
+    return;
+  }
+  for (int64_t i = k0; i < 2 * L; i += stride) {
+    const int ch = i >= L ? 1 : 0;
+    const int64_t t = i - ch * L;
     float acc = 0.0f;
     for (int s = 0; s < ns; ++s) {
       float v;
@@ -80,10 +116,13 @@ __global__ __launch_bounds__(MG_BLOCK) void k_sum(const NodeDesc* __restrict__ d
 
 void launch_sum(const Ctx& c, int desc_off, int n, const SrcRef* srcs, float* out_base, int dest_kind) {
   if (n <= 0) return;
-  dim3 grid(256, n);
+  // one float4 (or sample) per thread where the grid allows, up to 4096 blocks per node
+  const int64_t items = c.vec4 ? (2 * c.L) / 4 : 2 * c.L;
+  const unsigned bx = (unsigned)std::min<int64_t>(4096, std::max<int64_t>(1, (items + MG_BLOCK - 1) / MG_BLOCK));
+  dim3 grid(bx, n);
   ProfScope ps(c, "sum", (double)n * 8.0 * c.L * 2);
   MG_LAUNCH(c, k_sum, grid, dim3(MG_BLOCK), 0, c.st, c.desc + desc_off, srcs, c.dry, c.U, c.G, out_base, c.L,
-                     c.C, dest_kind);
+            c.C, dest_kind, c.vec4);
 }
 
 // ---------------------------------------------------------------- pointwise processors
@@ -176,22 +215,6 @@ __device__ __forceinline__ void pw_level_bwd(const PW<T>& f, float w, float l, f
   f.bwd(l, r, w * dl, w * dr, bl, br, pp);
   gl = fmaf(1.0f - w, dl, bl);
   gr = fmaf(1.0f - w, dr, br);
-}
-
-// Sample visiting shared by every pointwise kernel: with vec set (L a
-// multiple of 4 and 16-byte aligned rows, decided once per call on the host)
-// each thread takes runs of 4 consecutive samples, one float4 per channel
-// row, else single samples; the order is the same in the per-stage and the
-// fused kernels, so their per-thread partial sums agree bit for bit.
-__device__ __forceinline__ void ld4(const float* p, float (&v)[4]) {
-  const float4 t = *reinterpret_cast<const float4*>(p);
-  v[0] = t.x;
-  v[1] = t.y;
-  v[2] = t.z;
-  v[3] = t.w;
-}
-__device__ __forceinline__ void st4(float* p, const float (&v)[4]) {
-  *reinterpret_cast<float4*>(p) = make_float4(v[0], v[1], v[2], v[3]);
 }
 
 template <int T>
@@ -497,8 +520,17 @@ __global__ __launch_bounds__(MG_BLOCK) void k_pw_chain_bwd(PwChain ch, const flo
 
 #pragma clang fp contract(fast)
 
+// forward grids (no per-block partials): 128 blocks per node, more for small
+// stages so that a launch has about 2048 blocks
+static dim3 pw_fwd_grid(const Ctx& c, int n) {
+  const int64_t items = c.vec4 ? (c.L + 3) / 4 : c.L;
+  const int64_t want = std::max<int64_t>(128, 2048 / std::max(1, n));
+  const int64_t need = std::max<int64_t>(1, (items + MG_BLOCK - 1) / MG_BLOCK);
+  return dim3((unsigned)std::min(want, need), n);
+}
+
 void launch_pointwise_fwd(const Ctx& c, int type, int desc_off, int n) {
-  dim3 grid(128, n), blk(MG_BLOCK);
+  dim3 grid = pw_fwd_grid(c, n), blk(MG_BLOCK);
   ProfScope ps(c, "pointwise", (double)n * 16.0 * c.L);
   const NodeDesc* d = c.desc + desc_off;
   switch (type) {
@@ -548,7 +580,7 @@ static PwChain pw_chain(const Ctx& c, const int* types, const int* offs, int K) 
 }
 
 void launch_pw_chain_fwd(const Ctx& c, const int* types, const int* offs, int K, int n) {
-  dim3 grid(128, n), blk(MG_BLOCK);
+  dim3 grid = pw_fwd_grid(c, n), blk(MG_BLOCK);
   ProfScope ps(c, "pointwise", (double)n * (8.0 + 8.0 * K) * c.L);
   MG_LAUNCH(c, k_pw_chain_fwd, grid, blk, 0, c.st, pw_chain(c, types, offs, K), c.dry, c.U, c.theta, c.wet, c.mask,
             c.L, c.C, c.vec4);
