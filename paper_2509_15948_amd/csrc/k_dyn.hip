@@ -2,9 +2,10 @@
 //   e[n] = (u_l + u_r)^2;  g[n] = a g[n-1] + (1 - a) e[n];  G = log(g + eps)
 //   ybar_c = exp(f(G) - G) u_c  with the quadratic-knee curve f.
 // One coefficient (a linear recursion): a chunked scan.  Each 4096-sample
-// chunk is summarised (state reached from zero), the chunk carries are
-// chained in FP64, and a second pass rescans every chunk from its carry with
-// a workgroup-level scan of per-thread 16-sample segments.
+// chunk is summarised (state reached from zero); the second pass chains the
+// chunk carries in FP64 (one lane per workgroup, over the chunks before its
+// own) and rescans its chunk from that carry with a workgroup-level scan of
+// per-thread 16-sample segments.
 // Attack/release (a[n] depends on e[n] > g[n-1], not linear): one lane per
 // node walks the samples in order; the other lanes of its wave stage inputs
 // and outputs through LDS.
@@ -164,31 +165,32 @@ __global__ __launch_bounds__(MG_BLOCK) void k_dyn_sum(DynView v, float* __restri
   if (t == 0) sums[(int64_t)blockIdx.y * nchunks + blockIdx.x] = red[0];
 }
 
-// pass 2: carries (state entering each chunk), FP64 chain.  One block of 64
-// threads per node: the chunk sums are staged in LDS, one lane runs the chain
-// in order, and the carries are written back by all lanes.
-constexpr int DYN_MAXCH = 4096;  // chunks per node staged in LDS
-
-__global__ __launch_bounds__(64) void k_dyn_carry(DynView v, const float* __restrict__ sums,
-                                                  double* __restrict__ carry, int nchunks, int n) {
-  __shared__ float s_in[DYN_MAXCH];
-  __shared__ double s_out[DYN_MAXCH];
-  const int j = blockIdx.x;
-  const NodeDesc d = v.desc[j];
-  const float* p = v.theta + d.theta_off;
-  const double loga = -log1p(exp(-(double)p[0]));
-  const double aC = exp(loga * DYN_CH);
-  for (int k = threadIdx.x; k < nchunks; k += blockDim.x) s_in[k] = sums[(int64_t)j * nchunks + k];
-  __syncthreads();
+// The FP64 carry entering this workgroup's chunk (node blockIdx.y, chunk
+// blockIdx.x), chained by one lane over the chunk states in order: forward
+// over the chunks before it, reverse over the chunks after it.  Every
+// workgroup of a node runs the same chain, so all of them see the carries a
+// separate chaining pass would produce, without its launch.  slot: one
+// double of LDS.
+__device__ __forceinline__ float chunk_carry(const DynView& v, const NodeDesc& d, const float* __restrict__ sums,
+                                             int nchunks, bool reverse, double* slot) {
   if (threadIdx.x == 0) {
+    const float* p = v.theta + d.theta_off;
+    const double loga = -log1p(exp(-(double)p[0]));
+    const double aC = exp(loga * DYN_CH);
+    const float* sr = sums + (int64_t)blockIdx.y * nchunks;
+    const int k0 = (int)blockIdx.x;
     double c = 0.0;
-    for (int k = 0; k < nchunks; ++k) {
-      s_out[k] = c;
-      c = aC * c + (double)s_in[k];
+    if (!reverse) {
+#pragma unroll 4
+      for (int k = 0; k < k0; ++k) c = aC * c + (double)sr[k];
+    } else {
+#pragma unroll 4
+      for (int k = nchunks - 1; k > k0; --k) c = (double)sr[k] + aC * c;
     }
+    *slot = c;
   }
   __syncthreads();
-  for (int k = threadIdx.x; k < nchunks; k += blockDim.x) carry[(int64_t)j * nchunks + k] = s_out[k];
+  return (float)*slot;
 }
 
 // exclusive scan across threads of per-thread segment states (uniform decay
@@ -209,9 +211,10 @@ __device__ __forceinline__ float seg_entry(float seg, float carry_in, float loga
 }
 
 template <int GATE>
-__global__ __launch_bounds__(MG_BLOCK) void k_dyn_apply(DynView v, const double* __restrict__ carry, int nchunks) {
+__global__ __launch_bounds__(MG_BLOCK) void k_dyn_apply(DynView v, const float* __restrict__ sums, int nchunks) {
   __shared__ float le[DYN_SPT * DYN_PAD];
   __shared__ float red[MG_BLOCK];
+  __shared__ double cslot;
   const NodeDesc d = v.desc[blockIdx.y];
   const DynParams q = dyn_params(v.theta + d.theta_off, 0);
   int64_t cs;
@@ -223,7 +226,7 @@ __global__ __launch_bounds__(MG_BLOCK) void k_dyn_apply(DynView v, const double*
   float s = 0.f;
 #pragma unroll
   for (int i = 0; i < DYN_SPT; ++i) s = fmaf(q.a, s, q.b * le[i * DYN_PAD + t]);
-  const float cin = (float)carry[(int64_t)blockIdx.y * nchunks + blockIdx.x];
+  const float cin = chunk_carry(v, d, sums, nchunks, false, &cslot);
   float gst = seg_entry(s, cin, q.loga, red);
   // envelope into LDS (reuse le in place: each thread owns its column)
 #pragma unroll
@@ -309,33 +312,11 @@ __global__ __launch_bounds__(MG_BLOCK) void k_dyn_bsum(DynView v, float* __restr
   if (t == 0) sums[(int64_t)blockIdx.y * nchunks + blockIdx.x] = red[0];
 }
 
-// pass 2 (reverse): lambda entering each chunk from the right
-__global__ __launch_bounds__(64) void k_dyn_bcarry(DynView v, const float* __restrict__ sums,
-                                                   double* __restrict__ carry, int nchunks, int n) {
-  __shared__ float s_in[DYN_MAXCH];
-  __shared__ double s_out[DYN_MAXCH];
-  const int j = blockIdx.x;
-  const NodeDesc d = v.desc[j];
-  const float* p = v.theta + d.theta_off;
-  const double loga = -log1p(exp(-(double)p[0]));
-  const double aC = exp(loga * DYN_CH);
-  for (int k = threadIdx.x; k < nchunks; k += blockDim.x) s_in[k] = sums[(int64_t)j * nchunks + k];
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    double c = 0.0;
-    for (int k = nchunks - 1; k >= 0; --k) {
-      s_out[k] = c;  // lambda at the first sample of chunk k+1
-      c = (double)s_in[k] + aC * c;
-    }
-  }
-  __syncthreads();
-  for (int k = threadIdx.x; k < nchunks; k += blockDim.x) carry[(int64_t)j * nchunks + k] = s_out[k];
-}
-
 template <int GATE>
-__global__ __launch_bounds__(MG_BLOCK) void k_dyn_bapply(DynView v, const double* __restrict__ carry, int nchunks) {
+__global__ __launch_bounds__(MG_BLOCK) void k_dyn_bapply(DynView v, const float* __restrict__ sums, int nchunks) {
   __shared__ float lg[DYN_SPT * DYN_PAD];
   __shared__ float red[MG_BLOCK];
+  __shared__ double cslot;
   const NodeDesc d = v.desc[blockIdx.y];
   const DynParams q = dyn_params(v.theta + d.theta_off, 0);
   float w = node_w(v.wet, v.mask, d);
@@ -368,7 +349,7 @@ __global__ __launch_bounds__(MG_BLOCK) void k_dyn_bapply(DynView v, const double
   }
   const float excl = (t + 1 < MG_BLOCK) ? red[t + 1] : 0.f;
   __syncthreads();
-  const float cin = (float)carry[(int64_t)blockIdx.y * nchunks + blockIdx.x];
+  const float cin = chunk_carry(v, d, sums, nchunks, true, &cslot);
   float lam = fmaf(cin, expf(q.loga * (float)(DYN_SPT * (MG_BLOCK - 1 - t))), excl);
 #pragma unroll
   for (int i = DYN_SPT - 1; i >= 0; --i) {
@@ -566,11 +547,9 @@ void dyn_forward(const Ctx& c, int type, int desc_off, int n) {
   }
   const int nch = g->dyn_chunks;
   float* sums = wsp<float>(c, g->ws.cmp_sum);
-  double* carry = wsp<double>(c, g->ws.cmp_carry);
   MG_LAUNCH(c, k_dyn_sum, dim3(nch, n), dim3(MG_BLOCK), 0, c.st, v, sums, nch);
-  MG_LAUNCH(c, k_dyn_carry, dim3(n), dim3(64), 0, c.st, v, sums, carry, nch, n);
-  if (type == MG_GATE) MG_LAUNCH(c, k_dyn_apply<1>, dim3(nch, n), dim3(MG_BLOCK), 0, c.st, v, carry, nch);
-  else MG_LAUNCH(c, k_dyn_apply<0>, dim3(nch, n), dim3(MG_BLOCK), 0, c.st, v, carry, nch);
+  if (type == MG_GATE) MG_LAUNCH(c, k_dyn_apply<1>, dim3(nch, n), dim3(MG_BLOCK), 0, c.st, v, sums, nch);
+  else MG_LAUNCH(c, k_dyn_apply<0>, dim3(nch, n), dim3(MG_BLOCK), 0, c.st, v, sums, nch);
 }
 
 void dyn_backward(const Ctx& c, int type, int desc_off, int n) {
@@ -584,15 +563,12 @@ void dyn_backward(const Ctx& c, int type, int desc_off, int n) {
   }
   const int nch = g->dyn_chunks;
   float* sums = wsp<float>(c, g->ws.cmp_sum);
-  double* carry = wsp<double>(c, g->ws.cmp_carry);
   if (type == MG_GATE) {
     MG_LAUNCH(c, k_dyn_bsum<1>, dim3(nch, n), dim3(MG_BLOCK), 0, c.st, v, sums, nch);
-    MG_LAUNCH(c, k_dyn_bcarry, dim3(n), dim3(64), 0, c.st, v, sums, carry, nch, n);
-    MG_LAUNCH(c, k_dyn_bapply<1>, dim3(nch, n), dim3(MG_BLOCK), 0, c.st, v, carry, nch);
+    MG_LAUNCH(c, k_dyn_bapply<1>, dim3(nch, n), dim3(MG_BLOCK), 0, c.st, v, sums, nch);
   } else {
     MG_LAUNCH(c, k_dyn_bsum<0>, dim3(nch, n), dim3(MG_BLOCK), 0, c.st, v, sums, nch);
-    MG_LAUNCH(c, k_dyn_bcarry, dim3(n), dim3(64), 0, c.st, v, sums, carry, nch, n);
-    MG_LAUNCH(c, k_dyn_bapply<0>, dim3(nch, n), dim3(MG_BLOCK), 0, c.st, v, carry, nch);
+    MG_LAUNCH(c, k_dyn_bapply<0>, dim3(nch, n), dim3(MG_BLOCK), 0, c.st, v, sums, nch);
   }
 }
 

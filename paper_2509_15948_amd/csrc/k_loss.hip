@@ -226,10 +226,16 @@ __global__ __launch_bounds__(MG_BLOCK) void k_loss_reduce(ReduceArgs ra) {
   const double* tgt = ra.tgt[i];
   const int nblocks = ra.nblocks[i], mode = ra.mode;
   if (mode == 1 && tgt != stats && threadIdx.x < 4) stats[threadIdx.x * 4 + 0] = tgt[threadIdx.x * 4 + 0];
+  // one pass over the partial rows (each thread: blocks t, t + MG_BLOCK, ...
+  // in order, all eight sums at once), then the eight block sums
+  double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  for (int b = threadIdx.x; b < nblocks; b += MG_BLOCK) {
+    const double* pb = part + (int64_t)b * 8;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) acc[q] += pb[q];
+  }
   for (int q = 0; q < 8; ++q) {
-    double s = 0.0;
-    for (int b = threadIdx.x; b < nblocks; b += MG_BLOCK) s += part[(int64_t)b * 8 + q];
-    s = block_sum<MG_BLOCK>(s, red);
+    const double s = block_sum<MG_BLOCK>(acc[q], red);
     if (threadIdx.x == 0) {
       const int x = q % 4;
       if (mode == 0) {

@@ -110,7 +110,6 @@ static size_t plan_ws(mg_graph& g, int mode, bool commit) {
   }
   if (n_dyn) {
     take(w.cmp_sum, (size_t)std::max(1, g.max_stage) * g.dyn_chunks * 4);
-    take(w.cmp_carry, (size_t)std::max(1, g.max_stage) * g.dyn_chunks * 8);
   }
   take(w.part, (size_t)std::max(1, n_win) * g.part_blocks * PK * 4);
   take(w.lg, (size_t)std::max(1, n_win) * 2 * 8);
@@ -412,7 +411,7 @@ extern "C" int mg_setup(mg_graph* g, void* workspace, size_t workspace_bytes, in
         {"eq_dh", w.eq_dh}, {"eq_dhp", w.eq_dhp}, {"eq_XU", w.eq_XU}, {"eq_cos", w.eq_cos}, {"dl_tab", w.dl_tab},
         {"dl_dh", w.dl_dh}, {"dl_cos", w.dl_cos}, {"rv_U", w.rv_U}, {"rv_fr", w.rv_fr}, {"rv_h", w.rv_h},
         {"rv_dh", w.rv_dh}, {"rv_dM", w.rv_dM}, {"rv_cs", w.rv_cs}, {"rv_win", w.rv_win},
-        {"rv_wsum", w.rv_wsum}, {"cmp_sum", w.cmp_sum}, {"cmp_carry", w.cmp_carry}, {"part", w.part},
+        {"rv_wsum", w.rv_wsum}, {"cmp_sum", w.cmp_sum}, {"part", w.part},
         {"lg", w.lg}, {"ls_stats", w.ls_stats}, {"ls_part", w.ls_part}, {"total", w.total}};
     for (const auto& x : r) fprintf(stderr, "mg layout %s %zu\n", x.first, x.second);
   }

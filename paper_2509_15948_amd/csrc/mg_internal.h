@@ -66,7 +66,7 @@ struct WsPlan {
   size_t eq_h = 0, eq_dh = 0, eq_cos = 0, eq_HP = 0, eq_dhp = 0, eq_XU = 0;
   size_t dl_tab = 0, dl_h = 0, dl_dh = 0, dl_cos = 0, dl_zp = 0;
   size_t rv_U = 0, rv_fr = 0, rv_h = 0, rv_dh = 0, rv_dM = 0, rv_cs = 0, rv_win = 0, rv_wsum = 0;
-  size_t cmp_sum = 0, cmp_carry = 0;
+  size_t cmp_sum = 0;
   size_t part = 0;           // per (node, block) partial sums
   size_t pgrad = 0;          // per node parameter gradient staging (double)
   size_t ls_tgt = 0, ls_part = 0, ls_norm = 0, ls_tab = 0, ls_aw = 0, ls_win = 0;
