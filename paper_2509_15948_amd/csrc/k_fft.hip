@@ -264,6 +264,18 @@ struct StGradH {
   __device__ void end(int, int) {}
 };
 
+// Column tile of workgroup b of n.  Tiles narrower than a 128-byte line
+// (TC < 16 columns) are ordered for the XCDs: workgroups are dealt to the
+// eight XCDs in turn and each XCD has its own L2, so workgroup b takes tile
+// (b % 8) (n / 8) + b / 8; neighbouring tiles, whose row segments share L2
+// lines, then run on one XCD at about the same time.  Partial sums stay
+// indexed by tile.
+template <int TC>
+__device__ __forceinline__ int col_tile(int b, int n) {
+  if (TC >= 16 || n % 8) return b;
+  return (b % 8) * (n / 8) + b / 8;
+}
+
 // ---------------------------------------------------------------- KA: columns forward
 template <int N2, int TC, typename LD>
 __global__ __launch_bounds__(COL_NT) void k_cols(LD ld, float2* __restrict__ T, EngineArgs ea) {
@@ -272,14 +284,15 @@ __global__ __launch_bounds__(COL_NT) void k_cols(LD ld, float2* __restrict__ T, 
   __shared__ TwTab<N2, float2> tt;
   tw_fill<N2>(tt, ea.tw, ea.twdl);
   const int j = blockIdx.y;
-  const int c0 = blockIdx.x * TC;
+  const int tile = col_tile<TC>(blockIdx.x, gridDim.x);
+  const int c0 = tile * TC;
   const int N1 = ea.N1;
   ld.begin(j);
   for (int idx = threadIdx.x; idx < TC * N2; idx += COL_NT) {
     const int n2 = idx / TC, cc = idx % TC;
     buf[cc * BS + px<N2, false>(n2)] = ld.load((int64_t)(c0 + cc) + (int64_t)N1 * n2);
   }
-  ld.end(j, blockIdx.x);
+  ld.end(j, tile);
   __syncthreads();
   fft_lds<N2, TC, BS, COL_NT, -1, eng_pad<N2, false>()>(buf, tt);
   float2* Tn = T + (int64_t)j * ea.N;
@@ -300,7 +313,8 @@ __global__ __launch_bounds__(COL_NT) void k_icols(ST st, const float2* __restric
   __shared__ TwTab<N2, float2> tt;
   tw_fill<N2>(tt, ea.tw, ea.twdl);
   const int j = blockIdx.y;
-  const int c0 = blockIdx.x * TC;
+  const int tile = col_tile<TC>(blockIdx.x, gridDim.x);
+  const int c0 = tile * TC;
   const int N1 = ea.N1;
   const float2* Tn = T + (int64_t)j * ea.N;
   for (int idx = threadIdx.x; idx < TC * N2; idx += COL_NT) {
@@ -315,7 +329,7 @@ __global__ __launch_bounds__(COL_NT) void k_icols(ST st, const float2* __restric
     const int n2 = idx / TC, cc = idx % TC;
     st.store((int64_t)(c0 + cc) + (int64_t)N1 * n2, c_scale(buf[cc * BS + px<N2, false>(n2)], sc));
   }
-  st.end(j, blockIdx.x);
+  st.end(j, tile);
 }
 
 // ---------------------------------------------------------------- KB: rows

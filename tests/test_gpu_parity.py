@@ -96,6 +96,32 @@ def test_backward_parity_per_type(chain):
     assert err <= tol["w"]
 
 
+def test_narrow_column_tiles_against_the_oracle():
+    """One track and one subgroup with delay and reverb, 70 s at 16 kHz: a
+    2^21-point engine with 1024-point columns, so the column kernels take
+    8-column tiles (64-byte row segments) in their XCD-aware order.  Waveform,
+    losses and the delay/reverb/dry-wet gradients against the oracle."""
+    case = Case(_small("dr", seconds=70.0, n_tracks=1, n_subgroups=1), alpha_p=1e-2)
+    assert case.bg.info.fft_size == 1 << 21
+    mix, gl = case.gpu_forward()
+    gth, gwe = case.gpu_backward()
+    omix, ol, oth, owe = case.oracle()
+    err = rel_l2(mix, omix)
+    print("narrow tiles wave", err, flush=True)
+    assert err <= WAVE_TOL
+    _check_losses(gl, ol, loss_tolerances(case, omix))
+    tol, sens = grad_tolerances(case, oth, owe)
+    procs = case.g.processors()
+    for t in ("d", "r"):
+        vs = [v for v in procs if case.g.types[v] == t]
+        err = rel_l2(np.concatenate([gth[v] for v in vs]), np.concatenate([oth[v] for v in vs]))
+        print("narrow tiles", t, "grad err", err, "bound", tol[t], flush=True)
+        assert err <= tol[t]
+    err = rel_l2([gwe[v] for v in procs], [owe[v] for v in procs])
+    print("narrow tiles wet grad err", err, "bound", tol["w"], flush=True)
+    assert err <= tol["w"]
+
+
 def test_tiny_console_attack_release_full_size():
     """4 mono tracks, 2 s at 44.1 kHz, gain/pan + 1023-tap EQ + attack/release
     compressor, one subgroup; forward and backward at full size."""
