@@ -128,7 +128,7 @@ __global__ __launch_bounds__(EQ_NT, 8) void k_eq_fwd(EqArgs a) {
   }
 }
 
-// backward: grid (nblk, nodes); one P-point window in LDS.
+// backward: grid (nblk, nodes, 2); one P-point window in LDS.
 //   input gradient: gbar over the whole window (packed l + i r) times H_P;
 //   FIR gradient: gbar over the valid part only, times the conjugate of the
 //   input-window spectrum the forward kept, inverse -> lags -half..half.
@@ -150,7 +150,12 @@ __global__ __launch_bounds__(EQ_BNT, 8) void k_eq_bwd(EqArgs a) {
   const double diff = 0.5 * log(Ey) - 0.5 * log(Eu);
   const double sgn = diff > 0 ? 1.0 : (diff < 0 ? -1.0 : 0.0);
   const float ky = (float)((double)a.alpha_g * sgn / Ey), ku = (float)((double)a.alpha_g * sgn / Eu);
-  float* gin = d.gin >= 0 ? a.G + (int64_t)d.gin * 2 * a.L : nullptr;
+  // grid.z = 2 gives the two halves to separate workgroups (z = 0: dL/du;
+  // z = 1: FIR gradient and dry/wet partial), each with the arithmetic it has
+  // in one workgroup: twice the workgroups, half the transforms in a row
+  const bool do_gin = gridDim.z == 1 || blockIdx.z == 0;
+  const bool do_dh = gridDim.z == 1 || blockIdx.z == 1;
+  float* gin = (do_gin && d.gin >= 0) ? a.G + (int64_t)d.gin * 2 * a.L : nullptr;
   if (gin) {
     for (int i = threadIdx.x; i < EQ_P; i += EQ_BNT) {
       const int64_t n = s0 + i;
@@ -176,6 +181,7 @@ __global__ __launch_bounds__(EQ_BNT, 8) void k_eq_bwd(EqArgs a) {
     }
     __syncthreads();
   }
+  if (!do_dh) return;
   // FIR gradient: the valid-part gradient correlated with the input window
   float dw = 0.f;
   for (int i = threadIdx.x; i < EQ_P; i += EQ_BNT) {
@@ -291,7 +297,7 @@ void eq_backward(const Ctx& c, int desc_off, int n) {
     // reads dL/dy, ybar, u (window each), u again and the kept window spectra;
     // writes dL/du and the block FIR gradients
     ProfScope ps(c, "eq_conv", (double)n * ((32.0 * EQ_P) * a.nblk + 16.0 * c.L + 4.0 * a.N * a.nblk));
-    MG_LAUNCH(c, k_eq_bwd, dim3(a.nblk, n), dim3(EQ_BNT), 0, c.st, a);
+    MG_LAUNCH(c, k_eq_bwd, dim3(a.nblk, n, 2), dim3(EQ_BNT), 0, c.st, a);
   }
 }
 
