@@ -22,11 +22,12 @@
 
 namespace mg {
 
-// threads per block: the column kernels hold 64 KB of LDS (two blocks per
+// threads per block: the column kernels hold 64-72 KB of LDS (two blocks per
 // CU) and need few registers, so 1024 threads give 32 waves per CU (512
 // threads, 16 waves, measured 4 % slower per step; 4096-element tiles, 64-byte
 // row segments, slower still); row kernels use 512 threads from N1 = 1024 up
-// (fewer rows of butterflies below)
+// (fewer rows of butterflies below), except the backward rows, which batch
+// four transforms and take 1024 from N1 = 2048 (rowb_nt)
 constexpr int COL_NT = 1024;
 template <int N1>
 constexpr int row_nt() { return N1 >= 4096 ? 1024 : (N1 >= 1024 ? 512 : 256); }
