@@ -2,6 +2,9 @@
 
   python -m paper_2509_15948_amd.profiling stats DIR CMD...
       markdown table of a `--kernel-trace --stats --output-format csv` run
+  python -m paper_2509_15948_amd.profiling counters DIR CMD...
+      markdown table of a `--pmc` run: every counter per dispatch, by kernel
+      (demangled name without its argument list) and grid, largest first
   python -m paper_2509_15948_amd.profiling traffic FETCH_DIR WRITE_DIR OUT_DIR WORKLOAD CMD...
       HBM bytes per launch of every kernel class from two `--pmc` runs
       (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch), each scaled by what the
@@ -74,6 +77,30 @@ def stats_markdown(dirpath, command):
             name = name[:87] + "..."
         out.append(f"| {t / 1e6:.3f} | {100 * t / total:.1f}% | {r['Calls']} | {float(r['AverageNs']) / 1e3:.1f} | "
                    f"`{name}` |")
+    return "\n".join(out) + "\n"
+
+
+def counters_markdown(dirpath, command, top=16):
+    """Per-dispatch averages of every counter of one --pmc run, by kernel and
+    grid (dispatches of the same kernel and grid are averaged)."""
+    path = _find(dirpath, "counter_collection.csv")
+    acc, disp = {}, {}
+    for r in csv.DictReader(open(path)):
+        name = re.sub(r"\(.*", "", r["Kernel_Name"]).replace("void ", "").replace("mg::", "")
+        key = (name, r["Grid_Size"])
+        acc.setdefault(key, {})
+        acc[key][r["Counter_Name"]] = acc[key].get(r["Counter_Name"], 0.0) + float(r["Counter_Value"])
+        disp.setdefault(key, set()).add(r["Dispatch_Id"])
+    names = sorted({c for v in acc.values() for c in v})
+    keys = [k for k in acc if k[0].startswith("k_")]
+    sort_by = "SQ_WAVE_CYCLES" if "SQ_WAVE_CYCLES" in names else names[0]
+    keys.sort(key=lambda k: -acc[k].get(sort_by, 0.0) / len(disp[k]))
+    out = ["Command: `" + command + "`", "", "Per dispatch (averaged over the dispatches of each kernel and grid):", "",
+           "| kernel | grid | dispatches | " + " | ".join(names) + " |",
+           "|---|---:|---:|" + "---:|" * len(names)]
+    for k in keys[:top]:
+        n = len(disp[k])
+        out.append(f"| `{k[0]}` | {k[1]} | {n} | " + " | ".join(f"{acc[k].get(c, 0.0) / n:.3g}" for c in names) + " |")
     return "\n".join(out) + "\n"
 
 
@@ -165,6 +192,8 @@ def main(argv):
     if argv[0] == "stats":
         sys.stdout.write(stats_markdown(argv[1], " ".join(argv[2:])))
         sys.stdout.write("\nBy kernel class:\n\n" + class_markdown(argv[1]))
+    elif argv[0] == "counters":
+        sys.stdout.write(counters_markdown(argv[1], " ".join(argv[2:])))
     elif argv[0] == "traffic":
         # argv: traffic FETCH_DIR WRITE_DIR OUT_DIR WORKLOAD CMD...
         recs = traffic_records(argv[1], argv[2], " ".join(argv[5:]))
