@@ -40,8 +40,9 @@ constexpr int rowb_nt() { return N1 >= 2048 ? 1024 : row_nt<N1>(); }
 // two lanes on a bank where they put eight to sixteen (1.9 % faster per step
 // at 2^19 points).  The longer transforms of a 2^22-point engine stay
 // unpadded: there the larger blocks left less LDS to the other stream's
-// kernels and the step measured 4 % slower.  The equalizer and loss windows
-// stay unpadded too (register spills, extra index arithmetic: slower).
+// kernels and the step measured 4 % slower.  The equalizer windows stay
+// unpadded too (register spills: slower); the FP64 loss frames, with 16-byte
+// points, keep one spare slot per 8 points instead.
 template <int N, bool ROW>
 constexpr int eng_pad() { return (ROW ? N <= 2048 : N <= 256) ? 4 : 0; }
 template <int N, bool ROW>

@@ -31,6 +31,15 @@ constexpr double LOG_EPS = 1e-7;
 template <int N>
 constexpr int loss_fpb() { return N >= 1024 ? 1 : 1024 / N; }
 
+// frames sit in LDS with one spare slot per 8 points: point t of frame fl at
+// buf[fl * loss_bs<N>() + lx(t)].  With 16-byte points the first radix-8
+// passes otherwise put the 8 lanes of each 128-byte LDS cycle on one bank
+// group; with the spare slots they fall on disjoint ones.
+constexpr int LOSS_PAD = 3;
+template <int N>
+constexpr int loss_bs() { return lds_len<N, LOSS_PAD>(); }
+__device__ __forceinline__ int lx(int i) { return lds_ix<LOSS_PAD>(i); }
+
 struct LossTabs {
   const double* win;    // [N]
   const double* aw;     // [N/2+1]
@@ -66,7 +75,7 @@ __device__ __forceinline__ void load_frames(double2* buf, const LossArgs& a, int
       const double wv = a.tb.win[t];
       z = make_double2((double)a.y[s] * wv, (double)a.y[a.L + s] * wv);
     }
-    buf[idx] = z;
+    buf[fl * loss_bs<N>() + lx(t)] = z;
   }
 }
 
@@ -83,7 +92,7 @@ __device__ __forceinline__ void frame_mags(const double2* buf, double* mag, cons
   for (int idx = threadIdx.x; idx < FPB * NB; idx += blockDim.x) {
     const int fl = idx / NB, k = idx % NB;
     double2 xl, xr;
-    split_pair(buf[fl * N + k], buf[fl * N + ((N - k) & (N - 1))], xl, xr);
+    split_pair(buf[fl * loss_bs<N>() + lx(k)], buf[fl * loss_bs<N>() + lx((N - k) & (N - 1))], xl, xr);
     const double aw = a.tb.aw[k];
     double* m = mag + (fl * 4) * NB + k;
     m[0] = aw * sqrt(xl.x * xl.x + xl.y * xl.y);
@@ -110,7 +119,7 @@ __device__ __forceinline__ void frame_mags_inplace(double2* buf, const LossArgs&
     if (idx >= FPB * NB) break;
     const int fl = idx / NB, k = idx % NB;
     double2 xl, xr;
-    split_pair(buf[fl * N + k], buf[fl * N + ((N - k) & (N - 1))], xl, xr);
+    split_pair(buf[fl * loss_bs<N>() + lx(k)], buf[fl * loss_bs<N>() + lx((N - k) & (N - 1))], xl, xr);
     const double aw = a.tb.aw[k];
     m4[q][0] = aw * sqrt(xl.x * xl.x + xl.y * xl.y);
     m4[q][1] = aw * sqrt(xr.x * xr.x + xr.y * xr.y);
@@ -146,11 +155,11 @@ __device__ __forceinline__ double mel_of(const double* mag, const LossArgs& a, i
 // twiddles, magnitudes, dL/dYh per (frame, combo, band)
 template <int N>
 constexpr int loss_fwd_lds() {
-  return loss_fpb<N>() * (N + 2) * 16 + (int)sizeof(TwTab<N, double2>) + LOSS_NT / 64 * 8;
+  return loss_fpb<N>() * loss_bs<N>() * 16 + (int)sizeof(TwTab<N, double2>) + LOSS_NT / 64 * 8;
 }
 template <int N>
 constexpr int loss_bwd_lds() {
-  return loss_fpb<N>() * N * 16 + (int)sizeof(TwTab<N, double2>) + loss_fpb<N>() * 4 * (N / 2 + 1) * 8 +
+  return loss_fpb<N>() * loss_bs<N>() * 16 + (int)sizeof(TwTab<N, double2>) + loss_fpb<N>() * 4 * (N / 2 + 1) * 8 +
          loss_fpb<N>() * 4 * 128 * 8;
 }
 constexpr int cmax(int x, int y) { return x > y ? x : y; }
@@ -169,14 +178,15 @@ template <int N, int MODE>
 __device__ __forceinline__ void loss_fwd_body(const LossArgs& a, int blk, double2* smem) {
   constexpr int FPB = loss_fpb<N>();
   double2* buf = smem;   // spectra, then the magnitudes over them
-  TwTab<N, double2>& tt = *reinterpret_cast<TwTab<N, double2>*>(smem + FPB * (N + 2));
+  static_assert(loss_bs<N>() >= N + 2, "the magnitudes fit over the padded frames");
+  TwTab<N, double2>& tt = *reinterpret_cast<TwTab<N, double2>*>(smem + FPB * loss_bs<N>());
   double* red = reinterpret_cast<double*>(reinterpret_cast<char*>(&tt) + sizeof(TwTab<N, double2>));
   tw_fill<N>(tt, a.tw, (const double2*)nullptr);
   const double* mag = reinterpret_cast<const double*>(buf);
   const int f0 = blk * FPB;
   load_frames<N>(buf, a, f0);
   __syncthreads();
-  fft_lds<N, FPB, N, LOSS_NT, -1>(buf, tt);
+  fft_lds<N, FPB, loss_bs<N>(), LOSS_NT, -1, LOSS_PAD>(buf, tt);
   frame_mags_inplace<N>(buf, a);
   __syncthreads();
   double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
@@ -256,14 +266,14 @@ __device__ __forceinline__ void loss_bwd_body(const LossArgs& a, int blk, double
   constexpr int FPB = loss_fpb<N>();
   constexpr int NB = N / 2 + 1;
   double2* buf = smem;
-  TwTab<N, double2>& tt = *reinterpret_cast<TwTab<N, double2>*>(smem + FPB * N);
+  TwTab<N, double2>& tt = *reinterpret_cast<TwTab<N, double2>*>(smem + FPB * loss_bs<N>());
   double* mag = reinterpret_cast<double*>(reinterpret_cast<char*>(&tt) + sizeof(TwTab<N, double2>));
   double* dyh = mag + FPB * 4 * NB;
   tw_fill<N>(tt, a.tw, (const double2*)nullptr);
   const int f0 = blk * FPB;
   load_frames<N>(buf, a, f0);
   __syncthreads();
-  fft_lds<N, FPB, N, LOSS_NT, -1>(buf, tt);
+  fft_lds<N, FPB, loss_bs<N>(), LOSS_NT, -1, LOSS_PAD>(buf, tt);
   frame_mags<N>(buf, mag, a);
   __syncthreads();
   // dL/dYh per (frame, combo, band); every combo carries weight 1/4 in L_a
@@ -295,7 +305,7 @@ __device__ __forceinline__ void loss_bwd_body(const LossArgs& a, int blk, double
     const int fl = idx / NB, k = idx % NB;
     const int km = (N - k) & (N - 1);
     double2 xl, xr;
-    split_pair(buf[fl * N + k], buf[fl * N + km], xl, xr);
+    split_pair(buf[fl * loss_bs<N>() + lx(k)], buf[fl * loss_bs<N>() + lx(km)], xl, xr);
     const double2 X[4] = {xl, xr, c_add(xl, xr), c_sub(xl, xr)};
     double2 dX[4];
     const double aw = a.tb.aw[k];
@@ -311,22 +321,23 @@ __device__ __forceinline__ void loss_bwd_body(const LossArgs& a, int blk, double
     }
     const double2 gl = c_add(c_add(dX[0], dX[2]), dX[3]);
     const double2 gr = c_sub(c_add(dX[1], dX[2]), dX[3]);
+    double2* fr = buf + fl * loss_bs<N>();
     if (k == 0 || k == N / 2) {
-      buf[fl * N + k] = make_double2(gl.x, gr.x);
+      fr[lx(k)] = make_double2(gl.x, gr.x);
     } else {
       // P[k] = (gl + i gr)/2, P[N-k] = (conj(gl) + i conj(gr))/2
-      buf[fl * N + k] = make_double2(0.5 * (gl.x - gr.y), 0.5 * (gl.y + gr.x));
-      buf[fl * N + km] = make_double2(0.5 * (gl.x + gr.y), 0.5 * (-gl.y + gr.x));
+      fr[lx(k)] = make_double2(0.5 * (gl.x - gr.y), 0.5 * (gl.y + gr.x));
+      fr[lx(km)] = make_double2(0.5 * (gl.x + gr.y), 0.5 * (-gl.y + gr.x));
     }
   }
   __syncthreads();
-  fft_lds<N, FPB, N, LOSS_NT, +1>(buf, tt);
+  fft_lds<N, FPB, loss_bs<N>(), LOSS_NT, +1, LOSS_PAD>(buf, tt);
   for (int idx = threadIdx.x; idx < FPB * N; idx += LOSS_NT) {
     const int fl = idx / N, t = idx % N;
     const int f = f0 + fl;
     if (f >= a.F) continue;
     const double wv = a.tb.win[t];
-    const double2 v = buf[idx];
+    const double2 v = buf[fl * loss_bs<N>() + lx(t)];
     float* o = a.scratch + ((int64_t)f * N + t) * 2;
     o[0] = (float)(v.x * wv);
     o[1] = (float)(v.y * wv);
