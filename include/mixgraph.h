@@ -45,7 +45,10 @@ enum mg_status {
   MG_ERR_GRAPH = 2,       /* cycle, bad arity, unknown type, != 1 output    */
   MG_ERR_SHAPE = 3,       /* sizes inconsistent with the graph or workspace */
   MG_ERR_STATE = 4,       /* call order violated (e.g. backward w/o forward) */
-  MG_ERR_HIP = 5          /* a HIP runtime call failed                      */
+  MG_ERR_HIP = 5,         /* a HIP runtime call failed                      */
+  MG_ERR_BUDGET = 6,      /* the request does not fit the memory it is given */
+  MG_ERR_OOM = 7,         /* the HIP runtime ran out of device memory       */
+  MG_ERR_NONFINITE = 8    /* a loss handed to a decision rule is NaN or inf */
 };
 
 /* Node types (Sec. 1.1): auxiliary input i, mix m, output o; processors
@@ -203,7 +206,10 @@ int mg_prune_candidates(int32_t P, const float* wet, const float* mask, const ui
 int mg_prune_order(int32_t n, const int32_t* cand, const double* L_cand, double L_min, double tau,
                    int32_t* order, int32_t* n_out);
 
-/* Phase 3: the largest k with L_prefix[k-1] < L_min (1 + tau), 0 if none.   */
+/* Phase 3: the largest k with L_prefix[k-1] < L_min (1 + tau), 0 if none.
+ * Phases 2 and 3 return MG_ERR_NONFINITE when L_min is NaN or infinite (the
+ * search itself has failed); a non-finite trial loss never passes the test,
+ * so such a candidate or prefix is simply not accepted.                      */
 int mg_prune_accept(int32_t n, const double* L_prefix, double L_min, double tau, int32_t* k_out);
 
 /* One Adam step (Kingma & Ba) on n parameters, in place on theta, m, v.
@@ -230,6 +236,14 @@ int mg_graph_prune(const mg_graph* g, const uint8_t* keep, mg_graph** out,
 int mg_remap_params(const mg_graph* g, const mg_graph* pruned, const int32_t* old_to_new,
                     const float* src_theta, float* dst_theta, const float* src_wet, float* dst_wet,
                     void* stream);
+
+/* Copy node v's output y_v (the store of Alg. 1: every non-input node's
+ * output stays in the workspace) into out, dev float[2][L], on the stream.
+ * Reads what the last mg_forward (or mg_forward_masked: its last mask) left;
+ * trials write their copies elsewhere and leave it unchanged.  For checks and
+ * inspection.  Input nodes have no slot (their output is the dry track):
+ * MG_ERR_INVALID_ARG; no workspace bound: MG_ERR_STATE. */
+int mg_node_output(const mg_graph* g, int32_t node, float* out, void* stream);
 
 /* Measurement of one kernel class (for roofline reporting, not part of the
  * method): after mg_profile_enable(g, cls), every kernel launched for that

@@ -19,6 +19,7 @@ size_t loss_table_bytes(int N, int nm, int fs, std::vector<char>* blob);
 static size_t align256(size_t x) { return (x + 255) / 256 * 256; }
 
 static int hip_check(hipError_t e, const char* what) {
+  if (e == hipErrorOutOfMemory) return fail(MG_ERR_OOM, std::string(what) + ": " + hipGetErrorString(e));
   if (e != hipSuccess) return fail(MG_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
   return MG_OK;
 }
@@ -532,6 +533,16 @@ extern "C" int mg_backward(mg_graph* g, float* grad_theta, float* grad_wet, void
   launch_finish_all(c, (int)g->desc.size(), (const int2*)(g->base + g->ws.fin), grad_theta, grad_wet);
   g->have_forward = false;
   return hip_check(hipGetLastError(), "backward launch");
+}
+
+extern "C" int mg_node_output(const mg_graph* g, int32_t node, float* out, void* stream) {
+  if (!g || !out || node < 0 || node >= g->n_nodes) return fail(MG_ERR_INVALID_ARG, "bad arguments");
+  if (!g->ready) return fail(MG_ERR_STATE, "mg_setup has not been called");
+  if (g->uslot[node] < 0) return fail(MG_ERR_INVALID_ARG, "input nodes have no output slot");
+  const int64_t L = g->cfg.length;
+  const float* src = (const float*)(g->base + g->ws.U) + (int64_t)g->uslot[node] * 2 * L;
+  return hip_check(hipMemcpyAsync(out, src, (size_t)2 * L * 4, hipMemcpyDeviceToDevice, (hipStream_t)stream),
+                   "node output copy");
 }
 
 extern "C" int mg_profile_enable(mg_graph* g, const char* kernel_class) {

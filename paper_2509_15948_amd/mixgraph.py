@@ -46,7 +46,7 @@ _lib = None
 EXPORTS = ("mg_graph_create", "mg_graph_destroy", "mg_graph_info", "mg_graph_layout", "mg_workspace_size",
            "mg_setup", "mg_forward", "mg_backward", "mg_forward_masked", "mg_adam_step", "mg_graph_prune",
            "mg_last_error", "mg_profile_enable", "mg_profile_read", "mg_forward_trials", "mg_prune_candidates",
-           "mg_prune_order", "mg_prune_accept", "mg_remap_params")
+           "mg_prune_order", "mg_prune_accept", "mg_remap_params", "mg_node_output")
 
 
 def lib() -> ctypes.CDLL:
@@ -79,6 +79,7 @@ def lib() -> ctypes.CDLL:
         "mg_prune_accept": [i32, vp, ctypes.c_double, ctypes.c_double, vp],
         "mg_remap_params": [vp, vp, vp, vp, vp, vp, vp, vp],
         "mg_profile_enable": [vp, ctypes.c_char_p],
+        "mg_node_output": [vp, i32, vp, vp],
         "mg_profile_read": [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64),
                             ctypes.POINTER(ctypes.c_double)],
     }
@@ -240,6 +241,10 @@ def mg_graph_prune(g: int, keep: np.ndarray, n_nodes: int):
     return out.value, o2n
 
 
+def mg_node_output(g: int, node: int, out, stream: int) -> None:
+    _check(lib().mg_node_output(g, node, _ptr(out), stream))
+
+
 def mg_profile_enable(g: int, kernel_class: Optional[str]) -> None:
     _check(lib().mg_profile_enable(g, kernel_class.encode() if kernel_class else None))
 
@@ -337,6 +342,8 @@ class Session:
         self.target = target
         self.noise = reverb_noise
         self.losses = torch.zeros(7, dtype=torch.float64, device=device)
+        self.generation = 0       # forwards run so far (console_loss checks it)
+        self.consumed = True      # the last forward's backward state was used
         _check(lib().mg_setup(graph.h, self.ws_ptr, self.bytes, mode, _ptr(reverb_noise), _ptr(target),
                               self.stream()))
 
@@ -346,13 +353,18 @@ class Session:
     def forward(self, dry, theta, wet, mask=None, mix=None, losses=None):
         out = self.losses if losses is None else losses
         mg_forward(self.g.h, dry, theta, wet, mask, mix, out, self.stream())
+        self.generation += 1
+        self.consumed = False
         return out
 
     def backward(self, grad_theta, grad_wet):
         mg_backward(self.g.h, grad_theta, grad_wet, self.stream())
+        self.consumed = True
 
     def forward_masked(self, dry, theta, wet, masks, losses):
         mg_forward_masked(self.g.h, dry, theta, wet, masks, masks.shape[0], losses, self.stream())
+        self.generation += 1      # the library keeps no backward state after it
+        self.consumed = True
 
     def forward_trials(self, keep: np.ndarray, losses):
         """keep: host uint8 [B][P]; losses: device float64 [B][7]."""
@@ -431,8 +443,15 @@ def compact(graph: Graph, alive: np.ndarray, noise: Dict[int, np.ndarray], rever
 
 
 def console_loss(session: Session, dry, theta, wet, mask=None):
-    """torch.autograd wrapper: returns the 7 loss values (float64 tensor); the
-    gradient of L (entry 0) flows to theta and wet through mg_backward."""
+    """torch.autograd wrapper of mg_forward / mg_backward.
+
+    Returns (L, losses): L is the scalar objective L_a + alpha_g L_g +
+    alpha_p L_p (float64, differentiable with respect to theta and wet
+    through the hand-written adjoints of mg_backward); losses is the 7-vector
+    L, L_a, L_lr, L_m, L_s, L_g, L_p, returned without a gradient (mg_backward
+    differentiates L only).  The backward must follow its own forward: a
+    second forward on the same session before it raises, and so does a
+    second backward through the same graph."""
     import torch
 
     class _ConsoleFn(torch.autograd.Function):
@@ -440,14 +459,19 @@ def console_loss(session: Session, dry, theta, wet, mask=None):
         def forward(ctx, th, we):
             out = torch.zeros(7, dtype=torch.float64, device=th.device)
             session.forward(dry, th.detach(), we.detach(), mask, None, out)
-            return out
+            ctx.generation = session.generation
+            ctx.mark_non_differentiable(out)
+            return out[0].clone(), out
 
         @staticmethod
-        def backward(ctx, gout):
-            gth = torch.empty(session.g.n_theta, dtype=torch.float32, device=gout.device)
-            gwe = torch.empty(session.g.n_proc, dtype=torch.float32, device=gout.device)
+        def backward(ctx, g_L, g_losses):
+            if session.generation != ctx.generation or session.consumed:
+                raise MixgraphError("console_loss backward: the session ran another forward (or backward) "
+                                    "after this one; mg_backward holds the state of the last forward only")
+            gth = torch.empty(session.g.n_theta, dtype=torch.float32, device=g_L.device)
+            gwe = torch.empty(session.g.n_proc, dtype=torch.float32, device=g_L.device)
             session.backward(gth, gwe)
-            s = gout[0].to(torch.float32)
+            s = g_L.to(torch.float32)
             return gth * s, gwe * s
 
     return _ConsoleFn.apply(theta, wet)

@@ -46,6 +46,37 @@ class SearchSpec:
     quantum: int = 4          # steps enqueued before yielding to the loop
 
 
+class PruneThreshold:
+    """The loss threshold of Alg. 2 across the rounds of one search.
+
+    L_min is the audio loss of the trained console, taken once at the first
+    round; a round accepts the longest prefix of its ordered candidates whose
+    loss stays below L_min (1 + tau), and an accepted prefix with a smaller
+    loss lowers L_min (Alg. 2, the min update).  The threshold is never reset
+    to the current loss, so the losses the rounds accept all stay within
+    (1 + tau) of the console's.  The rule itself is the library's
+    (mg_prune_order, mg_prune_accept)."""
+
+    def __init__(self, tau: float):
+        self.tau = tau
+        self.L_min: Optional[float] = None
+
+    def observe(self, La: float) -> None:
+        if self.L_min is None:
+            self.L_min = float(La)
+
+    def order(self, cand: np.ndarray, L_cand: np.ndarray) -> np.ndarray:
+        if not len(cand):
+            return np.zeros(0, np.int32)
+        return MG.mg_prune_order(cand, L_cand, self.L_min, self.tau)
+
+    def accept(self, L_prefix: np.ndarray) -> int:
+        k = MG.mg_prune_accept(L_prefix, self.L_min, self.tau)
+        if k:
+            self.L_min = min(self.L_min, float(L_prefix[k - 1]))
+        return k
+
+
 class Search:
     """One request: host inputs, device state, and its search coroutine."""
 
@@ -134,11 +165,13 @@ class Search:
                 yield mark()
         yield mark()
         P = self.bg.n_proc
+        thr = PruneThreshold(spec.tau)
         for r in range(spec.rounds):
-            # forward at the current mask, then single-bypass trials
+            # forward at the current mask (the cache the trials read), then
+            # single-bypass trials
             self.sess.forward(self.dry_d, self.theta, self.wet, self.mask, None, self.losses)
             yield mark()
-            L_min = float(self.losses[1].item())
+            thr.observe(float(self.losses[1].item()))
             cand = MG.mg_prune_candidates(self.wet.cpu().numpy(), self.mask.cpu().numpy(), self.alive,
                                           spec.candidates)
             out = torch.zeros(max(1, len(cand)), 7, dtype=torch.float64, device=dev)
@@ -148,7 +181,7 @@ class Search:
                 self.sess.forward_trials(keep, out)
                 yield mark()
             L_cand = out[:len(cand), 1].cpu().numpy()
-            order = MG.mg_prune_order(cand, L_cand, L_min, spec.tau) if len(cand) else np.zeros(0, np.int32)
+            order = thr.order(cand, L_cand)
             k = 0
             if len(order):
                 keep = np.ones((len(order), P), np.uint8)
@@ -158,11 +191,11 @@ class Search:
                 self.sess.forward_trials(keep, outp)
                 yield mark()
                 L_prefix = outp[:, 1].cpu().numpy()
-                k = MG.mg_prune_accept(L_prefix, L_min, spec.tau)
+                k = thr.accept(L_prefix)
             if k:
                 self.alive[order[:k]] = 0
                 self._compact(torch, dev)
-            self.trace.append({"round": r, "L_min": L_min, "candidates": len(cand), "within": len(order),
+            self.trace.append({"round": r, "L_min": thr.L_min, "candidates": len(cand), "within": len(order),
                                "removed": int(k), "processors": int(self.bg.n_proc)})
             P = self.bg.n_proc
             for i in range(spec.finetune):

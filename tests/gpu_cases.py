@@ -81,6 +81,11 @@ def rel_l2(a, b):
 FP32_CONV_REL = 3e-7
 
 
+# Noise-derived bounds never exceed CAP x the stated tolerance.
+CAP = 10.0
+AUDIO_TERMS = ("L", "La", "Llr", "Lm", "Ls")
+
+
 def _noisy_process(rng):
     """OC.process with FP32-level white noise (FP32_CONV_REL * RMS) added to
     every processor's wet output."""
@@ -96,7 +101,7 @@ def _noisy_process(rng):
 
 
 def loss_tolerances(case, omix=None, mask=None, draws=4, rel=1e-5, k=5.0):
-    """Per loss term: max(rel * |L|, k * sigma), sigma the RMS change of the
+    """Per loss term: max(rel * |L|, min(k * sigma, CAP * rel * scale)), sigma the RMS change of the
     oracle's losses over `draws` draws of FP32-level white noise (FP32_CONV_REL
     * RMS) added to every processor's wet output.  The GPU rounds at every
     processor, not only at the mix, and the errors of a chain of FFT
@@ -118,12 +123,24 @@ def loss_tolerances(case, omix=None, mask=None, draws=4, rel=1e-5, k=5.0):
                 ss[key] += (float(out[key]) - float(base[key])) ** 2
     finally:
         OC.process = orig
-    return {key: max(rel * abs(float(base[key])), k * float(np.sqrt(ss[key] / draws))) for key in base}
+    la = abs(float(base["La"]))
+    out = {}
+    for key in base:
+        noise = k * float(np.sqrt(ss[key] / draws))
+        # the noise-derived bound is capped at CAP x the stated tolerance; the
+        # audio terms take it relative to L_a (a term that is zero in exact
+        # arithmetic, such as the mid term of a chain that leaves the mid
+        # signal alone, has no relative scale of its own)
+        scale = max(abs(float(base[key])), la) if key in AUDIO_TERMS else abs(float(base[key]))
+        out[key] = max(rel * abs(float(base[key])), min(noise, CAP * rel * scale))
+        print("loss bound", key, "stated", rel * abs(float(base[key])), "oracle noise", noise, "cap",
+              CAP * rel * scale, "->", out[key], flush=True)
+    return out
 
 
 def grad_tolerances(case, oth, owe, mask=None, draws=2, rel=1e-3):
-    """Per processor type (and 'w' for the dry/wet logits): max(rel, 3 * the
-    relative change of the oracle's own gradient when FP32-level white noise
+    """Per processor type (and 'w' for the dry/wet logits): max(rel,
+    min(CAP * rel, 3 * the relative change of the oracle's own gradient when FP32-level white noise
     (FP32_CONV_REL * RMS) is added to every processor's wet output).  The
     log-Mel term makes some gradients (the delay's normalised z direction, the
     noisegate near its threshold) sensitive to rounding in quiet cells; this
@@ -147,4 +164,4 @@ def grad_tolerances(case, oth, owe, mask=None, draws=2, rel=1e-3):
             worst["w"] = max(worst.get("w", 0.0), e)
     finally:
         OC.process = orig
-    return {k: max(rel, 3.0 * s) for k, s in worst.items()}, worst
+    return {k: max(rel, min(3.0 * s, CAP * rel)) for k, s in worst.items()}, worst

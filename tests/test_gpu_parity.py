@@ -1,9 +1,11 @@
 """GPU parity: the HIP path through the C-ABI against the FP64 oracle on the
 same seeded inputs.  Tolerances: waveform relative L2 <= 1e-4, loss terms
-relative <= 1e-5, gradients relative L2 per parameter tensor <= 1e-3.  Where
-the oracle itself moves by more than a third of that under FP32-level noise on
-its processor outputs (quiet log-Mel cells), the bound is 3x that measured
-sensitivity (gpu_cases.loss_tolerances / grad_tolerances)."""
+relative <= 1e-5, gradients relative L2 per parameter tensor <= 1e-3.  On the
+small consoles, where the oracle itself moves by more than that under
+FP32-level noise on its processor outputs (quiet log-Mel cells), the bound is
+that measured sensitivity, capped at 10x the stated tolerance
+(gpu_cases.loss_tolerances / grad_tolerances); the full-size cases use the
+stated tolerances alone."""
 import numpy as np
 import pytest
 import torch
@@ -141,7 +143,8 @@ def test_tiny_console_attack_release_full_size():
 def test_full_console_full_size():
     """16 stereo tracks, 4 subgroups, 10 s at 44.1 kHz, full processor set
     (EQ 2047 taps, 4-tap delay over 0.5 s, 1.5 s reverb): forward and backward
-    at full size from the initial parameters."""
+    at full size from the initial parameters, held to the stated tolerances
+    (waveform 1e-4, losses 1e-5, gradients 1e-3) outright."""
     cfg = synth.CONFIGS["full"]
     case = Case(cfg, seed=1, params="init")
     mix, gl = case.gpu_forward()
@@ -149,7 +152,7 @@ def test_full_console_full_size():
     omix, ol, oth, owe = case.oracle()
     print("full wave", rel_l2(mix, omix), flush=True)
     assert rel_l2(mix, omix) <= WAVE_TOL
-    _check_losses(gl, ol, loss_tolerances(case, omix))
+    _check_losses(gl, ol)
     for t in "ecxsgdr":
         vs = [v for v in case.g.processors() if case.g.types[v] == t]
         err = rel_l2(np.concatenate([gth[v] for v in vs]), np.concatenate([oth[v] for v in vs]))
@@ -165,13 +168,12 @@ def test_full_console_full_size():
                       "fir err", rel_l2(a[c, m, 2:], b[c, m, 2:]), flush=True)
     procs = case.g.processors()
     print("full wet grad err", rel_l2([gwe[v] for v in procs], [owe[v] for v in procs]), flush=True)
-    tol, sens = grad_tolerances(case, oth, owe)
+    # full size: the stated tolerances, with no noise-derived widening
     for t in "ecxsgdr":
         vs = [v for v in case.g.processors() if case.g.types[v] == t]
         err = rel_l2(np.concatenate([gth[v] for v in vs]), np.concatenate([oth[v] for v in vs]))
-        print("full", t, "grad err", err, "oracle FP32 sensitivity", sens[t], "bound", tol[t], flush=True)
-        assert err <= tol[t], (t, err, tol[t])
-    assert rel_l2([gwe[v] for v in procs], [owe[v] for v in procs]) <= tol["w"]
+        assert err <= GRAD_TOL, (t, err)
+    assert rel_l2([gwe[v] for v in procs], [owe[v] for v in procs]) <= GRAD_TOL
 
 
 def test_masked_forward_equals_separate_forwards():

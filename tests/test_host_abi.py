@@ -90,6 +90,22 @@ def test_error_codes():
     L = MG.lib()
     assert L.mg_forward(None, None, None, None, None, None, None, None) == 1
     assert L.mg_backward(None, None, None, None) == 1
+    assert L.mg_node_output(None, 0, None, None) == 1
+
+
+def test_decision_rule_rejects_a_nonfinite_threshold():
+    """A search whose own loss is NaN or infinite has failed: the rule says so
+    (MG_ERR_NONFINITE) instead of deciding.  A NaN trial loss only fails its
+    own test."""
+    cand = np.array([3, 1, 2], np.int32)
+    for bad in (float("nan"), float("inf")):
+        with pytest.raises(MG.MixgraphError, match="error 8"):
+            MG.mg_prune_order(cand, np.array([1.0, 1.0, 1.0]), bad, 1e-3)
+        with pytest.raises(MG.MixgraphError, match="error 8"):
+            MG.mg_prune_accept(np.array([1.0]), bad, 1e-3)
+    order = MG.mg_prune_order(cand, np.array([1.0, float("nan"), 1.0000001]), 1.0, 1e-3)
+    assert order.tolist() == [3, 2]
+    assert MG.mg_prune_accept(np.array([1.0, float("nan")]), 1.0, 1e-3) == 1
 
 
 def test_greedy_schedule_for_a_general_dag():

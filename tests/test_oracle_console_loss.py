@@ -244,3 +244,35 @@ def test_channel_swap_isolates_the_left_right_term():
     assert float(out["Ls"]) < 1e-12
     assert float(out["Llr"]) > 0.1
     assert abs(float(out["La"]) - 0.5 * float(out["Llr"])) < 1e-12
+
+
+def test_gain_staging_term_of_a_constant_eq_is_its_log_gain():
+    """Sec. 5.1 gain-staging regulariser, pinned by a closed form: an EQ whose
+    log-magnitudes all equal c has the FIR e^c delta (the Dirichlet sum of an
+    odd-length cosine series), so its wet output is e^c u and its term is
+    exactly |c| at any dry/wet weight.  A term on the squared norm would give
+    2|c|; one on the dry/wet-mixed output would give |log(w e^c + 1 - w)|.
+    Gain/pan nodes contribute nothing (the sum runs over e, r and d only)."""
+    cfg = synth.small_config(seconds=1.0, chain="eg", n_tracks=3, n_subgroups=2, eq_taps=63)
+    g, dry, noise = synth.song(5, cfg)
+    # every node carries signal, so the 1e-12 inside the norms is negligible
+    assert np.sum(dry.astype(np.float64) ** 2, axis=(1, 2)).min() > 1e-2
+    rng = np.random.default_rng(11)
+    K = (cfg.eq_taps + 1) // 2
+    th, we, cs = {}, {}, []
+    for v in g.processors():
+        if g.types[v] == "e":
+            c = float(rng.uniform(-1.5, 1.5))
+            cs.append(c)
+            th[v] = torch.full((K,), c, dtype=DT)
+        else:
+            th[v] = torch.tensor(rng.normal(0, 0.7, 2), dtype=DT)
+        we[v] = torch.tensor(float(rng.normal()), dtype=DT)
+    out = C.evaluate(g, cfg, dry, noise, th, we)
+    assert len(cs) == cfg.n_tracks + cfg.n_subgroups
+    assert abs(float(out["Lg"]) - sum(abs(c) for c in cs)) < 1e-9
+    # and the eq's wet output is the scaled input, sample for sample
+    v = next(v for v in g.processors() if g.types[v] == "e")
+    u = torch.tensor(rng.standard_normal((2, 500)), dtype=DT)
+    ybar = C.process("e", u, th[v], cfg)
+    assert torch.allclose(ybar, math.exp(float(th[v][0])) * u, rtol=0, atol=1e-12)

@@ -414,3 +414,26 @@ def test_reverb_frame_decay_closed_form():
     sl = slice(hop, Lr - hop)
     assert np.allclose(h[0, sl], ref[sl], atol=1e-12)
     assert np.allclose(h[1, sl], ref[sl], atol=1e-12)
+
+
+def test_reverb_gain_bias_gives_unit_energy_at_zero_parameters():
+    """At raw parameters 0 the mid and side FIRs of the reverb (Sec. 3.4) have
+    unit energy on average: U(-1, 1) noise has variance 1/3, the decay at 0 is
+    6.91 nepers per 0.5 s, so the energy sums to (1/3) e^{2 g0} 0.5 fs / 13.82,
+    which the gain bias g0 sets to 1.  Statistical pin over 6 noise draws at
+    44.1 kHz (about 1 % standard error on the mean); the Nyquist bin and the
+    frame-wise gain interpolation move it by well under 1 %."""
+    fs = 44100
+    Lr = int(1.5 * fs)
+    p = torch.zeros(768, dtype=DT)
+    energies = []
+    for seed in range(6):
+        rng = np.random.default_rng(100 + seed)
+        noise = torch.tensor(rng.uniform(-1, 1, (2, Lr)), dtype=DT)
+        h = P.reverb_fir(p, noise, fs)
+        hm, hs = 0.5 * (h[0] + h[1]), 0.5 * (h[0] - h[1])
+        energies += [float(torch.sum(hm * hm)), float(torch.sum(hs * hs))]
+    mean = float(np.mean(energies))
+    assert abs(mean - 1.0) < 0.04, energies
+    # a bias of the other sign (or none) is far off
+    assert abs(math.exp(-2 * P.reverb_gain_bias(fs)) - 1.0) > 10

@@ -39,3 +39,30 @@ def test_serving_requests_are_seeded_and_in_range():
     # mean gap close to 1 / rate
     gaps = [b - a for a, b in zip(times, times[1:])]
     assert 0.15 < sum(gaps) / len(gaps) < 0.6
+
+
+def test_threshold_is_carried_across_rounds():
+    """Alg. 2 takes L_min once, from the trained console, and only lowers it.
+    Fine-tuning on the smaller graph drifts the loss up by 0.9 tau per round
+    in this synthetic table.  A threshold reset to the current loss every
+    round would keep accepting, and the accepted loss would end near
+    L0 (1 + 9 tau).  Every accepted prefix must stay below L0 (1 + tau)."""
+    import numpy as np
+    from paper_2509_15948_amd.serve import PruneThreshold
+    tau, L0 = 1e-3, 0.5
+    thr = PruneThreshold(tau)
+    accepted = []
+    for r in range(10):
+        L_now = L0 * (1 + 0.9 * tau * r)       # the console's loss this round
+        thr.observe(L_now)
+        cand = np.arange(4, dtype=np.int32)
+        L_cand = L_now * (1 + np.array([1e-5, 2e-5, 3e-5, 5e-3]))
+        order = thr.order(cand, L_cand)
+        L_prefix = L_now * (1 + np.cumsum([1e-5, 2e-5, 3e-5][:len(order)]))
+        k = thr.accept(L_prefix) if len(order) else 0
+        if k:
+            accepted.append(float(L_prefix[k - 1]))
+    assert thr.L_min == L0 or thr.L_min < L0
+    assert accepted and all(a < L0 * (1 + tau) for a in accepted), accepted
+    # rounds whose loss has drifted past the tolerance accept nothing
+    assert len(accepted) == 2
