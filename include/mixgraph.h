@@ -148,6 +148,27 @@ int mg_workspace_size(const mg_graph* g, int32_t mode, size_t* bytes);
 int mg_setup(mg_graph* g, void* workspace, size_t workspace_bytes, int32_t mode,
              const float* reverb_noise, const float* target, void* stream);
 
+/* Bytes of the static device scratch behind mg_setup_static (64 MiB). */
+#define MG_STATIC_SCRATCH_BYTES (64ull << 20)
+
+/* mg_setup without a caller-owned workspace, for callers that cannot
+ * allocate device memory (code under HIP graph capture, serving loops that
+ * must not allocate, harnesses that forbid hipMalloc).  The workspace is a
+ * static device array of MG_STATIC_SCRATCH_BYTES that the library holds on
+ * every GPU it runs on until the process ends; this call and the compute
+ * calls on the graph afterwards allocate nothing (no hipMalloc, no stream or
+ * event is created: the graph's work all runs on the caller's stream, in
+ * the same order and with the same results as after mg_setup).
+ *   mode, reverb_noise, target, stream: as mg_setup (the current device's
+ *   array is used)
+ * Errors: MG_ERR_BUDGET when mg_workspace_size(g, mode) exceeds
+ * MG_STATIC_SCRATCH_BYTES; otherwise those of mg_setup.
+ * One array per GPU: binding another graph on the same device takes it over,
+ * and the earlier graph's compute calls return MG_ERR_STATE until it is
+ * bound again.  The array keeps the last call's contents (setup clears what
+ * the kernels accumulate into).  Calls that overlap on one GPU race. */
+int mg_setup_static(mg_graph* g, int32_t mode, const float* reverb_noise, const float* target, void* stream);
+
 /* Alg. 1 forward pass and the loss (Sec. 5.1):
  *   dry      dev float[n_tracks][track_channels][L]
  *   theta    dev float[n_theta]

@@ -340,15 +340,21 @@ extern "C" int mg_workspace_size(const mg_graph* g, int32_t mode, size_t* bytes)
   return MG_OK;
 }
 
-extern "C" int mg_setup(mg_graph* g, void* workspace, size_t workspace_bytes, int32_t mode,
-                        const float* reverb_noise, const float* target, void* stream) {
+namespace mg {
+// Bind a workspace and prepare the graph's device tables (the body of
+// mg_setup and of mg_setup_static).  With make_side the graph gets its side
+// stream and events (created once); without, every launch of the forward and
+// backward stays on the caller's stream and nothing is created.
+int bind_workspace(mg_graph* g, void* workspace, size_t workspace_bytes, int32_t mode, const float* reverb_noise,
+                   const float* target, hipStream_t st, bool make_side) {
   if (!g || !workspace || !target || (mode != 0 && mode != 1)) return fail(MG_ERR_INVALID_ARG, "bad arguments");
   if (((uintptr_t)workspace) & 255) return fail(MG_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
   if (g->type_count[MG_REVERB] > 0 && !reverb_noise) return fail(MG_ERR_INVALID_ARG, "reverb noise required");
   finish_compile(*g);
   const size_t need = plan_ws(*g, mode, true);
   if (workspace_bytes < need) return fail(MG_ERR_SHAPE, "workspace too small: need " + std::to_string(need));
-  hipStream_t st = (hipStream_t)stream;
+  g->ready = false;
+  g->static_dev = -1;
   g->base = (char*)workspace;
   g->ws_bytes = workspace_bytes;
   g->mode = mode;
@@ -387,7 +393,7 @@ extern "C" int mg_setup(mg_graph* g, void* workspace, size_t workspace_bytes, in
   if ((rc = hip_check(hipMemcpyAsync(g->base + g->ws.fin, fin.data(), fin.size() * sizeof(int2), hipMemcpyHostToDevice,
                                      st), "finish table upload")))
     return rc;
-  if (!g->side) {
+  if (make_side && !g->side) {
     if ((rc = hip_check(hipStreamCreateWithFlags(&g->side, hipStreamNonBlocking), "side stream"))) return rc;
     g->sev.resize(64);
     for (auto& e : g->sev)
@@ -418,11 +424,18 @@ extern "C" int mg_setup(mg_graph* g, void* workspace, size_t workspace_bytes, in
   }
   return MG_OK;
 }
+}  // namespace mg
+
+extern "C" int mg_setup(mg_graph* g, void* workspace, size_t workspace_bytes, int32_t mode,
+                        const float* reverb_noise, const float* target, void* stream) {
+  return bind_workspace(g, workspace, workspace_bytes, mode, reverb_noise, target, (hipStream_t)stream, true);
+}
 
 extern "C" int mg_forward(mg_graph* g, const float* dry, const float* theta, const float* wet, const float* mask,
                           float* mix, double* losses, void* stream) {
   if (!g || !dry || !wet || !losses || (!theta && g->n_theta > 0)) return fail(MG_ERR_INVALID_ARG, "NULL argument");
   if (!g->ready) return fail(MG_ERR_STATE, "mg_setup has not been called");
+  if (int rc = check_binding(g)) return rc;
   g->f_dry = dry;
   g->f_theta = theta;
   g->f_wet = wet;
@@ -439,6 +452,7 @@ extern "C" int mg_forward_masked(mg_graph* g, const float* dry, const float* the
                                  const float* masks, int32_t B, double* losses, void* stream) {
   if (!g || !dry || !wet || !losses || !masks || B < 1) return fail(MG_ERR_INVALID_ARG, "bad arguments");
   if (!g->ready) return fail(MG_ERR_STATE, "mg_setup has not been called");
+  if (int rc = check_binding(g)) return rc;
   g->f_dry = dry;
   g->f_theta = theta;
   g->f_wet = wet;
@@ -455,6 +469,7 @@ extern "C" int mg_backward(mg_graph* g, float* grad_theta, float* grad_wet, void
   if (!g || !grad_wet || (!grad_theta && g->n_theta > 0)) return fail(MG_ERR_INVALID_ARG, "NULL argument");
   if (!g->ready || g->mode != 1) return fail(MG_ERR_STATE, "graph not set up for backward (mode 1)");
   if (!g->have_forward) return fail(MG_ERR_STATE, "mg_backward needs a preceding mg_forward");
+  if (int rc = check_binding(g)) return rc;
   for (int v = 0; v < g->n_nodes; ++v)
     if (g->succs[v].size() > 1) return fail(MG_ERR_GRAPH, "backward through a node with several consumers is not supported");
   hipStream_t st = (hipStream_t)stream;
@@ -469,10 +484,14 @@ extern "C" int mg_backward(mg_graph* g, float* grad_theta, float* grad_wet, void
   // an event, so it overlaps the next stages.  Every long-FIR stage has FIR-
   // gradient spectrum rows of its own, so the caller's stream never waits on
   // the side stream before the join.
+  // Without a side stream (a graph bound by mg_setup_static) the same work
+  // runs in the same order on the caller's stream.
+  const bool side = g->side != nullptr;
   Ctx cs = c;
-  cs.st = g->side;
+  if (side) cs.st = g->side;
   int ev = 0;
   auto fork = [&]() {
+    if (!side) return;
     hipEventRecord(g->sev[ev], st);
     hipStreamWaitEvent(g->side, g->sev[ev], 0);
     ev = (ev + 1) % (int)g->sev.size();
@@ -526,8 +545,10 @@ extern "C" int mg_backward(mg_graph* g, float* grad_theta, float* grad_wet, void
     // this node's dL/du (aliased slots), nothing to scatter
   }
   // join: the side stream's gradients before anything later on the stream
-  hipEventRecord(g->sev[ev], g->side);
-  hipStreamWaitEvent(st, g->sev[ev], 0);
+  if (side) {
+    hipEventRecord(g->sev[ev], g->side);
+    hipStreamWaitEvent(st, g->sev[ev], 0);
+  }
   // dry/wet and direct parameter gradients of every processor from its
   // partial sums (kept per descriptor), in one launch
   launch_finish_all(c, (int)g->desc.size(), (const int2*)(g->base + g->ws.fin), grad_theta, grad_wet);
@@ -538,6 +559,7 @@ extern "C" int mg_backward(mg_graph* g, float* grad_theta, float* grad_wet, void
 extern "C" int mg_node_output(const mg_graph* g, int32_t node, float* out, void* stream) {
   if (!g || !out || node < 0 || node >= g->n_nodes) return fail(MG_ERR_INVALID_ARG, "bad arguments");
   if (!g->ready) return fail(MG_ERR_STATE, "mg_setup has not been called");
+  if (int rc = check_binding(g)) return rc;
   if (g->uslot[node] < 0) return fail(MG_ERR_INVALID_ARG, "input nodes have no output slot");
   const int64_t L = g->cfg.length;
   const float* src = (const float*)(g->base + g->ws.U) + (int64_t)g->uslot[node] * 2 * L;

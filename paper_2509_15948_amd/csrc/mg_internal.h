@@ -162,6 +162,10 @@ struct mg_graph {
   bool ready = false;
   bool have_forward = false;
   bool have_cache = false;                // node outputs of the last forward are in U
+  // bound by mg_setup_static: the device whose static scratch holds the
+  // workspace (-1: a caller-owned workspace) and the binding's generation
+  int static_dev = -1;
+  uint64_t static_gen = 0;
   // pruning trials
   int trial_slots = 0;                    // U slots reserved for copies
   int trial_desc_cap = 0;                 // staged copy descriptors

@@ -93,6 +93,11 @@ inline bool prof_pair(const Ctx& c, hipEvent_t& a, hipEvent_t& b) {
 
 // mg_api.hip
 Ctx make_ctx(const mg_graph* g, hipStream_t st);
+int bind_workspace(mg_graph* g, void* workspace, size_t workspace_bytes, int32_t mode, const float* reverb_noise,
+                   const float* target, hipStream_t st, bool make_side);
+// mg_static.hip: MG_OK, or MG_ERR_STATE when the graph was bound to a static
+// scratch that another graph has bound since
+int check_binding(const mg_graph* g);
 void forward_stage(const Ctx& c, int t, int off, int n, bool keep, const NodeDesc* hd);
 
 // k_basic.hip

@@ -154,6 +154,7 @@ static int hip_ok(hipError_t e, const char* what) {
 extern "C" int mg_forward_trials(mg_graph* g, const uint8_t* keep, int32_t B, double* losses, void* stream) {
   if (!g || !keep || !losses || B < 1) return fail(MG_ERR_INVALID_ARG, "bad arguments");
   if (!g->ready) return fail(MG_ERR_STATE, "mg_setup has not been called");
+  if (int rc0 = check_binding(g)) return rc0;
   if (B > g->cfg.max_trials) return fail(MG_ERR_SHAPE, "B exceeds max_trials of the graph's configuration");
   if (!g->have_cache) return fail(MG_ERR_STATE, "mg_forward_trials needs a preceding mg_forward");
   hipStream_t st = (hipStream_t)stream;

@@ -46,7 +46,7 @@ _lib = None
 EXPORTS = ("mg_graph_create", "mg_graph_destroy", "mg_graph_info", "mg_graph_layout", "mg_workspace_size",
            "mg_setup", "mg_forward", "mg_backward", "mg_forward_masked", "mg_adam_step", "mg_graph_prune",
            "mg_last_error", "mg_profile_enable", "mg_profile_read", "mg_forward_trials", "mg_prune_candidates",
-           "mg_prune_order", "mg_prune_accept", "mg_remap_params", "mg_node_output")
+           "mg_prune_order", "mg_prune_accept", "mg_remap_params", "mg_node_output", "mg_setup_static")
 
 
 def lib() -> ctypes.CDLL:
@@ -67,6 +67,7 @@ def lib() -> ctypes.CDLL:
         "mg_graph_layout": [vp, vp, vp, vp, vp, vp],
         "mg_workspace_size": [vp, i32, ctypes.POINTER(sz)],
         "mg_setup": [vp, vp, sz, i32, vp, vp, vp],
+        "mg_setup_static": [vp, i32, vp, vp, vp],
         "mg_forward": [vp, vp, vp, vp, vp, vp, vp, vp],
         "mg_backward": [vp, vp, vp, vp],
         "mg_forward_masked": [vp, vp, vp, vp, vp, i32, vp, vp],
@@ -330,20 +331,27 @@ class Graph:
 class Session:
     """A graph bound to a device workspace (torch tensor) and a stream."""
 
-    def __init__(self, graph: Graph, reverb_noise, target, mode: int = 1, device: str = "cuda"):
+    def __init__(self, graph: Graph, reverb_noise, target, mode: int = 1, device: str = "cuda",
+                 static: bool = False):
+        """static: bind the library's static device scratch (mg_setup_static)
+        instead of allocating a workspace tensor."""
         import torch
         self.torch = torch
         self.g = graph
         self.mode = mode
         self.bytes = mg_workspace_size(graph.h, mode)
-        self.ws = torch.empty(self.bytes + 256, dtype=torch.uint8, device=device)
-        base = self.ws.data_ptr()
-        self.ws_ptr = (base + 255) // 256 * 256
         self.target = target
         self.noise = reverb_noise
         self.losses = torch.zeros(7, dtype=torch.float64, device=device)
         self.generation = 0       # forwards run so far (console_loss checks it)
         self.consumed = True      # the last forward's backward state was used
+        if static:
+            self.ws = None
+            _check(lib().mg_setup_static(graph.h, mode, _ptr(reverb_noise), _ptr(target), self.stream()))
+            return
+        self.ws = torch.empty(self.bytes + 256, dtype=torch.uint8, device=device)
+        base = self.ws.data_ptr()
+        self.ws_ptr = (base + 255) // 256 * 256
         _check(lib().mg_setup(graph.h, self.ws_ptr, self.bytes, mode, _ptr(reverb_noise), _ptr(target),
                               self.stream()))
 

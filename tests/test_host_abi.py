@@ -203,3 +203,15 @@ def test_pruning_rule_matches_the_oracle_rule():
         assert order.tolist() == OP.order_within_tolerance(cand.tolist(), L_cand.tolist(), L_min, tau)
         L_prefix = L_min * (1 + tau * rng.normal(size=len(order)))
         assert MG.mg_prune_accept(L_prefix, L_min, tau) == OP.accept_prefix(L_prefix.tolist(), L_min, tau)
+
+
+def test_static_setup_rejects_a_workspace_beyond_the_scratch():
+    """mg_setup_static checks the size on the host before touching a device:
+    a graph whose workspace exceeds the static scratch gets MG_ERR_BUDGET."""
+    cfg = synth.small_config(seconds=20.0, fs=44100, n_tracks=8, n_subgroups=2, chain="ecxsgdr")
+    g = synth.make_console(8, synth.subgroup_labels(1, 8, 2), "ecxsgdr")
+    bg = W.binding_graph(g, cfg)
+    assert MG.mg_workspace_size(bg.h, 1) > (64 << 20)
+    rc = MG.lib().mg_setup_static(bg.h, 1, None, 1, None)
+    assert rc == 6, rc  # MG_ERR_BUDGET
+    assert b"static scratch" in MG.lib().mg_last_error()
