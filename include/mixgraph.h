@@ -221,22 +221,75 @@ int mg_prune_candidates(int32_t P, const float* wet, const float* mask, const ui
                         int32_t* cand, int32_t* n_out);
 
 /* Phase 2: from the single-bypass losses L_cand[i] of cand[i] (i < n), keep
- * those with L_cand - L_min < tau * L_min, ordered by (L_cand - L_min, index)
- * into order; *n_out their count.  The trial masks of phase 3 bypass the
- * prefixes order[0..k-1], k = 1..*n_out.                                    */
+ * those with L_cand - L_min < tol, ordered by (L_cand - L_min, index) into
+ * order; *n_out their count.  tol = tau * L_min when relative != 0 (the
+ * benchmark configuration's 1e-3), tol = tau otherwise (the paper's absolute
+ * tolerance, Sec. 6.1).  The trial masks of phase 3 bypass the prefixes
+ * order[0..k-1], k = 1..*n_out.                                            */
 int mg_prune_order(int32_t n, const int32_t* cand, const double* L_cand, double L_min, double tau,
-                   int32_t* order, int32_t* n_out);
+                   int32_t relative, int32_t* order, int32_t* n_out);
 
-/* Phase 3: the largest k with L_prefix[k-1] < L_min (1 + tau), 0 if none.
+/* Phase 3: the largest k with L_prefix[k-1] < L_min (1 + tau) (relative) or
+ * < L_min + tau (absolute), 0 if none.
  * Phases 2 and 3 return MG_ERR_NONFINITE when L_min is NaN or infinite (the
  * search itself has failed); a non-finite trial loss never passes the test,
  * so such a candidate or prefix is simply not accepted.                      */
-int mg_prune_accept(int32_t n, const double* L_prefix, double L_min, double tau, int32_t* k_out);
+int mg_prune_accept(int32_t n, const double* L_prefix, double L_min, double tau, int32_t relative,
+                    int32_t* k_out);
+
+/* The dry/wet method (Alg. 3, Sec. 6.2 "Candidate Sampling"), host only: one
+ * pruning iteration as a sequence of trials the caller evaluates.
+ *   mg_drywet_begin: P processors; proc_type host int32[P] (enum mg_type of
+ *     each processor, proc_index order); wet, mask (NULL: ones), alive as
+ *     mg_prune_candidates; L_min the threshold; tau with relative as
+ *     mg_prune_order; u host double[n_u]: the uniform draws in [0, 1) that
+ *     pick the type of each trial (the floor(u |T|)-th remaining type in the
+ *     order e c n x s g d r), one per trial.  Per type: N_t = its alive count,
+ *     r_t = 0.1.
+ *   mg_drywet_next: keep host uint8[P] receives the next trial (0: bypassed:
+ *     what is pruned so far plus the floor(N_t r_t + 1/2) least-weight alive
+ *     processors of the drawn type, at least one, ties by index); *done = 1
+ *     and keep untouched when no type is left.  MG_ERR_SHAPE when the draws
+ *     run out, MG_ERR_STATE when the last trial's loss was not reported.
+ *   mg_drywet_report: the loss L_a of that trial.  L passing the tolerance
+ *     test prunes the candidates and sets L_min = min(L_min, L) (the type
+ *     leaves once all its processors are pruned); otherwise r_t is halved if
+ *     floor(N_t r_t + 1/2) > 1, else the type leaves.  A NaN loss fails.
+ *   mg_drywet_end: keep host uint8[P] (may be NULL) receives the final mask
+ *     (1 = kept), *L_min the threshold, *trials the trial count; frees s.   */
+typedef struct mg_drywet mg_drywet;
+int mg_drywet_begin(int32_t P, const int32_t* proc_type, const float* wet, const float* mask,
+                    const uint8_t* alive, double L_min, double tau, int32_t relative, const double* u,
+                    int32_t n_u, mg_drywet** out);
+int mg_drywet_next(mg_drywet* s, uint8_t* keep, int32_t* done);
+int mg_drywet_report(mg_drywet* s, double L);
+int mg_drywet_end(mg_drywet* s, uint8_t* keep, double* L_min, int32_t* trials);
 
 /* One Adam step (Kingma & Ba) on n parameters, in place on theta, m, v.
  * step counts from 1.  All pointers dev float[n]. */
 int mg_adam_step(float* theta, float* m, float* v, const float* grad, int64_t n,
                  float lr, float beta1, float beta2, float eps, int32_t step, void* stream);
+
+/* AdamW (Loshchilov & Hutter, the optimiser of Sec. 5.1): the decoupled
+ * weight decay scales theta by 1 - lr * weight_decay, then the Adam step of
+ * mg_adam_step follows (weight_decay = 0 gives mg_adam_step bit for bit).
+ * All pointers dev float[n]; step counts from 1.                            */
+int mg_adamw_step(float* theta, float* m, float* v, const float* grad, int64_t n, float lr, float beta1,
+                  float beta2, float eps, float weight_decay, int32_t step, void* stream);
+
+/* A new target mix for the loss (Sec. 5.1: each step compares the mix of a
+ * random segment with the same segment of the target): recomputes the
+ * resident target Mel features from target, dev float[2][L] of the graph's
+ * length, on the stream.  A pending mg_backward and the cached forward of
+ * mg_forward_trials are dropped (MG_ERR_STATE until the next mg_forward).   */
+int mg_target_prepare(mg_graph* g, const float* target, void* stream);
+
+/* The regulariser weights alpha_g and alpha_p of L = L_a + alpha_g L_g +
+ * alpha_p L_p (Sec. 5.1, Sec. 6.3: alpha_p rises during pruning), used from
+ * the next mg_forward on.  MG_ERR_STATE between a forward and its backward
+ * (the two must see the same weights); MG_ERR_INVALID_ARG for a negative
+ * weight.  Host only.                                                       */
+int mg_set_alpha(mg_graph* g, double alpha_g, double alpha_p);
 
 /* Graph surgery for pruning (Sec. 1.2: removing a node and rerouting its
  * edges is equivalent to bypass).  keep: host uint8[P] over processors in

@@ -101,3 +101,13 @@ def adam_step(theta: np.ndarray, m: np.ndarray, v: np.ndarray, g: np.ndarray, st
     vh = v / (1.0 - b2 ** step)
     theta -= lr * mh / (np.sqrt(vh) + eps)
     return theta, m, v
+
+
+def adamw_step(theta: np.ndarray, m: np.ndarray, v: np.ndarray, g: np.ndarray, step: int,
+               lr: float = 1e-2, b1: float = 0.9, b2: float = 0.999, eps: float = 1e-8,
+               weight_decay: float = 1e-2):
+    """One AdamW update (Loshchilov & Hutter, decoupled weight decay), in
+    place: the parameters shrink by lr * weight_decay times themselves, then
+    take the Adam step; step counts from 1."""
+    theta *= 1.0 - lr * weight_decay
+    return adam_step(theta, m, v, g, step, lr, b1, b2, eps)

@@ -778,27 +778,33 @@ void launch_finalize_trials(const Ctx& c, double* losses, const double* lstats, 
 }
 
 // ---------------------------------------------------------------- Adam
+// Adam (Kingma & Ba); with decay != 1 the decoupled weight decay of AdamW
+// (Loshchilov & Hutter) scales the parameter first: decay = 1 - lr * wd.
+// decay = 1 multiplies exactly, so Adam is AdamW with wd = 0 bit for bit.
 __global__ __launch_bounds__(MG_BLOCK) void k_adam(float* __restrict__ th, float* __restrict__ m,
                                                     float* __restrict__ v, const float* __restrict__ g, int64_t n,
-                                                    float lr, float b1, float b2, float eps, float c1, float c2) {
+                                                    float lr, float b1, float b2, float eps, float c1, float c2,
+                                                    float decay) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
     const float gi = g[i];
     const float mi = b1 * m[i] + (1.0f - b1) * gi;
     const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
     m[i] = mi;
     v[i] = vi;
-    th[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+    th[i] = th[i] * decay - lr * (mi / c1) / (sqrtf(vi / c2) + eps);
   }
 }
 
 void launch_adam(float* th, float* m, float* v, const float* g, int64_t n, float lr, float b1, float b2, float eps,
-                 int step, hipStream_t st) {
+                 int step, hipStream_t st, float weight_decay) {
   const float c1 = (float)(1.0 - pow((double)b1, step));
   const float c2 = (float)(1.0 - pow((double)b2, step));
+  const float decay = (float)(1.0 - (double)lr * (double)weight_decay);
   int64_t blocks = (n + MG_BLOCK - 1) / MG_BLOCK;
   if (blocks > 4096) blocks = 4096;
   if (blocks < 1) blocks = 1;
-  hipLaunchKernelGGL(k_adam, dim3((unsigned)blocks), dim3(MG_BLOCK), 0, st, th, m, v, g, n, lr, b1, b2, eps, c1, c2);
+  hipLaunchKernelGGL(k_adam, dim3((unsigned)blocks), dim3(MG_BLOCK), 0, st, th, m, v, g, n, lr, b1, b2, eps, c1, c2,
+                     decay);
 }
 
 // Trial masks: the mask of the cached forward times each trial's keep flags.

@@ -658,7 +658,11 @@ void loss_setup(const Ctx& c, const float* target) {
     hipMemcpyAsync(c.base + g->lres[i].tab_off, blob.data(), blob.size(), hipMemcpyHostToDevice, c.st);
     hipStreamSynchronize(c.st);
   }
-  launch_zero(c.base + g->ws.ls_stats, 8 * sizeof(double) * 16, c.st);
+  loss_target(c, target);
+}
+
+void loss_target(const Ctx& c, const float* target) {
+  launch_zero(c.base + c.g->ws.ls_stats, 8 * sizeof(double) * 16, c.st);
   run_loss_fwd(c, target, 0, nullptr);
 }
 

@@ -118,7 +118,7 @@ void launch_finalize_losses(const Ctx& c, double* losses, const double* lstats, 
 void launch_finalize_trials(const Ctx& c, double* losses, const double* lstats, int n_res, int n_desc,
                             const float* mask, int P, const int* sub, int n_trials);
 void launch_adam(float* th, float* m, float* v, const float* g, int64_t n, float lr, float b1, float b2, float eps,
-                 int step, hipStream_t st);
+                 int step, hipStream_t st, float weight_decay = 0.0f);
 void launch_zero(void* p, size_t bytes, hipStream_t st);
 // mask[b][p] = (base ? base[p] : 1) * keep[b][p]
 void launch_trial_mask(float* mask, const float* base, const float* keep, int P, int B, hipStream_t st);
@@ -152,6 +152,8 @@ void dyn_backward(const Ctx& c, int type, int desc_off, int n);
 
 // k_loss.hip
 void loss_setup(const Ctx& c, const float* target);
+// the resident target features of a new target mix (tables already set up)
+void loss_target(const Ctx& c, const float* target);
 // stats: per-resolution statistics output (nullptr: the graph's own, which
 // the backward reads)
 void loss_forward(const Ctx& c, const float* yhat, double* stats = nullptr);

@@ -241,12 +241,12 @@ extern "C" int mg_prune_candidates(int32_t P, const float* wet, const float* mas
 }
 
 extern "C" int mg_prune_order(int32_t n, const int32_t* cand, const double* L_cand, double L_min, double tau,
-                              int32_t* order, int32_t* n_out) {
+                              int32_t relative, int32_t* order, int32_t* n_out) {
   if (n < 0 || (n > 0 && (!cand || !L_cand || !order)) || !n_out) return fail(MG_ERR_INVALID_ARG, "bad arguments");
   if (!std::isfinite(L_min)) return fail(MG_ERR_NONFINITE, "L_min is not finite");
   std::vector<int> keep;
   for (int i = 0; i < n; ++i)
-    if (L_cand[i] - L_min < tau * L_min) keep.push_back(i);
+    if (L_cand[i] - L_min < (relative ? tau * L_min : tau)) keep.push_back(i);
   std::stable_sort(keep.begin(), keep.end(), [&](int a, int b) {
     const double da = L_cand[a] - L_min, db = L_cand[b] - L_min;
     return da < db || (da == db && cand[a] < cand[b]);
@@ -256,12 +256,13 @@ extern "C" int mg_prune_order(int32_t n, const int32_t* cand, const double* L_ca
   return MG_OK;
 }
 
-extern "C" int mg_prune_accept(int32_t n, const double* L_prefix, double L_min, double tau, int32_t* k_out) {
+extern "C" int mg_prune_accept(int32_t n, const double* L_prefix, double L_min, double tau, int32_t relative,
+                               int32_t* k_out) {
   if (n < 0 || (n > 0 && !L_prefix) || !k_out) return fail(MG_ERR_INVALID_ARG, "bad arguments");
   if (!std::isfinite(L_min)) return fail(MG_ERR_NONFINITE, "L_min is not finite");
   int k = 0;
   for (int i = 0; i < n; ++i)
-    if (L_prefix[i] < L_min * (1.0 + tau)) k = i + 1;
+    if (L_prefix[i] < (relative ? L_min * (1.0 + tau) : L_min + tau)) k = i + 1;
   *k_out = k;
   return MG_OK;
 }

@@ -46,7 +46,9 @@ _lib = None
 EXPORTS = ("mg_graph_create", "mg_graph_destroy", "mg_graph_info", "mg_graph_layout", "mg_workspace_size",
            "mg_setup", "mg_forward", "mg_backward", "mg_forward_masked", "mg_adam_step", "mg_graph_prune",
            "mg_last_error", "mg_profile_enable", "mg_profile_read", "mg_forward_trials", "mg_prune_candidates",
-           "mg_prune_order", "mg_prune_accept", "mg_remap_params", "mg_node_output", "mg_setup_static")
+           "mg_prune_order", "mg_prune_accept", "mg_remap_params", "mg_node_output", "mg_setup_static",
+           "mg_drywet_begin", "mg_drywet_next", "mg_drywet_report", "mg_drywet_end", "mg_adamw_step",
+           "mg_target_prepare", "mg_set_alpha")
 
 
 def lib() -> ctypes.CDLL:
@@ -76,8 +78,17 @@ def lib() -> ctypes.CDLL:
         "mg_graph_prune": [vp, vp, ctypes.POINTER(vp), vp],
         "mg_forward_trials": [vp, vp, i32, vp, vp],
         "mg_prune_candidates": [i32, vp, vp, vp, i32, vp, vp],
-        "mg_prune_order": [i32, vp, vp, ctypes.c_double, ctypes.c_double, vp, vp],
-        "mg_prune_accept": [i32, vp, ctypes.c_double, ctypes.c_double, vp],
+        "mg_prune_order": [i32, vp, vp, ctypes.c_double, ctypes.c_double, i32, vp, vp],
+        "mg_prune_accept": [i32, vp, ctypes.c_double, ctypes.c_double, i32, vp],
+        "mg_drywet_begin": [i32, vp, vp, vp, vp, ctypes.c_double, ctypes.c_double, i32, vp, i32,
+                            ctypes.POINTER(vp)],
+        "mg_drywet_next": [vp, vp, vp],
+        "mg_adamw_step": [vp, vp, vp, vp, i64, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                          ctypes.c_float, i32, vp],
+        "mg_target_prepare": [vp, vp, vp],
+        "mg_set_alpha": [vp, ctypes.c_double, ctypes.c_double],
+        "mg_drywet_report": [vp, ctypes.c_double],
+        "mg_drywet_end": [vp, vp, vp, vp],
         "mg_remap_params": [vp, vp, vp, vp, vp, vp, vp, vp],
         "mg_profile_enable": [vp, ctypes.c_char_p],
         "mg_node_output": [vp, i32, vp, vp],
@@ -205,21 +216,82 @@ def mg_prune_candidates(wet: np.ndarray, mask: Optional[np.ndarray], alive: np.n
     return out[:n.value].copy()
 
 
-def mg_prune_order(cand: np.ndarray, L_cand: np.ndarray, L_min: float, tau: float) -> np.ndarray:
+def mg_prune_order(cand: np.ndarray, L_cand: np.ndarray, L_min: float, tau: float,
+                   relative: bool = True) -> np.ndarray:
     c = np.ascontiguousarray(cand, dtype=np.int32)
     lc = np.ascontiguousarray(L_cand, dtype=np.float64)
     out = np.zeros(max(1, len(c)), np.int32)
     n = ctypes.c_int32()
-    _check(lib().mg_prune_order(len(c), c.ctypes.data, lc.ctypes.data, L_min, tau, out.ctypes.data,
+    _check(lib().mg_prune_order(len(c), c.ctypes.data, lc.ctypes.data, L_min, tau, int(relative), out.ctypes.data,
                                 ctypes.byref(n)))
     return out[:n.value].copy()
 
 
-def mg_prune_accept(L_prefix: np.ndarray, L_min: float, tau: float) -> int:
+def mg_prune_accept(L_prefix: np.ndarray, L_min: float, tau: float, relative: bool = True) -> int:
     lp = np.ascontiguousarray(L_prefix, dtype=np.float64)
     k = ctypes.c_int32()
-    _check(lib().mg_prune_accept(len(lp), lp.ctypes.data if len(lp) else None, L_min, tau, ctypes.byref(k)))
+    _check(lib().mg_prune_accept(len(lp), lp.ctypes.data if len(lp) else None, L_min, tau, int(relative),
+                                 ctypes.byref(k)))
     return k.value
+
+
+class DryWet:
+    """The dry/wet method's trial sequence (mg_drywet_*): next() proposes a
+    keep mask (uint8 [P], 0 = bypassed) or None when done; report(L) hands
+    back its loss; end() returns (final keep mask, L_min, trial count)."""
+
+    def __init__(self, proc_type: np.ndarray, wet: np.ndarray, mask: Optional[np.ndarray], alive: np.ndarray,
+                 L_min: float, tau: float, relative: bool, uniforms: np.ndarray):
+        self.P = len(proc_type)
+        self._pt = np.ascontiguousarray(proc_type, dtype=np.int32)
+        self._we = np.ascontiguousarray(wet, dtype=np.float32)
+        self._m = None if mask is None else np.ascontiguousarray(mask, dtype=np.float32)
+        self._al = np.ascontiguousarray(alive, dtype=np.uint8)
+        self._u = np.ascontiguousarray(uniforms, dtype=np.float64)
+        h = ctypes.c_void_p()
+        _check(lib().mg_drywet_begin(self.P, self._pt.ctypes.data, self._we.ctypes.data,
+                                     None if self._m is None else self._m.ctypes.data, self._al.ctypes.data,
+                                     float(L_min), float(tau), int(relative), self._u.ctypes.data, len(self._u),
+                                     ctypes.byref(h)))
+        self.h = h.value
+
+    def next(self) -> Optional[np.ndarray]:
+        keep = np.ones(max(1, self.P), np.uint8)
+        done = ctypes.c_int32()
+        _check(lib().mg_drywet_next(self.h, keep.ctypes.data, ctypes.byref(done)))
+        return None if done.value else keep[:self.P]
+
+    def report(self, L: float) -> None:
+        _check(lib().mg_drywet_report(self.h, float(L)))
+
+    def end(self):
+        keep = np.ones(max(1, self.P), np.uint8)
+        L = ctypes.c_double()
+        n = ctypes.c_int32()
+        _check(lib().mg_drywet_end(self.h, keep.ctypes.data, ctypes.byref(L), ctypes.byref(n)))
+        self.h = None
+        return keep[:self.P], L.value, n.value
+
+    def __del__(self):
+        if getattr(self, "h", None):
+            try:
+                lib().mg_drywet_end(self.h, None, None, None)
+            except Exception:
+                pass
+
+
+def mg_adamw_step(theta, m, v, grad, n: int, lr: float, b1: float, b2: float, eps: float, weight_decay: float,
+                  step: int, stream: int) -> None:
+    _check(lib().mg_adamw_step(_ptr(theta), _ptr(m), _ptr(v), _ptr(grad), n, lr, b1, b2, eps, weight_decay, step,
+                               stream))
+
+
+def mg_target_prepare(g: int, target, stream: int) -> None:
+    _check(lib().mg_target_prepare(g, _ptr(target), stream))
+
+
+def mg_set_alpha(g: int, alpha_g: float, alpha_p: float) -> None:
+    _check(lib().mg_set_alpha(g, float(alpha_g), float(alpha_p)))
 
 
 def mg_remap_params(g: int, pruned: int, old_to_new: np.ndarray, src_theta, dst_theta, src_wet, dst_wet,
@@ -308,6 +380,14 @@ class Graph:
         wet = {v: float(we[int(self.proc_index[v])]) for v in sizes}
         return theta, wet
 
+    def proc_types(self) -> np.ndarray:
+        """enum mg_type of every processor, in proc_index order."""
+        out = np.zeros(self.n_proc, np.int32)
+        for v, t in enumerate(self.types):
+            if int(self.proc_index[v]) >= 0:
+                out[int(self.proc_index[v])] = TYPE_CODES[t]
+        return out
+
     def mask_vector(self, mask: Dict[int, float]) -> np.ndarray:
         m = np.ones(self.n_proc, np.float32)
         for v, x in mask.items():
@@ -380,7 +460,7 @@ class Session:
 
 
 def prune_round(session: Session, dry, theta, wet, mask=None, tau: float = 1e-3, max_candidates: int = 64,
-                L_min: Optional[float] = None):
+                L_min: Optional[float] = None, relative: bool = True):
     """One pruning round (Alg. 2 with batched trials): a forward at the
     current mask, single-bypass trials of the candidates, prefix trials of
     those within tolerance, and the accept step; the rule itself is the C
@@ -407,7 +487,7 @@ def prune_round(session: Session, dry, theta, wet, mask=None, tau: float = 1e-3,
         session.forward_trials(keep, res)
         L_cand = res[:, 1].cpu().numpy()
         evaluated += [((alive & keep[i]).tolist(), float(L_cand[i])) for i in range(len(cand))]
-    order = mg_prune_order(cand, L_cand, L_min, tau) if len(cand) else np.zeros(0, np.int32)
+    order = mg_prune_order(cand, L_cand, L_min, tau, relative) if len(cand) else np.zeros(0, np.int32)
     L_prefix = np.zeros(0)
     if len(order):
         keep = np.ones((len(order), P), np.uint8)
@@ -417,12 +497,44 @@ def prune_round(session: Session, dry, theta, wet, mask=None, tau: float = 1e-3,
         session.forward_trials(keep, res)
         L_prefix = res[:, 1].cpu().numpy()
         evaluated += [((alive & keep[i]).tolist(), float(L_prefix[i])) for i in range(len(order))]
-    k = mg_prune_accept(L_prefix, L_min, tau)
+    k = mg_prune_accept(L_prefix, L_min, tau, relative)
     new_alive = alive.copy()
     new_alive[order[:k]] = 0
     return {"alive": new_alive, "L_min": min(L_min, float(L_prefix[k - 1])) if k else L_min, "L_start": L_min,
             "La": La, "candidates": cand.tolist(), "L_cand": L_cand.tolist(), "order": order.tolist(),
             "L_prefix": L_prefix.tolist(), "k": k, "evaluated": evaluated}
+
+
+def drywet_round(session: Session, dry, theta, wet, uniforms: np.ndarray, mask=None, tau: float = 0.01,
+                 relative: bool = False, L_min: Optional[float] = None):
+    """One iteration of the dry/wet method (Alg. 3): a forward at the current
+    mask (the cache the trials read), then one trial at a time, each a
+    suffix recomputation of a single mask (mg_forward_trials, B = 1) whose
+    L_a goes back to the library's rule (mg_drywet_*).  uniforms: the draws
+    that pick each trial's type.  Returns the new alive vector, L_min and the
+    trace of (keep mask, L_a) pairs."""
+    torch = session.torch
+    P = session.g.n_proc
+    out = torch.zeros(7, dtype=torch.float64, device=theta.device)
+    session.forward(dry, theta, wet, mask, None, out)
+    torch.cuda.synchronize()
+    La = float(out[1].item())
+    L_min = La if L_min is None else float(L_min)
+    mask_h = None if mask is None else mask.detach().cpu().numpy().astype(np.float32)
+    alive = np.ones(P, np.uint8) if mask_h is None else (mask_h != 0).astype(np.uint8)
+    dw = DryWet(session.g.proc_types(), wet.detach().cpu().numpy(), mask_h, alive, L_min, tau, relative, uniforms)
+    res = torch.zeros(1, 7, dtype=torch.float64, device=theta.device)
+    evaluated = []
+    while True:
+        keep = dw.next()
+        if keep is None:
+            break
+        session.forward_trials(keep[None, :], res)
+        L = float(res[0, 1].item())
+        dw.report(L)
+        evaluated.append((keep.tolist(), L))
+    new_alive, L_new, n = dw.end()
+    return {"alive": new_alive, "L_min": L_new, "L_start": L_min, "La": La, "trials": n, "evaluated": evaluated}
 
 
 def compact(graph: Graph, alive: np.ndarray, noise: Dict[int, np.ndarray], reverb_length: int, target,

@@ -1,0 +1,271 @@
+"""The paper's search regime on the library (host control only; every step
+of the arithmetic runs in libmixgraph):
+
+  * console phase: AdamW steps on random segments of the song, the first
+    second of each segment excluded from the loss (it warms up the
+    processors with long states), Sec. 5.1;
+  * pruning phase: iterations of candidate trials and graph surgery, each
+    followed by fine-tuning, with the dry/wet l1 weight alpha_p ramped
+    linearly from 0 over the first steps of the phase, Sec. 6.3; candidates
+    from the brute-force method (batched single bypasses and prefix trials),
+    the dry/wet method (Alg. 3) or the hybrid of the two (Sec. 6.2), with an
+    absolute tolerance tau;
+  * the consistency check of Sec. 7.7: the pruned graph and its mix become a
+    synthetic ground truth, the search runs again on that mix, and the two
+    graphs are compared processor by processor (per type: accuracy,
+    precision, recall, F1).
+
+Two sessions share one parameter vector: a training graph compiled for the
+segment length, and an evaluation graph for the whole song, which the
+pruning trials and L_min use.  Both have the same topology, so the same
+parameter layout.
+"""
+from __future__ import annotations
+
+import dataclasses
+import time
+from typing import Dict, List, Optional, Sequence
+
+import numpy as np
+
+from . import mixgraph as MG
+from . import workloads as W
+
+
+@dataclasses.dataclass(frozen=True)
+class Regime:
+    console_steps: int = 6000     # console training (Sec. 6.3: 6k)
+    rounds: int = 12              # pruning iterations (N_iter = 12)
+    finetune: int = 500           # fine-tune steps after each iteration
+    segment_s: float = 3.8        # random segment per step (Sec. 5.1)
+    warmup_s: float = 1.0         # leading part of a segment excluded from the loss
+    lr: float = 1e-2
+    weight_decay: float = 1e-2    # AdamW; the paper does not state it (PyTorch's default)
+    alpha_g: float = 1e-3
+    alpha_p: float = 1e-4         # final weight of the dry/wet l1 term
+    alpha_p_ramp: int = 4000      # steps of the pruning phase over which alpha_p rises from 0
+    tau: float = 0.01             # absolute tolerance (the paper's default)
+    sampler: str = "hybrid"       # "brute", "drywet" or "hybrid"
+    seed: int = 0                 # segment offsets and type draws
+
+
+def _alpha_p(reg: Regime, t: int) -> float:
+    return reg.alpha_p * min(1.0, t / max(1, reg.alpha_p_ramp))
+
+
+class _State:
+    """Graphs, sessions and parameters of one search (device tensors)."""
+
+    def __init__(self, torch, song_graph, cfg, dry_d, noise: Dict[int, np.ndarray], target_d, th0, we0, reg, dev):
+        self.torch, self.cfg, self.reg, self.dev = torch, cfg, reg, dev
+        self.seg_len = int(round(reg.segment_s * cfg.fs))
+        if self.seg_len > cfg.length:
+            raise ValueError("the song is shorter than one segment")
+        seg_cfg = dataclasses.replace(cfg, seconds=self.seg_len / cfg.fs)
+        self.seg_cfg = seg_cfg
+        skip = int(round(reg.warmup_s * cfg.fs))
+        P = len(song_graph.processors())
+        self.train_g = MG.Graph(self.train_g.types, song_graph.edge_array(), self._tracks(song_graph),
+                                cfg.n_tracks, 2 if cfg.stereo_tracks else 1,
+                                W.binding_config(seg_cfg, reg.alpha_g, 0.0, loss_skip=skip))
+        self.eval_g = MG.Graph(song_graph.types, song_graph.edge_array(), self._tracks(song_graph), cfg.n_tracks,
+                               2 if cfg.stereo_tracks else 1,
+                               W.binding_config(cfg, reg.alpha_g, 0.0, loss_skip=skip, max_trials=P,
+                                                trial_slots=4 * song_graph.n_nodes))
+        self.dry_d, self.target_d = dry_d, target_d
+        self.noise = dict(noise)
+        self.orig = list(range(song_graph.n_nodes))      # current node -> node of the first console
+        self.seg_dry = torch.empty(cfg.n_tracks, dry_d.shape[1], self.seg_len, device=dev)
+        self.seg_tgt = torch.empty(2, self.seg_len, device=dev)
+        self._sessions()
+        th, we = self.eval_g.flatten(th0, we0)
+        self.theta = torch.from_numpy(th).to(dev)
+        self.wet = torch.from_numpy(we).to(dev)
+        self.m_t, self.v_t = torch.zeros_like(self.theta), torch.zeros_like(self.theta)
+        self.m_w, self.v_w = torch.zeros_like(self.wet), torch.zeros_like(self.wet)
+        self.gth, self.gwe = torch.empty_like(self.theta), torch.empty_like(self.wet)
+        self.n_step = 0
+
+    @staticmethod
+    def _tracks(g):
+        return [g.track_of_input.get(v, -1) for v in range(g.n_nodes)]
+
+    def _noise_rows(self, g: MG.Graph):
+        rows = g.reverb_rows()
+        if not rows:
+            return np.zeros((1, 2, max(self.cfg.reverb_length, 1)), np.float32)
+        return np.stack([self.noise[self.orig[v]] for v in rows]).astype(np.float32)
+
+    def _sessions(self):
+        torch = self.torch
+        self.train_s = None
+        self.eval_s = None
+        self.noise_tr = torch.from_numpy(self._noise_rows(self.train_g)).to(self.dev)
+        self.eval_s = MG.Session(self.eval_g, self.noise_tr, self.target_d, mode=0, device=self.dev)
+        self.seg_tgt.copy_(self.target_d[:, :self.seg_len])
+        self.train_s = MG.Session(self.train_g, self.noise_tr, self.seg_tgt, mode=1, device=self.dev)
+
+    def step(self, rng: np.random.Generator, alpha_p: float):
+        torch, reg = self.torch, self.reg
+        off = int(rng.integers(0, self.cfg.length - self.seg_len + 1))
+        self.seg_dry.copy_(self.dry_d[:, :, off:off + self.seg_len])
+        self.seg_tgt.copy_(self.target_d[:, off:off + self.seg_len])
+        s = self.train_s
+        st = s.stream()
+        MG.mg_set_alpha(self.train_g.h, reg.alpha_g, alpha_p)
+        MG.mg_target_prepare(self.train_g.h, self.seg_tgt, st)
+        s.forward(self.seg_dry, self.theta, self.wet)
+        s.backward(self.gth, self.gwe)
+        self.n_step += 1
+        MG.mg_adamw_step(self.theta, self.m_t, self.v_t, self.gth, self.train_g.n_theta, reg.lr, 0.9, 0.999, 1e-8,
+                         reg.weight_decay, self.n_step, st)
+        MG.mg_adamw_step(self.wet, self.m_w, self.v_w, self.gwe, self.train_g.n_proc, reg.lr, 0.9, 0.999, 1e-8,
+                         reg.weight_decay, self.n_step, st)
+
+    def evaluate(self) -> float:
+        out = self.torch.zeros(7, dtype=self.torch.float64, device=self.dev)
+        self.eval_s.forward(self.dry_d, self.theta, self.wet, None, None, out)
+        return float(out[1].item())
+
+    def mix(self):
+        out = self.torch.zeros(7, dtype=self.torch.float64, device=self.dev)
+        y = self.torch.empty(2, self.cfg.length, device=self.dev)
+        self.eval_s.forward(self.dry_d, self.theta, self.wet, None, y, out)
+        return y, float(out[1].item())
+
+    def compact(self, alive: np.ndarray):
+        """Graph surgery on both graphs, parameters and AdamW moments carried
+        over (Sec. 1.2: bypass equals removal)."""
+        torch = self.torch
+        self.train_s = None
+        self.eval_s = None
+        new_eval, o2n = self.eval_g.prune(np.asarray(alive, np.uint8))
+        new_train, o2n_t = self.train_g.prune(np.asarray(alive, np.uint8))
+        assert np.array_equal(o2n, o2n_t)
+        st = torch.cuda.current_stream().cuda_stream
+        out = []
+        for a in (self.theta, self.m_t, self.v_t):
+            b = torch.empty(new_eval.n_theta, dtype=torch.float32, device=self.dev)
+            MG.mg_remap_params(self.eval_g.h, new_eval.h, o2n, a, b, None, None, st)
+            out.append(b)
+        outw = []
+        for a in (self.wet, self.m_w, self.v_w):
+            b = torch.empty(new_eval.n_proc, dtype=torch.float32, device=self.dev)
+            MG.mg_remap_params(self.eval_g.h, new_eval.h, o2n, None, None, a, b, st)
+            outw.append(b)
+        torch.cuda.synchronize()
+        orig = [0] * int((o2n >= 0).sum())
+        for v, u in enumerate(o2n):
+            if u >= 0:
+                orig[u] = self.orig[v]
+        self.orig = orig
+        self.eval_g, self.train_g = new_eval, new_train
+        self.theta, self.m_t, self.v_t = out
+        self.wet, self.m_w, self.v_w = outw
+        self.gth, self.gwe = torch.empty_like(self.theta), torch.empty_like(self.wet)
+        self._sessions()
+
+    def kept(self, n_orig_nodes: int) -> np.ndarray:
+        """1 for every node of the first console still in the graph."""
+        k = np.zeros(n_orig_nodes, np.uint8)
+        k[self.orig] = 1
+        return k
+
+
+def run_search(song_graph, cfg, dry: np.ndarray, noise: Dict[int, np.ndarray], target, reg: Regime,
+               th0, we0, device: str = "cuda", log=None) -> Dict:
+    """The whole search of one song (console phase, then the pruning
+    iterations).  target: host float32 [2][L] or a device tensor."""
+    import torch
+    dev = device
+    dry_d = torch.from_numpy(np.ascontiguousarray(dry, np.float32)).to(dev)
+    target_d = (torch.from_numpy(np.ascontiguousarray(target, np.float32)).to(dev)
+                if isinstance(target, np.ndarray) else target)
+    S = _State(torch, song_graph, cfg, dry_d, noise, target_d, th0, we0, reg, dev)
+    rng = np.random.default_rng([reg.seed, 1])
+    draws = np.random.default_rng([reg.seed, 2])
+    t0 = time.perf_counter()
+    for _ in range(reg.console_steps):
+        S.step(rng, 0.0)
+    torch.cuda.synchronize()
+    t_console = time.perf_counter() - t0
+    L_min = S.evaluate()
+    La_console = L_min
+    if log:
+        log(f"console phase: {reg.console_steps} steps in {t_console:.1f} s, L_a {La_console:.4f}")
+    trace = []
+    t_prune = 0
+    P0 = S.eval_g.n_proc
+    for n in range(1, reg.rounds + 1):
+        method = reg.sampler if reg.sampler != "hybrid" else ("brute" if n % 4 == 0 else "drywet")
+        t1 = time.perf_counter()
+        P = S.eval_g.n_proc
+        if method == "brute":
+            res = MG.prune_round(S.eval_s, S.dry_d, S.theta, S.wet, None, tau=reg.tau, max_candidates=P,
+                                 L_min=L_min, relative=False)
+            trials = len(res["candidates"]) + len(res["order"])
+        else:
+            u = draws.random(4 * P + 64)
+            res = MG.drywet_round(S.eval_s, S.dry_d, S.theta, S.wet, u, tau=reg.tau, relative=False, L_min=L_min)
+            trials = res["trials"]
+        L_min = res["L_min"]
+        removed = int((res["alive"] == 0).sum())
+        if removed:
+            S.compact(res["alive"])
+        for _ in range(reg.finetune):
+            S.step(rng, _alpha_p(reg, t_prune))
+            t_prune += 1
+        torch.cuda.synchronize()
+        trace.append({"round": n, "method": method, "trials": trials, "removed": removed,
+                      "processors": S.eval_g.n_proc, "L_min": L_min, "seconds": time.perf_counter() - t1})
+        if log:
+            log(f"round {n} ({method}): {trials} trials, removed {removed}, {S.eval_g.n_proc} processors left")
+    y, La_final = S.mix()
+    kept = S.kept(song_graph.n_nodes)
+    out = {"La_console": La_console, "La_final": La_final, "processors_start": P0,
+           "processors_end": S.eval_g.n_proc, "pruning_ratio": 1.0 - S.eval_g.n_proc / max(P0, 1),
+           "kept": kept, "trace": trace, "console_s": t_console, "total_s": time.perf_counter() - t0,
+           "theta": S.theta.cpu().numpy(), "wet": S.wet.cpu().numpy(), "mix": y.cpu().numpy(),
+           "types": list(S.eval_g.types), "orig": list(S.orig)}
+    return out
+
+
+def processor_agreement(types: Sequence[str], truth: np.ndarray, pred: np.ndarray) -> Dict:
+    """Per processor type and micro-averaged over all processors: accuracy,
+    precision, recall and F1 of `pred` (1 = the processor is kept) against
+    `truth`, over the processors of the first console (Sec. 7.7: per track
+    and subgroup, whether a type is present)."""
+    out = {}
+    procs = [v for v, t in enumerate(types) if t not in "imo"]
+
+    def metrics(vs):
+        t = truth[vs].astype(bool)
+        p = pred[vs].astype(bool)
+        tp, fp = int((t & p).sum()), int((~t & p).sum())
+        fn, tn = int((t & ~p).sum()), int((~t & ~p).sum())
+        acc = (tp + tn) / max(1, len(vs))
+        prec = tp / (tp + fp) if tp + fp else 1.0
+        rec = tp / (tp + fn) if tp + fn else 1.0
+        f1 = 2 * prec * rec / (prec + rec) if prec + rec else 0.0
+        return {"n": len(vs), "tp": tp, "fp": fp, "fn": fn, "tn": tn, "accuracy": acc, "precision": prec,
+                "recall": rec, "f1": f1}
+
+    for ty in sorted({types[v] for v in procs}):
+        out[ty] = metrics([v for v in procs if types[v] == ty])
+    out["micro"] = metrics(procs)
+    return out
+
+
+def consistency_check(song_graph, cfg, dry, noise, target, reg: Regime, init, device="cuda", log=None) -> Dict:
+    """Sec. 7.7: search once on the target; take the pruned graph and its
+    matched mix as a synthetic ground truth; search again from a fresh
+    console on that mix; compare the two pruned graphs processor by
+    processor."""
+    th0, we0 = init
+    first = run_search(song_graph, cfg, dry, noise, target, reg, th0, we0, device, log)
+    reg2 = dataclasses.replace(reg, seed=reg.seed + 1)
+    second = run_search(song_graph, cfg, dry, noise, first["mix"].astype(np.float32), reg2, th0, we0, device, log)
+    agree = processor_agreement(song_graph.types, first["kept"], second["kept"])
+    return {"first": {k: first[k] for k in ("La_console", "La_final", "processors_end", "pruning_ratio")},
+            "second": {k: second[k] for k in ("La_console", "La_final", "processors_end", "pruning_ratio")},
+            "agreement": agree}

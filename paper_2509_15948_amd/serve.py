@@ -44,6 +44,7 @@ class SearchSpec:
     candidates: int = 64      # trials per round
     lr: float = 1e-2
     quantum: int = 4          # steps enqueued before yielding to the loop
+    stop_when_none: bool = False  # end the rounds at the first that removes nothing
 
 
 class PruneThreshold:
@@ -57,8 +58,9 @@ class PruneThreshold:
     (1 + tau) of the console's.  The rule itself is the library's
     (mg_prune_order, mg_prune_accept)."""
 
-    def __init__(self, tau: float):
+    def __init__(self, tau: float, relative: bool = True):
         self.tau = tau
+        self.relative = relative
         self.L_min: Optional[float] = None
 
     def observe(self, La: float) -> None:
@@ -68,10 +70,10 @@ class PruneThreshold:
     def order(self, cand: np.ndarray, L_cand: np.ndarray) -> np.ndarray:
         if not len(cand):
             return np.zeros(0, np.int32)
-        return MG.mg_prune_order(cand, L_cand, self.L_min, self.tau)
+        return MG.mg_prune_order(cand, L_cand, self.L_min, self.tau, self.relative)
 
     def accept(self, L_prefix: np.ndarray) -> int:
-        k = MG.mg_prune_accept(L_prefix, self.L_min, self.tau)
+        k = MG.mg_prune_accept(L_prefix, self.L_min, self.tau, self.relative)
         if k:
             self.L_min = min(self.L_min, float(L_prefix[k - 1]))
         return k
@@ -124,7 +126,13 @@ class Search:
 
     def _compact(self, torch, dev):
         """Remove the pruned processors from the graph (graph surgery) and
-        carry parameters and Adam moments over to the smaller graph."""
+        carry parameters and Adam moments over to the smaller graph.  The old
+        workspace is released first (surgery and the parameter remap need the
+        host graph and the parameter vectors only), so a compacting search
+        never holds two workspaces.  The allocator orders the reuse of the
+        freed workspace on this search's stream after the work that read it
+        (the side stream's work has joined that stream by then)."""
+        self.sess = None
         new, o2n, sess, noise_d, th, we = MG.compact(self.bg, self.alive, self.noise_by_node, self.cfg.reverb_length,
                                                      self.target_d, (self.theta, self.m_t, self.v_t),
                                                      (self.wet, self.m_w, self.v_w), dev)
@@ -166,19 +174,30 @@ class Search:
         yield mark()
         P = self.bg.n_proc
         thr = PruneThreshold(spec.tau)
+
+        def timed():
+            ev = torch.cuda.Event(enable_timing=True)
+            ev.record()
+            return ev
+
         for r in range(spec.rounds):
+            t_round = time.perf_counter()
             # forward at the current mask (the cache the trials read), then
             # single-bypass trials
             self.sess.forward(self.dry_d, self.theta, self.wet, self.mask, None, self.losses)
             yield mark()
             thr.observe(float(self.losses[1].item()))
+            L_start = thr.L_min
+            trial_ev = []
             cand = MG.mg_prune_candidates(self.wet.cpu().numpy(), self.mask.cpu().numpy(), self.alive,
                                           spec.candidates)
             out = torch.zeros(max(1, len(cand)), 7, dtype=torch.float64, device=dev)
             if len(cand):
                 keep = np.ones((len(cand), P), np.uint8)
                 keep[np.arange(len(cand)), cand] = 0
+                trial_ev.append(timed())
                 self.sess.forward_trials(keep, out)
+                trial_ev.append(timed())
                 yield mark()
             L_cand = out[:len(cand), 1].cpu().numpy()
             order = thr.order(cand, L_cand)
@@ -188,21 +207,30 @@ class Search:
                 for j in range(len(order)):
                     keep[j, order[:j + 1]] = 0
                 outp = torch.zeros(len(order), 7, dtype=torch.float64, device=dev)
+                trial_ev.append(timed())
                 self.sess.forward_trials(keep, outp)
+                trial_ev.append(timed())
                 yield mark()
                 L_prefix = outp[:, 1].cpu().numpy()
                 k = thr.accept(L_prefix)
             if k:
                 self.alive[order[:k]] = 0
                 self._compact(torch, dev)
-            self.trace.append({"round": r, "L_min": thr.L_min, "candidates": len(cand), "within": len(order),
-                               "removed": int(k), "processors": int(self.bg.n_proc)})
+            trial_ms = sum(a.elapsed_time(b) for a, b in zip(trial_ev[0::2], trial_ev[1::2]))
+            entry = {"round": r, "L_start": L_start, "L_min": thr.L_min, "candidates": len(cand),
+                     "within": len(order), "removed": int(k), "processors": int(self.bg.n_proc),
+                     "trial_ms": trial_ms}
+            self.trace.append(entry)
             P = self.bg.n_proc
+            if k == 0 and spec.stop_when_none:
+                entry["seconds"] = time.perf_counter() - t_round
+                break
             for i in range(spec.finetune):
                 self._step()
                 if (i + 1) % spec.quantum == 0:
                     yield mark()
             yield mark()
+            entry["seconds"] = time.perf_counter() - t_round
         # final loss at the final parameters and mask
         self.sess.forward(self.dry_d, self.theta, self.wet, self.mask, None, self.losses)
         yield mark()

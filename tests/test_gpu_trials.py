@@ -218,3 +218,37 @@ def test_compacted_graph_gives_the_masked_audio_loss():
     sess.backward(gth, gwe)
     torch.cuda.synchronize()
     assert torch.isfinite(gth).all() and torch.isfinite(gwe).all()
+
+
+def test_drywet_round_matches_the_oracle_rule():
+    """One iteration of the dry/wet method (Alg. 3) on the GPU (the binding's
+    driver: one suffix-recomputed trial at a time, the library's rule)
+    against the oracle's rule applied to the GPU's own trial losses, with the
+    paper's absolute tolerance; every trial loss against the oracle's loss of
+    the same mask."""
+    case = _trial_case(16, mode=0, seed=5)
+    rng = np.random.default_rng(11)
+    u = rng.random(4 * case.bg.n_proc + 64)
+    res = MG.drywet_round(case.sess, case.dry_d, case.theta_d, case.wet_d, u, tau=0.05, relative=False)
+    print("dry/wet round: trials", res["trials"], "pruned", int((res["alive"] == 0).sum()), "L_min", res["L_min"],
+          flush=True)
+    lookup = {tuple(bool(x) for x in k): L for k, L in res["evaluated"]}
+    wet = case.wet_d.cpu().numpy()
+    w32 = (np.float32(1.0) / (np.float32(1.0) + np.exp(-wet))).astype(np.float32).tolist()
+    procs = case.g.processors()
+    node_of = {int(case.bg.proc_index[v]): v for v in procs}
+    types = [case.g.types[node_of[p]] for p in range(case.bg.n_proc)]
+    new, L_new, info = OP.drywet_round(lambda a: lookup[tuple(bool(x) for x in a)], [True] * case.bg.n_proc, w32,
+                                       types, res["L_start"], 0.05, u.tolist(), relative=False)
+    assert len(info["trials"]) == res["trials"]
+    assert new == [bool(x) for x in res["alive"]]
+    assert L_new == res["L_min"]
+    # the trial losses themselves against the oracle
+    worst = 0.0
+    for keep, L in res["evaluated"][:6]:
+        mask = {node_of[p]: float(k) for p, k in enumerate(keep)}
+        ref = case.oracle(mask, grads=False)[1]["La"]
+        tol = loss_tolerances(case, mask=mask)
+        worst = max(worst, abs(L - ref) / abs(ref))
+        assert abs(L - ref) <= max(tol["La"], 1e-5 * abs(ref)), (L, ref)
+    print("worst trial loss rel err", worst, flush=True)

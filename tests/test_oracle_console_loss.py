@@ -234,6 +234,31 @@ def test_adam_first_step_moves_by_lr_times_sign():
     assert np.allclose(th, -2e-2 * g / (np.abs(g) + 1e-8), rtol=1e-10)
 
 
+def test_adamw_matches_the_library_optimizer_and_its_closed_form():
+    """AdamW (decoupled weight decay): against torch.optim.AdamW in FP64 over
+    several steps, and with a zero gradient the parameters only decay,
+    theta_t = (1 - lr wd)^t theta_0."""
+    rng = np.random.default_rng(9)
+    th0 = rng.normal(size=7)
+    th = th0.copy()
+    m = np.zeros(7)
+    v = np.zeros(7)
+    p = torch.nn.Parameter(torch.tensor(th0, dtype=DT))
+    opt = torch.optim.AdamW([p], lr=1e-2, betas=(0.9, 0.999), eps=1e-8, weight_decay=0.05)
+    for step in range(1, 6):
+        g = rng.normal(size=7)
+        TR.adamw_step(th, m, v, g, step, lr=1e-2, weight_decay=0.05)
+        p.grad = torch.tensor(g, dtype=DT)
+        opt.step()
+    assert np.allclose(th, p.detach().numpy(), rtol=1e-13, atol=1e-15)
+    th = th0.copy()
+    m = np.zeros(7)
+    v = np.zeros(7)
+    for step in range(1, 4):
+        TR.adamw_step(th, m, v, np.zeros(7), step, lr=1e-2, weight_decay=0.1)
+    assert np.allclose(th, (1 - 1e-3) ** 3 * th0, rtol=1e-14)
+
+
 def test_channel_swap_isolates_the_left_right_term():
     """Swapping l and r leaves |mid| and |side| spectra unchanged, so
     L_m = L_s = 0 and L_a = 0.5 L_lr exactly."""
