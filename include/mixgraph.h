@@ -87,6 +87,12 @@ typedef struct mg_config {
                               results; for checks)                           */
   double alpha_g;          /* gain-staging regulariser weight                 */
   double alpha_p;          /* dry/wet l1 regulariser weight                   */
+  int32_t schedule_rule;   /* type schedule (Sec. 4.2): 0 the shortest of the
+                              three below; 1 the console walk (the substring
+                              of the console type string); 2 greedy (the type
+                              with the most computable nodes each step); 3
+                              beam search                                   */
+  int32_t beam_width;      /* beam of rule 3 (and of rule 0); 0 picks 8      */
 } mg_config;
 
 typedef struct mg_graph mg_graph;

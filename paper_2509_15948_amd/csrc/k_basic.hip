@@ -125,6 +125,15 @@ void launch_sum(const Ctx& c, int desc_off, int n, const SrcRef* srcs, float* ou
             c.C, dest_kind, c.vec4);
 }
 
+void launch_grad_sum(const Ctx& c, const NodeDesc* gdesc, int n) {
+  if (n <= 0) return;
+  const int64_t items = c.vec4 ? (2 * c.L) / 4 : 2 * c.L;
+  const unsigned bx = (unsigned)std::min<int64_t>(4096, std::max<int64_t>(1, (items + MG_BLOCK - 1) / MG_BLOCK));
+  dim3 grid(bx, n);
+  ProfScope ps(c, "sum", (double)n * 8.0 * c.L * 2);
+  MG_LAUNCH(c, k_sum, grid, dim3(MG_BLOCK), 0, c.st, gdesc, c.srcs, c.dry, c.U, c.G, c.G, c.L, c.C, 1, c.vec4);
+}
+
 // ---------------------------------------------------------------- pointwise processors
 // Each processor keeps two numbers (a, b) derived from its raw parameters.
 // Contraction is off from here to the end of the fused chains and every

@@ -43,6 +43,7 @@ static size_t plan_ws(mg_graph& g, int mode, bool commit) {
   const int P = g.n_proc, Bt = c.max_trials;
   take(w.desc, std::max<size_t>(1, n_win) * sizeof(NodeDesc));
   take(w.srcs, std::max<size_t>(1, g.n_src_base + g.trial_src_cap) * sizeof(SrcRef));
+  take(w.gdesc, std::max<size_t>(1, g.gdesc.size()) * sizeof(NodeDesc));
   take(w.losses_tmp, std::max(1, n_desc) * sizeof(int));
   take(w.fin, std::max(1, n_desc) * 8);
   take(w.U, (size_t)(g.n_uslots + g.trial_slots) * 2 * L * 4);
@@ -376,6 +377,10 @@ int bind_workspace(mg_graph* g, void* workspace, size_t workspace_bytes, int32_t
   if (!all.empty() && (rc = hip_check(hipMemcpyAsync(g->base + g->ws.srcs, all.data(), all.size() * sizeof(SrcRef),
                                                      hipMemcpyHostToDevice, st), "source upload")))
     return rc;
+  if (!g->gdesc.empty() &&
+      (rc = hip_check(hipMemcpyAsync(g->base + g->ws.gdesc, g->gdesc.data(), g->gdesc.size() * sizeof(NodeDesc),
+                                     hipMemcpyHostToDevice, st), "fan-out descriptor upload")))
+    return rc;
   if ((rc = hip_check(hipMemcpyAsync(g->base + g->ws.losses_tmp, flag.data(), flag.size() * sizeof(int),
                                      hipMemcpyHostToDevice, st), "flag upload")))
     return rc;
@@ -470,8 +475,6 @@ extern "C" int mg_backward(mg_graph* g, float* grad_theta, float* grad_wet, void
   if (!g->ready || g->mode != 1) return fail(MG_ERR_STATE, "graph not set up for backward (mode 1)");
   if (!g->have_forward) return fail(MG_ERR_STATE, "mg_backward needs a preceding mg_forward");
   if (int rc = check_binding(g)) return rc;
-  for (int v = 0; v < g->n_nodes; ++v)
-    if (g->succs[v].size() > 1) return fail(MG_ERR_GRAPH, "backward through a node with several consumers is not supported");
   hipStream_t st = (hipStream_t)stream;
   Ctx c = make_ctx(g, st);
   const int o = g->output_node;
@@ -506,11 +509,16 @@ extern "C" int mg_backward(mg_graph* g, float* grad_theta, float* grad_wet, void
   std::vector<int> chain_start(g->stages.size(), -1);
   for (size_t s = 1; s < g->stages.size(); ++s)
     if (g->pw_run[s] >= 2) chain_start[s + g->pw_run[s] - 1] = (int)s;
+  const NodeDesc* gdesc = (const NodeDesc*)(g->base + g->ws.gdesc);
   for (size_t s = g->stages.size() - 1; s >= 1; --s) {
     const Stage& S = g->stages[s];
     const int n = (int)S.nodes.size();
     const int off = S.desc_off;
     const int t = S.type;
+    // nodes of this stage with several consumers: dL/dy is the sum of what
+    // every consumer (a later stage, done by now) passed back
+    if (g->gdesc_off[s + 1] > g->gdesc_off[s])
+      launch_grad_sum(c, gdesc + g->gdesc_off[s], g->gdesc_off[s + 1] - g->gdesc_off[s]);
     if (t == MG_MIX || t == MG_OUT) continue;
     if (chain_start[s] >= 0) {
       const int s0 = chain_start[s], K = g->pw_run[s0];

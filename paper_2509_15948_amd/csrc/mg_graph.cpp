@@ -112,6 +112,81 @@ std::vector<Stage> schedule(const mg_graph& g, bool greedy) {
   return st;
 }
 
+// Beam search over type strings (Sec. 4.2: the search tree of the shortest
+// node subset sequence grows exponentially; a beam keeps it bounded).  A
+// state is the set of processed nodes after some stages; a step takes one
+// type and processes every computable node of it (the maximal subset).
+// States of equal depth are ranked by processed nodes (more first), then by
+// their type string; duplicates (the same processed set) are dropped; the
+// first depth at which a state is complete gives the schedule.
+std::vector<Stage> beam_schedule(const mg_graph& g, int width) {
+  struct State {
+    std::vector<char> done;
+    int n_done = 0;
+    std::vector<Stage> st;
+    std::string key;   // type string, for a deterministic order
+  };
+  auto ready_of = [&](const std::vector<char>& done, std::vector<int>* ready) {
+    for (int v = 0; v < g.n_nodes; ++v) {
+      if (done[v]) continue;
+      bool ok = true;
+      for (int p : g.preds[v])
+        if (!done[p]) ok = false;
+      if (ok) ready[g.type[v]].push_back(v);
+    }
+  };
+  State s0;
+  s0.done.assign(g.n_nodes, 0);
+  Stage in;
+  in.type = MG_IN;
+  for (int v = 0; v < g.n_nodes; ++v)
+    if (g.type[v] == MG_IN) {
+      in.nodes.push_back(v);
+      s0.done[v] = 1;
+      ++s0.n_done;
+    }
+  s0.st.push_back(in);
+  s0.key = "i";
+  std::vector<State> beam{s0};
+  while (true) {
+    for (const State& s : beam)
+      if (s.n_done == g.n_nodes) return s.st;
+    std::vector<State> next;
+    for (const State& s : beam) {
+      std::vector<int> ready[NTYPES];
+      ready_of(s.done, ready);
+      bool other = false;
+      for (int t = 0; t < NTYPES; ++t)
+        if (t != MG_OUT && !ready[t].empty()) other = true;
+      for (int t = 0; t < NTYPES; ++t) {
+        if (ready[t].empty() || (t == MG_OUT && other)) continue;  // the output stage comes last
+        State c = s;
+        Stage st;
+        st.type = t;
+        st.nodes = ready[t];
+        for (int v : st.nodes) c.done[v] = 1;
+        c.n_done += (int)st.nodes.size();
+        c.st.push_back(st);
+        c.key += type_char(t);
+        next.push_back(std::move(c));
+      }
+    }
+    if (next.empty()) return {};  // cannot happen for a validated DAG
+    std::stable_sort(next.begin(), next.end(), [](const State& a, const State& b) {
+      return a.n_done > b.n_done || (a.n_done == b.n_done && a.key < b.key);
+    });
+    std::vector<State> kept;
+    for (State& c : next) {
+      bool dup = false;
+      for (const State& k : kept)
+        if (k.n_done == c.n_done && k.done == c.done) dup = true;
+      if (!dup) kept.push_back(std::move(c));
+      if ((int)kept.size() >= width) break;
+    }
+    beam = std::move(kept);
+  }
+}
+
 int64_t next_pow2(int64_t x) {
   int64_t p = 1;
   while (p < x) p <<= 1;
@@ -125,8 +200,20 @@ namespace mg {
 // Build schedule, layout and slots of a validated graph.
 int compile(mg_graph& g) {
   const mg_config& c = g.cfg;
-  auto a = schedule(g, false), b = schedule(g, true);
-  g.stages = (b.size() < a.size()) ? b : a;
+  const int rule = c.schedule_rule;
+  const int width = c.beam_width > 0 ? c.beam_width : 8;
+  if (rule < 0 || rule > 3) return fail(MG_ERR_INVALID_ARG, "schedule_rule must be 0..3");
+  if (rule == 1) g.stages = schedule(g, false);
+  else if (rule == 2) g.stages = schedule(g, true);
+  else if (rule == 3) g.stages = beam_schedule(g, width);
+  else {
+    // the shortest of the three; ties keep the earlier rule
+    g.stages = schedule(g, false);
+    auto b = schedule(g, true);
+    if (b.size() < g.stages.size()) g.stages = b;
+    auto m = beam_schedule(g, width);
+    if (!m.empty() && m.size() < g.stages.size()) g.stages = m;
+  }
   // sigma: stage by stage, ascending node id inside a stage
   g.order.clear();
   g.pos.assign(g.n_nodes, -1);
@@ -264,15 +351,38 @@ int compile(mg_graph& g) {
       g.desc.push_back(d);
     }
   }
-  // backward fan-out sums: contributions of each successor
-  for (int v : g.fanout_sum) {
-    for (int s : g.succs[v]) {
-      SrcRef r;
-      r.kind = 2;
-      r.slot = (g.type[s] == MG_MIX || g.type[s] == MG_OUT) ? g.gslot[s] : g.ginslot[s];
-      g.gsrcs.push_back(r);
+  // backward fan-out sums: a node with several consumers gets dL/dy as the
+  // sum of what each consumer passes back (its dL/du, or the dL/dy of a mix);
+  // one sum descriptor per such node, grouped by stage so the backward runs
+  // them before the stage's own adjoints
+  g.gdesc.clear();
+  g.gdesc_off.assign(g.stages.size() + 1, 0);
+  std::vector<char> fan(g.n_nodes, 0);
+  for (int v : g.fanout_sum) fan[v] = 1;
+  for (size_t s = 0; s < g.stages.size(); ++s) {
+    g.gdesc_off[s] = (int)g.gdesc.size();
+    for (int v : g.stages[s].nodes) {
+      if (!fan[v] || g.type[v] == MG_IN) continue;
+      NodeDesc d{};
+      d.node = v;
+      d.proc = -1;
+      d.mrow = -1;
+      d.gout = g.gslot[v];
+      d.gin = -1;
+      d.src_begin = (int)(g.srcs.size() + g.gsrcs.size());
+      std::vector<int> ss = g.succs[v];
+      std::sort(ss.begin(), ss.end());
+      for (int s2 : ss) {
+        SrcRef r;
+        r.kind = 2;
+        r.slot = (g.type[s2] == MG_MIX || g.type[s2] == MG_OUT) ? g.gslot[s2] : g.ginslot[s2];
+        g.gsrcs.push_back(r);
+      }
+      d.src_count = (int)ss.size();
+      g.gdesc.push_back(d);
     }
   }
+  g.gdesc_off[g.stages.size()] = (int)g.gdesc.size();
   // FFT plan for the FIR convolutions
   int64_t ext = 0;
   bool any_conv = false;

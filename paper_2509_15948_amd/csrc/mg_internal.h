@@ -59,7 +59,7 @@ struct FftPlan {
 // Offsets (bytes) of everything carved out of the caller's workspace.
 struct WsPlan {
   size_t total = 0;
-  size_t desc = 0, srcs = 0;
+  size_t desc = 0, srcs = 0, gdesc = 0;
   size_t U = 0, YB = 0, ENV = 0, G = 0;
   size_t ZU = 0, ZH = 0, T1 = 0, T1s = 0, T2 = 0, T3 = 0;
   size_t tw = 0, twd = 0, twdl = 0, twhi = 0, twlo = 0;
@@ -147,6 +147,9 @@ struct mg_graph {
   std::vector<mg::NodeDesc> desc;
   std::vector<mg::SrcRef> srcs;
   std::vector<mg::SrcRef> gsrcs;          // backward fan-out sums
+  std::vector<mg::NodeDesc> gdesc;        // one per fan-out node: gout = its dL/dy slot,
+                                          // sources in gsrcs (offset by srcs.size())
+  std::vector<int> gdesc_off;             // per stage: first gdesc entry (size stages + 1)
   mg::FftPlan fft;
   std::vector<mg::LossRes> lres;
   int max_conv_stage = 0, max_stage = 0;

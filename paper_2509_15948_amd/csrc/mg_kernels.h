@@ -102,6 +102,8 @@ void forward_stage(const Ctx& c, int t, int off, int n, bool keep, const NodeDes
 
 // k_basic.hip
 void launch_sum(const Ctx& c, int desc_off, int n, const SrcRef* srcs, float* out_base, int dest_kind);
+// backward fan-out sums: dL/dy of each gdesc node from its consumers' slots
+void launch_grad_sum(const Ctx& c, const NodeDesc* gdesc, int n);
 void launch_pointwise_fwd(const Ctx& c, int type, int desc_off, int n);
 void launch_pointwise_bwd(const Ctx& c, int type, int desc_off, int n);
 // K (<= PW_MAXK) consecutive pointwise stages of n nodes each (types[i], descriptor offsets offs[i])

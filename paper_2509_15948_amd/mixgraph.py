@@ -32,7 +32,8 @@ class mg_config(ctypes.Structure):
                 ("reverb_nfft", ctypes.c_int32), ("reverb_hop", ctypes.c_int32), ("n_loss_ffts", ctypes.c_int32),
                 ("loss_ffts", ctypes.c_int32 * 8), ("n_mels", ctypes.c_int32), ("loss_skip", ctypes.c_int32),
                 ("max_trials", ctypes.c_int32), ("trial_slots", ctypes.c_int32), ("unfused", ctypes.c_int32),
-                ("alpha_g", ctypes.c_double), ("alpha_p", ctypes.c_double)]
+                ("alpha_g", ctypes.c_double), ("alpha_p", ctypes.c_double), ("schedule_rule", ctypes.c_int32),
+                ("beam_width", ctypes.c_int32)]
 
 
 class mg_info(ctypes.Structure):
@@ -121,7 +122,8 @@ def make_config(length: int, sample_rate: int, eq_taps: int = 2047, comp_mode: i
                 delay_range: int = 5512, delay_fir_taps: int = 39, reverb_length: int = 66150,
                 reverb_nfft: int = 384, reverb_hop: int = 192, loss_ffts: Sequence[int] = (512, 1024, 2048),
                 n_mels: int = 96, loss_skip: int = 0, alpha_g: float = 1e-3, alpha_p: float = 0.0,
-                max_trials: int = 0, trial_slots: int = 0, unfused: int = 0) -> mg_config:
+                max_trials: int = 0, trial_slots: int = 0, unfused: int = 0, schedule_rule: int = 0,
+                beam_width: int = 0) -> mg_config:
     c = mg_config()
     c.length = length
     c.sample_rate = sample_rate
@@ -143,6 +145,8 @@ def make_config(length: int, sample_rate: int, eq_taps: int = 2047, comp_mode: i
     c.unfused = unfused
     c.alpha_g = alpha_g
     c.alpha_p = alpha_p
+    c.schedule_rule = schedule_rule
+    c.beam_width = beam_width
     return c
 
 

@@ -65,7 +65,7 @@ class _State:
         self.seg_cfg = seg_cfg
         skip = int(round(reg.warmup_s * cfg.fs))
         P = len(song_graph.processors())
-        self.train_g = MG.Graph(self.train_g.types, song_graph.edge_array(), self._tracks(song_graph),
+        self.train_g = MG.Graph(song_graph.types, song_graph.edge_array(), self._tracks(song_graph),
                                 cfg.n_tracks, 2 if cfg.stereo_tracks else 1,
                                 W.binding_config(seg_cfg, reg.alpha_g, 0.0, loss_skip=skip))
         self.eval_g = MG.Graph(song_graph.types, song_graph.edge_array(), self._tracks(song_graph), cfg.n_tracks,

@@ -38,7 +38,11 @@ def test_adamw_matches_the_oracle_update():
     MG.mg_adamw_step(d[0], d[1], d[2], d[3], n, 1e-2, 0.9, 0.999, 1e-8, 0.05, 7, st)
     torch.cuda.synchronize()
     t64, m64, v64 = th.astype(np.float64), m.astype(np.float64), v.astype(np.float64)
-    TR.adamw_step(t64, m64, v64, g.astype(np.float64), 7, lr=1e-2, weight_decay=0.05)
+    # the kernel sees the FP32 values of the hyper-parameters (1 - beta2 in
+    # FP32 differs from 0.001 by 1.3e-5 relative)
+    f = lambda x: float(np.float32(x))
+    TR.adamw_step(t64, m64, v64, g.astype(np.float64), 7, lr=f(1e-2), b1=f(0.9), b2=f(0.999), eps=f(1e-8),
+                  weight_decay=f(0.05))
     err = np.abs(d[0].cpu().numpy() - t64).max()
     print("adamw max abs err", err, flush=True)
     assert err < 1e-6
