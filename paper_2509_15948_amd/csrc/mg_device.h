@@ -1,8 +1,8 @@
 // Device-side helpers shared by the mixgraph kernels (gfx950, wave64).
 //
 //  * complex float arithmetic on float2
-//  * an LDS-resident, batched, Stockham-autosort complex FFT (radix-4 passes
-//    plus one radix-2 pass when log2 n is odd), data kept in LDS and each
+//  * an LDS-resident, batched, Stockham-autosort complex FFT (radix-8 passes
+//    plus one radix-4 or radix-2 pass for the rest of log2 n), data kept in LDS and each
 //    butterfly's operands in registers between a read phase and a write phase,
 //    so one buffer of n complex values per transform suffices
 //  * fixed-order block reductions (no floating-point atomics anywhere, so every

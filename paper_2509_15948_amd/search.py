@@ -269,3 +269,91 @@ def consistency_check(song_graph, cfg, dry, noise, target, reg: Regime, init, de
     return {"first": {k: first[k] for k in ("La_console", "La_final", "processors_end", "pruning_ratio")},
             "second": {k: second[k] for k in ("La_console", "La_final", "processors_end", "pruning_ratio")},
             "agreement": agree}
+
+
+def paper_song_config(n_tracks: int = 18, n_subgroups: int = 4, seconds: float = 30.0):
+    """A synthetic song shaped like the paper's data (Sec. 5.3: 17.6 tracks on
+    average in MedleyDB) and console (Sec. 3, Sec. 5.1): chain e c n s g d r,
+    a 2047-tap EQ (1024 parameters), 20 delay taps over 2 s, a 2 s reverb,
+    30 kHz, loss FFTs 512 / 1024 / 4096."""
+    import synth
+    return synth.ConsoleConfig("paper", n_tracks, n_subgroups, seconds, 30000, True, chain="ecnsgdr",
+                               eq_taps=2047, delay_taps=20, delay_range_s=2.0, delay_fir_taps=39,
+                               reverb_seconds=2.0, loss_ffts=(512, 1024, 4096))
+
+
+def render(song_graph, cfg, dry: np.ndarray, noise: Dict[int, np.ndarray], theta, wet, device: str = "cuda"):
+    """The mix of a graph for per-node raw parameters, rendered by the
+    library (a forward-only session); host float32 [2][L]."""
+    import torch
+    bg = W.binding_graph(song_graph, cfg)
+    noise_d = torch.from_numpy(W.noise_rows(bg, noise, cfg.reverb_length)).to(device)
+    y = torch.zeros(2, cfg.length, device=device)
+    sess = MG.Session(bg, noise_d, y, mode=0, device=device)
+    th, we = bg.flatten(theta, wet)
+    out = torch.zeros(7, dtype=torch.float64, device=device)
+    sess.forward(torch.from_numpy(dry).to(device), torch.from_numpy(th).to(device), torch.from_numpy(we).to(device),
+                 None, y, out)
+    torch.cuda.synchronize()
+    return y.cpu().numpy()
+
+
+def main(argv=None) -> None:
+    """The paper's search on a synthetic song: a sweep over candidate samplers
+    and tolerances (the analogue of the sampling-method comparison of Sec.
+    7.4), then the consistency check of Sec. 7.7; one JSON line per run."""
+    import argparse
+    import json
+    import sys
+
+    import synth
+    ap = argparse.ArgumentParser(description=main.__doc__.splitlines()[0])
+    ap.add_argument("--tracks", type=int, default=18)
+    ap.add_argument("--subgroups", type=int, default=4)
+    ap.add_argument("--seconds", type=float, default=30.0)
+    ap.add_argument("--seed", type=int, default=7)
+    ap.add_argument("--console-steps", type=int, default=6000)
+    ap.add_argument("--rounds", type=int, default=12)
+    ap.add_argument("--finetune", type=int, default=500)
+    ap.add_argument("--samplers", default="brute,drywet,hybrid")
+    ap.add_argument("--taus", default="0.001,0.01,0.1")
+    ap.add_argument("--consistency", action="store_true", help="also run the consistency check (hybrid, tau 0.01)")
+    a = ap.parse_args(argv)
+
+    def log(msg):
+        print(msg, file=sys.stderr, flush=True)
+
+    cfg = paper_song_config(a.tracks, a.subgroups, a.seconds)
+    g, dry, noise = synth.song(a.seed, cfg)
+    gt, gw = synth.ground_truth_params(a.seed + 100, g, cfg)
+    target = render(g, cfg, dry, noise, gt, gw)
+    init = synth.init_params(a.seed, g, cfg)
+    base = Regime(console_steps=a.console_steps, rounds=a.rounds, finetune=a.finetune, seed=a.seed)
+    types = g.types
+    for sampler in a.samplers.split(","):
+        for tau in [float(x) for x in a.taus.split(",")]:
+            reg = dataclasses.replace(base, sampler=sampler, tau=tau)
+            log(f"search: sampler {sampler}, tau {tau}")
+            r = run_search(g, cfg, dry, noise, target, reg, init[0], init[1], log=log)
+            kept_by_type = {}
+            for v in g.processors():
+                kept_by_type.setdefault(types[v], []).append(int(r["kept"][v]))
+            print(json.dumps({
+                "run": "search", "sampler": sampler, "tau": tau, "La_console": round(r["La_console"], 5),
+                "La_final": round(r["La_final"], 5), "processors_start": r["processors_start"],
+                "processors_end": r["processors_end"], "pruning_ratio": round(r["pruning_ratio"], 4),
+                "kept_ratio_by_type": {t: round(float(np.mean(k)), 3) for t, k in kept_by_type.items()},
+                "trials": sum(x["trials"] for x in r["trace"]), "console_s": round(r["console_s"], 2),
+                "total_s": round(r["total_s"], 2),
+                "workload": f"{cfg.n_tracks} tracks, {cfg.n_subgroups} subgroups, {cfg.seconds:g} s at {cfg.fs} Hz, "
+                            f"chain {cfg.chain}; {reg.console_steps} console steps, {reg.rounds} rounds x "
+                            f"{reg.finetune} fine-tune steps, {reg.segment_s} s segments"}), flush=True)
+    if a.consistency:
+        reg = dataclasses.replace(base, sampler="hybrid", tau=0.01)
+        log("consistency check")
+        c = consistency_check(g, cfg, dry, noise, target, reg, init, log=log)
+        print(json.dumps({"run": "consistency", **c}, default=float), flush=True)
+
+
+if __name__ == "__main__":
+    main()

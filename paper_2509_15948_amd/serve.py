@@ -276,7 +276,7 @@ class Server:
         self.device = device
 
     def run(self, arrivals: List[tuple], make_search: Callable[[int, object, int], Search],
-            clock=time.perf_counter) -> Dict:
+            clock=time.perf_counter, on_done: Optional[Callable[[int, float], None]] = None) -> Dict:
         """arrivals: (arrival time s, cfg, seed) sorted by time.  Requests are
         built on the host ahead of time (data preparation is not search
         latency); each is admitted at or after its arrival time."""
@@ -312,6 +312,8 @@ class Server:
                         active[i] = (co, stream, ev)
                     except StopIteration:
                         finish[i] = clock() - t0
+                        if on_done:
+                            on_done(i, finish[i] - arrivals[i][0])
                         searches[i].release()
                         self.adm.retire(searches[i].bytes)
                         del active[i]
@@ -344,3 +346,78 @@ def run_alone(search: Search, device: str = "cuda") -> Dict:
     res = search.result
     search.release()
     return res
+
+
+def main(argv=None) -> None:
+    """A serving stream of whole-song searches (Poisson arrivals), printed as
+    one JSON line: p50/p99 latency, throughput, concurrency.  The arrival
+    rate is --load times the saturated throughput measured first by a
+    closed-loop run (every request of a short stream arriving at once)."""
+    import argparse
+    import json
+    import sys
+
+    import torch
+
+    import synth
+    ap = argparse.ArgumentParser(description=main.__doc__.splitlines()[0])
+    ap.add_argument("--requests", type=int, default=256)
+    ap.add_argument("--tracks", type=int, nargs=2, default=(4, 32))
+    ap.add_argument("--subgroups", type=int, nargs=2, default=(2, 8))
+    ap.add_argument("--seconds", type=float, nargs=2, default=(5.0, 30.0))
+    ap.add_argument("--steps", type=int, default=300)
+    ap.add_argument("--rounds", type=int, default=10)
+    ap.add_argument("--finetune", type=int, default=50)
+    ap.add_argument("--candidates", type=int, default=64)
+    ap.add_argument("--tau", type=float, default=1e-3)
+    ap.add_argument("--load", type=float, default=0.8, help="arrival rate as a fraction of the saturated rate")
+    ap.add_argument("--calib-requests", type=int, default=6)
+    ap.add_argument("--budget-gb", type=float, default=200.0)
+    ap.add_argument("--max-active", type=int, default=8)
+    ap.add_argument("--seed", type=int, default=3)
+    a = ap.parse_args(argv)
+    spec = SearchSpec(steps=a.steps, rounds=a.rounds, finetune=a.finetune, tau=a.tau, candidates=a.candidates,
+                      quantum=8)
+    budget = int(a.budget_gb * (1 << 30))
+
+    def log(msg):
+        print(msg, file=sys.stderr, flush=True)
+
+    def make(i, cfg, seed):
+        return Search(i, cfg, seed, spec)
+
+    # closed loop: the saturated rate of this mix
+    calib = synth.serving_requests(a.seed + 1000, a.calib_requests, rate=0.0, tracks=tuple(a.tracks),
+                                   subgroups=tuple(a.subgroups), seconds=tuple(a.seconds))
+    t0 = time.perf_counter()
+    c = Server(budget, a.max_active).run(calib, make, on_done=lambda i, lat: log(f"calibration request {i} done"))
+    sat = c["songs_per_s"]
+    rate = a.load * sat
+    log(f"saturated {sat:.3f} songs/s ({time.perf_counter() - t0:.1f} s); arrival rate {rate:.3f} songs/s")
+    reqs = synth.serving_requests(a.seed, a.requests, rate=rate, tracks=tuple(a.tracks),
+                                  subgroups=tuple(a.subgroups), seconds=tuple(a.seconds))
+    n_done = [0]
+
+    def done(i, lat):
+        n_done[0] += 1
+        log(f"request {i} done ({n_done[0]}/{len(reqs)}), latency {lat:.2f} s")
+
+    out = Server(budget, a.max_active).run(reqs, make, on_done=done)
+    removed = [sum(r["removed"] for r in res["trace"]) for res in out["results"]]
+    starts = [7 * (cfg.n_tracks + cfg.n_subgroups) for _, cfg, _ in reqs]
+    rec = {"requests": len(reqs), "saturated_songs_per_s": round(sat, 4), "arrival_rate_per_s": round(rate, 4),
+           "load": a.load,
+           "workload": f"tracks U{{{a.tracks[0]}..{a.tracks[1]}}}, subgroups U{{{a.subgroups[0]}..{a.subgroups[1]}}}, "
+                       f"{a.seconds[0]:g}-{a.seconds[1]:g} s at 44.1 kHz, chain ecxsgdr; search = {spec.steps} steps "
+                       f"+ {spec.rounds} rounds x ({spec.candidates} candidates + {spec.finetune} fine-tune steps)",
+           "p50_latency_s": round(out["p50_s"], 3), "p99_latency_s": round(out["p99_s"], 3),
+           "songs_per_s": round(out["songs_per_s"], 4), "audio_s_per_s": round(out["audio_s_per_s"], 1),
+           "makespan_s": round(out["makespan_s"], 2), "peak_active": out["peak_active"],
+           "peak_gb": round(out["peak_bytes"] / (1 << 30), 2),
+           "mean_queue_wait_s": round(float(np.mean(out["queue_wait_s"])), 3),
+           "pruning_ratio_mean": round(float(np.mean([r / s for r, s in zip(removed, starts)])), 4)}
+    print(json.dumps(rec), flush=True)
+
+
+if __name__ == "__main__":
+    main()
