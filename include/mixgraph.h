@@ -144,6 +144,14 @@ int mg_graph_layout(const mg_graph* g, int64_t* param_offset, int32_t* proc_inde
  * mode 1: forward and backward. */
 int mg_workspace_size(const mg_graph* g, int32_t mode, size_t* bytes);
 
+/* Device memory one search on this graph holds (bytes), for admission by a
+ * memory budget: *workspace = mg_workspace_size(g, mode); *state = the
+ * caller-side buffers the calls read and write: dry tracks, reverb noise,
+ * target, mix, theta with its gradient and two optimiser moments, the
+ * dry/wet logits likewise, the loss record and (max_trials > 0) the trial
+ * losses.  Host only.                                                        */
+int mg_footprint(const mg_graph* g, int32_t mode, size_t* workspace, size_t* state);
+
 /* Bind a caller-owned device workspace (>= mg_workspace_size bytes, 256-byte
  * aligned) and prepare per-graph device tables: FFT twiddles, Mel/A-weight
  * tables, the STFT of every reverb's fixed noise, and the Mel spectra of the

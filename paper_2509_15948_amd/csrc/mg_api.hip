@@ -431,6 +431,20 @@ int bind_workspace(mg_graph* g, void* workspace, size_t workspace_bytes, int32_t
 }
 }  // namespace mg
 
+extern "C" int mg_footprint(const mg_graph* g, int32_t mode, size_t* workspace, size_t* state) {
+  if (!g || !workspace || !state || (mode != 0 && mode != 1)) return fail(MG_ERR_INVALID_ARG, "bad arguments");
+  if (int rc = mg_workspace_size(g, mode, workspace)) return rc;
+  const size_t L = (size_t)g->cfg.length;
+  const size_t f = sizeof(float);
+  size_t b = (size_t)g->n_tracks * g->track_ch * L * f;                        // dry tracks
+  b += (size_t)std::max(1, g->type_count[MG_REVERB]) * 2 * std::max(1, g->cfg.reverb_length) * f;  // noise
+  b += 2 * 2 * L * f;                                                          // target, mix
+  b += 4 * ((size_t)g->n_theta + (size_t)g->n_proc) * f;                       // values, grads, 2 moments
+  b += 7 * sizeof(double) * (1 + (size_t)std::max(0, g->cfg.max_trials));      // loss records
+  *state = b;
+  return MG_OK;
+}
+
 extern "C" int mg_setup(mg_graph* g, void* workspace, size_t workspace_bytes, int32_t mode,
                         const float* reverb_noise, const float* target, void* stream) {
   return bind_workspace(g, workspace, workspace_bytes, mode, reverb_noise, target, (hipStream_t)stream, true);

@@ -49,7 +49,7 @@ EXPORTS = ("mg_graph_create", "mg_graph_destroy", "mg_graph_info", "mg_graph_lay
            "mg_last_error", "mg_profile_enable", "mg_profile_read", "mg_forward_trials", "mg_prune_candidates",
            "mg_prune_order", "mg_prune_accept", "mg_remap_params", "mg_node_output", "mg_setup_static",
            "mg_drywet_begin", "mg_drywet_next", "mg_drywet_report", "mg_drywet_end", "mg_adamw_step",
-           "mg_target_prepare", "mg_set_alpha")
+           "mg_target_prepare", "mg_set_alpha", "mg_footprint")
 
 
 def lib() -> ctypes.CDLL:
@@ -88,6 +88,7 @@ def lib() -> ctypes.CDLL:
                           ctypes.c_float, i32, vp],
         "mg_target_prepare": [vp, vp, vp],
         "mg_set_alpha": [vp, ctypes.c_double, ctypes.c_double],
+        "mg_footprint": [vp, i32, ctypes.POINTER(sz), ctypes.POINTER(sz)],
         "mg_drywet_report": [vp, ctypes.c_double],
         "mg_drywet_end": [vp, vp, vp, vp],
         "mg_remap_params": [vp, vp, vp, vp, vp, vp, vp, vp],
@@ -298,6 +299,13 @@ def mg_set_alpha(g: int, alpha_g: float, alpha_p: float) -> None:
     _check(lib().mg_set_alpha(g, float(alpha_g), float(alpha_p)))
 
 
+def mg_footprint(g: int, mode: int):
+    """(workspace bytes, caller-side state bytes) of one search on graph g."""
+    w, st = ctypes.c_size_t(), ctypes.c_size_t()
+    _check(lib().mg_footprint(g, mode, ctypes.byref(w), ctypes.byref(st)))
+    return w.value, st.value
+
+
 def mg_remap_params(g: int, pruned: int, old_to_new: np.ndarray, src_theta, dst_theta, src_wet, dst_wet,
                     stream: int) -> None:
     o2n = np.ascontiguousarray(old_to_new, dtype=np.int32)
@@ -445,6 +453,10 @@ class Session:
     def forward(self, dry, theta, wet, mask=None, mix=None, losses=None):
         out = self.losses if losses is None else losses
         mg_forward(self.g.h, dry, theta, wet, mask, mix, out, self.stream())
+        # mg_backward and mg_forward_trials read these buffers again: hold
+        # them, so that a temporary passed here is not freed and reused by
+        # the allocator while the library still reads it
+        self._inputs = (dry, theta, wet, mask)
         self.generation += 1
         self.consumed = False
         return out

@@ -90,10 +90,12 @@ class Search:
         self.init = params if params is not None else synth.init_params(seed, self.g, cfg)
         self.bg = W.binding_graph(self.g, cfg, max_trials=spec.candidates)
         P, nt = self.bg.n_proc, self.bg.n_theta
-        self.ws_bytes = MG.mg_workspace_size(self.bg.h, 1)
-        # workspace + dry + noise + target + mix + theta/wet with grads and moments
-        self.bytes = (self.ws_bytes + self.dry.nbytes + sum(n.nbytes for n in self.noise.values())
-                      + 3 * 2 * cfg.length * 4 + 5 * 4 * (nt + P))
+        # the library's footprint of one search: workspace plus the buffers
+        # its calls read and write (dry, noise, target, mix, parameters with
+        # gradients and moments, loss records); the target render's
+        # forward-only workspace is released before the search's own is made
+        self.ws_bytes, state = MG.mg_footprint(self.bg.h, 1)
+        self.bytes = self.ws_bytes + state
         self.trace: List[Dict] = []
         self.result: Optional[Dict] = None
 

@@ -19,8 +19,18 @@ from gpu_cases import f32, rel_l2
 pytestmark = pytest.mark.gpu
 
 
-def _dag():
-    # 0,1,2: inputs.  0 -> e(3) -> c(4) ; 1 -> x(5) ; 2 -> g(6)
+def _dag(kind="both"):
+    if kind == "multi":
+        # a processor with two inputs, no fan-out: e(3) -> c(4) and x(5) -> s(6)
+        types = ["i", "i", "i", "e", "c", "x", "s", "g", "m", "r", "o"]
+        edges = [(0, 3), (3, 4), (1, 5), (4, 6), (5, 6), (2, 7), (6, 8), (7, 8), (8, 9), (9, 10)]
+        return synth.Graph(types, edges, {0: 0, 1: 1, 2: 2})
+    if kind == "fanout":
+        # fan-out only: c(4) feeds g(5) and d(6); m(7) sums them
+        types = ["i", "i", "e", "c", "g", "d", "m", "x", "o"]
+        edges = [(0, 2), (2, 3), (3, 4), (3, 5), (4, 6), (5, 6), (1, 7), (7, 6), (6, 8)]
+        return synth.Graph(types, edges, {0: 0, 1: 1})
+    # both: 0,1,2 inputs.  0 -> e(3) -> c(4) ; 1 -> x(5) ; 2 -> g(6)
     # c(4) and x(5) -> s(7) (two inputs); c(4) also -> d(8) (send)
     # g(6) -> m(9); s(7) -> m(9); d(8) -> r(10) ; m(9) -> n(11) and -> e(12)
     # r(10), n(11), e(12) -> o(13)
@@ -30,9 +40,11 @@ def _dag():
     return synth.Graph(types, edges, {0: 0, 1: 1, 2: 2})
 
 
-def test_general_dag_against_the_oracle():
-    cfg = synth.small_config(seconds=0.75, fs=16000, n_tracks=3, n_subgroups=1)
-    g = _dag()
+@pytest.mark.parametrize("kind", ["multi", "fanout", "both"])
+def test_general_dag_against_the_oracle(kind):
+    g = _dag(kind)
+    n_in = sum(1 for t in g.types if t == "i")
+    cfg = synth.small_config(seconds=0.75, fs=16000, n_tracks=n_in, n_subgroups=1)
     dry = synth.dry_tracks(21, cfg)
     noise = synth.reverb_noise_all(21, g, cfg)
     gt, gw = synth.ground_truth_params(121, g, cfg)
@@ -48,7 +60,8 @@ def test_general_dag_against_the_oracle():
     theta, wet = torch.from_numpy(th_f).cuda(), torch.from_numpy(we_f).cuda()
     mix = torch.empty(2, cfg.length, device="cuda")
     losses = torch.zeros(7, dtype=torch.float64, device="cuda")
-    sess.forward(torch.from_numpy(dry).cuda(), theta, wet, None, mix, losses)
+    dry_d = torch.from_numpy(dry).cuda()   # read again by the backward: kept alive
+    sess.forward(dry_d, theta, wet, None, mix, losses)
     nodes = {}
     buf = torch.empty(2, cfg.length, device="cuda")
     st = torch.cuda.current_stream().cuda_stream
@@ -78,11 +91,14 @@ def test_general_dag_against_the_oracle():
         assert abs(gl[k] - vals[k]) <= 1e-4 * abs(vals[k]), k
     sizes = {v: len(p) for v, p in th.items()}
     gth_h, gwe_h = bg.unflatten(gth.cpu().numpy(), gwe.cpu().numpy(), sizes)
+    bad = []
     for v in g.processors():
         e = rel_l2(gth_h[v], oth[v])
         print("grad", v, g.types[v], e, flush=True)
         # the delay's z entries follow the surrogate rule, normalised per tap
-        assert e <= (2e-2 if g.types[v] in "dn" else 1e-3), (v, g.types[v], e)
+        if e > (2e-2 if g.types[v] in "dn" else 1e-3):
+            bad.append((v, g.types[v], e))
     e = rel_l2([gwe_h[v] for v in g.processors()], [owe[v] for v in g.processors()])
-    print("wet grad", e, flush=True)
+    print("wet grad", e, [(v, gwe_h[v], owe[v]) for v in g.processors()], flush=True)
+    assert not bad, bad
     assert e <= 1e-3

@@ -215,3 +215,18 @@ def test_static_setup_rejects_a_workspace_beyond_the_scratch():
     rc = MG.lib().mg_setup_static(bg.h, 1, None, 1, None)
     assert rc == 6, rc  # MG_ERR_BUDGET
     assert b"static scratch" in MG.lib().mg_last_error()
+
+
+def test_footprint_covers_workspace_and_caller_buffers():
+    """mg_footprint: the workspace of mg_workspace_size plus the caller-side
+    buffers of one search (dry tracks, noise, target, mix, parameters with
+    gradients and two moments, loss records), growing with the length."""
+    cfg, g, bg = _graph()
+    ws, st = MG.mg_footprint(bg.h, 1)
+    assert ws == MG.mg_workspace_size(bg.h, 1)
+    L = cfg.length
+    floor = cfg.n_tracks * 2 * L * 4 + 4 * 4 * (bg.n_theta + bg.n_proc) + 2 * 2 * L * 4
+    assert st >= floor
+    cfg2, g2, bg2 = _graph(seconds=2 * cfg.seconds)
+    ws2, st2 = MG.mg_footprint(bg2.h, 1)
+    assert ws2 > ws and st2 > st
