@@ -16,8 +16,13 @@
 namespace mg {
 
 constexpr int EQ_P = 8192;
-constexpr int EQ_NT = 1024;   // forward and spectrum: 16 waves per block, two blocks per CU (LDS; registers capped at 64)
-constexpr int EQ_BNT = 1024;  // backward: one window in LDS, two blocks per CU (registers capped at 64)
+// 16 waves per block, two blocks per CU (one 66 KB window each), so the
+// registers are capped at 64.  The window transform wants 73 (forward) to 81
+// (backward); the rest spill to scratch (16 and 64 bytes per lane), which
+// costs far less than one block per CU: uncapped, the EQ class took twice as
+// long per step.
+constexpr int EQ_NT = 1024;   // forward and spectrum
+constexpr int EQ_BNT = 1024;  // backward: one window in LDS
 
 struct EqArgs {
   const NodeDesc* desc;

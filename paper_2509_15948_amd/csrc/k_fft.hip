@@ -50,6 +50,31 @@ constexpr int pad_len() { return lds_len<N, eng_pad<N, ROW>()>(); }
 template <int N, bool ROW>
 __device__ __forceinline__ int px(int i) { return lds_ix<eng_pad<N, ROW>()>(i); }
 
+// Rows of 3072 points (3 x 1024) let the engine take N = 3 * 2^k where the
+// next power of two would hold a third more points.  Such a row is
+// transformed as three interleaved 1024-point transforms plus one radix-3
+// pass: element i of the time-domain row sits at LDS slot (i % 3) 1024 + i / 3,
+// frequency bin k at slot k.  Other rows are powers of two, in natural order
+// (with the spare slots of eng_pad) on both sides.
+template <int N1>
+constexpr bool row3() { return N1 == 3072; }
+template <int N1>
+constexpr int row_tw() { return row3<N1>() ? 1024 : N1; }
+template <int N1>
+constexpr int row_len() { return row3<N1>() ? N1 : pad_len<N1, true>(); }
+template <int N1>
+using RowTw = TwTab<row_tw<N1>(), float2>;
+template <int N1>
+__device__ __forceinline__ int tslot(int i) {
+  if constexpr (row3<N1>()) return (i % 3) * 1024 + i / 3;
+  else return px<N1, true>(i);
+}
+template <int N1>
+__device__ __forceinline__ int fslot(int k) {
+  if constexpr (row3<N1>()) return k;
+  else return px<N1, true>(k);
+}
+
 // W_N^e for e in [0, N) as h (1 + d), from two FP32 tables rounded from FP64
 // on the host: twhi[j] = W_N^{1024 j} and twlo[j] = W_N^j - 1 (small, so the
 // product adds little to the rounding of h).
@@ -67,6 +92,60 @@ struct EngineArgs {
   const float2* twhi;
   const float2* twlo;
 };
+
+// Radix-3 pass of B 3072-point rows (row b at buf + 3072 b).  Forward (DIR =
+// -1): slots r 1024 + k hold the 1024-point transforms F_r[k] of the
+// elements 3m + r; X[k + 1024 s] = sum_r W_3072^{rk} W_3^{rs} F_r[k] goes to
+// slot k + 1024 s.  Inverse (DIR = +1), the transpose: from the bins in
+// natural order, slot r 1024 + k receives W_3072^{-rk} sum_s X[k + 1024 s]
+// W_3^{-rs}, whose 1024-point inverse transforms give the elements 3m + r.
+// W_3072^e = W_N^{e N2} comes from the engine's table of W_N.
+template <int B, int NT, int DIR>
+__device__ __forceinline__ void radix3_pass(float2* buf, const EngineArgs& ea) {
+  const float c3 = -0.5f, s3 = 0.866025403784438647f;
+  for (int idx = threadIdx.x; idx < B * 1024; idx += NT) {
+    float2* r = buf + (idx >> 10) * 3072;
+    const int k = idx & 1023;
+    const float2 w1 = big_tw(ea.twhi, ea.twlo, (int64_t)k * ea.N2);
+    const float2 w2 = big_tw(ea.twhi, ea.twlo, (int64_t)(2 * k) * ea.N2);
+    float2 a0 = r[k], a1 = r[1024 + k], a2 = r[2048 + k];
+    if (DIR < 0) {
+      a1 = c_mul(a1, w1);
+      a2 = c_mul(a2, w2);
+    }
+    // 3-point DFT with the sign of DIR
+    const float2 sm = c_add(a1, a2), df = c_sub(a1, a2);
+    const float2 m = make_float2(a0.x + c3 * sm.x, a0.y + c3 * sm.y);
+    const float2 t = DIR < 0 ? make_float2(s3 * df.y, -s3 * df.x) : make_float2(-s3 * df.y, s3 * df.x);
+    float2 y1 = c_add(m, t), y2 = c_sub(m, t);
+    if (DIR > 0) {
+      y1 = c_mul(y1, c_conj(w1));
+      y2 = c_mul(y2, c_conj(w2));
+    }
+    r[k] = c_add(a0, sm);
+    r[1024 + k] = y1;
+    r[2048 + k] = y2;
+  }
+}
+
+// B row transforms in LDS (rows at stride row_len<N1>), unnormalised; ends
+// with a barrier like fft_lds.
+template <int N1, int B, int NT, int DIR>
+__device__ __forceinline__ void row_fft(float2* buf, const RowTw<N1>& tt, const EngineArgs& ea) {
+  if constexpr (row3<N1>()) {
+    if (DIR > 0) {
+      radix3_pass<B, NT, DIR>(buf, ea);
+      __syncthreads();
+    }
+    fft_lds<1024, 3 * B, 1024, NT, DIR, 0>(buf, tt);
+    if (DIR < 0) {
+      radix3_pass<B, NT, DIR>(buf, ea);
+      __syncthreads();
+    }
+  } else {
+    fft_lds<N1, B, pad_len<N1, true>(), NT, DIR, eng_pad<N1, true>()>(buf, tt);
+  }
+}
 
 // ---------------------------------------------------------------- loaders
 struct NodeView {
@@ -298,11 +377,10 @@ __global__ __launch_bounds__(COL_NT) void k_cols(LD ld, float2* __restrict__ T, 
   __syncthreads();
   fft_lds<N2, TC, BS, COL_NT, -1, eng_pad<N2, false>()>(buf, tt);
   float2* Tn = T + (int64_t)j * ea.N;
-  const int64_t mask = ea.N - 1;
   for (int idx = threadIdx.x; idx < TC * N2; idx += COL_NT) {
     const int k2 = idx / TC, cc = idx % TC;
     const int n1 = c0 + cc;
-    const float2 w = big_tw(ea.twhi, ea.twlo, ((int64_t)n1 * k2) & mask);
+    const float2 w = big_tw(ea.twhi, ea.twlo, (int64_t)n1 * k2);  // n1 k2 < N
     Tn[(int64_t)k2 * N1 + n1] = c_mul(buf[cc * BS + px<N2, false>(k2)], w);
   }
 }
@@ -353,7 +431,7 @@ __device__ __forceinline__ bool mirror_pair(int p, int q, int& ia, int& ib) {
   }
   if (q <= N1 / 2) {  // row 0: k1 <-> (N1 - k1) mod N1
     ia = q;
-    ib = (N1 - q) & (N1 - 1);
+    ib = q == 0 ? 0 : N1 - q;
     return true;
   }
   q -= N1 / 2 + 1;   // row N2/2: k1 <-> N1 - 1 - k1
@@ -377,26 +455,25 @@ __device__ __forceinline__ float2 pack_lr(float2 l, float2 r) {  // l + i r
 // LDS slot of element i in [0, 2 N1) of a row pair (row a, then row b)
 template <int N1>
 __device__ __forceinline__ int rslot(int i) {
-  return i < N1 ? px<N1, true>(i) : pad_len<N1, true>() + px<N1, true>(i - N1);
+  return i < N1 ? fslot<N1>(i) : row_len<N1>() + fslot<N1>(i - N1);
 }
 
 template <int N1>
 __device__ __forceinline__ void load_rows(float2* buf, const float2* __restrict__ Tn, int ra, int rb) {
   for (int i = threadIdx.x; i < N1; i += blockDim.x) {
-    buf[px<N1, true>(i)] = Tn[(int64_t)ra * N1 + i];
-    buf[pad_len<N1, true>() + px<N1, true>(i)] = Tn[(int64_t)rb * N1 + i];
+    buf[tslot<N1>(i)] = Tn[(int64_t)ra * N1 + i];
+    buf[row_len<N1>() + tslot<N1>(i)] = Tn[(int64_t)rb * N1 + i];
   }
 }
 
 template <int N1>
 __device__ __forceinline__ void store_rows(const float2* buf, float2* __restrict__ To, int ra, int rb,
                                            const EngineArgs& ea) {
-  const int64_t mask = ea.N - 1;
   for (int i = threadIdx.x; i < N1; i += blockDim.x) {
-    float2 wa = big_tw(ea.twhi, ea.twlo, ((int64_t)i * ra) & mask);
-    float2 wb = big_tw(ea.twhi, ea.twlo, ((int64_t)i * rb) & mask);
-    To[(int64_t)ra * N1 + i] = c_mul(buf[px<N1, true>(i)], c_conj(wa));
-    To[(int64_t)rb * N1 + i] = c_mul(buf[pad_len<N1, true>() + px<N1, true>(i)], c_conj(wb));
+    float2 wa = big_tw(ea.twhi, ea.twlo, (int64_t)i * ra);  // i ra < N
+    float2 wb = big_tw(ea.twhi, ea.twlo, (int64_t)i * rb);
+    To[(int64_t)ra * N1 + i] = c_mul(buf[tslot<N1>(i)], c_conj(wa));
+    To[(int64_t)rb * N1 + i] = c_mul(buf[row_len<N1>() + tslot<N1>(i)], c_conj(wb));
   }
 }
 
@@ -404,11 +481,10 @@ __device__ __forceinline__ void store_rows(const float2* buf, float2* __restrict
 template <int N1>
 __device__ __forceinline__ void store_rows2(const float2* x, const float2* z, float2* __restrict__ To,
                                             float2* __restrict__ Tz, int ra, int rb, const EngineArgs& ea) {
-  const int64_t mask = ea.N - 1;
   for (int i = threadIdx.x; i < N1; i += blockDim.x) {
-    const float2 wa = c_conj(big_tw(ea.twhi, ea.twlo, ((int64_t)i * ra) & mask));
-    const float2 wb = c_conj(big_tw(ea.twhi, ea.twlo, ((int64_t)i * rb) & mask));
-    const int ia = px<N1, true>(i), ib = pad_len<N1, true>() + px<N1, true>(i);
+    const float2 wa = c_conj(big_tw(ea.twhi, ea.twlo, (int64_t)i * ra));  // i ra < N
+    const float2 wb = c_conj(big_tw(ea.twhi, ea.twlo, (int64_t)i * rb));
+    const int ia = tslot<N1>(i), ib = row_len<N1>() + tslot<N1>(i);
     To[(int64_t)ra * N1 + i] = c_mul(x[ia], wa);
     To[(int64_t)rb * N1 + i] = c_mul(x[ib], wb);
     Tz[(int64_t)ra * N1 + i] = c_mul(z[ia], wa);
@@ -420,19 +496,79 @@ __device__ __forceinline__ void store_rows2(const float2* x, const float2* z, fl
 template <int N1>
 __global__ __launch_bounds__(row_nt<N1>()) void k_rows_spec(const float2* __restrict__ T, float2* __restrict__ Z,
                                                          int z0, const NodeDesc* __restrict__ desc, EngineArgs ea) {
-  __shared__ float2 buf[2 * pad_len<N1, true>()];
-  __shared__ TwTab<N1, float2> tt;
-  tw_fill<N1>(tt, ea.tw, ea.twdl);
+  __shared__ float2 buf[2 * row_len<N1>()];
+  __shared__ RowTw<N1> tt;
+  tw_fill<row_tw<N1>()>(tt, ea.tw, ea.twdl);
   const int j = blockIdx.y;
   int ra, rb;
   row_pair(blockIdx.x, ea.N2, ra, rb);
   load_rows<N1>(buf, T + (int64_t)j * ea.N, ra, rb);
   __syncthreads();
-  fft_lds<N1, 2, pad_len<N1, true>(), row_nt<N1>(), -1, eng_pad<N1, true>()>(buf, tt);
+  row_fft<N1, 2, row_nt<N1>(), -1>(buf, tt, ea);
   float2* Zn = Z + (int64_t)(z0 + desc[j].aux) * ea.N;
   for (int i = threadIdx.x; i < N1; i += row_nt<N1>()) {
-    Zn[(int64_t)ra * N1 + i] = buf[px<N1, true>(i)];
-    Zn[(int64_t)rb * N1 + i] = buf[pad_len<N1, true>() + px<N1, true>(i)];
+    Zn[(int64_t)ra * N1 + i] = buf[fslot<N1>(i)];
+    Zn[(int64_t)rb * N1 + i] = buf[row_len<N1>() + fslot<N1>(i)];
+  }
+}
+
+// FIR spectrum rows straight from the compact FIR.  The FIR's taps occupy
+// few of the N2 rows of the index map n = n1 + N1 n2 (lags [lag0, lag0 + Nh)
+// are short next to N), so the column transform is a direct sum over those
+// rows: for the row pair (ra, rb) and every n1,
+//   t[k2][n1] = W_N^{n1 k2} sum_{n2 in S} h[n1 + N1 n2] W_N2^{n2 k2},
+// with S the rows 0 .. khi-1 (lags from 0 up) and the last klo rows (the
+// negative lags, circularly at the end); then the row FFT of k_rows_spec.
+// This replaces the column pass over all N2 rows, most of them zero, and the
+// HBM round trip of its N-point intermediate, but every row-pair workgroup
+// reads all the FIR's rows again: on the 3 x 2^20-point engine with 64 nodes
+// a stage took 2.2 ms at 9 rows against 3.1 ms for the column path, and
+// 5.5 ms at 32 rows.  So only FIRs within FIRSPEC_MAXK rows take it.
+constexpr int FIRSPEC_MAXK = 16;
+template <int N1>
+__global__ __launch_bounds__(row_nt<N1>()) void k_rows_firspec(LdFir ld, float2* __restrict__ Z, int z0, int khi,
+                                                             int klo, const NodeDesc* __restrict__ desc,
+                                                             EngineArgs ea) {
+  __shared__ float2 buf[2 * row_len<N1>()];
+  __shared__ RowTw<N1> tt;
+  __shared__ float2 twa[FIRSPEC_MAXK], twb[FIRSPEC_MAXK];
+  tw_fill<row_tw<N1>()>(tt, ea.tw, ea.twdl);
+  const int j = blockIdx.y;
+  int ra, rb;
+  row_pair(blockIdx.x, ea.N2, ra, rb);
+  const int nS = khi + klo;
+  for (int q = threadIdx.x; q < nS; q += row_nt<N1>()) {
+    const int64_t n2 = q < khi ? q : ea.N2 - klo + (q - khi);
+    // W_N2^{n2 r} = W_N^{N1 ((n2 r) mod N2)}
+    twa[q] = big_tw(ea.twhi, ea.twlo, (int64_t)N1 * ((n2 * ra) % ea.N2));
+    twb[q] = big_tw(ea.twhi, ea.twlo, (int64_t)N1 * ((n2 * rb) % ea.N2));
+  }
+  ld.begin(j);
+  __syncthreads();
+  for (int n1 = threadIdx.x; n1 < N1; n1 += row_nt<N1>()) {
+    // FP64 accumulation: a direct FP32 sum over up to 64 rows rounds about
+    // twice as much as the column FFT it replaces; in FP64 it rounds less
+    double ax = 0.0, ay = 0.0, bx = 0.0, by = 0.0;
+    for (int q = 0; q < nS; ++q) {
+      const int64_t n2 = q < khi ? q : ea.N2 - klo + (q - khi);
+      const float2 x = ld.load((int64_t)n1 + (int64_t)N1 * n2);
+      const float2 ta = twa[q], tb = twb[q];
+      ax += (double)x.x * ta.x - (double)x.y * ta.y;
+      ay += (double)x.x * ta.y + (double)x.y * ta.x;
+      bx += (double)x.x * tb.x - (double)x.y * tb.y;
+      by += (double)x.x * tb.y + (double)x.y * tb.x;
+    }
+    const float2 wa = big_tw(ea.twhi, ea.twlo, (int64_t)n1 * ra);  // n1 ra < N
+    const float2 wb = big_tw(ea.twhi, ea.twlo, (int64_t)n1 * rb);
+    buf[tslot<N1>(n1)] = make_float2((float)(ax * wa.x - ay * wa.y), (float)(ax * wa.y + ay * wa.x));
+    buf[row_len<N1>() + tslot<N1>(n1)] = make_float2((float)(bx * wb.x - by * wb.y), (float)(bx * wb.y + by * wb.x));
+  }
+  __syncthreads();
+  row_fft<N1, 2, row_nt<N1>(), -1>(buf, tt, ea);
+  float2* Zn = Z + (int64_t)(z0 + desc[j].aux) * ea.N;
+  for (int i = threadIdx.x; i < N1; i += row_nt<N1>()) {
+    Zn[(int64_t)ra * N1 + i] = buf[fslot<N1>(i)];
+    Zn[(int64_t)rb * N1 + i] = buf[row_len<N1>() + fslot<N1>(i)];
   }
 }
 
@@ -441,23 +577,23 @@ template <int N1>
 __global__ __launch_bounds__(row_nt<N1>()) void k_rows_conv(const float2* __restrict__ Tin, float2* __restrict__ Tout,
                                                          const float2* __restrict__ ZH, float2* __restrict__ ZU,
                                                          int z0, const NodeDesc* __restrict__ desc, EngineArgs ea) {
-  __shared__ float2 buf[2 * pad_len<N1, true>()];
-  __shared__ TwTab<N1, float2> tt;
-  tw_fill<N1>(tt, ea.tw, ea.twdl);
+  __shared__ float2 buf[2 * row_len<N1>()];
+  __shared__ RowTw<N1> tt;
+  tw_fill<row_tw<N1>()>(tt, ea.tw, ea.twdl);
   const int j = blockIdx.y;
   const int p = blockIdx.x;
   int ra, rb;
   row_pair(p, ea.N2, ra, rb);
   load_rows<N1>(buf, Tin + (int64_t)j * ea.N, ra, rb);
   __syncthreads();
-  fft_lds<N1, 2, pad_len<N1, true>(), row_nt<N1>(), -1, eng_pad<N1, true>()>(buf, tt);
+  row_fft<N1, 2, row_nt<N1>(), -1>(buf, tt, ea);
   const int64_t zr = (int64_t)(z0 + desc[j].aux) * ea.N;
   const float2* H = ZH + zr;
   if (ZU) {  // keep the input spectrum for the backward
     float2* Zs = ZU + zr;
     for (int i = threadIdx.x; i < N1; i += row_nt<N1>()) {
-      Zs[(int64_t)ra * N1 + i] = buf[px<N1, true>(i)];
-      Zs[(int64_t)rb * N1 + i] = buf[pad_len<N1, true>() + px<N1, true>(i)];
+      Zs[(int64_t)ra * N1 + i] = buf[fslot<N1>(i)];
+      Zs[(int64_t)rb * N1 + i] = buf[row_len<N1>() + fslot<N1>(i)];
     }
     __syncthreads();  // every bin stored before the product below overwrites it
   }
@@ -480,7 +616,7 @@ __global__ __launch_bounds__(row_nt<N1>()) void k_rows_conv(const float2* __rest
     buf[sb] = yb;
   }
   __syncthreads();
-  fft_lds<N1, 2, pad_len<N1, true>(), row_nt<N1>(), +1, eng_pad<N1, true>()>(buf, tt);
+  row_fft<N1, 2, row_nt<N1>(), +1>(buf, tt, ea);
   store_rows<N1>(buf, Tout + (int64_t)j * ea.N, ra, rb, ea);
 }
 
@@ -492,18 +628,18 @@ __global__ __launch_bounds__(rowb_nt<N1>(), 4) void k_rows_bwd(const float2* __r
                                                         const float2* __restrict__ ZU, int z0,
                                                         const NodeDesc* __restrict__ desc, int want_u,
                                                         EngineArgs ea) {
-  __shared__ float2 buf[4 * pad_len<N1, true>()];
-  __shared__ TwTab<N1, float2> tt;
-  tw_fill<N1>(tt, ea.tw, ea.twdl);
+  __shared__ float2 buf[4 * row_len<N1>()];
+  __shared__ RowTw<N1> tt;
+  tw_fill<row_tw<N1>()>(tt, ea.tw, ea.twdl);
   float2* b1 = buf;
-  float2* b2 = buf + 2 * pad_len<N1, true>();
+  float2* b2 = buf + 2 * row_len<N1>();
   const int j = blockIdx.y;
   const int p = blockIdx.x;
   int ra, rb;
   row_pair(p, ea.N2, ra, rb);
   load_rows<N1>(b1, Tin + (int64_t)j * ea.N, ra, rb);
   __syncthreads();
-  fft_lds<N1, 2, pad_len<N1, true>(), rowb_nt<N1>(), -1, eng_pad<N1, true>()>(b1, tt);
+  row_fft<N1, 2, rowb_nt<N1>(), -1>(b1, tt, ea);
   const int64_t zr = (int64_t)(z0 + desc[j].aux) * ea.N;
   const float2* H = ZH + zr;
   const float2* X = ZU + zr;
@@ -538,10 +674,10 @@ __global__ __launch_bounds__(rowb_nt<N1>(), 4) void k_rows_bwd(const float2* __r
   if (want_u) {
     // both products (b1, b2: four consecutive rows) in one batch of
     // transforms: half the barriers, twice the butterflies between them
-    fft_lds<N1, 4, pad_len<N1, true>(), rowb_nt<N1>(), +1, eng_pad<N1, true>()>(buf, tt);
+    row_fft<N1, 4, rowb_nt<N1>(), +1>(buf, tt, ea);
     store_rows2<N1>(b1, b2, Tu + (int64_t)j * ea.N, Th + (int64_t)j * ea.N, ra, rb, ea);
   } else {
-    fft_lds<N1, 2, pad_len<N1, true>(), rowb_nt<N1>(), +1, eng_pad<N1, true>()>(b2, tt);
+    row_fft<N1, 2, rowb_nt<N1>(), +1>(b2, tt, ea);
     store_rows<N1>(b2, Th + (int64_t)j * ea.N, ra, rb, ea);
   }
 }
@@ -635,11 +771,20 @@ static void rows_bwd_n(const Ctx& c, const float2* Tin, float2* Tu, float2* Th, 
                      c.desc + desc_off, want_u, ea);
 }
 
+template <int N1>
+static void rows_firspec_n(const Ctx& c, const LdFir& ld, float2* Z, int z0, int khi, int klo, int desc_off, int n,
+                           const EngineArgs& ea) {
+  ProfScope ps(c, "conv_rows", (double)n * 8.0 * ea.N);
+  MG_LAUNCH(c, k_rows_firspec<N1>, dim3(ea.N2 / 2, n), dim3(row_nt<N1>()), 0, c.st, ld, Z, z0, khi, klo,
+            c.desc + desc_off, ea);
+}
+
 #define MG_N1_SWITCH(FN, ...)                   \
   switch (ea.N1) {                              \
     case 512: FN<512>(__VA_ARGS__); break;      \
     case 1024: FN<1024>(__VA_ARGS__); break;    \
     case 2048: FN<2048>(__VA_ARGS__); break;    \
+    case 3072: FN<3072>(__VA_ARGS__); break;    \
     case 4096: FN<4096>(__VA_ARGS__); break;    \
   }
 
@@ -650,38 +795,43 @@ void conv_fir_spectrum(const Ctx& c, int type, int desc_off, int n, float2* T1) 
   EngineArgs ea = engine_args(c);
   float2* ZH = wsp<float2>(c, g->ws.ZH);
   const int z0 = conv_base(g, type);
+  LdFir ld;
+  ld.desc = c.desc + desc_off;
+  ld.N = ea.N;
+  double bytes;
   if (type == MG_EQ) {
-    LdFir ld;
-    ld.desc = c.desc + desc_off;
     ld.h = wsp<float>(c, g->ws.eq_h);
     ld.Nh = cf.eq_taps;
     ld.lag0 = -(cf.eq_taps - 1) / 2;
-    ld.N = ea.N;
     ld.stride = cf.eq_taps;
     ld.shared = 1;
-    run_cols(c, ld, T1, n, ea, 4.0 * cf.eq_taps);
+    bytes = 4.0 * cf.eq_taps;
   } else if (type == MG_REVERB) {
-    LdFir ld;
-    ld.desc = c.desc + desc_off;
     ld.h = wsp<float>(c, g->ws.rv_h);
     ld.Nh = cf.reverb_length;
     ld.lag0 = 0;
-    ld.N = ea.N;
     ld.stride = 2 * (int64_t)cf.reverb_length;
     ld.shared = 0;
-    run_cols(c, ld, T1, n, ea, 8.0 * cf.reverb_length);
+    bytes = 8.0 * cf.reverb_length;
   } else {
     // the compact delay FIR [2][dl_len] written by the synthesis
-    LdFir ld;
-    ld.desc = c.desc + desc_off;
     ld.h = wsp<float>(c, g->ws.dl_h);
     ld.Nh = g->dl_len;
     ld.lag0 = -(cf.delay_fir_taps - 1) / 2;
-    ld.N = ea.N;
     ld.stride = 2 * g->dl_len;
     ld.shared = 0;
-    run_cols(c, ld, T1, n, ea, 8.0 * g->dl_len);
+    bytes = 8.0 * g->dl_len;
   }
+  // rows of the index map that hold taps: lags from 0 up fill the first khi
+  // rows, negative lags the last klo
+  const int64_t hi = ld.lag0 + ld.Nh;  // one past the last lag
+  const int khi = hi > 0 ? (int)((hi + ea.N1 - 1) / ea.N1) : 0;
+  const int klo = ld.lag0 < 0 ? (int)((-ld.lag0 + ea.N1 - 1) / ea.N1) : 0;
+  if (khi + klo <= FIRSPEC_MAXK && khi + klo <= ea.N2 / 2) {
+    MG_N1_SWITCH(rows_firspec_n, c, ld, ZH, z0, khi, klo, desc_off, n, ea);
+    return;
+  }
+  run_cols(c, ld, T1, n, ea, bytes);
   MG_N1_SWITCH(rows_spec_n, c, T1, ZH, z0, desc_off, n, ea);
 }
 

@@ -394,9 +394,18 @@ int compile(mg_graph& g) {
   }
   g.fft = FftPlan{};
   if (any_conv) {
-    int64_t N = std::max<int64_t>(next_pow2(c.length + ext), 8192);
+    const int64_t need = c.length + ext;
+    int64_t N = std::max<int64_t>(next_pow2(need), 8192);
     int64_t N2 = std::min<int64_t>(std::max<int64_t>(N / 2048, 16), 1024);
     int64_t N1 = N / N2;
+    // rows of 3072 points (3 x 1024) where N = 3072 N2 suffices and is
+    // smaller than the power of two (up to a quarter fewer points)
+    const int64_t N2r = next_pow2((need + 3071) / 3072);
+    if (N2r >= 16 && N2r <= 1024 && 3072 * N2r < N) {
+      N = 3072 * N2r;
+      N1 = 3072;
+      N2 = N2r;
+    }
     if (N1 > 4096) return fail(MG_ERR_INVALID_ARG, "signal too long for the FFT engine (N > 2^22)");
     g.fft.N = (int)N;
     g.fft.N1 = (int)N1;

@@ -31,7 +31,7 @@ CALIB_BYTES = 256 << 20
 # kernel name patterns of each class (demangled names as rocprofv3 prints them)
 CLASSES = {
     "conv_cols": r"mg::k_cols<",
-    "conv_rows": r"mg::k_rows_(spec|conv|bwd)<",
+    "conv_rows": r"mg::k_rows_(spec|conv|bwd|firspec)<",
     "conv_icols": r"mg::k_icols<",
     "eq_conv": r"mg::k_eq_(fwd|bwd)\b",
     "eq_spec": r"mg::k_eq_spec\b",

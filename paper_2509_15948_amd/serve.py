@@ -375,12 +375,23 @@ def main(argv=None) -> None:
     ap.add_argument("--load", type=float, default=0.8, help="arrival rate as a fraction of the saturated rate")
     ap.add_argument("--calib-requests", type=int, default=6)
     ap.add_argument("--budget-gb", type=float, default=200.0)
+    ap.add_argument("--torch-fraction", type=float, default=0.85,
+                    help="share of device memory torch's allocator may hold, cached blocks included")
     ap.add_argument("--max-active", type=int, default=8)
     ap.add_argument("--seed", type=int, default=3)
     a = ap.parse_args(argv)
     spec = SearchSpec(steps=a.steps, rounds=a.rounds, finetune=a.finetune, tau=a.tau, candidates=a.candidates,
                       quantum=8)
     budget = int(a.budget_gb * (1 << 30))
+    # Searches of uneven sizes leave torch's allocator with cached blocks that
+    # fit no later request; unchecked, the cache grows until device memory is
+    # full, and then the runtime's own allocations (a queue's scratch, say)
+    # fail and abort the queue.  Capped, torch releases cached blocks and
+    # retries first, and the rest of device memory stays with the runtime.
+    torch.cuda.set_per_process_memory_fraction(a.torch_fraction)
+    # admitted footprints stay within 80 % of torch's share (the rest absorbs
+    # the allocator's rounding and the target renders' transient workspaces)
+    budget = min(budget, int(0.8 * a.torch_fraction * torch.cuda.get_device_properties(0).total_memory))
 
     def log(msg):
         print(msg, file=sys.stderr, flush=True)
@@ -415,7 +426,7 @@ def main(argv=None) -> None:
            "p50_latency_s": round(out["p50_s"], 3), "p99_latency_s": round(out["p99_s"], 3),
            "songs_per_s": round(out["songs_per_s"], 4), "audio_s_per_s": round(out["audio_s_per_s"], 1),
            "makespan_s": round(out["makespan_s"], 2), "peak_active": out["peak_active"],
-           "peak_gb": round(out["peak_bytes"] / (1 << 30), 2),
+           "peak_gb": round(out["peak_bytes"] / (1 << 30), 2), "budget_gb": round(budget / (1 << 30), 1),
            "mean_queue_wait_s": round(float(np.mean(out["queue_wait_s"])), 3),
            "pruning_ratio_mean": round(float(np.mean([r / s for r, s in zip(removed, starts)])), 4)}
     print(json.dumps(rec), flush=True)

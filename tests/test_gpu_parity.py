@@ -62,10 +62,19 @@ def test_zero_dry_wet_is_the_sum_of_the_sources():
 @pytest.mark.parametrize("chain", ["g", "s", "x", "e", "c", "n", "d", "r", "ecxsgdr", "ecxsgdr-odd"])
 def test_backward_parity_per_type(chain):
     """Per processor type; "-odd" runs 12001 samples, which no kernel's
-    vector width or tile divides."""
+    vector width or tile divides.  The delay case runs 1.5 s: at 0.75 s the
+    oracle's own delay gradient moves by 1.9 % under FP32-level noise at the
+    processor outputs (quiet log-Mel cells), so the case could not tell a
+    1 % error from rounding; at 1.5 s that sensitivity is 1.7e-4."""
     odd = chain.endswith("-odd")
     chain = chain.replace("-odd", "")
-    case = Case(_small(chain, seconds=12001 / 16000) if odd else _small(chain), alpha_p=1e-2)
+    if odd:
+        cfg = _small(chain, seconds=12001 / 16000)
+    elif chain == "d":
+        cfg = _small(chain, seconds=1.5)
+    else:
+        cfg = _small(chain)
+    case = Case(cfg, alpha_p=1e-2)
     mix, gl = case.gpu_forward()
     gth, gwe = case.gpu_backward()
     omix, ol, oth, owe = case.oracle()
@@ -99,11 +108,12 @@ def test_backward_parity_per_type(chain):
 
 
 def test_narrow_column_tiles_against_the_oracle():
-    """One track and one subgroup with delay and reverb, 70 s at 16 kHz: a
-    2^21-point engine with 1024-point columns, so the column kernels take
-    8-column tiles (64-byte row segments) in their XCD-aware order.  Waveform,
-    losses and the delay/reverb/dry-wet gradients against the oracle."""
-    case = Case(_small("dr", seconds=70.0, n_tracks=1, n_subgroups=1), alpha_p=1e-2)
+    """One track and one subgroup with delay and reverb, 100 s at 16 kHz: a
+    2^21-point engine (the signal is too long for 3072 x 512) with 1024-point
+    columns, so the column kernels take 8-column tiles (64-byte row segments)
+    in their XCD-aware order.  Waveform, losses and the delay/reverb/dry-wet
+    gradients against the oracle."""
+    case = Case(_small("dr", seconds=100.0, n_tracks=1, n_subgroups=1), alpha_p=1e-2)
     assert case.bg.info.fft_size == 1 << 21
     mix, gl = case.gpu_forward()
     gth, gwe = case.gpu_backward()

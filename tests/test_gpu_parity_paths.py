@@ -77,13 +77,14 @@ def _oracle_nodes(case, mask=None):
 def test_large_console_geometry_against_the_oracle():
     """One delay + reverb chain per level, 45 s at 48 kHz, 2 s (96 000-tap)
     reverb, 0.5 s delay range, loss at 256/512/1024/2048/4096 points: the FFT
-    engine is 2^22 points (4096-point rows, 1024-point columns in 8-column
-    tiles), as in the large console.  Waveform, losses and the delay, reverb
+    engine is 3 x 2^20 points (3072-point rows, each three 1024-point
+    transforms and a radix-3 pass, and 1024-point columns in 8-column tiles),
+    as in the large console.  Waveform, losses and the delay, reverb
     and dry/wet gradients against the oracle."""
     cfg = synth.small_config(seconds=45.0, fs=48000, n_tracks=1, n_subgroups=1, chain="dr", reverb_seconds=2.0,
                              delay_range_s=0.5, loss_ffts=(256, 512, 1024, 2048, 4096))
     case = Case(cfg, alpha_p=1e-2)
-    assert case.bg.info.fft_size == 1 << 22
+    assert case.bg.info.fft_size == 3 << 20       # 3072-point rows x 1024-point columns
     assert cfg.reverb_length == 96000
     mix, gl = case.gpu_forward()
     gth, gwe = case.gpu_backward()

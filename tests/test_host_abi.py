@@ -230,3 +230,23 @@ def test_footprint_covers_workspace_and_caller_buffers():
     cfg2, g2, bg2 = _graph(seconds=2 * cfg.seconds)
     ws2, st2 = MG.mg_footprint(bg2.h, 1)
     assert ws2 > ws and st2 > st
+
+
+def test_build_rejects_kernels_that_use_scratch():
+    """The build's scan of the compiler's resource remarks finds each kernel
+    with nonzero scratch bytes per lane and nothing else; only the listed EQ
+    window kernels may use any."""
+    from paper_2509_15948_amd.build import scratch_kernels
+    remarks = "\n".join([
+        "k.hip:10:1: remark: Function Name: _Z5k_onePf [-Rpass-analysis=kernel-resource-usage]",
+        "k.hip:10:1: remark:     VGPRs: 40 [-Rpass-analysis=kernel-resource-usage]",
+        "k.hip:10:1: remark:     ScratchSize [bytes/lane]: 0 [-Rpass-analysis=kernel-resource-usage]",
+        "k.hip:20:1: remark: Function Name: _Z5k_twoPf [-Rpass-analysis=kernel-resource-usage]",
+        "k.hip:20:1: remark:     ScratchSize [bytes/lane]: 64 [-Rpass-analysis=kernel-resource-usage]",
+    ])
+    assert scratch_kernels(remarks) == [("_Z5k_twoPf", 64)]
+    assert scratch_kernels("") == []
+    from paper_2509_15948_amd.build import _allowed
+    assert _allowed("_ZN2mg8k_eq_bwdENS_6EqArgsE") == 64
+    assert _allowed("_ZN2mg8k_eq_fwdENS_6EqArgsE") == 16
+    assert _allowed("_ZN2mg6k_colsILi1024ELi8ENS_5LdFirEEEvT1_P15HIP_vector_typeIfLj2EENS_10EngineArgsE") == 0
