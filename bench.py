@@ -289,20 +289,29 @@ def committed_traffic(kernel_class, workload):
 
 
 def serving_leg(args):
-    """Whole-song searches arriving as a Poisson stream, served with
-    continuous batching (serve.Server): p50/p99 latency and throughput."""
+    """Whole-song searches of the serving configuration's shape (tracks
+    U{4..32}, subgroups U{2..8}, 5-30 s at 44.1 kHz; 300 steps, then 10
+    rounds of 64 candidates and 50 fine-tune steps) arriving as a Poisson
+    stream, served with continuous batching (serve.Server): p50/p99 latency
+    and throughput.  A short stream (--serve-requests); the long one is
+    `python -m paper_2509_15948_amd.serve`."""
     import synth
     from paper_2509_15948_amd import serve as SV
-    reqs = synth.serving_requests(3, args.serve_requests, rate=args.serve_rate, tracks=(4, 16), subgroups=(2, 4),
-                                  seconds=(2.0, 6.0), fs=44100)
-    spec = SV.SearchSpec(steps=args.serve_steps, rounds=2, finetune=5, tau=1e-3, candidates=16, quantum=4)
-    server = SV.Server(budget_bytes=int(args.serve_budget_gb * (1 << 30)), max_active=4)
+    reqs = synth.serving_requests(3, args.serve_requests, rate=args.serve_rate, tracks=(4, 32), subgroups=(2, 8),
+                                  seconds=(5.0, 30.0), fs=44100)
+    spec = SV.SearchSpec(steps=args.serve_steps, rounds=10, finetune=50, tau=1e-3, candidates=64, quantum=8)
+    import torch
+    # as in the serving entry point: torch's cached blocks stay below 85 % of
+    # device memory, so the runtime keeps room for its own allocations
+    torch.cuda.set_per_process_memory_fraction(0.85)
+    budget = min(int(args.serve_budget_gb * (1 << 30)), int(0.68 * torch.cuda.get_device_properties(0).total_memory))
+    server = SV.Server(budget_bytes=budget, max_active=8)
     out = server.run(reqs, lambda i, cfg, seed: SV.Search(i, cfg, seed, spec))
     removed = [sum(r["removed"] for r in res["trace"]) for res in out["results"]]
     final = [res["processors"] for res in out["results"]]
     return {"requests": len(reqs), "rate_per_s": args.serve_rate,
-            "workload": f"tracks U{{4..16}}, subgroups U{{2..4}}, 2-6 s at 44.1 kHz, chain ecxsgdr; search = "
-                        f"{spec.steps} steps + {spec.rounds} pruning rounds x ({spec.candidates} trials + "
+            "workload": f"tracks U{{4..32}}, subgroups U{{2..8}}, 5-30 s at 44.1 kHz, chain ecxsgdr; search = "
+                        f"{spec.steps} steps + {spec.rounds} pruning rounds x ({spec.candidates} candidates + "
                         f"{spec.finetune} fine-tune steps)",
             "p50_latency_s": round(out["p50_s"], 4), "p99_latency_s": round(out["p99_s"], 4),
             "songs_per_s": round(out["songs_per_s"], 3), "audio_s_per_s": round(out["audio_s_per_s"], 1),
@@ -527,9 +536,9 @@ def main():
     ap.add_argument("--prune-rounds", type=int, default=30, help="rounds of the pruning schedule (0 skips it)")
     ap.add_argument("--serve-requests", type=int, default=12,
                     help="requests of the serving leg (0 skips it)")
-    ap.add_argument("--serve-rate", type=float, default=20.0, help="Poisson arrival rate, requests/s")
-    ap.add_argument("--serve-steps", type=int, default=20, help="optimisation steps per search")
-    ap.add_argument("--serve-budget-gb", type=float, default=64.0)
+    ap.add_argument("--serve-rate", type=float, default=0.35, help="Poisson arrival rate, requests/s")
+    ap.add_argument("--serve-steps", type=int, default=300, help="optimisation steps per search")
+    ap.add_argument("--serve-budget-gb", type=float, default=160.0)
     ap.add_argument("--pmc-run", action="store_true",
                     help="for rocprofv3 counter runs: a calibration copy, then --steps steps, nothing else")
     args = ap.parse_args()

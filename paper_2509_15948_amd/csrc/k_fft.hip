@@ -27,10 +27,14 @@ namespace mg {
 // threads, 16 waves, measured 4 % slower per step; 4096-element tiles, 64-byte
 // row segments, slower still); row kernels use 512 threads from N1 = 1024 up
 // (fewer rows of butterflies below), except the backward rows, which batch
-// four transforms and take 1024 from N1 = 2048 (rowb_nt)
+// four transforms and take 1024 from N1 = 2048 (rowb_nt).  A pair of
+// 3072-point rows is six 1024-point transforms, 768 radix-8 butterflies per
+// pass: 768 threads take one each (512 left half the lanes idle in every
+// second round) and, at 57 KB of LDS, two blocks still fit a CU (24 waves;
+// the large console's step 49.2 -> 48.5 ms)
 constexpr int COL_NT = 1024;
 template <int N1>
-constexpr int row_nt() { return N1 >= 4096 ? 1024 : (N1 >= 1024 ? 512 : 256); }
+constexpr int row_nt() { return N1 == 3072 ? 768 : (N1 >= 4096 ? 1024 : (N1 >= 1024 ? 512 : 256)); }
 // the backward rows batch four transforms: 1024 threads from 2048 points
 template <int N1>
 constexpr int rowb_nt() { return N1 >= 2048 ? 1024 : row_nt<N1>(); }
