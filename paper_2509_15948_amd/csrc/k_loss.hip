@@ -26,10 +26,17 @@ constexpr int LOSS_NT = 512;
 
 constexpr double LOG_EPS = 1e-7;
 
-// Frames per workgroup: 1024 complex FP64 points per batch (16 KB of LDS),
-// so two or three workgroups share a CU; one frame from 1024 points up.
+// Frames per workgroup of the backward: 1024 complex FP64 points per batch
+// (16 KB of LDS, beside the magnitudes and band gradients it keeps), one
+// frame from 1024 points up.
 template <int N>
 constexpr int loss_fpb() { return N >= 1024 ? 1 : 1024 / N; }
+// The forward holds 4096 / N frames per workgroup (64 KB of LDS, two
+// workgroups per CU): each radix-8 pass then has 512 butterflies, one per
+// thread (one 1024- or 2048-point frame left three quarters or half of the
+// lanes idle in every pass; 64 pruning trials 10.25 -> 9.24 ms).
+template <int N>
+constexpr int loss_fpb_fwd() { return N >= 4096 ? 1 : 4096 / N; }
 
 // frames sit in LDS with one spare slot per 8 points: point t of frame fl at
 // buf[fl * loss_bs<N>() + lx(t)].  With 16-byte points the first radix-8
@@ -63,9 +70,8 @@ struct LossArgs {
   const double2* tw;
 };
 
-template <int N>
+template <int N, int FPB>
 __device__ __forceinline__ void load_frames(double2* buf, const LossArgs& a, int f0) {
-  constexpr int FPB = loss_fpb<N>();
   for (int idx = threadIdx.x; idx < FPB * N; idx += blockDim.x) {
     const int fl = idx / N, t = idx % N;
     const int f = f0 + fl;
@@ -107,9 +113,8 @@ __device__ __forceinline__ void frame_mags(const double2* buf, double* mag, cons
 // the spectrum no further): every thread first takes its bins' values into
 // registers, the block synchronises, then the magnitudes go to mag, which
 // aliases buf (FPB (N + 2) complex values hold FPB * 4 * (N/2 + 1) doubles).
-template <int N>
+template <int N, int FPB>
 __device__ __forceinline__ void frame_mags_inplace(double2* buf, const LossArgs& a) {
-  constexpr int FPB = loss_fpb<N>();
   constexpr int NB = N / 2 + 1;
   constexpr int Q = (FPB * NB + LOSS_NT - 1) / LOSS_NT;
   double m4[Q][4];
@@ -155,7 +160,7 @@ __device__ __forceinline__ double mel_of(const double* mag, const LossArgs& a, i
 // twiddles, magnitudes, dL/dYh per (frame, combo, band)
 template <int N>
 constexpr int loss_fwd_lds() {
-  return loss_fpb<N>() * loss_bs<N>() * 16 + (int)sizeof(TwTab<N, double2>) + LOSS_NT / 64 * 8;
+  return loss_fpb_fwd<N>() * loss_bs<N>() * 16 + (int)sizeof(TwTab<N, double2>) + LOSS_NT / 64 * 8;
 }
 template <int N>
 constexpr int loss_bwd_lds() {
@@ -176,7 +181,7 @@ constexpr int loss_lds_max() {
 // bytes of LDS (16-byte aligned)
 template <int N, int MODE>
 __device__ __forceinline__ void loss_fwd_body(const LossArgs& a, int blk, double2* smem) {
-  constexpr int FPB = loss_fpb<N>();
+  constexpr int FPB = loss_fpb_fwd<N>();
   double2* buf = smem;   // spectra, then the magnitudes over them
   static_assert(loss_bs<N>() >= N + 2, "the magnitudes fit over the padded frames");
   TwTab<N, double2>& tt = *reinterpret_cast<TwTab<N, double2>*>(smem + FPB * loss_bs<N>());
@@ -184,10 +189,10 @@ __device__ __forceinline__ void loss_fwd_body(const LossArgs& a, int blk, double
   tw_fill<N>(tt, a.tw, (const double2*)nullptr);
   const double* mag = reinterpret_cast<const double*>(buf);
   const int f0 = blk * FPB;
-  load_frames<N>(buf, a, f0);
+  load_frames<N, FPB>(buf, a, f0);
   __syncthreads();
   fft_lds<N, FPB, loss_bs<N>(), LOSS_NT, -1, LOSS_PAD>(buf, tt);
-  frame_mags_inplace<N>(buf, a);
+  frame_mags_inplace<N, FPB>(buf, a);
   __syncthreads();
   double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   const int items = FPB * 4 * a.nm;
@@ -271,7 +276,7 @@ __device__ __forceinline__ void loss_bwd_body(const LossArgs& a, int blk, double
   double* dyh = mag + FPB * 4 * NB;
   tw_fill<N>(tt, a.tw, (const double2*)nullptr);
   const int f0 = blk * FPB;
-  load_frames<N>(buf, a, f0);
+  load_frames<N, FPB>(buf, a, f0);
   __syncthreads();
   fft_lds<N, FPB, loss_bs<N>(), LOSS_NT, -1, LOSS_PAD>(buf, tt);
   frame_mags<N>(buf, mag, a);
@@ -597,14 +602,14 @@ static void bwd_multi(const Ctx& c, const LossMulti& m) {
 // launch groups: every resolution in [lo, hi] points, with its args from
 // args_of(i); fills the group's grid layout and returns its largest size
 template <typename F>
-static int loss_group(const mg_graph* g, int lo, int hi, LossMulti& m, F args_of) {
+static int loss_group(const mg_graph* g, int lo, int hi, bool fwd, LossMulti& m, F args_of) {
   m.nres = 0;
   m.first[0] = 0;
   int nmax = 0;
   for (size_t i = 0; i < g->lres.size(); ++i) {
     const LossRes& r = g->lres[i];
     if (r.nfft < lo || r.nfft > hi) continue;
-    const int FPB = loss_frames_per_block(r.nfft);
+    const int FPB = fwd ? loss_frames_per_block_fwd(r.nfft) : loss_frames_per_block(r.nfft);
     const int k = m.nres++;
     m.a[k] = args_of((int)i);
     m.nfft[k] = r.nfft;
@@ -621,7 +626,7 @@ static void run_loss_fwd(const Ctx& c, const float* y, int mode, double* stats_o
   ra.mode = mode;
   for (size_t i = 0; i < g->lres.size(); ++i) {
     const LossRes& r = g->lres[i];
-    const int FPB = loss_frames_per_block(r.nfft);
+    const int FPB = loss_frames_per_block_fwd(r.nfft);
     ra.part[i] = (double*)(c.base + r.part_off);
     ra.nblocks[i] = (r.frames + FPB - 1) / FPB;
     ra.cells[i] = r.frames * g->cfg.n_mels;
@@ -634,7 +639,7 @@ static void run_loss_fwd(const Ctx& c, const float* y, int mode, double* stats_o
   for (int k = 0; k < 2; ++k) {
     const Ctx& cc = (k == 1) ? cs : c;
     LossMulti m;
-    const int nmax = loss_group(g, groups[k][0], groups[k][1], m, [&](int i) { return loss_args(c, i, y); });
+    const int nmax = loss_group(g, groups[k][0], groups[k][1], true, m, [&](int i) { return loss_args(c, i, y); });
     if (m.nres == 0) continue;
 #define MG_F0(NN) fwd_multi<NN, 0>(cc, m)
 #define MG_F1(NN) fwd_multi<NN, 1>(cc, m)
@@ -697,7 +702,7 @@ void loss_backward(const Ctx& c, const float* yhat, float* dyhat) {
   for (int k = 0; k < 2; ++k) {
     const Ctx& cc = (k == 1) ? cs : c;
     LossMulti m;
-    const int nmax = loss_group(g, groups[k][0], groups[k][1], m, [&](int i) {
+    const int nmax = loss_group(g, groups[k][0], groups[k][1], false, m, [&](int i) {
       LossArgs a = loss_args(c, i, yhat);
       a.scratch = scratch[i];
       return a;

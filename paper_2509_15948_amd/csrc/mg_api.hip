@@ -117,7 +117,7 @@ static size_t plan_ws(mg_graph& g, int mode, bool commit) {
   take(w.lg, (size_t)std::max(1, n_win) * 2 * 8);
   take(w.ls_stats, 8 * 16 * 8);
   for (auto& r : g.lres) {
-    const int FPB = loss_frames_per_block(r.nfft);
+    const int FPB = loss_frames_per_block_fwd(r.nfft);  // partial rows: one per forward block
     const int blocks = (r.frames + FPB - 1) / FPB;
     size_t tgt, part, tab;
     take(tgt, (size_t)r.frames * 4 * c.n_mels * 8);

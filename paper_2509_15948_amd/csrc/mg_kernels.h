@@ -7,8 +7,11 @@
 namespace mg {
 
 constexpr int PW_MAXK = 4;  // pointwise stages fused into one launch at most
-// frames of one loss resolution per workgroup (host and kernels agree)
+// frames of one loss resolution per workgroup of the backward (host and
+// kernels agree)
 inline int loss_frames_per_block(int nfft) { return nfft >= 1024 ? 1 : 1024 / nfft; }
+// the forward's (its partial rows are per block of these)
+inline int loss_frames_per_block_fwd(int nfft) { return nfft >= 4096 ? 1 : 4096 / nfft; }
 constexpr int PK = 8;  // floats of partial sums per (node, block)
 // elements of one column block of the FFT engine (TC = COL_TILE / N2 columns)
 constexpr int COL_TILE = 8192;
