@@ -194,6 +194,7 @@ def run_search(song_graph, cfg, dry: np.ndarray, noise: Dict[int, np.ndarray], t
     if log:
         log(f"console phase: {reg.console_steps} steps in {t_console:.1f} s, L_a {La_console:.4f}")
     trace = []
+    w_delta = []
     t_prune = 0
     P0 = S.eval_g.n_proc
     for n in range(1, reg.rounds + 1):
@@ -201,9 +202,15 @@ def run_search(song_graph, cfg, dry: np.ndarray, noise: Dict[int, np.ndarray], t
         t1 = time.perf_counter()
         P = S.eval_g.n_proc
         if method == "brute":
+            w_now = 1.0 / (1.0 + np.exp(-S.wet.detach().cpu().numpy().astype(np.float64)))
+            ptype = S.eval_g.proc_types()
             res = MG.prune_round(S.eval_s, S.dry_d, S.theta, S.wet, None, tau=reg.tau, max_candidates=P,
                                  L_min=L_min, relative=False)
             trials = len(res["candidates"]) + len(res["order"])
+            # each candidate's dry/wet weight against the loss increase of
+            # bypassing it alone (the relation the dry/wet method relies on)
+            for j, Lj in zip(res["candidates"], res["L_cand"]):
+                w_delta.append((float(w_now[j]), float(Lj) - float(res["La"]), int(ptype[j])))
         else:
             u = draws.random(4 * P + 64)
             res = MG.drywet_round(S.eval_s, S.dry_d, S.theta, S.wet, u, tau=reg.tau, relative=False, L_min=L_min)
@@ -226,8 +233,53 @@ def run_search(song_graph, cfg, dry: np.ndarray, noise: Dict[int, np.ndarray], t
            "processors_end": S.eval_g.n_proc, "pruning_ratio": 1.0 - S.eval_g.n_proc / max(P0, 1),
            "kept": kept, "trace": trace, "console_s": t_console, "total_s": time.perf_counter() - t0,
            "theta": S.theta.cpu().numpy(), "wet": S.wet.cpu().numpy(), "mix": y.cpu().numpy(),
-           "types": list(S.eval_g.types), "orig": list(S.orig)}
+           "types": list(S.eval_g.types), "orig": list(S.orig), "w_delta": w_delta}
     return out
+
+
+def _ranks(x: np.ndarray) -> np.ndarray:
+    """Ranks 0..n-1, ties given their mean rank."""
+    order = np.argsort(x, kind="stable")
+    r = np.empty(len(x), np.float64)
+    r[order] = np.arange(len(x), dtype=np.float64)
+    for v in np.unique(x):
+        sel = x == v
+        if sel.sum() > 1:
+            r[sel] = r[sel].mean()
+    return r
+
+
+def w_delta_summary(pairs, tau: float) -> Dict:
+    """Dry/wet weight w of every brute-force candidate against the loss
+    increase Delta of bypassing it alone: the Spearman rank correlation, and
+    per quarter of the candidates by w the median Delta and the share within
+    the tolerance (Delta < tau), overall and by processor type."""
+    if not pairs:
+        return {}
+    w = np.array([p[0] for p in pairs])
+    d = np.array([p[1] for p in pairs])
+    t = np.array([p[2] for p in pairs])
+
+    def spearman(a, b):
+        if len(a) < 3:
+            return None
+        ra, rb = _ranks(a), _ranks(b)
+        ra, rb = ra - ra.mean(), rb - rb.mean()
+        den = np.sqrt((ra * ra).sum() * (rb * rb).sum())
+        return round(float((ra * rb).sum() / den), 4) if den > 0 else None
+
+    q = np.quantile(w, [0.0, 0.25, 0.5, 0.75, 1.0])
+    bins = []
+    for i in range(4):
+        sel = (w >= q[i]) & ((w <= q[i + 1]) if i == 3 else (w < q[i + 1]))
+        if sel.any():
+            bins.append({"w_range": [round(float(q[i]), 4), round(float(q[i + 1]), 4)], "n": int(sel.sum()),
+                         "median_delta": round(float(np.median(d[sel])), 6),
+                         "within_tau": round(float(np.mean(d[sel] < tau)), 3)})
+    names = {v: k for k, v in MG.TYPE_CODES.items()}
+    by_type = {names.get(int(k), str(k)): spearman(w[t == k], d[t == k]) for k in np.unique(t)}
+    return {"candidates": len(pairs), "spearman_w_delta": spearman(w, d), "by_w_quarter": bins,
+            "spearman_by_type": by_type}
 
 
 def processor_agreement(types: Sequence[str], truth: np.ndarray, pred: np.ndarray) -> Dict:
@@ -344,6 +396,7 @@ def main(argv=None) -> None:
                 "processors_end": r["processors_end"], "pruning_ratio": round(r["pruning_ratio"], 4),
                 "kept_ratio_by_type": {t: round(float(np.mean(k)), 3) for t, k in kept_by_type.items()},
                 "trials": sum(x["trials"] for x in r["trace"]), "console_s": round(r["console_s"], 2),
+                "w_vs_delta": w_delta_summary(r["w_delta"], tau),
                 "total_s": round(r["total_s"], 2),
                 "workload": f"{cfg.n_tracks} tracks, {cfg.n_subgroups} subgroups, {cfg.seconds:g} s at {cfg.fs} Hz, "
                             f"chain {cfg.chain}; {reg.console_steps} console steps, {reg.rounds} rounds x "
