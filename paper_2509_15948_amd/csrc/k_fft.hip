@@ -64,18 +64,23 @@ template <int N1>
 constexpr bool row3() { return N1 == 3072; }
 template <int N1>
 constexpr int row_tw() { return row3<N1>() ? 1024 : N1; }
+// the three 1024-point transforms of a 3072-point row keep one spare slot
+// per 16 points, as the power-of-two rows up to 2048 do (bit-identical
+// results; the large console's step 48.4 -> 48.2 ms)
+constexpr int R3_PAD = 4;
+constexpr int R3_SB = lds_len<1024, R3_PAD>();
 template <int N1>
-constexpr int row_len() { return row3<N1>() ? N1 : pad_len<N1, true>(); }
+constexpr int row_len() { return row3<N1>() ? 3 * R3_SB : pad_len<N1, true>(); }
 template <int N1>
 using RowTw = TwTab<row_tw<N1>(), float2>;
 template <int N1>
 __device__ __forceinline__ int tslot(int i) {
-  if constexpr (row3<N1>()) return (i % 3) * 1024 + i / 3;
+  if constexpr (row3<N1>()) return (i % 3) * R3_SB + lds_ix<R3_PAD>(i / 3);
   else return px<N1, true>(i);
 }
 template <int N1>
 __device__ __forceinline__ int fslot(int k) {
-  if constexpr (row3<N1>()) return k;
+  if constexpr (row3<N1>()) return (k >> 10) * R3_SB + lds_ix<R3_PAD>(k & 1023);
   else return px<N1, true>(k);
 }
 
@@ -108,11 +113,12 @@ template <int B, int NT, int DIR>
 __device__ __forceinline__ void radix3_pass(float2* buf, const EngineArgs& ea) {
   const float c3 = -0.5f, s3 = 0.866025403784438647f;
   for (int idx = threadIdx.x; idx < B * 1024; idx += NT) {
-    float2* r = buf + (idx >> 10) * 3072;
+    float2* r = buf + (idx >> 10) * (3 * R3_SB);
     const int k = idx & 1023;
+    const int kk = lds_ix<R3_PAD>(k);
     const float2 w1 = big_tw(ea.twhi, ea.twlo, (int64_t)k * ea.N2);
     const float2 w2 = big_tw(ea.twhi, ea.twlo, (int64_t)(2 * k) * ea.N2);
-    float2 a0 = r[k], a1 = r[1024 + k], a2 = r[2048 + k];
+    float2 a0 = r[kk], a1 = r[R3_SB + kk], a2 = r[2 * R3_SB + kk];
     if (DIR < 0) {
       a1 = c_mul(a1, w1);
       a2 = c_mul(a2, w2);
@@ -126,9 +132,9 @@ __device__ __forceinline__ void radix3_pass(float2* buf, const EngineArgs& ea) {
       y1 = c_mul(y1, c_conj(w1));
       y2 = c_mul(y2, c_conj(w2));
     }
-    r[k] = c_add(a0, sm);
-    r[1024 + k] = y1;
-    r[2048 + k] = y2;
+    r[kk] = c_add(a0, sm);
+    r[R3_SB + kk] = y1;
+    r[2 * R3_SB + kk] = y2;
   }
 }
 
@@ -141,7 +147,7 @@ __device__ __forceinline__ void row_fft(float2* buf, const RowTw<N1>& tt, const 
       radix3_pass<B, NT, DIR>(buf, ea);
       __syncthreads();
     }
-    fft_lds<1024, 3 * B, 1024, NT, DIR, 0>(buf, tt);
+    fft_lds<1024, 3 * B, R3_SB, NT, DIR, R3_PAD>(buf, tt);
     if (DIR < 0) {
       radix3_pass<B, NT, DIR>(buf, ea);
       __syncthreads();
@@ -576,9 +582,14 @@ __global__ __launch_bounds__(row_nt<N1>()) void k_rows_firspec(LdFir ld, float2*
   }
 }
 
+// 3072-point rows: registers held to 80 (6 waves per SIMD), so that two
+// 768-thread workgroups share a CU; the padded index arithmetic took 81
+template <int N1>
+constexpr int rows_conv_min_waves() { return N1 == 3072 ? 6 : 1; }
+
 // forward convolution: Y = Xl Hl + i Xr Hr
 template <int N1>
-__global__ __launch_bounds__(row_nt<N1>()) void k_rows_conv(const float2* __restrict__ Tin, float2* __restrict__ Tout,
+__global__ __launch_bounds__(row_nt<N1>(), rows_conv_min_waves<N1>()) void k_rows_conv(const float2* __restrict__ Tin, float2* __restrict__ Tout,
                                                          const float2* __restrict__ ZH, float2* __restrict__ ZU,
                                                          int z0, const NodeDesc* __restrict__ desc, EngineArgs ea) {
   __shared__ float2 buf[2 * row_len<N1>()];
