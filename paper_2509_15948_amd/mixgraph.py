@@ -475,6 +475,31 @@ class Session:
         mg_forward_trials(self.g.h, keep, losses, self.stream())
 
 
+class StepGraph:
+    """mg_forward + mg_backward of a session captured once as a HIP graph and
+    replayed with one launch per step: the same device buffers every time
+    (dry tracks, parameters, dry/wet logits, mask, loss record, gradients),
+    read and written at replay time.  A step of a small song is some sixty
+    short kernels, and enqueueing them one by one from the host costs about
+    as much as running them.  The optimiser stays outside the graph (its step
+    count changes every call).  The step enqueues kernels, event records and
+    waits and device copies only, so it can be captured; the library's side
+    stream joins the capture through those events.  Capture again after the
+    session or any of the buffers changes."""
+
+    def __init__(self, session: Session, dry, theta, wet, mask, losses, grad_theta, grad_wet):
+        torch = session.torch
+        self.session = session
+        self.buffers = (dry, theta, wet, mask, losses, grad_theta, grad_wet)
+        self.graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(self.graph):
+            session.forward(dry, theta, wet, mask, None, losses)
+            session.backward(grad_theta, grad_wet)
+
+    def replay(self):
+        self.graph.replay()
+
+
 def prune_round(session: Session, dry, theta, wet, mask=None, tau: float = 1e-3, max_candidates: int = 64,
                 L_min: Optional[float] = None, relative: bool = True):
     """One pruning round (Alg. 2 with batched trials): a forward at the

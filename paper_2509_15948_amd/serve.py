@@ -45,6 +45,11 @@ class SearchSpec:
     lr: float = 1e-2
     quantum: int = 4          # steps enqueued before yielding to the loop
     stop_when_none: bool = False  # end the rounds at the first that removes nothing
+    # forward + backward replayed as one captured HIP graph (mixgraph.StepGraph).
+    # Off: with it on, a serving test that admits searches one at a time
+    # ended in a host segmentation fault inside the graph replay, whose cause
+    # has not been found; the captured step itself replays bit for bit.
+    graph_steps: bool = False
 
 
 class PruneThreshold:
@@ -125,6 +130,7 @@ class Search:
         self.noise_by_node = dict(self.noise)
         self.losses = torch.zeros(7, dtype=torch.float64, device=dev)
         self.n_step = 0
+        self._graph = None
 
     def _compact(self, torch, dev):
         """Remove the pruned processors from the graph (graph surgery) and
@@ -135,6 +141,7 @@ class Search:
         freed workspace on this search's stream after the work that read it
         (the side stream's work has joined that stream by then)."""
         self.sess = None
+        self._graph = None
         new, o2n, sess, noise_d, th, we = MG.compact(self.bg, self.alive, self.noise_by_node, self.cfg.reverb_length,
                                                      self.target_d, (self.theta, self.m_t, self.v_t),
                                                      (self.wet, self.m_w, self.v_w), dev)
@@ -151,8 +158,16 @@ class Search:
         s = self.sess
         st = s.stream()
         self.n_step += 1
-        s.forward(self.dry_d, self.theta, self.wet, self.mask, None, self.losses)
-        s.backward(self.gth, self.gwe)
+        if self.spec.graph_steps:
+            # captured at the first step on this session and these buffers
+            # (graph surgery replaces both), then one launch per step
+            if self._graph is None or self._graph.session is not s:
+                self._graph = MG.StepGraph(s, self.dry_d, self.theta, self.wet, self.mask, self.losses, self.gth,
+                                           self.gwe)
+            self._graph.replay()
+        else:
+            s.forward(self.dry_d, self.theta, self.wet, self.mask, None, self.losses)
+            s.backward(self.gth, self.gwe)
         MG.mg_adam_step(self.theta, self.m_t, self.v_t, self.gth, self.bg.n_theta, self.spec.lr, 0.9, 0.999, 1e-8,
                         self.n_step, st)
         MG.mg_adam_step(self.wet, self.m_w, self.v_w, self.gwe, self.bg.n_proc, self.spec.lr, 0.9, 0.999, 1e-8,
@@ -241,8 +256,8 @@ class Search:
                        "types": list(self.bg.types), "trace": list(self.trace)}
 
     def release(self):
-        for name in ("sess", "dry_d", "noise_d", "target_d", "theta", "wet", "gth", "gwe", "m_t", "v_t", "m_w",
-                     "v_w", "mask", "losses", "noise_by_node"):
+        for name in ("_graph", "sess", "dry_d", "noise_d", "target_d", "theta", "wet", "gth", "gwe", "m_t", "v_t",
+                     "m_w", "v_w", "mask", "losses", "noise_by_node"):
             if hasattr(self, name):
                 delattr(self, name)
 
@@ -379,9 +394,11 @@ def main(argv=None) -> None:
                     help="share of device memory torch's allocator may hold, cached blocks included")
     ap.add_argument("--max-active", type=int, default=8)
     ap.add_argument("--seed", type=int, default=3)
+    ap.add_argument("--graphs", action="store_true",
+                    help="replay each step as a captured HIP graph (experimental: see SearchSpec.graph_steps)")
     a = ap.parse_args(argv)
     spec = SearchSpec(steps=a.steps, rounds=a.rounds, finetune=a.finetune, tau=a.tau, candidates=a.candidates,
-                      quantum=8)
+                      quantum=8, graph_steps=a.graphs)
     budget = int(a.budget_gb * (1 << 30))
     # Searches of uneven sizes leave torch's allocator with cached blocks that
     # fit no later request; unchecked, the cache grows until device memory is
@@ -427,7 +444,7 @@ def main(argv=None) -> None:
            "songs_per_s": round(out["songs_per_s"], 4), "audio_s_per_s": round(out["audio_s_per_s"], 1),
            "makespan_s": round(out["makespan_s"], 2), "peak_active": out["peak_active"],
            "peak_gb": round(out["peak_bytes"] / (1 << 30), 2), "budget_gb": round(budget / (1 << 30), 1),
-           "mean_queue_wait_s": round(float(np.mean(out["queue_wait_s"])), 3),
+           "mean_queue_wait_s": round(float(np.mean(out["queue_wait_s"])), 3), "graph_steps": spec.graph_steps,
            "pruning_ratio_mean": round(float(np.mean([r / s for r, s in zip(removed, starts)])), 4)}
     print(json.dumps(rec), flush=True)
 
