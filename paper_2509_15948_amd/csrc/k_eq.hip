@@ -23,6 +23,10 @@ constexpr int EQ_P = 8192;
 // long per step.
 constexpr int EQ_NT = 1024;   // forward and spectrum
 constexpr int EQ_BNT = 1024;  // backward: one window in LDS
+// window elements per thread whose global loads are issued together before
+// any is used (a rolled loop over batches keeps the registers within 64)
+constexpr int EQ_LB = 4;
+static_assert(EQ_P % (EQ_NT * EQ_LB) == 0 && EQ_P % (EQ_BNT * EQ_LB) == 0, "whole batches");
 
 struct EqArgs {
   const NodeDesc* desc;
@@ -90,18 +94,33 @@ __global__ __launch_bounds__(EQ_NT, 8) void k_eq_fwd(EqArgs a) {
   const float* u = eq_input(a, d, cs);
   const int half = (a.N - 1) / 2;
   const int64_t s0 = (int64_t)blk * a.V - half;   // window start
-  for (int i = threadIdx.x; i < EQ_P; i += EQ_NT) {
-    const int64_t n = s0 + i;
-    buf[i] = (n >= 0 && n < a.L) ? make_float2(u[n], u[cs + n]) : make_float2(0.f, 0.f);
+#pragma unroll 1
+  for (int i0 = threadIdx.x; i0 < EQ_P; i0 += EQ_NT * EQ_LB) {
+    float2 v[EQ_LB];
+#pragma unroll
+    for (int k = 0; k < EQ_LB; ++k) {
+      const int64_t n = s0 + i0 + k * EQ_NT;
+      v[k] = (n >= 0 && n < a.L) ? make_float2(u[n], u[cs + n]) : make_float2(0.f, 0.f);
+    }
+#pragma unroll
+    for (int k = 0; k < EQ_LB; ++k) buf[i0 + k * EQ_NT] = v[k];
   }
   __syncthreads();
   fft_lds<EQ_P, 1, EQ_P, EQ_NT, -1>(buf, tt);
   const float* H = a.HP + (int64_t)d.aux * EQ_P;
   float2* xu = a.XU ? a.XU + ((int64_t)d.aux * a.nblk + blk) * EQ_P : nullptr;
-  for (int i = threadIdx.x; i < EQ_P; i += EQ_NT) {
-    const float2 x = buf[i];
-    if (xu) xu[i] = x;   // kept for the FIR gradient of the backward
-    buf[i] = c_scale(x, H[i] * (1.0f / EQ_P));
+#pragma unroll 1
+  for (int i0 = threadIdx.x; i0 < EQ_P; i0 += EQ_NT * EQ_LB) {
+    float hv[EQ_LB];
+#pragma unroll
+    for (int k = 0; k < EQ_LB; ++k) hv[k] = H[i0 + k * EQ_NT];
+#pragma unroll
+    for (int k = 0; k < EQ_LB; ++k) {
+      const int i = i0 + k * EQ_NT;
+      const float2 x = buf[i];
+      if (xu) xu[i] = x;   // kept for the FIR gradient of the backward
+      buf[i] = c_scale(x, hv[k] * (1.0f / EQ_P));
+    }
   }
   __syncthreads();
   fft_lds<EQ_P, 1, EQ_P, EQ_NT, +1>(buf, tt);
@@ -162,19 +181,37 @@ __global__ __launch_bounds__(EQ_BNT, 8) void k_eq_bwd(EqArgs a) {
   const bool do_dh = gridDim.z == 1 || blockIdx.z == 1;
   float* gin = (do_gin && d.gin >= 0) ? a.G + (int64_t)d.gin * 2 * a.L : nullptr;
   if (gin) {
-    for (int i = threadIdx.x; i < EQ_P; i += EQ_BNT) {
-      const int64_t n = s0 + i;
-      float2 g = make_float2(0.f, 0.f);
-      if (n >= 0 && n < a.L) {
-        const float rm = ky * (yb[n] + yb[a.L + n]);
-        g = make_float2(w * dy[n] + rm, w * dy[a.L + n] + rm);
+#pragma unroll 1
+    for (int i0 = threadIdx.x; i0 < EQ_P; i0 += EQ_BNT * EQ_LB) {
+      float4 r[EQ_LB];  // ybar (l, r), dL/dy (l, r)
+#pragma unroll
+      for (int k = 0; k < EQ_LB; ++k) {
+        const int64_t n = s0 + i0 + k * EQ_BNT;
+        r[k] = (n >= 0 && n < a.L) ? make_float4(yb[n], yb[a.L + n], dy[n], dy[a.L + n])
+                                   : make_float4(0.f, 0.f, 0.f, 0.f);
       }
-      A[i] = g;
+#pragma unroll
+      for (int k = 0; k < EQ_LB; ++k) {
+        const int64_t n = s0 + i0 + k * EQ_BNT;
+        float2 g = make_float2(0.f, 0.f);
+        if (n >= 0 && n < a.L) {
+          const float rm = ky * (r[k].x + r[k].y);
+          g = make_float2(w * r[k].z + rm, w * r[k].w + rm);
+        }
+        A[i0 + k * EQ_BNT] = g;
+      }
     }
     __syncthreads();
     fft_lds<EQ_P, 1, EQ_P, EQ_BNT, -1>(A, tt);
     const float* H = a.HP + (int64_t)d.aux * EQ_P;
-    for (int i = threadIdx.x; i < EQ_P; i += EQ_BNT) A[i] = c_scale(A[i], H[i] * (1.0f / EQ_P));
+#pragma unroll 1
+    for (int i0 = threadIdx.x; i0 < EQ_P; i0 += EQ_BNT * EQ_LB) {
+      float hv[EQ_LB];
+#pragma unroll
+      for (int k = 0; k < EQ_LB; ++k) hv[k] = H[i0 + k * EQ_BNT];
+#pragma unroll
+      for (int k = 0; k < EQ_LB; ++k) A[i0 + k * EQ_BNT] = c_scale(A[i0 + k * EQ_BNT], hv[k] * (1.0f / EQ_P));
+    }
     __syncthreads();
     fft_lds<EQ_P, 1, EQ_P, EQ_BNT, +1>(A, tt);
     for (int i = half + threadIdx.x; i < half + a.V; i += EQ_BNT) {
@@ -189,22 +226,44 @@ __global__ __launch_bounds__(EQ_BNT, 8) void k_eq_bwd(EqArgs a) {
   if (!do_dh) return;
   // FIR gradient: the valid-part gradient correlated with the input window
   float dw = 0.f;
-  for (int i = threadIdx.x; i < EQ_P; i += EQ_BNT) {
-    const int64_t n = s0 + i;
-    float2 g = make_float2(0.f, 0.f);
-    if (i >= half && i < half + a.V && n < a.L) {
-      const float bl = yb[n], br = yb[a.L + n];
-      const float rm = ky * (bl + br);
-      const float gl = dy[n], gr = dy[a.L + n];
-      g = make_float2(w * gl + rm, w * gr + rm);
-      dw += gl * (bl - u[n]) + gr * (br - u[cs + n]);
+#pragma unroll 1
+  for (int i0 = threadIdx.x; i0 < EQ_P; i0 += EQ_BNT * EQ_LB) {
+    float4 r[EQ_LB];   // ybar (l, r), dL/dy (l, r)
+    float2 uv[EQ_LB];  // u (l, r)
+#pragma unroll
+    for (int k = 0; k < EQ_LB; ++k) {
+      const int i = i0 + k * EQ_BNT;
+      const int64_t n = s0 + i;
+      const bool ok = i >= half && i < half + a.V && n < a.L;
+      r[k] = ok ? make_float4(yb[n], yb[a.L + n], dy[n], dy[a.L + n]) : make_float4(0.f, 0.f, 0.f, 0.f);
+      uv[k] = ok ? make_float2(u[n], u[cs + n]) : make_float2(0.f, 0.f);
     }
-    A[i] = g;
+#pragma unroll
+    for (int k = 0; k < EQ_LB; ++k) {
+      const int i = i0 + k * EQ_BNT;
+      const int64_t n = s0 + i;
+      float2 g = make_float2(0.f, 0.f);
+      if (i >= half && i < half + a.V && n < a.L) {
+        const float bl = r[k].x, br = r[k].y;
+        const float rm = ky * (bl + br);
+        const float gl = r[k].z, gr = r[k].w;
+        g = make_float2(w * gl + rm, w * gr + rm);
+        dw += gl * (bl - uv[k].x) + gr * (br - uv[k].y);
+      }
+      A[i] = g;
+    }
   }
   __syncthreads();
   fft_lds<EQ_P, 1, EQ_P, EQ_BNT, -1>(A, tt);
   const float2* xu = a.XU + ((int64_t)d.aux * a.nblk + blk) * EQ_P;
-  for (int i = threadIdx.x; i < EQ_P; i += EQ_BNT) A[i] = c_scale(c_mulc(A[i], xu[i]), 1.0f / EQ_P);
+#pragma unroll 1
+  for (int i0 = threadIdx.x; i0 < EQ_P; i0 += EQ_BNT * EQ_LB) {
+    float2 xv[EQ_LB];
+#pragma unroll
+    for (int k = 0; k < EQ_LB; ++k) xv[k] = xu[i0 + k * EQ_BNT];
+#pragma unroll
+    for (int k = 0; k < EQ_LB; ++k) A[i0 + k * EQ_BNT] = c_scale(c_mulc(A[i0 + k * EQ_BNT], xv[k]), 1.0f / EQ_P);
+  }
   __syncthreads();
   fft_lds<EQ_P, 1, EQ_P, EQ_BNT, +1>(A, tt);
   // lag m sits at circular index m mod P; dh index = m + half

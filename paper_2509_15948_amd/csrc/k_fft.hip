@@ -33,11 +33,25 @@ namespace mg {
 // second round) and, at 57 KB of LDS, two blocks still fit a CU (24 waves;
 // the large console's step 49.2 -> 48.5 ms)
 constexpr int COL_NT = 1024;
+// two 1024-thread column workgroups per CU (their LDS tiles fit twice): the
+// registers are held to 64
+constexpr int COL_MIN_WAVES = 8;
+// elements per thread whose loads are in flight together in the column
+// passes (data, then twiddles): within 64 registers the short columns, whose
+// transforms hold more registers, take smaller batches
+template <int N2>
+constexpr int col_batch() { return N2 >= 512 ? 8 : 4; }
+template <int N2>
+constexpr int col_tw_batch() { return N2 >= 512 ? 4 : 2; }
 template <int N1>
 constexpr int row_nt() { return N1 == 3072 ? 768 : (N1 >= 4096 ? 1024 : (N1 >= 1024 ? 512 : 256)); }
 // the backward rows batch four transforms: 1024 threads from 2048 points
 template <int N1>
 constexpr int rowb_nt() { return N1 >= 2048 ? 1024 : row_nt<N1>(); }
+// 2048-point backward rows: two 1024-thread workgroups per CU (70 KB of LDS
+// each), registers held to 64; longer rows hold one workgroup per CU
+template <int N1>
+constexpr int rows_bwd_min_waves() { return N1 == 2048 ? 8 : 4; }
 
 // Row transforms up to 2048 points and column transforms up to 256 keep one
 // spare LDS slot per 16 points: the first two radix-8 passes then put at most
@@ -87,9 +101,23 @@ __device__ __forceinline__ int fslot(int k) {
 // W_N^e for e in [0, N) as h (1 + d), from two FP32 tables rounded from FP64
 // on the host: twhi[j] = W_N^{1024 j} and twlo[j] = W_N^j - 1 (small, so the
 // product adds little to the rounding of h).
-__device__ __forceinline__ float2 big_tw(const float2* __restrict__ twhi, const float2* __restrict__ twlo, int64_t e) {
-  const float2 h = twhi[e >> 10], d = twlo[e & 1023];
+constexpr int cmin(int a, int b) { return a < b ? a : b; }
+
+// big_tw in two halves, the table loads and the product, so that a loop can
+// issue the loads of all its twiddles before it uses the first one
+struct TwRaw {
+  float2 h, d;
+};
+__device__ __forceinline__ TwRaw big_tw_fetch(const float2* __restrict__ twhi, const float2* __restrict__ twlo,
+                                              int64_t e) {
+  return TwRaw{twhi[e >> 10], twlo[e & 1023]};
+}
+__device__ __forceinline__ float2 big_tw_make(const TwRaw& t) {
+  const float2 h = t.h, d = t.d;
   return make_float2(h.x + (h.x * d.x - h.y * d.y), h.y + (h.x * d.y + h.y * d.x));
+}
+__device__ __forceinline__ float2 big_tw(const float2* __restrict__ twhi, const float2* __restrict__ twlo, int64_t e) {
+  return big_tw_make(big_tw_fetch(twhi, twlo, e));
 }
 
 __device__ __forceinline__ int64_t signed_lag(int64_t n, int64_t N) { return n < N / 2 ? n : n - N; }
@@ -109,47 +137,70 @@ struct EngineArgs {
 // natural order, slot r 1024 + k receives W_3072^{-rk} sum_s X[k + 1024 s]
 // W_3^{-rs}, whose 1024-point inverse transforms give the elements 3m + r.
 // W_3072^e = W_N^{e N2} comes from the engine's table of W_N.
-template <int B, int NT, int DIR>
-__device__ __forceinline__ void radix3_pass(float2* buf, const EngineArgs& ea) {
+// one bin of the radix-3 pass (slots kk, kk + R3_SB, kk + 2 R3_SB of row r)
+template <int DIR>
+__device__ __forceinline__ void radix3_bin(float2* r, int kk, float2 w1, float2 w2) {
   const float c3 = -0.5f, s3 = 0.866025403784438647f;
-  for (int idx = threadIdx.x; idx < B * 1024; idx += NT) {
-    float2* r = buf + (idx >> 10) * (3 * R3_SB);
-    const int k = idx & 1023;
-    const int kk = lds_ix<R3_PAD>(k);
-    const float2 w1 = big_tw(ea.twhi, ea.twlo, (int64_t)k * ea.N2);
-    const float2 w2 = big_tw(ea.twhi, ea.twlo, (int64_t)(2 * k) * ea.N2);
-    float2 a0 = r[kk], a1 = r[R3_SB + kk], a2 = r[2 * R3_SB + kk];
-    if (DIR < 0) {
-      a1 = c_mul(a1, w1);
-      a2 = c_mul(a2, w2);
+  float2 a0 = r[kk], a1 = r[R3_SB + kk], a2 = r[2 * R3_SB + kk];
+  if (DIR < 0) {
+    a1 = c_mul(a1, w1);
+    a2 = c_mul(a2, w2);
+  }
+  // 3-point DFT with the sign of DIR
+  const float2 sm = c_add(a1, a2), df = c_sub(a1, a2);
+  const float2 m = make_float2(a0.x + c3 * sm.x, a0.y + c3 * sm.y);
+  const float2 t = DIR < 0 ? make_float2(s3 * df.y, -s3 * df.x) : make_float2(-s3 * df.y, s3 * df.x);
+  float2 y1 = c_add(m, t), y2 = c_sub(m, t);
+  if (DIR > 0) {
+    y1 = c_mul(y1, c_conj(w1));
+    y2 = c_mul(y2, c_conj(w2));
+  }
+  r[kk] = c_add(a0, sm);
+  r[R3_SB + kk] = y1;
+  r[2 * R3_SB + kk] = y2;
+}
+
+// LEAN: one bin's twiddle loads in flight at a time (kernels held to few
+// registers); otherwise every bin's twiddles are fetched first.
+template <int B, int NT, int DIR, bool LEAN>
+__device__ __forceinline__ void radix3_pass(float2* buf, const EngineArgs& ea) {
+  if constexpr (LEAN) {
+    for (int idx = threadIdx.x; idx < B * 1024; idx += NT) {
+      const int k = idx & 1023;
+      radix3_bin<DIR>(buf + (idx >> 10) * (3 * R3_SB), lds_ix<R3_PAD>(k),
+                      big_tw(ea.twhi, ea.twlo, (int64_t)k * ea.N2), big_tw(ea.twhi, ea.twlo, (int64_t)(2 * k) * ea.N2));
     }
-    // 3-point DFT with the sign of DIR
-    const float2 sm = c_add(a1, a2), df = c_sub(a1, a2);
-    const float2 m = make_float2(a0.x + c3 * sm.x, a0.y + c3 * sm.y);
-    const float2 t = DIR < 0 ? make_float2(s3 * df.y, -s3 * df.x) : make_float2(-s3 * df.y, s3 * df.x);
-    float2 y1 = c_add(m, t), y2 = c_sub(m, t);
-    if (DIR > 0) {
-      y1 = c_mul(y1, c_conj(w1));
-      y2 = c_mul(y2, c_conj(w2));
+  } else {
+    constexpr int PER = (B * 1024 + NT - 1) / NT;
+    TwRaw t1[PER], t2[PER];
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+      const int k = (threadIdx.x + i * NT) & 1023;  // past the end: in-bounds table entries, unused
+      t1[i] = big_tw_fetch(ea.twhi, ea.twlo, (int64_t)k * ea.N2);
+      t2[i] = big_tw_fetch(ea.twhi, ea.twlo, (int64_t)(2 * k) * ea.N2);
     }
-    r[kk] = c_add(a0, sm);
-    r[R3_SB + kk] = y1;
-    r[2 * R3_SB + kk] = y2;
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+      const int idx = threadIdx.x + i * NT;
+      if (idx >= B * 1024) break;
+      const int k = idx & 1023;
+      radix3_bin<DIR>(buf + (idx >> 10) * (3 * R3_SB), lds_ix<R3_PAD>(k), big_tw_make(t1[i]), big_tw_make(t2[i]));
+    }
   }
 }
 
 // B row transforms in LDS (rows at stride row_len<N1>), unnormalised; ends
 // with a barrier like fft_lds.
-template <int N1, int B, int NT, int DIR>
+template <int N1, int B, int NT, int DIR, bool LEAN = false>
 __device__ __forceinline__ void row_fft(float2* buf, const RowTw<N1>& tt, const EngineArgs& ea) {
   if constexpr (row3<N1>()) {
     if (DIR > 0) {
-      radix3_pass<B, NT, DIR>(buf, ea);
+      radix3_pass<B, NT, DIR, LEAN>(buf, ea);
       __syncthreads();
     }
     fft_lds<1024, 3 * B, R3_SB, NT, DIR, R3_PAD>(buf, tt);
     if (DIR < 0) {
-      radix3_pass<B, NT, DIR>(buf, ea);
+      radix3_pass<B, NT, DIR, LEAN>(buf, ea);
       __syncthreads();
     }
   } else {
@@ -176,16 +227,25 @@ __device__ __forceinline__ const float* node_input(const NodeView& v, const Node
   return v.U + (int64_t)d.in_slot * 2 * v.L;
 }
 
+// Loaders of the column pass: fetch(n) issues the global loads of element n,
+// finish(n, raw) turns them into the packed value (and does any per-element
+// arithmetic, in the order of the calls); BATCH elements are fetched before
+// the first is finished.  Stores of the inverse column pass work the same
+// way: fetch(n) loads what store(n, value, raw) needs.
+
 // forward input u packed l + i r
 struct LdSignal {
   NodeView v;
   const float* u;
   int64_t cs;
+  using Raw = float2;
+  static constexpr int BATCH = 8;
   __device__ void begin(int j) {
     const NodeDesc d = v.desc[j];
     u = node_input(v, d, cs);
   }
-  __device__ float2 load(int64_t n) const { return n < v.L ? make_float2(u[n], u[cs + n]) : make_float2(0.f, 0.f); }
+  __device__ Raw fetch(int64_t n) const { return n < v.L ? make_float2(u[n], u[cs + n]) : make_float2(0.f, 0.f); }
+  __device__ float2 finish(int64_t, const Raw& r) { return r; }
   __device__ void end(int, int) {}
 };
 
@@ -202,10 +262,14 @@ struct LdFir {
     hl = h + (int64_t)d.aux * stride;
     hr = shared ? hl : hl + Nh;
   }
-  __device__ float2 load(int64_t n) const {
+  using Raw = float2;
+  static constexpr int BATCH = 8;
+  __device__ Raw fetch(int64_t n) const {
     const int64_t i = signed_lag(n, N) - lag0;
     return (i >= 0 && i < Nh) ? make_float2(hl[i], hr[i]) : make_float2(0.f, 0.f);
   }
+  __device__ float2 finish(int64_t, const Raw& r) { return r; }
+  __device__ float2 load(int64_t n) const { return fetch(n); }
   __device__ void end(int, int) {}
 };
 
@@ -239,13 +303,19 @@ struct LdGrad {
     kreg = (float)((double)alpha_g * s / Ey);
     acc = 0.f;
   }
-  __device__ float2 load(int64_t n) {
+  struct Raw {
+    float gl, gr, bl, br, ul, ur;
+  };
+  static constexpr int BATCH = 4;
+  __device__ Raw fetch(int64_t n) const {
+    if (n >= v.L) return Raw{0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    return Raw{dy[n], dy[v.L + n], yb[n], yb[v.L + n], u[n], u[cs + n]};
+  }
+  __device__ float2 finish(int64_t n, const Raw& r) {
     if (n >= v.L) return make_float2(0.f, 0.f);
-    const float gl = dy[n], gr = dy[v.L + n];
-    const float bl = yb[n], br = yb[v.L + n];
-    acc += gl * (bl - u[n]) + gr * (br - u[cs + n]);
-    const float rm = kreg * (bl + br);
-    return make_float2(w * gl + rm, w * gr + rm);
+    acc += r.gl * (r.bl - r.ul) + r.gr * (r.br - r.ur);
+    const float rm = kreg * (r.bl + r.br);
+    return make_float2(w * r.gl + rm, w * r.gr + rm);
   }
   __device__ void end(int j, int blk) {
     __shared__ float red[COL_NT];
@@ -277,9 +347,12 @@ struct StFwd {
     w = node_w(wet, mask, d);
     ey = eu = 0.f;
   }
-  __device__ void store(int64_t n, float2 val) {
+  using Raw = float2;
+  static constexpr int BATCH = 8;
+  __device__ Raw fetch(int64_t n) const { return n < v.L ? make_float2(u[n], u[cs + n]) : make_float2(0.f, 0.f); }
+  __device__ void store(int64_t n, float2 val, const Raw& ur) {
     if (n >= v.L) return;
-    const float l = u[n], r = u[cs + n];
+    const float l = ur.x, r = ur.y;
     if (yb) {
       yb[n] = val.x;
       yb[v.L + n] = val.y;
@@ -326,11 +399,17 @@ struct StGradU {
     const double s = diff > 0 ? 1.0 : (diff < 0 ? -1.0 : 0.0);
     kreg = (float)((double)alpha_g * s / Eu);
   }
-  __device__ void store(int64_t n, float2 val) {
+  using Raw = float4;  // dL/dy (l, r), u (l, r)
+  static constexpr int BATCH = 4;
+  __device__ Raw fetch(int64_t n) const {
+    if (!active || n >= v.L) return make_float4(0.f, 0.f, 0.f, 0.f);
+    return make_float4(dy[n], dy[v.L + n], u[n], u[cs + n]);
+  }
+  __device__ void store(int64_t n, float2 val, const Raw& r) {
     if (!active || n >= v.L) return;
-    const float um = u[n] + u[cs + n];
-    gin[n] = (1.0f - w) * dy[n] + val.x - kreg * um;
-    gin[v.L + n] = (1.0f - w) * dy[v.L + n] + val.y - kreg * um;
+    const float um = r.z + r.w;
+    gin[n] = (1.0f - w) * r.x + val.x - kreg * um;
+    gin[v.L + n] = (1.0f - w) * r.y + val.y - kreg * um;
   }
   __device__ void end(int, int) {}
 };
@@ -343,7 +422,10 @@ struct StGradH {
   int shared;
   float* o;
   __device__ void begin(int j) { o = dh + (int64_t)desc[j].aux * stride; }
-  __device__ void store(int64_t n, float2 val) {
+  struct Raw {};
+  static constexpr int BATCH = 8;
+  __device__ Raw fetch(int64_t) const { return Raw{}; }
+  __device__ void store(int64_t n, float2 val, const Raw&) {
     const int64_t i = signed_lag(n, N) - lag0;
     if (i < 0 || i >= Nh) return;
     if (shared) o[i] = val.x + val.y;
@@ -369,7 +451,7 @@ __device__ __forceinline__ int col_tile(int b, int n) {
 
 // ---------------------------------------------------------------- KA: columns forward
 template <int N2, int TC, typename LD>
-__global__ __launch_bounds__(COL_NT) void k_cols(LD ld, float2* __restrict__ T, EngineArgs ea) {
+__global__ __launch_bounds__(COL_NT, COL_MIN_WAVES) void k_cols(LD ld, float2* __restrict__ T, EngineArgs ea) {
   constexpr int BS = pad_len<N2, false>() + 1;
   __shared__ float2 buf[TC * BS];
   __shared__ TwTab<N2, float2> tt;
@@ -379,25 +461,52 @@ __global__ __launch_bounds__(COL_NT) void k_cols(LD ld, float2* __restrict__ T, 
   const int c0 = tile * TC;
   const int N1 = ea.N1;
   ld.begin(j);
-  for (int idx = threadIdx.x; idx < TC * N2; idx += COL_NT) {
-    const int n2 = idx / TC, cc = idx % TC;
-    buf[cc * BS + px<N2, false>(n2)] = ld.load((int64_t)(c0 + cc) + (int64_t)N1 * n2);
+  constexpr int PER = TC * N2 / COL_NT;
+  static_assert(TC * N2 % COL_NT == 0, "a column tile is a whole number of passes");
+  constexpr int BATCH = cmin(cmin(LD::BATCH, col_batch<N2>()), PER);
+  static_assert(PER % BATCH == 0, "whole batches");
+#pragma unroll 1  // one batch of loads in flight at a time
+  for (int k0 = 0; k0 < PER; k0 += BATCH) {
+    typename LD::Raw raw[BATCH];
+#pragma unroll
+    for (int k = 0; k < BATCH; ++k) {
+      const int idx = threadIdx.x + (k0 + k) * COL_NT;
+      raw[k] = ld.fetch((int64_t)(c0 + idx % TC) + (int64_t)N1 * (idx / TC));
+    }
+#pragma unroll
+    for (int k = 0; k < BATCH; ++k) {
+      const int idx = threadIdx.x + (k0 + k) * COL_NT;
+      const int n2 = idx / TC, cc = idx % TC;
+      buf[cc * BS + px<N2, false>(n2)] = ld.finish((int64_t)(c0 + cc) + (int64_t)N1 * n2, raw[k]);
+    }
   }
   ld.end(j, tile);
   __syncthreads();
   fft_lds<N2, TC, BS, COL_NT, -1, eng_pad<N2, false>()>(buf, tt);
   float2* Tn = T + (int64_t)j * ea.N;
-  for (int idx = threadIdx.x; idx < TC * N2; idx += COL_NT) {
-    const int k2 = idx / TC, cc = idx % TC;
-    const int n1 = c0 + cc;
-    const float2 w = big_tw(ea.twhi, ea.twlo, (int64_t)n1 * k2);  // n1 k2 < N
-    Tn[(int64_t)k2 * N1 + n1] = c_mul(buf[cc * BS + px<N2, false>(k2)], w);
+  constexpr int TB = col_tw_batch<N2>();  // twiddles fetched per batch
+  static_assert(PER % TB == 0, "whole batches");
+#pragma unroll 1  // one batch of loads in flight at a time
+  for (int k0 = 0; k0 < PER; k0 += TB) {
+    TwRaw tw[TB];
+#pragma unroll
+    for (int k = 0; k < TB; ++k) {
+      const int idx = threadIdx.x + (k0 + k) * COL_NT;
+      tw[k] = big_tw_fetch(ea.twhi, ea.twlo, (int64_t)(c0 + idx % TC) * (idx / TC));  // n1 k2 < N
+    }
+#pragma unroll
+    for (int k = 0; k < TB; ++k) {
+      const int idx = threadIdx.x + (k0 + k) * COL_NT;
+      const int k2 = idx / TC, cc = idx % TC;
+      const int n1 = c0 + cc;
+      Tn[(int64_t)k2 * N1 + n1] = c_mul(buf[cc * BS + px<N2, false>(k2)], big_tw_make(tw[k]));
+    }
   }
 }
 
 // ---------------------------------------------------------------- KC: columns inverse
 template <int N2, int TC, typename ST>
-__global__ __launch_bounds__(COL_NT) void k_icols(ST st, const float2* __restrict__ T, EngineArgs ea) {
+__global__ __launch_bounds__(COL_NT, COL_MIN_WAVES) void k_icols(ST st, const float2* __restrict__ T, EngineArgs ea) {
   constexpr int BS = pad_len<N2, false>() + 1;
   __shared__ float2 buf[TC * BS];
   __shared__ TwTab<N2, float2> tt;
@@ -407,17 +516,44 @@ __global__ __launch_bounds__(COL_NT) void k_icols(ST st, const float2* __restric
   const int c0 = tile * TC;
   const int N1 = ea.N1;
   const float2* Tn = T + (int64_t)j * ea.N;
-  for (int idx = threadIdx.x; idx < TC * N2; idx += COL_NT) {
-    const int k2 = idx / TC, cc = idx % TC;
-    buf[cc * BS + px<N2, false>(k2)] = Tn[(int64_t)k2 * N1 + c0 + cc];
+  constexpr int PER = TC * N2 / COL_NT;
+  static_assert(TC * N2 % COL_NT == 0, "a column tile is a whole number of passes");
+  constexpr int XB = col_batch<N2>();
+  static_assert(PER % XB == 0, "whole batches");
+#pragma unroll 1  // one batch of loads in flight at a time
+  for (int k0 = 0; k0 < PER; k0 += XB) {
+    float2 x[XB];
+#pragma unroll
+    for (int k = 0; k < XB; ++k) {
+      const int idx = threadIdx.x + (k0 + k) * COL_NT;
+      x[k] = Tn[(int64_t)(idx / TC) * N1 + c0 + idx % TC];
+    }
+#pragma unroll
+    for (int k = 0; k < XB; ++k) {
+      const int idx = threadIdx.x + (k0 + k) * COL_NT;
+      buf[(idx % TC) * BS + px<N2, false>(idx / TC)] = x[k];
+    }
   }
   __syncthreads();
   fft_lds<N2, TC, BS, COL_NT, +1, eng_pad<N2, false>()>(buf, tt);
   const float sc = 1.0f / (float)ea.N;
   st.begin(j);
-  for (int idx = threadIdx.x; idx < TC * N2; idx += COL_NT) {
-    const int n2 = idx / TC, cc = idx % TC;
-    st.store((int64_t)(c0 + cc) + (int64_t)N1 * n2, c_scale(buf[cc * BS + px<N2, false>(n2)], sc));
+  constexpr int BATCH = cmin(cmin(ST::BATCH, col_batch<N2>()), PER);
+  static_assert(PER % BATCH == 0, "whole batches");
+#pragma unroll 1  // one batch of loads in flight at a time
+  for (int k0 = 0; k0 < PER; k0 += BATCH) {
+    typename ST::Raw raw[BATCH];
+#pragma unroll
+    for (int k = 0; k < BATCH; ++k) {
+      const int idx = threadIdx.x + (k0 + k) * COL_NT;
+      raw[k] = st.fetch((int64_t)(c0 + idx % TC) + (int64_t)N1 * (idx / TC));
+    }
+#pragma unroll
+    for (int k = 0; k < BATCH; ++k) {
+      const int idx = threadIdx.x + (k0 + k) * COL_NT;
+      const int n2 = idx / TC, cc = idx % TC;
+      st.store((int64_t)(c0 + cc) + (int64_t)N1 * n2, c_scale(buf[cc * BS + px<N2, false>(n2)], sc), raw[k]);
+    }
   }
   st.end(j, tile);
 }
@@ -468,37 +604,99 @@ __device__ __forceinline__ int rslot(int i) {
   return i < N1 ? fslot<N1>(i) : row_len<N1>() + fslot<N1>(i - N1);
 }
 
-template <int N1>
+// Row loads and stores with NT threads; every thread issues the global loads
+// of all its elements (row data, twiddles) before it uses the first.
+// LEAN: one element's loads in flight, for kernels held to few registers.
+template <int N1, int NT, bool LEAN = false>
 __device__ __forceinline__ void load_rows(float2* buf, const float2* __restrict__ Tn, int ra, int rb) {
-  for (int i = threadIdx.x; i < N1; i += blockDim.x) {
-    buf[tslot<N1>(i)] = Tn[(int64_t)ra * N1 + i];
-    buf[row_len<N1>() + tslot<N1>(i)] = Tn[(int64_t)rb * N1 + i];
+  static_assert(N1 % NT == 0, "whole passes");
+  constexpr int PER = N1 / NT;
+  if constexpr (LEAN) {
+    for (int i = threadIdx.x; i < N1; i += NT) {
+      buf[tslot<N1>(i)] = Tn[(int64_t)ra * N1 + i];
+      buf[row_len<N1>() + tslot<N1>(i)] = Tn[(int64_t)rb * N1 + i];
+    }
+    return;
+  }
+  constexpr int LB = PER;
+#pragma unroll
+  for (int k0 = 0; k0 < PER; k0 += LB) {
+    float2 a[LB], b[LB];
+#pragma unroll
+    for (int k = 0; k < LB; ++k) {
+      const int i = threadIdx.x + (k0 + k) * NT;
+      a[k] = Tn[(int64_t)ra * N1 + i];
+      b[k] = Tn[(int64_t)rb * N1 + i];
+    }
+#pragma unroll
+    for (int k = 0; k < LB; ++k) {
+      const int i = threadIdx.x + (k0 + k) * NT;
+      buf[tslot<N1>(i)] = a[k];
+      buf[row_len<N1>() + tslot<N1>(i)] = b[k];
+    }
   }
 }
 
-template <int N1>
+template <int N1, int NT, bool LEAN = false>
 __device__ __forceinline__ void store_rows(const float2* buf, float2* __restrict__ To, int ra, int rb,
                                            const EngineArgs& ea) {
-  for (int i = threadIdx.x; i < N1; i += blockDim.x) {
-    float2 wa = big_tw(ea.twhi, ea.twlo, (int64_t)i * ra);  // i ra < N
-    float2 wb = big_tw(ea.twhi, ea.twlo, (int64_t)i * rb);
-    To[(int64_t)ra * N1 + i] = c_mul(buf[tslot<N1>(i)], c_conj(wa));
-    To[(int64_t)rb * N1 + i] = c_mul(buf[row_len<N1>() + tslot<N1>(i)], c_conj(wb));
+  static_assert(N1 % NT == 0, "whole passes");
+  constexpr int PER = N1 / NT;
+  if constexpr (LEAN) {
+    for (int i = threadIdx.x; i < N1; i += NT) {
+      const float2 wa = big_tw(ea.twhi, ea.twlo, (int64_t)i * ra);  // i ra < N
+      const float2 wb = big_tw(ea.twhi, ea.twlo, (int64_t)i * rb);
+      To[(int64_t)ra * N1 + i] = c_mul(buf[tslot<N1>(i)], c_conj(wa));
+      To[(int64_t)rb * N1 + i] = c_mul(buf[row_len<N1>() + tslot<N1>(i)], c_conj(wb));
+    }
+    return;
+  }
+  constexpr int SB = PER < 2 ? 1 : 2;  // elements whose twiddle loads are in flight together
+#pragma unroll
+  for (int k0 = 0; k0 < PER; k0 += SB) {
+    TwRaw ta[SB], tb[SB];
+#pragma unroll
+    for (int k = 0; k < SB && k0 + k < PER; ++k) {
+      const int i = threadIdx.x + (k0 + k) * NT;
+      ta[k] = big_tw_fetch(ea.twhi, ea.twlo, (int64_t)i * ra);  // i ra < N
+      tb[k] = big_tw_fetch(ea.twhi, ea.twlo, (int64_t)i * rb);
+    }
+#pragma unroll
+    for (int k = 0; k < SB && k0 + k < PER; ++k) {
+      const int i = threadIdx.x + (k0 + k) * NT;
+      To[(int64_t)ra * N1 + i] = c_mul(buf[tslot<N1>(i)], c_conj(big_tw_make(ta[k])));
+      To[(int64_t)rb * N1 + i] = c_mul(buf[row_len<N1>() + tslot<N1>(i)], c_conj(big_tw_make(tb[k])));
+    }
   }
 }
 
 // store_rows of two row pairs that share their twiddles (x -> To, z -> Tz)
-template <int N1>
+template <int N1, int NT>
 __device__ __forceinline__ void store_rows2(const float2* x, const float2* z, float2* __restrict__ To,
                                             float2* __restrict__ Tz, int ra, int rb, const EngineArgs& ea) {
-  for (int i = threadIdx.x; i < N1; i += blockDim.x) {
-    const float2 wa = c_conj(big_tw(ea.twhi, ea.twlo, (int64_t)i * ra));  // i ra < N
-    const float2 wb = c_conj(big_tw(ea.twhi, ea.twlo, (int64_t)i * rb));
-    const int ia = tslot<N1>(i), ib = row_len<N1>() + tslot<N1>(i);
-    To[(int64_t)ra * N1 + i] = c_mul(x[ia], wa);
-    To[(int64_t)rb * N1 + i] = c_mul(x[ib], wb);
-    Tz[(int64_t)ra * N1 + i] = c_mul(z[ia], wa);
-    Tz[(int64_t)rb * N1 + i] = c_mul(z[ib], wb);
+  static_assert(N1 % NT == 0, "whole passes");
+  constexpr int PER = N1 / NT;
+  constexpr int SB = PER < 2 ? PER : 2;
+#pragma unroll
+  for (int k0 = 0; k0 < PER; k0 += SB) {
+    TwRaw ta[SB], tb[SB];
+#pragma unroll
+    for (int k = 0; k < SB && k0 + k < PER; ++k) {
+      const int i = threadIdx.x + (k0 + k) * NT;
+      ta[k] = big_tw_fetch(ea.twhi, ea.twlo, (int64_t)i * ra);  // i ra < N
+      tb[k] = big_tw_fetch(ea.twhi, ea.twlo, (int64_t)i * rb);
+    }
+#pragma unroll
+    for (int k = 0; k < SB && k0 + k < PER; ++k) {
+      const int i = threadIdx.x + (k0 + k) * NT;
+      const float2 wa = c_conj(big_tw_make(ta[k]));
+      const float2 wb = c_conj(big_tw_make(tb[k]));
+      const int ia = tslot<N1>(i), ib = row_len<N1>() + tslot<N1>(i);
+      To[(int64_t)ra * N1 + i] = c_mul(x[ia], wa);
+      To[(int64_t)rb * N1 + i] = c_mul(x[ib], wb);
+      Tz[(int64_t)ra * N1 + i] = c_mul(z[ia], wa);
+      Tz[(int64_t)rb * N1 + i] = c_mul(z[ib], wb);
+    }
   }
 }
 
@@ -512,7 +710,7 @@ __global__ __launch_bounds__(row_nt<N1>()) void k_rows_spec(const float2* __rest
   const int j = blockIdx.y;
   int ra, rb;
   row_pair(blockIdx.x, ea.N2, ra, rb);
-  load_rows<N1>(buf, T + (int64_t)j * ea.N, ra, rb);
+  load_rows<N1, row_nt<N1>()>(buf, T + (int64_t)j * ea.N, ra, rb);
   __syncthreads();
   row_fft<N1, 2, row_nt<N1>(), -1>(buf, tt, ea);
   float2* Zn = Z + (int64_t)(z0 + desc[j].aux) * ea.N;
@@ -586,6 +784,24 @@ __global__ __launch_bounds__(row_nt<N1>()) void k_rows_firspec(LdFir ld, float2*
 // 768-thread workgroups share a CU; the padded index arithmetic took 81
 template <int N1>
 constexpr int rows_conv_min_waves() { return N1 == 3072 ? 6 : 1; }
+// under that cap the kernel keeps one element's loads in flight at a time:
+// batched loads would spill
+template <int N1>
+constexpr bool rows_conv_lean() { return rows_conv_min_waves<N1>() > 1; }
+
+// the product of one mirrored bin pair (LDS slots sa, sb; FIR bins ha, hb)
+__device__ __forceinline__ void conv_pair(float2* buf, int sa, int sb, float2 ha, float2 hb) {
+  const float2 za = buf[sa], zb = buf[sb];
+  float2 xl, xr, hl, hr;
+  split_lr(za, zb, xl, xr);
+  split_lr(ha, hb, hl, hr);
+  const float2 ya = pack_lr(c_mul(xl, hl), c_mul(xr, hr));
+  split_lr(zb, za, xl, xr);
+  split_lr(hb, ha, hl, hr);
+  const float2 yb = pack_lr(c_mul(xl, hl), c_mul(xr, hr));
+  buf[sa] = ya;
+  buf[sb] = yb;
+}
 
 // forward convolution: Y = Xl Hl + i Xr Hr
 template <int N1>
@@ -599,9 +815,10 @@ __global__ __launch_bounds__(row_nt<N1>(), rows_conv_min_waves<N1>()) void k_row
   const int p = blockIdx.x;
   int ra, rb;
   row_pair(p, ea.N2, ra, rb);
-  load_rows<N1>(buf, Tin + (int64_t)j * ea.N, ra, rb);
+  constexpr bool LEAN = rows_conv_lean<N1>();
+  load_rows<N1, row_nt<N1>(), LEAN>(buf, Tin + (int64_t)j * ea.N, ra, rb);
   __syncthreads();
-  row_fft<N1, 2, row_nt<N1>(), -1>(buf, tt, ea);
+  row_fft<N1, 2, row_nt<N1>(), -1, LEAN>(buf, tt, ea);
   const int64_t zr = (int64_t)(z0 + desc[j].aux) * ea.N;
   const float2* H = ZH + zr;
   if (ZU) {  // keep the input spectrum for the backward
@@ -612,33 +829,44 @@ __global__ __launch_bounds__(row_nt<N1>(), rows_conv_min_waves<N1>()) void k_row
     }
     __syncthreads();  // every bin stored before the product below overwrites it
   }
-  for (int q = threadIdx.x; q < N1 + 1; q += row_nt<N1>()) {
-    int ia, ib;
-    if (!mirror_pair<N1>(p, q, ia, ib)) continue;
-    const int64_t ga = (ia < N1) ? (int64_t)ra * N1 + ia : (int64_t)rb * N1 + (ia - N1);
-    const int64_t gb = (ib < N1) ? (int64_t)ra * N1 + ib : (int64_t)rb * N1 + (ib - N1);
-    const int sa = rslot<N1>(ia), sb = rslot<N1>(ib);
-    const float2 za = buf[sa], zb = buf[sb];
-    const float2 ha = H[ga], hb = H[gb];
-    float2 xl, xr, hl, hr;
-    split_lr(za, zb, xl, xr);
-    split_lr(ha, hb, hl, hr);
-    const float2 ya = pack_lr(c_mul(xl, hl), c_mul(xr, hr));
-    split_lr(zb, za, xl, xr);
-    split_lr(hb, ha, hl, hr);
-    const float2 yb = pack_lr(c_mul(xl, hl), c_mul(xr, hr));
-    buf[sa] = ya;
-    buf[sb] = yb;
+  if constexpr (LEAN) {
+    for (int q = threadIdx.x; q < N1 + 1; q += row_nt<N1>()) {
+      int ia, ib;
+      if (!mirror_pair<N1>(p, q, ia, ib)) continue;
+      const int64_t ga = (ia < N1) ? (int64_t)ra * N1 + ia : (int64_t)rb * N1 + (ia - N1);
+      const int64_t gb = (ib < N1) ? (int64_t)ra * N1 + ib : (int64_t)rb * N1 + (ib - N1);
+      conv_pair(buf, rslot<N1>(ia), rslot<N1>(ib), H[ga], H[gb]);
+    }
+  } else {
+    constexpr int NQ = (N1 + 1 + row_nt<N1>() - 1) / row_nt<N1>();
+    constexpr int QB = 3;  // pairs whose spectrum loads are in flight together
+#pragma unroll
+    for (int k0 = 0; k0 < NQ; k0 += QB) {
+      float2 hA[QB], hB[QB];
+#pragma unroll
+      for (int k = k0; k < k0 + QB && k < NQ; ++k) {
+        int ia, ib;
+        if (!mirror_pair<N1>(p, threadIdx.x + k * row_nt<N1>(), ia, ib)) continue;
+        hA[k - k0] = H[(ia < N1) ? (int64_t)ra * N1 + ia : (int64_t)rb * N1 + (ia - N1)];
+        hB[k - k0] = H[(ib < N1) ? (int64_t)ra * N1 + ib : (int64_t)rb * N1 + (ib - N1)];
+      }
+#pragma unroll
+      for (int k = k0; k < k0 + QB && k < NQ; ++k) {
+        int ia, ib;
+        if (!mirror_pair<N1>(p, threadIdx.x + k * row_nt<N1>(), ia, ib)) continue;
+        conv_pair(buf, rslot<N1>(ia), rslot<N1>(ib), hA[k - k0], hB[k - k0]);
+      }
+    }
   }
   __syncthreads();
-  row_fft<N1, 2, row_nt<N1>(), +1>(buf, tt, ea);
-  store_rows<N1>(buf, Tout + (int64_t)j * ea.N, ra, rb, ea);
+  row_fft<N1, 2, row_nt<N1>(), +1, LEAN>(buf, tt, ea);
+  store_rows<N1, row_nt<N1>(), LEAN>(buf, Tout + (int64_t)j * ea.N, ra, rb, ea);
 }
 
 // backward: P1 = Gl conj(Hl) + i Gr conj(Hr)   (input gradient)
 //           P2 = Gl conj(Xl) + i Gr conj(Xr)   (FIR gradient)
 template <int N1>
-__global__ __launch_bounds__(rowb_nt<N1>(), 4) void k_rows_bwd(const float2* __restrict__ Tin, float2* __restrict__ Tu,
+__global__ __launch_bounds__(rowb_nt<N1>(), rows_bwd_min_waves<N1>()) void k_rows_bwd(const float2* __restrict__ Tin, float2* __restrict__ Tu,
                                                         float2* __restrict__ Th, const float2* __restrict__ ZH,
                                                         const float2* __restrict__ ZU, int z0,
                                                         const NodeDesc* __restrict__ desc, int want_u,
@@ -652,21 +880,40 @@ __global__ __launch_bounds__(rowb_nt<N1>(), 4) void k_rows_bwd(const float2* __r
   const int p = blockIdx.x;
   int ra, rb;
   row_pair(p, ea.N2, ra, rb);
-  load_rows<N1>(b1, Tin + (int64_t)j * ea.N, ra, rb);
+  load_rows<N1, rowb_nt<N1>()>(b1, Tin + (int64_t)j * ea.N, ra, rb);
   __syncthreads();
   row_fft<N1, 2, rowb_nt<N1>(), -1>(b1, tt, ea);
   const int64_t zr = (int64_t)(z0 + desc[j].aux) * ea.N;
   const float2* H = ZH + zr;
   const float2* X = ZU + zr;
-  for (int q = threadIdx.x; q < N1 + 1; q += rowb_nt<N1>()) {
+  constexpr int NQ = (N1 + 1 + rowb_nt<N1>() - 1) / rowb_nt<N1>();
+  // pairs whose spectrum loads are in flight together (one within the
+  // 64-register budget of the 2048-point rows)
+  constexpr int QB = rows_bwd_min_waves<N1>() > 4 ? 1 : NQ;
+#pragma unroll
+  for (int k0 = 0; k0 < NQ; k0 += QB) {
+  float2 hA[QB], hB[QB], xA[QB], xB[QB];
+#pragma unroll
+  for (int kq = 0; kq < QB; ++kq) {
+    const int k = k0 + kq;
     int ia, ib;
-    if (!mirror_pair<N1>(p, q, ia, ib)) continue;
+    if (k >= NQ || !mirror_pair<N1>(p, threadIdx.x + k * rowb_nt<N1>(), ia, ib)) continue;
     const int64_t ga = (ia < N1) ? (int64_t)ra * N1 + ia : (int64_t)rb * N1 + (ia - N1);
     const int64_t gb = (ib < N1) ? (int64_t)ra * N1 + ib : (int64_t)rb * N1 + (ib - N1);
+    hA[kq] = H[ga];
+    hB[kq] = H[gb];
+    xA[kq] = X[ga];
+    xB[kq] = X[gb];
+  }
+#pragma unroll
+  for (int kq = 0; kq < QB; ++kq) {
+    const int k = k0 + kq;
+    int ia, ib;
+    if (k >= NQ || !mirror_pair<N1>(p, threadIdx.x + k * rowb_nt<N1>(), ia, ib)) continue;
     const int sa = rslot<N1>(ia), sb = rslot<N1>(ib);
     const float2 za = b1[sa], zb = b1[sb];
-    const float2 ha = H[ga], hb = H[gb];
-    const float2 xa = X[ga], xb = X[gb];
+    const float2 ha = hA[kq], hb = hB[kq];
+    const float2 xa = xA[kq], xb = xB[kq];
     float2 gl, gr, hl, hr, xl, xr;
     // bin k
     split_lr(za, zb, gl, gr);
@@ -685,15 +932,16 @@ __global__ __launch_bounds__(rowb_nt<N1>(), 4) void k_rows_bwd(const float2* __r
     b2[sa] = h_a;
     b2[sb] = h_b;
   }
+  }
   __syncthreads();
   if (want_u) {
     // both products (b1, b2: four consecutive rows) in one batch of
     // transforms: half the barriers, twice the butterflies between them
     row_fft<N1, 4, rowb_nt<N1>(), +1>(buf, tt, ea);
-    store_rows2<N1>(b1, b2, Tu + (int64_t)j * ea.N, Th + (int64_t)j * ea.N, ra, rb, ea);
+    store_rows2<N1, rowb_nt<N1>()>(b1, b2, Tu + (int64_t)j * ea.N, Th + (int64_t)j * ea.N, ra, rb, ea);
   } else {
     row_fft<N1, 2, rowb_nt<N1>(), +1>(b2, tt, ea);
-    store_rows<N1>(b2, Th + (int64_t)j * ea.N, ra, rb, ea);
+    store_rows<N1, rowb_nt<N1>()>(b2, Th + (int64_t)j * ea.N, ra, rb, ea);
   }
 }
 
