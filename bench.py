@@ -479,6 +479,17 @@ def prune_eval(con, B):
         e2.record()
         torch.cuda.synchronize()
     fwd_ms, trial_ms = e0.elapsed_time(e1), e1.elapsed_time(e2)
+    # one more trial batch per kernel class, each class timed by its own
+    # dispatch events (the batch's time by where it goes)
+    by_class = {}
+    for cls in KERNEL_CLASSES:
+        MG.mg_profile_enable(bg.h, cls)
+        con.sess.forward_trials(keep, out)
+        ms, n, _ = MG.mg_profile_read(bg.h)
+        if n:
+            by_class[cls] = round(ms, 3)
+    MG.mg_profile_enable(bg.h, None)
+    torch.cuda.synchronize()
     masks = torch.from_numpy(keep.astype(np.float32)).to("cuda")
     ref = torch.zeros(B, 7, dtype=torch.float64, device="cuda")
     e0.record()
@@ -490,7 +501,8 @@ def prune_eval(con, B):
             "candidates_per_s": round(B / ((fwd_ms + trial_ms) / 1000.0), 1),
             "complete_forwards_ms": round(full_ms, 3),
             "speedup_vs_complete_forwards": round(full_ms / (fwd_ms + trial_ms), 2),
-            "bitwise_equal_to_complete_forwards": bool(torch.equal(out, ref))}
+            "bitwise_equal_to_complete_forwards": bool(torch.equal(out, ref)),
+            "trial_ms_by_class": by_class}
 
 
 def prune_schedule_leg(steps=500, rounds=30, finetune=50, candidates=64, tau=1e-3):
@@ -541,6 +553,9 @@ def main():
     ap.add_argument("--serve-budget-gb", type=float, default=160.0)
     ap.add_argument("--pmc-run", action="store_true",
                     help="for rocprofv3 counter runs: a calibration copy, then --steps steps, nothing else")
+    ap.add_argument("--trials-run", action="store_true",
+                    help="for rocprofv3 kernel traces of the pruning trials: on the full console, --steps "
+                         "times one forward and a batch of --prune-masks trials, nothing else")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py runs on one GPU only: the console of one song lives on one device "
@@ -548,6 +563,19 @@ def main():
         sys.exit(2)
 
     import torch
+    if args.trials_run:
+        fc = Console(torch, "full", max_trials=args.prune_masks)
+        B = min(args.prune_masks, fc.bg.n_proc)
+        cand = fc.MG.mg_prune_candidates(fc.wet.cpu().numpy(), None, np.ones(fc.bg.n_proc, np.uint8), B)
+        keep = np.ones((B, fc.bg.n_proc), np.uint8)
+        keep[np.arange(B), cand] = 0
+        out = torch.zeros(B, 7, dtype=torch.float64, device="cuda")
+        for _ in range(args.steps):
+            fc.sess.forward(fc.dry_d, fc.theta, fc.wet, None, None, fc.losses)
+            fc.sess.forward_trials(keep, out)
+        torch.cuda.synchronize()
+        log(f"trials run: {args.steps} x (one forward + {B} trials) on the full console")
+        return
     con = Console(torch, args.config, max_trials=0)
     cfg = con.cfg
 
