@@ -70,20 +70,63 @@ struct LossArgs {
   const double2* tw;
 };
 
+// The frame kernels run LOSS_NT threads.  Their loops over frame points,
+// bins and (frame, combo, band) items fetch what a batch of iterations reads
+// from global memory (signal, window, tables, target features) before the
+// first is used; the arithmetic and its order are those of one iteration
+// after another.
 template <int N, int FPB>
 __device__ __forceinline__ void load_frames(double2* buf, const LossArgs& a, int f0) {
-  for (int idx = threadIdx.x; idx < FPB * N; idx += blockDim.x) {
-    const int fl = idx / N, t = idx % N;
-    const int f = f0 + fl;
-    double2 z = make_double2(0.0, 0.0);
-    if (f < a.F) {
+  static_assert(FPB * N % LOSS_NT == 0, "whole passes");
+  constexpr int PER = FPB * N / LOSS_NT;
+  constexpr int B = PER < 8 ? PER : 8;
+  static_assert(PER % B == 0, "whole batches");
+#pragma unroll 1
+  for (int k0 = 0; k0 < PER; k0 += B) {
+    float yl[B], yr[B];
+    double wv[B];
+#pragma unroll
+    for (int k = 0; k < B; ++k) {
+      const int idx = threadIdx.x + (k0 + k) * LOSS_NT;
+      const int fl = idx / N, t = idx % N;
+      const int f = f0 + fl;
       const int64_t s = (int64_t)a.skip + (int64_t)f * a.hop + t;
-      const double wv = a.tb.win[t];
-      z = make_double2((double)a.y[s] * wv, (double)a.y[a.L + s] * wv);
+      const bool ok = f < a.F;
+      yl[k] = ok ? a.y[s] : 0.f;
+      yr[k] = ok ? a.y[a.L + s] : 0.f;
+      wv[k] = ok ? a.tb.win[t] : 0.0;
     }
-    buf[fl * loss_bs<N>() + lx(t)] = z;
+#pragma unroll
+    for (int k = 0; k < B; ++k) {
+      const int idx = threadIdx.x + (k0 + k) * LOSS_NT;
+      const int fl = idx / N, t = idx % N;
+      const double2 z = (f0 + fl < a.F) ? make_double2((double)yl[k] * wv[k], (double)yr[k] * wv[k])
+                                        : make_double2(0.0, 0.0);
+      buf[fl * loss_bs<N>() + lx(t)] = z;
+    }
   }
 }
+
+// a (frame, combo, band) item of the Mel stage with what it reads from
+// global memory: the band's first bin, weight offset and width, and the
+// target feature
+struct MelItem {
+  int lo, off, cnt;
+  double yt;
+};
+__device__ __forceinline__ MelItem mel_fetch(const LossArgs& a, int b, int64_t tgt_ix, bool want_tgt) {
+  return MelItem{a.tb.band_lo[b], a.tb.band_off[b], a.tb.band_cnt[b], want_tgt ? a.tgt[tgt_ix] : 0.0};
+}
+template <int N>
+__device__ __forceinline__ double mel_sum(const double* mag, const LossArgs& a, int fl, int x, const MelItem& m) {
+  constexpr int NB = N / 2 + 1;
+  const double* mg = mag + (fl * 4 + x) * NB + m.lo;
+  const double* wt = a.tb.band_w + m.off;
+  double yh = 0.0;
+  for (int j = 0; j < m.cnt; ++j) yh = fma(wt[j], mg[j], yh);
+  return yh;
+}
+constexpr int MEL_B = 4;  // Mel items per thread whose loads are in flight together
 
 // packed spectrum z (bin k) and zm (bin N-k) -> left and right spectra
 __device__ __forceinline__ void split_pair(double2 z, double2 zm, double2& xl, double2& xr) {
@@ -145,16 +188,6 @@ __device__ __forceinline__ void frame_mags_inplace(double2* buf, const LossArgs&
   }
 }
 
-template <int N>
-__device__ __forceinline__ double mel_of(const double* mag, const LossArgs& a, int fl, int x, int b) {
-  constexpr int NB = N / 2 + 1;
-  const double* m = mag + (fl * 4 + x) * NB + a.tb.band_lo[b];
-  const double* wt = a.tb.band_w + a.tb.band_off[b];
-  double yh = 0.0;
-  for (int j = 0; j < a.tb.band_cnt[b]; ++j) yh = fma(wt[j], m[j], yh);
-  return yh;
-}
-
 // LDS of one frame workgroup, in bytes: forward = spectra (the magnitudes
 // are written over them), twiddles, block-sum slots; backward = spectra,
 // twiddles, magnitudes, dL/dYh per (frame, combo, band)
@@ -196,20 +229,32 @@ __device__ __forceinline__ void loss_fwd_body(const LossArgs& a, int blk, double
   __syncthreads();
   double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   const int items = FPB * 4 * a.nm;
-  for (int it = threadIdx.x; it < items; it += LOSS_NT) {
-    const int fl = it / (4 * a.nm), x = (it / a.nm) % 4, b = it % a.nm;
-    const int f = f0 + fl;
-    if (f >= a.F) continue;
-    const double yh = mel_of<N>(mag, a, fl, x, b);
-    double* tp = a.tgt + ((int64_t)f * 4 + x) * a.nm + b;
-    if (MODE == 0) {
-      *tp = yh;
-      acc[x] += yh * yh;
-    } else {
-      const double yt = *tp;
-      acc[x] += fabs(log(yt + LOG_EPS) - log(yh + LOG_EPS));
-      const double dd = yt - yh;
-      acc[4 + x] += dd * dd;
+#pragma unroll 1
+  for (int it0 = threadIdx.x; it0 < items; it0 += MEL_B * LOSS_NT) {
+    MelItem mi[MEL_B];
+#pragma unroll
+    for (int k = 0; k < MEL_B; ++k) {
+      const int it = it0 + k * LOSS_NT;
+      const int fl = it / (4 * a.nm), x = (it / a.nm) % 4, b = it % a.nm;
+      const int f = f0 + fl;
+      if (it < items && f < a.F) mi[k] = mel_fetch(a, b, ((int64_t)f * 4 + x) * a.nm + b, MODE == 1);
+    }
+#pragma unroll
+    for (int k = 0; k < MEL_B; ++k) {
+      const int it = it0 + k * LOSS_NT;
+      const int fl = it / (4 * a.nm), x = (it / a.nm) % 4, b = it % a.nm;
+      const int f = f0 + fl;
+      if (it >= items || f >= a.F) continue;
+      const double yh = mel_sum<N>(mag, a, fl, x, mi[k]);
+      if (MODE == 0) {
+        a.tgt[((int64_t)f * 4 + x) * a.nm + b] = yh;
+        acc[x] += yh * yh;
+      } else {
+        const double yt = mi[k].yt;
+        acc[x] += fabs(log(yt + LOG_EPS) - log(yh + LOG_EPS));
+        const double dd = yt - yh;
+        acc[4 + x] += dd * dd;
+      }
     }
   }
   for (int k = 0; k < 8; ++k) {
@@ -291,18 +336,32 @@ __device__ __forceinline__ void loss_bwd_body(const LossArgs& a, int blk, double
     ksc[x] = D > 0.0 ? 0.25 / (D * (sqrt(Y2) + 1e-12)) : 0.0;
   }
   const int items = FPB * 4 * a.nm;
-  for (int it = threadIdx.x; it < items; it += LOSS_NT) {
-    const int fl = it / (4 * a.nm), x = (it / a.nm) % 4, b = it % a.nm;
-    const int f = f0 + fl;
-    double g = 0.0;
-    if (f < a.F) {
-      const double yh = mel_of<N>(mag, a, fl, x, b);
-      const double yt = a.tgt[((int64_t)f * 4 + x) * a.nm + b];
-      const double dl = log(yh + LOG_EPS) - log(yt + LOG_EPS);
-      const double sg = dl > 0.0 ? 1.0 : (dl < 0.0 ? -1.0 : 0.0);
-      g = kl[x] * sg / (yh + LOG_EPS) + ksc[x] * (yh - yt);
+#pragma unroll 1
+  for (int it0 = threadIdx.x; it0 < items; it0 += MEL_B * LOSS_NT) {
+    MelItem mi[MEL_B];
+#pragma unroll
+    for (int k = 0; k < MEL_B; ++k) {
+      const int it = it0 + k * LOSS_NT;
+      const int fl = it / (4 * a.nm), x = (it / a.nm) % 4, b = it % a.nm;
+      const int f = f0 + fl;
+      if (it < items && f < a.F) mi[k] = mel_fetch(a, b, ((int64_t)f * 4 + x) * a.nm + b, true);
     }
-    dyh[(fl * 4 + x) * 128 + b] = g;
+#pragma unroll
+    for (int k = 0; k < MEL_B; ++k) {
+      const int it = it0 + k * LOSS_NT;
+      if (it >= items) break;
+      const int fl = it / (4 * a.nm), x = (it / a.nm) % 4, b = it % a.nm;
+      const int f = f0 + fl;
+      double g = 0.0;
+      if (f < a.F) {
+        const double yh = mel_sum<N>(mag, a, fl, x, mi[k]);
+        const double yt = mi[k].yt;
+        const double dl = log(yh + LOG_EPS) - log(yt + LOG_EPS);
+        const double sg = dl > 0.0 ? 1.0 : (dl < 0.0 ? -1.0 : 0.0);
+        g = kl[x] * sg / (yh + LOG_EPS) + ksc[x] * (yh - yt);
+      }
+      dyh[(fl * 4 + x) * 128 + b] = g;
+    }
   }
   __syncthreads();
   // per bin pair (k, N-k): dL/dX for l and r, packed Hermitian spectrum
