@@ -125,17 +125,37 @@ __device__ __forceinline__ const float* dyn_input(const DynView& v, const NodeDe
   return v.U + (int64_t)d.in_slot * 2 * v.L;
 }
 
+// The loops over a chunk's samples (DYN_SPT per thread, MG_BLOCK apart)
+// fetch a batch of samples' operands from global memory before the first is
+// used; the arithmetic and its order are those of one sample after another.
+// Two-operand loops take 8 samples per batch, the wider ones 4, so the
+// registers stay within 64 (eight workgroups per CU).
+constexpr int DYN_B2 = 8;
+constexpr int DYN_B6 = 4;
+static_assert(DYN_SPT % DYN_B2 == 0 && DYN_SPT % DYN_B6 == 0, "whole batches");
+
 // Stage the chunk's energy into LDS (padded transpose: sample s of thread t
 // at i * DYN_PAD + t) so each thread walks 16 consecutive samples.
 __device__ __forceinline__ void stage_energy(float* le, const float* u, int64_t cs, int64_t s0, int64_t L) {
-  for (int idx = threadIdx.x; idx < DYN_CH; idx += MG_BLOCK) {
-    const int64_t n = s0 + idx;
-    float e = 0.f;
-    if (n < L) {
-      const float m = u[n] + u[cs + n];
-      e = m * m;
+#pragma unroll 1
+  for (int k0 = 0; k0 < DYN_SPT; k0 += DYN_B2) {
+    float ul[DYN_B2], ur[DYN_B2];
+#pragma unroll
+    for (int k = 0; k < DYN_B2; ++k) {
+      const int64_t n = s0 + threadIdx.x + (k0 + k) * MG_BLOCK;
+      ul[k] = n < L ? u[n] : 0.f;
+      ur[k] = n < L ? u[cs + n] : 0.f;
     }
-    le[(idx % DYN_SPT) * DYN_PAD + idx / DYN_SPT] = e;
+#pragma unroll
+    for (int k = 0; k < DYN_B2; ++k) {
+      const int idx = threadIdx.x + (k0 + k) * MG_BLOCK;
+      float e = 0.f;
+      if (s0 + idx < L) {
+        const float m = ul[k] + ur[k];
+        e = m * m;
+      }
+      le[(idx % DYN_SPT) * DYN_PAD + idx / DYN_SPT] = e;
+    }
   }
 }
 
@@ -238,18 +258,30 @@ __global__ __launch_bounds__(MG_BLOCK) void k_dyn_apply(DynView v, const float* 
   float w = node_w(v.wet, v.mask, d);
   float* y = v.U + (int64_t)d.out_slot * 2 * v.L;
   float* env = v.env ? v.env + (int64_t)(v.env0 + d.aux) * v.L : nullptr;
-  for (int idx = threadIdx.x; idx < DYN_CH; idx += MG_BLOCK) {
-    const int64_t n = s0 + idx;
-    if (n >= v.L) break;
-    const float g = le[(idx % DYN_SPT) * DYN_PAD + idx / DYN_SPT];
-    const float G = logf(g + COMP_EPS);
-    float a0, a1, a2, a3;
-    const float f = curve<GATE>(G, q, a0, a1, a2, a3);
-    const float gain = expf(f - G);
-    const float l = u[n], r = u[cs + n];
-    y[n] = w * gain * l + (1.0f - w) * l;
-    y[v.L + n] = w * gain * r + (1.0f - w) * r;
-    if (env) env[n] = g;
+#pragma unroll 1
+  for (int k0 = 0; k0 < DYN_SPT; k0 += DYN_B2) {
+    float ul[DYN_B2], ur[DYN_B2];
+#pragma unroll
+    for (int k = 0; k < DYN_B2; ++k) {
+      const int64_t n = s0 + threadIdx.x + (k0 + k) * MG_BLOCK;
+      ul[k] = n < v.L ? u[n] : 0.f;
+      ur[k] = n < v.L ? u[cs + n] : 0.f;
+    }
+#pragma unroll
+    for (int k = 0; k < DYN_B2; ++k) {
+      const int idx = threadIdx.x + (k0 + k) * MG_BLOCK;
+      const int64_t n = s0 + idx;
+      if (n >= v.L) break;
+      const float g = le[(idx % DYN_SPT) * DYN_PAD + idx / DYN_SPT];
+      const float G = logf(g + COMP_EPS);
+      float a0, a1, a2, a3;
+      const float f = curve<GATE>(G, q, a0, a1, a2, a3);
+      const float gain = expf(f - G);
+      const float l = ul[k], r = ur[k];
+      y[n] = w * gain * l + (1.0f - w) * l;
+      y[v.L + n] = w * gain * r + (1.0f - w) * r;
+      if (env) env[n] = g;
+    }
   }
 }
 
@@ -278,6 +310,33 @@ struct DynBwdView {
   const float* dyb;  // unused placeholder
 };
 
+// dL/dg of the chunk's samples into LDS (layout of stage_energy); acc as in dyn_dg
+template <int GATE>
+__device__ __forceinline__ void stage_dg(float* lg, const DynParams& q, float w, const float* env, const float* u,
+                                         int64_t cs, const float* dy, int64_t L, int64_t s0, float* acc) {
+#pragma unroll 1
+  for (int k0 = 0; k0 < DYN_SPT; k0 += DYN_B6) {
+    float ge[DYN_B6], ul[DYN_B6], ur[DYN_B6], dl[DYN_B6], dr[DYN_B6];
+#pragma unroll
+    for (int k = 0; k < DYN_B6; ++k) {
+      const int64_t n = s0 + threadIdx.x + (k0 + k) * MG_BLOCK;
+      const bool ok = n < L;
+      ge[k] = ok ? env[n] : 0.f;
+      ul[k] = ok ? u[n] : 0.f;
+      ur[k] = ok ? u[cs + n] : 0.f;
+      dl[k] = ok ? dy[n] : 0.f;
+      dr[k] = ok ? dy[L + n] : 0.f;
+    }
+#pragma unroll
+    for (int k = 0; k < DYN_B6; ++k) {
+      const int idx = threadIdx.x + (k0 + k) * MG_BLOCK;
+      float dg = 0.f;
+      if (s0 + idx < L) dg = dyn_dg<GATE>(q, w, ge[k], ul[k], ur[k], dl[k], dr[k], acc);
+      lg[(idx % DYN_SPT) * DYN_PAD + idx / DYN_SPT] = dg;
+    }
+  }
+}
+
 // pass 1 (reverse): per chunk, lambda at the chunk's first sample from zero
 template <int GATE>
 __global__ __launch_bounds__(MG_BLOCK) void k_dyn_bsum(DynView v, float* __restrict__ sums, int nchunks) {
@@ -291,12 +350,7 @@ __global__ __launch_bounds__(MG_BLOCK) void k_dyn_bsum(DynView v, float* __restr
   const float* dy = v.G + (int64_t)d.gout * 2 * v.L;
   const float* env = v.env + (int64_t)(v.env0 + d.aux) * v.L;
   const int64_t s0 = (int64_t)blockIdx.x * DYN_CH;
-  for (int idx = threadIdx.x; idx < DYN_CH; idx += MG_BLOCK) {
-    const int64_t n = s0 + idx;
-    float dg = 0.f;
-    if (n < v.L) dg = dyn_dg<GATE>(q, w, env[n], u[n], u[cs + n], dy[n], dy[v.L + n], nullptr);
-    lg[(idx % DYN_SPT) * DYN_PAD + idx / DYN_SPT] = dg;
-  }
+  stage_dg<GATE>(lg, q, w, env, u, cs, dy, v.L, s0, nullptr);
   __syncthreads();
   const int t = threadIdx.x;
   float s = 0.f;
@@ -327,12 +381,7 @@ __global__ __launch_bounds__(MG_BLOCK) void k_dyn_bapply(DynView v, const float*
   float* gin = d.gin >= 0 ? v.G + (int64_t)d.gin * 2 * v.L : nullptr;
   const int64_t s0 = (int64_t)blockIdx.x * DYN_CH;
   float acc[4] = {0.f, 0.f, 0.f, 0.f};
-  for (int idx = threadIdx.x; idx < DYN_CH; idx += MG_BLOCK) {
-    const int64_t n = s0 + idx;
-    float dg = 0.f;
-    if (n < v.L) dg = dyn_dg<GATE>(q, w, env[n], u[n], u[cs + n], dy[n], dy[v.L + n], acc);
-    lg[(idx % DYN_SPT) * DYN_PAD + idx / DYN_SPT] = dg;
-  }
+  stage_dg<GATE>(lg, q, w, env, u, cs, dy, v.L, s0, acc);
   __syncthreads();
   const int t = threadIdx.x;
   float s = 0.f;
@@ -358,23 +407,40 @@ __global__ __launch_bounds__(MG_BLOCK) void k_dyn_bapply(DynView v, const float*
   }
   __syncthreads();
   float dth = 0.f;
-  for (int idx = threadIdx.x; idx < DYN_CH; idx += MG_BLOCK) {
-    const int64_t n = s0 + idx;
-    if (n >= v.L) break;
-    const float lm = lg[(idx % DYN_SPT) * DYN_PAD + idx / DYN_SPT];
-    const float l = u[n], r = u[cs + n];
-    const float um = l + r;
-    const float e = um * um;
-    const float gprev = (n > 0) ? env[n - 1] : 0.f;
-    dth += lm * (gprev - e);
-    if (gin) {
-      const float g = env[n];
-      const float G = logf(g + COMP_EPS);
-      float a0, a1, a2, a3;
-      const float gain = expf(curve<GATE>(G, q, a0, a1, a2, a3) - G);
-      const float de2 = q.b * lm * 2.0f * um;
-      gin[n] = (1.0f - w) * dy[n] + w * gain * dy[n] + de2;
-      gin[v.L + n] = (1.0f - w) * dy[v.L + n] + w * gain * dy[v.L + n] + de2;
+#pragma unroll 1
+  for (int k0 = 0; k0 < DYN_SPT; k0 += DYN_B6) {
+    float ul[DYN_B6], ur[DYN_B6], gp[DYN_B6], ge[DYN_B6], dl[DYN_B6], dr[DYN_B6];
+#pragma unroll
+    for (int k = 0; k < DYN_B6; ++k) {
+      const int64_t n = s0 + threadIdx.x + (k0 + k) * MG_BLOCK;
+      const bool ok = n < v.L;
+      ul[k] = ok ? u[n] : 0.f;
+      ur[k] = ok ? u[cs + n] : 0.f;
+      gp[k] = (ok && n > 0) ? env[n - 1] : 0.f;
+      ge[k] = (ok && gin) ? env[n] : 0.f;
+      dl[k] = (ok && gin) ? dy[n] : 0.f;
+      dr[k] = (ok && gin) ? dy[v.L + n] : 0.f;
+    }
+#pragma unroll
+    for (int k = 0; k < DYN_B6; ++k) {
+      const int idx = threadIdx.x + (k0 + k) * MG_BLOCK;
+      const int64_t n = s0 + idx;
+      if (n >= v.L) break;
+      const float lm = lg[(idx % DYN_SPT) * DYN_PAD + idx / DYN_SPT];
+      const float l = ul[k], r = ur[k];
+      const float um = l + r;
+      const float e = um * um;
+      const float gprev = gp[k];
+      dth += lm * (gprev - e);
+      if (gin) {
+        const float g = ge[k];
+        const float G = logf(g + COMP_EPS);
+        float a0, a1, a2, a3;
+        const float gain = expf(curve<GATE>(G, q, a0, a1, a2, a3) - G);
+        const float de2 = q.b * lm * 2.0f * um;
+        gin[n] = (1.0f - w) * dl[k] + w * gain * dl[k] + de2;
+        gin[v.L + n] = (1.0f - w) * dr[k] + w * gain * dr[k] + de2;
+      }
     }
   }
   float* pr = v.part + ((int64_t)blockIdx.y * v.PB + blockIdx.x) * PK;
