@@ -129,7 +129,8 @@ __device__ __forceinline__ const float* dyn_input(const DynView& v, const NodeDe
 // fetch a batch of samples' operands from global memory before the first is
 // used; the arithmetic and its order are those of one sample after another.
 // Two-operand loops take 8 samples per batch, the wider ones 4, so the
-// registers stay within 64 (eight workgroups per CU).
+// registers stay near 64 (eight workgroups per CU; the backward apply takes
+// 65, seven workgroups, as held to 64 it spilled).
 constexpr int DYN_B2 = 8;
 constexpr int DYN_B6 = 4;
 static_assert(DYN_SPT % DYN_B2 == 0 && DYN_SPT % DYN_B6 == 0, "whole batches");

@@ -604,9 +604,10 @@ __device__ __forceinline__ int rslot(int i) {
   return i < N1 ? fslot<N1>(i) : row_len<N1>() + fslot<N1>(i - N1);
 }
 
-// Row loads and stores with NT threads; every thread issues the global loads
-// of all its elements (row data, twiddles) before it uses the first.
-// LEAN: one element's loads in flight, for kernels held to few registers.
+// Row loads and stores with NT threads: every thread issues the global loads
+// of its row elements (all of them) or of their twiddles (two elements at a
+// time) before it uses the first.  LEAN: one element's loads in flight, for
+// kernels held to few registers.
 template <int N1, int NT, bool LEAN = false>
 __device__ __forceinline__ void load_rows(float2* buf, const float2* __restrict__ Tn, int ra, int rb) {
   static_assert(N1 % NT == 0, "whole passes");

@@ -70,11 +70,11 @@ struct LossArgs {
   const double2* tw;
 };
 
-// The frame kernels run LOSS_NT threads.  Their loops over frame points,
-// bins and (frame, combo, band) items fetch what a batch of iterations reads
-// from global memory (signal, window, tables, target features) before the
-// first is used; the arithmetic and its order are those of one iteration
-// after another.
+// The frame kernels run LOSS_NT threads.  Their loops over frame points and
+// over (frame, combo, band) items fetch what a batch of iterations reads
+// from global memory (signal, window, band tables, target features) before
+// the first is used; the arithmetic and its order are those of one
+// iteration after another.
 template <int N, int FPB>
 __device__ __forceinline__ void load_frames(double2* buf, const LossArgs& a, int f0) {
   static_assert(FPB * N % LOSS_NT == 0, "whole passes");
