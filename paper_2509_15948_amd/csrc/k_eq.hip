@@ -16,15 +16,17 @@
 namespace mg {
 
 constexpr int EQ_P = 8192;
-// 16 waves per block, two blocks per CU (one 66 KB window each), so the
-// registers are capped at 64.  The window transform wants 73 (forward) to 81
-// (backward); the rest spill to scratch (16 and 64 bytes per lane), which
-// costs far less than one block per CU: uncapped, the EQ class took twice as
-// long per step.
-constexpr int EQ_NT = 1024;   // forward and spectrum
-constexpr int EQ_BNT = 1024;  // backward: one window in LDS
+// 8 waves per block, two blocks per CU (one 66 KB window each), registers
+// held to 128: the forward takes 106, the backward 128 with a 20-byte spill.
+// With 1024 threads two blocks per CU left 64 registers and both kernels
+// spilled; one 1024-thread block per CU took twice as long per step.
+constexpr int EQ_NT = 512;   // forward and spectrum
+constexpr int EQ_BNT = 512;  // backward: one window in LDS
+// two windows per CU: waves per SIMD the register budget is sized for
+constexpr int EQ_MIN_WAVES = 2 * EQ_NT / 256;
+static_assert(EQ_NT == EQ_BNT, "one budget for both");
 // window elements per thread whose global loads are issued together before
-// any is used (a rolled loop over batches keeps the registers within 64)
+// any is used (a rolled loop over batches bounds the registers they hold)
 constexpr int EQ_LB = 4;
 static_assert(EQ_P % (EQ_NT * EQ_LB) == 0 && EQ_P % (EQ_BNT * EQ_LB) == 0, "whole batches");
 
@@ -83,7 +85,7 @@ __global__ __launch_bounds__(EQ_NT) void k_eq_spec(EqArgs a) {
 }
 
 // forward: grid (nblk, nodes)
-__global__ __launch_bounds__(EQ_NT, 8) void k_eq_fwd(EqArgs a) {
+__global__ __launch_bounds__(EQ_NT, EQ_MIN_WAVES) void k_eq_fwd(EqArgs a) {
   __shared__ float2 buf[EQ_P];
   __shared__ float red[EQ_NT / 64];
   __shared__ TwTab<EQ_P, float2> tt;
@@ -156,7 +158,7 @@ __global__ __launch_bounds__(EQ_NT, 8) void k_eq_fwd(EqArgs a) {
 //   input gradient: gbar over the whole window (packed l + i r) times H_P;
 //   FIR gradient: gbar over the valid part only, times the conjugate of the
 //   input-window spectrum the forward kept, inverse -> lags -half..half.
-__global__ __launch_bounds__(EQ_BNT, 8) void k_eq_bwd(EqArgs a) {
+__global__ __launch_bounds__(EQ_BNT, EQ_MIN_WAVES) void k_eq_bwd(EqArgs a) {
   __shared__ float2 A[EQ_P];
   __shared__ float red[EQ_BNT / 64];
   __shared__ TwTab<EQ_P, float2> tt;

@@ -247,6 +247,6 @@ def test_build_rejects_kernels_that_use_scratch():
     assert scratch_kernels(remarks) == [("_Z5k_twoPf", 64)]
     assert scratch_kernels("") == []
     from paper_2509_15948_amd.build import _allowed
-    assert _allowed("_ZN2mg8k_eq_bwdENS_6EqArgsE") == 64
-    assert _allowed("_ZN2mg8k_eq_fwdENS_6EqArgsE") == 32
+    assert _allowed("_ZN2mg8k_eq_bwdENS_6EqArgsE") == 32
+    assert _allowed("_ZN2mg8k_eq_fwdENS_6EqArgsE") == 0
     assert _allowed("_ZN2mg6k_colsILi1024ELi8ENS_5LdFirEEEvT1_P15HIP_vector_typeIfLj2EENS_10EngineArgsE") == 0
