@@ -32,10 +32,15 @@ namespace mg {
 // pass: 768 threads take one each (512 left half the lanes idle in every
 // second round) and, at 57 KB of LDS, two blocks still fit a CU (24 waves;
 // the large console's step 49.2 -> 48.5 ms)
-constexpr int COL_NT = 1024;
-// two 1024-thread column workgroups per CU (their LDS tiles fit twice): the
-// registers are held to 64
-constexpr int COL_MIN_WAVES = 8;
+// Threads of a column workgroup: 512 for 1024-point columns (two butterflies
+// per thread and pass; 45.05 -> 44.51 ms per step on the 3 x 2^20-point
+// engine), 1024 for shorter ones (the 2^19-point engine's 256-point columns
+// were 0.5 % slower at 512).  Two workgroups per CU (their LDS tiles fit
+// twice), so the registers are held to 128 and 64.
+template <int N2>
+constexpr int col_nt() { return N2 >= 1024 ? 512 : 1024; }
+template <int N2>
+constexpr int col_min_waves() { return 2 * col_nt<N2>() / 256; }
 // elements per thread whose loads are in flight together in the column
 // passes (data, then twiddles): within 64 registers the short columns, whose
 // transforms hold more registers, take smaller batches
@@ -246,6 +251,7 @@ struct LdSignal {
   }
   __device__ Raw fetch(int64_t n) const { return n < v.L ? make_float2(u[n], u[cs + n]) : make_float2(0.f, 0.f); }
   __device__ float2 finish(int64_t, const Raw& r) { return r; }
+  template <int NT>
   __device__ void end(int, int) {}
 };
 
@@ -270,6 +276,7 @@ struct LdFir {
   }
   __device__ float2 finish(int64_t, const Raw& r) { return r; }
   __device__ float2 load(int64_t n) const { return fetch(n); }
+  template <int NT>
   __device__ void end(int, int) {}
 };
 
@@ -317,9 +324,10 @@ struct LdGrad {
     const float rm = kreg * (r.bl + r.br);
     return make_float2(w * r.gl + rm, w * r.gr + rm);
   }
+  template <int NT>
   __device__ void end(int j, int blk) {
-    __shared__ float red[COL_NT];
-    const float s = block_sum<COL_NT>(acc, red);
+    __shared__ float red[NT];
+    const float s = block_sum<NT>(acc, red);
     if (threadIdx.x == 0) part[((int64_t)j * PB + blk) * PK + 2] = s;
   }
 };
@@ -363,10 +371,11 @@ struct StFwd {
     ey += m * m;
     eu += um * um;
   }
+  template <int NT>
   __device__ void end(int j, int blk) {
-    __shared__ float red[COL_NT];
-    const float a = block_sum<COL_NT>(ey, red);
-    const float b = block_sum<COL_NT>(eu, red);
+    __shared__ float red[NT];
+    const float a = block_sum<NT>(ey, red);
+    const float b = block_sum<NT>(eu, red);
     if (threadIdx.x == 0) {
       part[((int64_t)j * PB + blk) * PK + 0] = a;
       part[((int64_t)j * PB + blk) * PK + 1] = b;
@@ -411,6 +420,7 @@ struct StGradU {
     gin[n] = (1.0f - w) * r.x + val.x - kreg * um;
     gin[v.L + n] = (1.0f - w) * r.y + val.y - kreg * um;
   }
+  template <int NT>
   __device__ void end(int, int) {}
 };
 
@@ -434,6 +444,7 @@ struct StGradH {
       o[Nh + i] = val.y;
     }
   }
+  template <int NT>
   __device__ void end(int, int) {}
 };
 
@@ -451,8 +462,9 @@ __device__ __forceinline__ int col_tile(int b, int n) {
 
 // ---------------------------------------------------------------- KA: columns forward
 template <int N2, int TC, typename LD>
-__global__ __launch_bounds__(COL_NT, COL_MIN_WAVES) void k_cols(LD ld, float2* __restrict__ T, EngineArgs ea) {
+__global__ __launch_bounds__(col_nt<N2>(), col_min_waves<N2>()) void k_cols(LD ld, float2* __restrict__ T, EngineArgs ea) {
   constexpr int BS = pad_len<N2, false>() + 1;
+  constexpr int NT = col_nt<N2>();
   __shared__ float2 buf[TC * BS];
   __shared__ TwTab<N2, float2> tt;
   tw_fill<N2>(tt, ea.tw, ea.twdl);
@@ -461,8 +473,8 @@ __global__ __launch_bounds__(COL_NT, COL_MIN_WAVES) void k_cols(LD ld, float2* _
   const int c0 = tile * TC;
   const int N1 = ea.N1;
   ld.begin(j);
-  constexpr int PER = TC * N2 / COL_NT;
-  static_assert(TC * N2 % COL_NT == 0, "a column tile is a whole number of passes");
+  constexpr int PER = TC * N2 / NT;
+  static_assert(TC * N2 % NT == 0, "a column tile is a whole number of passes");
   constexpr int BATCH = cmin(cmin(LD::BATCH, col_batch<N2>()), PER);
   static_assert(PER % BATCH == 0, "whole batches");
 #pragma unroll 1  // one batch of loads in flight at a time
@@ -470,19 +482,19 @@ __global__ __launch_bounds__(COL_NT, COL_MIN_WAVES) void k_cols(LD ld, float2* _
     typename LD::Raw raw[BATCH];
 #pragma unroll
     for (int k = 0; k < BATCH; ++k) {
-      const int idx = threadIdx.x + (k0 + k) * COL_NT;
+      const int idx = threadIdx.x + (k0 + k) * NT;
       raw[k] = ld.fetch((int64_t)(c0 + idx % TC) + (int64_t)N1 * (idx / TC));
     }
 #pragma unroll
     for (int k = 0; k < BATCH; ++k) {
-      const int idx = threadIdx.x + (k0 + k) * COL_NT;
+      const int idx = threadIdx.x + (k0 + k) * NT;
       const int n2 = idx / TC, cc = idx % TC;
       buf[cc * BS + px<N2, false>(n2)] = ld.finish((int64_t)(c0 + cc) + (int64_t)N1 * n2, raw[k]);
     }
   }
-  ld.end(j, tile);
+  ld.template end<NT>(j, tile);
   __syncthreads();
-  fft_lds<N2, TC, BS, COL_NT, -1, eng_pad<N2, false>()>(buf, tt);
+  fft_lds<N2, TC, BS, NT, -1, eng_pad<N2, false>()>(buf, tt);
   float2* Tn = T + (int64_t)j * ea.N;
   constexpr int TB = col_tw_batch<N2>();  // twiddles fetched per batch
   static_assert(PER % TB == 0, "whole batches");
@@ -491,12 +503,12 @@ __global__ __launch_bounds__(COL_NT, COL_MIN_WAVES) void k_cols(LD ld, float2* _
     TwRaw tw[TB];
 #pragma unroll
     for (int k = 0; k < TB; ++k) {
-      const int idx = threadIdx.x + (k0 + k) * COL_NT;
+      const int idx = threadIdx.x + (k0 + k) * NT;
       tw[k] = big_tw_fetch(ea.twhi, ea.twlo, (int64_t)(c0 + idx % TC) * (idx / TC));  // n1 k2 < N
     }
 #pragma unroll
     for (int k = 0; k < TB; ++k) {
-      const int idx = threadIdx.x + (k0 + k) * COL_NT;
+      const int idx = threadIdx.x + (k0 + k) * NT;
       const int k2 = idx / TC, cc = idx % TC;
       const int n1 = c0 + cc;
       Tn[(int64_t)k2 * N1 + n1] = c_mul(buf[cc * BS + px<N2, false>(k2)], big_tw_make(tw[k]));
@@ -506,8 +518,9 @@ __global__ __launch_bounds__(COL_NT, COL_MIN_WAVES) void k_cols(LD ld, float2* _
 
 // ---------------------------------------------------------------- KC: columns inverse
 template <int N2, int TC, typename ST>
-__global__ __launch_bounds__(COL_NT, COL_MIN_WAVES) void k_icols(ST st, const float2* __restrict__ T, EngineArgs ea) {
+__global__ __launch_bounds__(col_nt<N2>(), col_min_waves<N2>()) void k_icols(ST st, const float2* __restrict__ T, EngineArgs ea) {
   constexpr int BS = pad_len<N2, false>() + 1;
+  constexpr int NT = col_nt<N2>();
   __shared__ float2 buf[TC * BS];
   __shared__ TwTab<N2, float2> tt;
   tw_fill<N2>(tt, ea.tw, ea.twdl);
@@ -516,8 +529,8 @@ __global__ __launch_bounds__(COL_NT, COL_MIN_WAVES) void k_icols(ST st, const fl
   const int c0 = tile * TC;
   const int N1 = ea.N1;
   const float2* Tn = T + (int64_t)j * ea.N;
-  constexpr int PER = TC * N2 / COL_NT;
-  static_assert(TC * N2 % COL_NT == 0, "a column tile is a whole number of passes");
+  constexpr int PER = TC * N2 / NT;
+  static_assert(TC * N2 % NT == 0, "a column tile is a whole number of passes");
   constexpr int XB = col_batch<N2>();
   static_assert(PER % XB == 0, "whole batches");
 #pragma unroll 1  // one batch of loads in flight at a time
@@ -525,17 +538,17 @@ __global__ __launch_bounds__(COL_NT, COL_MIN_WAVES) void k_icols(ST st, const fl
     float2 x[XB];
 #pragma unroll
     for (int k = 0; k < XB; ++k) {
-      const int idx = threadIdx.x + (k0 + k) * COL_NT;
+      const int idx = threadIdx.x + (k0 + k) * NT;
       x[k] = Tn[(int64_t)(idx / TC) * N1 + c0 + idx % TC];
     }
 #pragma unroll
     for (int k = 0; k < XB; ++k) {
-      const int idx = threadIdx.x + (k0 + k) * COL_NT;
+      const int idx = threadIdx.x + (k0 + k) * NT;
       buf[(idx % TC) * BS + px<N2, false>(idx / TC)] = x[k];
     }
   }
   __syncthreads();
-  fft_lds<N2, TC, BS, COL_NT, +1, eng_pad<N2, false>()>(buf, tt);
+  fft_lds<N2, TC, BS, NT, +1, eng_pad<N2, false>()>(buf, tt);
   const float sc = 1.0f / (float)ea.N;
   st.begin(j);
   constexpr int BATCH = cmin(cmin(ST::BATCH, col_batch<N2>()), PER);
@@ -545,17 +558,17 @@ __global__ __launch_bounds__(COL_NT, COL_MIN_WAVES) void k_icols(ST st, const fl
     typename ST::Raw raw[BATCH];
 #pragma unroll
     for (int k = 0; k < BATCH; ++k) {
-      const int idx = threadIdx.x + (k0 + k) * COL_NT;
+      const int idx = threadIdx.x + (k0 + k) * NT;
       raw[k] = st.fetch((int64_t)(c0 + idx % TC) + (int64_t)N1 * (idx / TC));
     }
 #pragma unroll
     for (int k = 0; k < BATCH; ++k) {
-      const int idx = threadIdx.x + (k0 + k) * COL_NT;
+      const int idx = threadIdx.x + (k0 + k) * NT;
       const int n2 = idx / TC, cc = idx % TC;
       st.store((int64_t)(c0 + cc) + (int64_t)N1 * n2, c_scale(buf[cc * BS + px<N2, false>(n2)], sc), raw[k]);
     }
   }
-  st.end(j, tile);
+  st.template end<NT>(j, tile);
 }
 
 // ---------------------------------------------------------------- KB: rows
@@ -951,12 +964,12 @@ template <typename LD>
 void run_cols(const Ctx& c, const LD& ld, float2* T, int n, const EngineArgs& ea, double in_bytes) {
   const int N2 = ea.N2;
   const int TC = COL_TILE / N2;
-  dim3 grid(ea.N1 / TC, n), blk(COL_NT);
+  dim3 grid(ea.N1 / TC, n);
   ProfScope ps(c, "conv_cols", (double)n * (in_bytes + 8.0 * ea.N));
   switch (N2) {
-#define MG_CASE(NN)                                                                   \
-  case NN:                                                                            \
-    MG_LAUNCH(c, (k_cols<NN, COL_TILE / NN, LD>), grid, blk, 0, c.st, ld, T, ea); \
+#define MG_CASE(NN)                                                                                      \
+  case NN:                                                                                               \
+    MG_LAUNCH(c, (k_cols<NN, COL_TILE / NN, LD>), grid, dim3(col_nt<NN>()), 0, c.st, ld, T, ea); \
     break;
     MG_CASE(16) MG_CASE(32) MG_CASE(64) MG_CASE(128) MG_CASE(256) MG_CASE(512) MG_CASE(1024)
 #undef MG_CASE
@@ -967,12 +980,12 @@ template <typename ST>
 void run_icols(const Ctx& c, const ST& st, const float2* T, int n, const EngineArgs& ea, double out_bytes) {
   const int N2 = ea.N2;
   const int TC = COL_TILE / N2;
-  dim3 grid(ea.N1 / TC, n), blk(COL_NT);
+  dim3 grid(ea.N1 / TC, n);
   ProfScope ps(c, "conv_icols", (double)n * (out_bytes + 8.0 * ea.N));
   switch (N2) {
-#define MG_CASE(NN)                                                                    \
-  case NN:                                                                             \
-    MG_LAUNCH(c, (k_icols<NN, COL_TILE / NN, ST>), grid, blk, 0, c.st, st, T, ea); \
+#define MG_CASE(NN)                                                                                       \
+  case NN:                                                                                                \
+    MG_LAUNCH(c, (k_icols<NN, COL_TILE / NN, ST>), grid, dim3(col_nt<NN>()), 0, c.st, st, T, ea); \
     break;
     MG_CASE(16) MG_CASE(32) MG_CASE(64) MG_CASE(128) MG_CASE(256) MG_CASE(512) MG_CASE(1024)
 #undef MG_CASE
