@@ -158,7 +158,12 @@ int mg_footprint(const mg_graph* g, int32_t mode, size_t* workspace, size_t* sta
  * target mix (Sec. 5.1, "target features are resident").
  *   reverb_noise dev float[n_reverbs][2][L_r], rows in type_row order of the
  *                reverb nodes: uniform noise for the mid and side FIR (Sec. 3.4)
- *   target       dev float[2][L]: the target mix y                            */
+ *   target       dev float[2][L]: the target mix y
+ * For signals shorter than 2^21 samples the graph also creates a second
+ * stream and its events (once), on which the forward and backward run the
+ * FIR synthesis, FIR spectra and parameter gradients beside the chain; for
+ * longer ones every launch stays on the caller's stream.  Results are the
+ * same either way.                                                          */
 int mg_setup(mg_graph* g, void* workspace, size_t workspace_bytes, int32_t mode,
              const float* reverb_noise, const float* target, void* stream);
 
